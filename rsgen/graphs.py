@@ -1,0 +1,394 @@
+"""Seeded generators of community-structured undirected graphs (inputs only).
+
+Every generator draws from numpy's PCG64 stream (``numpy.random.default_rng``)
+seeded by the caller, so the same seed yields the same arrays on every machine.
+Outputs are canonical CSR graphs: symmetric, rows sorted ascending, no
+self-loops, no duplicate edges, ``int64`` row offsets, ``int32`` column indices
+and ``int32`` community labels.
+
+Workload recipes (stand-ins for the paper's real social graphs, which are not
+available here):
+
+* ``sbm``: stochastic block model.  Each unordered vertex pair is an edge with
+  probability ``p_in`` (same block) or ``p_out`` (different blocks).  The edge
+  count of each kind is drawn from its binomial law and the edges themselves
+  are a uniform random subset of the eligible pairs, which is the same
+  distribution as independent Bernoulli trials.  Vertex ids and community ids
+  are randomly permuted afterwards so the input is not community sorted.
+* ``lfr``: an LFR-style benchmark written from the published model description
+  (power-law degrees, power-law community sizes, a mixing fraction ``mu`` of
+  each vertex's edges leaving its community).  Readings where the model is
+  infeasible or loose are listed in the function docstring.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Graph:
+    """Undirected simple graph in CSR form plus community labels."""
+
+    n: int
+    off: np.ndarray  # int64 [n+1]
+    col: np.ndarray  # int32 [nnz], rows sorted ascending
+    labels: np.ndarray  # int32 [n], non-negative community ids
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.off[-1])
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+    def edges(self):
+        """Return (u, v) arrays of the undirected edges with u < v."""
+        src = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.off))
+        dst = self.col.astype(np.int64)
+        keep = src < dst
+        return src[keep], dst[keep]
+
+
+def canonical_csr(n: int, u, v):
+    """Symmetrise, drop self-loops and duplicates, sort rows; return (off, col)."""
+    u = np.asarray(u, dtype=np.int64).ravel()
+    v = np.asarray(v, dtype=np.int64).ravel()
+    keep = u != v
+    u = u[keep]
+    v = v[keep]
+    a = np.minimum(u, v)
+    b = np.maximum(u, v)
+    del u, v, keep
+    key = np.unique(a * n + b)
+    del a, b
+    a = key // n
+    b = key - a * n
+    del key
+    both = np.concatenate([a * n + b, b * n + a])
+    del a, b
+    both.sort()
+    src = both // n
+    dst = (both - src * n).astype(np.int32)
+    del both
+    off = np.zeros(n + 1, dtype=np.int64)
+    if src.size:
+        np.cumsum(np.bincount(src, minlength=n), out=off[1:])
+    return off, dst
+
+
+def _relabel(rng, n, off, col, labels):
+    """Randomly permute vertex ids and community ids (keeps the graph isomorphic)."""
+    perm = rng.permutation(n).astype(np.int64)  # old -> new
+    src = np.repeat(perm, np.diff(off))
+    dst = perm[col.astype(np.int64)]
+    off2, col2 = canonical_csr(n, src, dst)
+    lab_new = np.empty(n, dtype=np.int64)
+    lab_new[perm] = labels
+    uniq = np.unique(lab_new)
+    cperm = rng.permutation(uniq.size)
+    remap = np.empty(int(uniq.max()) + 1 if uniq.size else 0, dtype=np.int64)
+    remap[uniq] = cperm
+    lab2 = remap[lab_new].astype(np.int32) if n else np.zeros(0, np.int32)
+    return off2, col2, lab2
+
+
+def _distinct(rng, m, draw):
+    """Draw exactly ``m`` distinct int64 keys, each uniformly from ``draw``'s support."""
+    got = np.zeros(0, dtype=np.int64)
+    while got.size < m:
+        need = m - got.size
+        got = np.unique(np.concatenate([got, draw(int(need * 1.05) + 16)]))
+    if got.size > m:
+        got = rng.permutation(got)[:m]
+    return got
+
+
+def sbm(block_sizes, p_in: float, p_out: float, seed: int, permute: bool = True) -> Graph:
+    """Stochastic block model with the given block sizes."""
+    rng = np.random.default_rng(seed)
+    sizes = np.asarray(block_sizes, dtype=np.int64)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(starts[-1])
+    block_of = np.repeat(np.arange(sizes.size, dtype=np.int64), sizes)
+    pair_in = sizes * (sizes - 1) // 2
+    n_in = int(pair_in.sum())
+    n_all = n * (n - 1) // 2
+    n_out = n_all - n_in
+    m_in = int(rng.binomial(n_in, p_in)) if n_in and p_in > 0 else 0
+    m_out = int(rng.binomial(n_out, p_out)) if n_out and p_out > 0 else 0
+    cdf_in = np.cumsum(pair_in) / max(n_in, 1)
+
+    def draw_in(k):
+        blk = np.searchsorted(cdf_in, rng.random(k), side="right")
+        blk = np.minimum(blk, sizes.size - 1)
+        s = sizes[blk]
+        ok = s >= 2
+        blk, s = blk[ok], s[ok]
+        i = (rng.random(blk.size) * s).astype(np.int64)
+        j = (rng.random(blk.size) * (s - 1)).astype(np.int64)
+        j = j + (j >= i)
+        gi = starts[blk] + i
+        gj = starts[blk] + j
+        return np.minimum(gi, gj) * n + np.maximum(gi, gj)
+
+    def draw_out(k):
+        a = rng.integers(0, n, size=k)
+        b = rng.integers(0, n, size=k)
+        ok = block_of[a] != block_of[b]
+        a, b = a[ok], b[ok]
+        return np.minimum(a, b) * n + np.maximum(a, b)
+
+    keys = np.concatenate([
+        _distinct(rng, m_in, draw_in) if m_in else np.zeros(0, np.int64),
+        _distinct(rng, m_out, draw_out) if m_out else np.zeros(0, np.int64),
+    ])
+    u = keys // n if n else keys
+    v = keys - u * n if n else keys
+    off, col = canonical_csr(n, u, v)
+    labels = block_of.astype(np.int32)
+    if permute and n:
+        off, col, labels = _relabel(rng, n, off, col, labels)
+    return Graph(n, off, col, labels, meta={
+        "kind": "sbm", "seed": seed, "blocks": int(sizes.size), "p_in": p_in, "p_out": p_out})
+
+
+def _powerlaw_int(rng, size, lo, hi, expo):
+    vals = np.arange(lo, hi + 1, dtype=np.float64)
+    w = vals ** (-expo)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    idx = np.searchsorted(cdf, rng.random(size), side="right")
+    return (lo + np.minimum(idx, vals.size - 1)).astype(np.int64)
+
+
+def _floor_powerlaw_pmf(x0, hi, expo):
+    """pmf of floor(X) for X with density ~x^-expo on [x0, hi+1)."""
+    a = x0 ** (1.0 - expo)
+    b = (hi + 1.0) ** (1.0 - expo)
+    ks = np.arange(int(np.floor(x0)), hi + 1, dtype=np.float64)
+    lo_edge = np.maximum(ks, x0)
+    hi_edge = ks + 1.0
+    cdf_lo = (a - lo_edge ** (1.0 - expo)) / (a - b)
+    cdf_hi = (a - hi_edge ** (1.0 - expo)) / (a - b)
+    return ks, cdf_hi - cdf_lo
+
+
+def _solve_x0(mean_deg, hi, expo):
+    """x0 such that floor(X) (X ~ x^-expo on [x0, hi+1)) has the requested mean."""
+    lo_x, hi_x = 1.0, float(hi)
+    for _ in range(80):
+        mid = 0.5 * (lo_x + hi_x)
+        ks, p = _floor_powerlaw_pmf(mid, hi, expo)
+        if float((ks * p).sum()) < mean_deg:
+            lo_x = mid
+        else:
+            hi_x = mid
+    return 0.5 * (lo_x + hi_x)
+
+
+def _floor_powerlaw(rng, size, x0, hi, expo):
+    a = x0 ** (1.0 - expo)
+    b = (hi + 1.0) ** (1.0 - expo)
+    x = (a - rng.random(size) * (a - b)) ** (1.0 / (1.0 - expo))
+    return np.minimum(np.floor(x), hi).astype(np.int64)
+
+
+def _pair_internal(rng, stubs, comm):
+    """Pair stubs uniformly at random inside each community; return edge keys (a<b)."""
+    if stubs.size < 2:
+        return np.zeros(0, np.int64)
+    n = comm.size
+    stubs = stubs[rng.permutation(stubs.size)]
+    stubs = stubs[np.argsort(comm[stubs], kind="stable")]
+    sc = comm[stubs]
+    gstart = np.flatnonzero(np.r_[True, sc[1:] != sc[:-1]])
+    glen = np.diff(np.r_[gstart, sc.size])
+    pos = np.arange(sc.size) - np.repeat(gstart, glen)
+    last = np.repeat(glen, glen)
+    first = np.flatnonzero((pos % 2 == 0) & (pos + 1 < last))
+    a, b = stubs[first], stubs[first + 1]
+    ok = a != b
+    a, b = a[ok], b[ok]
+    return np.minimum(a, b) * n + np.maximum(a, b)
+
+
+def _pair_external(rng, stubs, comm, rounds):
+    """Pair stubs uniformly across communities, redrawing same-community pairs."""
+    n = comm.size
+    out = []
+    for _ in range(rounds):
+        if stubs.size < 2:
+            break
+        stubs = stubs[rng.permutation(stubs.size)]
+        h = stubs.size // 2
+        a, b = stubs[:h], stubs[h:2 * h]
+        ok = comm[a] != comm[b]
+        out.append(np.minimum(a[ok], b[ok]) * n + np.maximum(a[ok], b[ok]))
+        stubs = np.concatenate([a[~ok], b[~ok], stubs[2 * h:]])
+    keys = np.concatenate(out) if out else np.zeros(0, np.int64)
+    return keys, stubs.size
+
+
+def _union_keys(keys, add, n):
+    """Sorted union of edge-key sets (duplicates dropped)."""
+    if add.size == 0:
+        return keys
+    add = np.unique(add)
+    if keys.size:
+        pos = np.searchsorted(keys, add)
+        pos = np.minimum(pos, keys.size - 1)
+        add = add[keys[pos] != add]
+    return np.union1d(keys, add) if keys.size else add
+
+
+def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
+        tau1: float = 2.5, tau2: float = 1.5, cmin: int = 50, cmax: int = 20000,
+        ext_rounds: int = 12, repair_rounds: int = 4) -> Graph:
+    """LFR-style graph.
+
+    Steps: (1) degrees i.i.d. as floor(X), X from the power law x^-tau1 on
+    [x_min, max_deg+1), x_min solved so the degree law's mean is ``mean_deg``; (2) each vertex's
+    external degree is mu*d rounded stochastically, the rest is internal;
+    (3) community sizes i.i.d. from s^-tau2 on [cmin, cmax] until they cover n
+    (the last one is trimmed); (4) each vertex joins a random community,
+    chosen with probability proportional to size among communities larger than
+    its internal degree (all communities if none is larger); (5) internal
+    degree is capped at (realised community size - 1) and the excess becomes
+    external (the only way to honour max_deg when it exceeds the largest
+    community); (6) internal stubs are paired uniformly at random inside each
+    community, external stubs uniformly at random across the graph with
+    same-community pairs rejected and redrawn for a bounded number of rounds;
+    (7) self-loops and multi-edges are removed; (8) vertex ids and community
+    ids are randomly permuted.  Realised statistics go to ``meta``.
+    """
+    rng = np.random.default_rng(seed)
+    x0 = _solve_x0(mean_deg, max_deg, tau1)
+    deg = _floor_powerlaw(rng, n, x0, max_deg, tau1)
+    k_ext = np.floor(mu * deg + rng.random(n)).astype(np.int64)
+    k_in = deg - k_ext
+
+    # community sizes
+    sizes = []
+    total = 0
+    est = max(16, int(2 * n / max(cmin, 1)))
+    while total < n:
+        s = _powerlaw_int(rng, est, cmin, cmax, tau2)
+        cs = np.cumsum(s) + total
+        cut = int(np.searchsorted(cs, n, side="left"))
+        if cut < s.size:
+            take = s[: cut + 1].copy()
+            take[-1] -= int(cs[cut] - n)
+            sizes.append(take)
+            total = n
+        else:
+            sizes.append(s)
+            total = int(cs[-1])
+    sizes = np.concatenate(sizes) if sizes else np.zeros(0, np.int64)
+    sizes = sizes[sizes > 0]
+    nc = sizes.size
+    order = np.argsort(-sizes, kind="stable")
+    sizes_desc = sizes[order]
+    csum = np.cumsum(sizes_desc).astype(np.float64)
+    elig = np.searchsorted(-sizes_desc, -k_in, side="left")  # communities with size > k_in
+    elig = np.maximum(elig, 1)
+    pick = np.searchsorted(csum, rng.random(n) * csum[elig - 1], side="right")
+    pick = np.minimum(pick, elig - 1)
+    comm = order[pick].astype(np.int64)
+    real = np.bincount(comm, minlength=nc)
+    cap = np.maximum(real[comm] - 1, 0)
+    over = np.maximum(k_in - cap, 0)
+    k_in = k_in - over
+    k_ext = k_ext + over
+
+    keys = _union_keys(np.zeros(0, np.int64),
+                       _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), k_in), comm), n)
+    ext_keys, left = _pair_external(rng, np.repeat(np.arange(n, dtype=np.int64), k_ext), comm, ext_rounds)
+    keys = _union_keys(keys, ext_keys, n)
+    # repair rounds: stubs lost to self-loops / multi-edges are paired again
+    for _ in range(repair_rounds):
+        a = keys // n
+        b = keys - a * n
+        same = comm[a] == comm[b]
+        r_in = np.bincount(a[same], minlength=n) + np.bincount(b[same], minlength=n)
+        r_ext = np.bincount(a[~same], minlength=n) + np.bincount(b[~same], minlength=n)
+        del a, b, same
+        def_in = np.maximum(k_in - r_in, 0)
+        def_ext = np.maximum(k_ext - r_ext, 0)
+        if def_in.sum() + def_ext.sum() < 2:
+            break
+        add = _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), def_in), comm)
+        add_e, _ = _pair_external(rng, np.repeat(np.arange(n, dtype=np.int64), def_ext), comm, ext_rounds)
+        keys = _union_keys(keys, np.concatenate([add, add_e]), n)
+    u = keys // n
+    v = keys - u * n
+    del keys
+    off, col = canonical_csr(n, u, v)
+    del u, v
+    off, col, labels = _relabel(rng, n, off, col, comm.astype(np.int32))
+    g = Graph(n, off, col, labels, meta={
+        "kind": "lfr", "seed": seed, "n": n, "mean_deg_target": mean_deg, "max_deg": max_deg,
+        "mu_target": mu, "x_min": x0, "communities": int(nc)})
+    g.meta.update(graph_stats(g))
+    return g
+
+
+def random_small(n: int, p: float, k: int, seed: int, label_values=None) -> Graph:
+    """Erdos-Renyi G(n, p) with uniform random labels in [0, k) (tiny test graphs).
+
+    ``label_values`` optionally maps the k labels to arbitrary non-negative ids.
+    """
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < p
+    off, col = canonical_csr(n, iu[keep], ju[keep])
+    lab = rng.integers(0, max(k, 1), size=n)
+    if label_values is not None:
+        lab = np.asarray(label_values, dtype=np.int64)[lab]
+    return Graph(n, off, col, lab.astype(np.int32), meta={"kind": "gnp", "seed": seed})
+
+
+def from_edges(n: int, edges, labels) -> Graph:
+    """Build a Graph from an explicit undirected edge list."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    off, col = canonical_csr(n, e[:, 0], e[:, 1])
+    return Graph(n, off, col, np.asarray(labels, dtype=np.int32), meta={"kind": "explicit"})
+
+
+def graph_stats(g: Graph) -> dict:
+    """Realised size statistics of a graph (counts only, no scoring arithmetic)."""
+    deg = np.diff(g.off)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    inter = int(np.count_nonzero(g.labels[src] != g.labels[g.col])) // 2 if g.n else 0
+    return {
+        "n_real": g.n,
+        "m_real": g.m,
+        "mean_deg_real": float(deg.mean()) if g.n else 0.0,
+        "max_deg_real": int(deg.max()) if g.n else 0,
+        "m_inter": inter,
+        "mu_real": inter / g.m if g.m else 0.0,
+        "communities_real": int(np.unique(g.labels).size) if g.n else 0,
+    }
+
+
+# Named workloads.  Sizes follow the benchmark configurations: a small SBM the
+# oracle scores in well under a second, an LFR-style graph of one million
+# vertices (~10M edges) and one of twenty million vertices (~300M edges).
+
+def cfg_sbm_small(seed: int = 0) -> Graph:
+    """SBM: n=2,000 in 20 planted communities of 100, p_in=0.05, p_out=0.001."""
+    return sbm([100] * 20, 0.05, 0.001, seed)
+
+
+def cfg_lfr_1m(seed: int = 0) -> Graph:
+    """LFR-style: n=1e6, degree law exponent 2.5, mean 20, max 5,000, sizes
+    exponent 1.5 on [50, 20,000], mixing 0.1."""
+    return lfr(1_000_000, 20.0, 5000, 0.1, seed)
+
+
+def cfg_lfr_20m(seed: int = 0) -> Graph:
+    """LFR-style: n=2e7, mean degree 30, max 100,000, mixing 0.15 (same size law)."""
+    return lfr(20_000_000, 30.0, 100_000, 0.15, seed)
