@@ -1,0 +1,211 @@
+"""Benchmark of the RS scoring pass on one MI355X.
+
+One step = one full scoring pass (rs_score: border detection, interaction
+matrix, weights, w_max, type-II aggregate, Eq. RSI scores) plus rs_topk(K) on a
+graph already resident in HBM.  Prints ONE JSON line (rank 0, N=1).
+
+  python bench.py [--steps K] [--warmup W] [--workload lfr_1m|sbm_2k|lfr_20m]
+                  [--no-cpu-baseline] [--copy-calibration]
+
+--copy-calibration runs only a plain device copy of known size, for scaling the
+FETCH_SIZE / WRITE_SIZE counters of rocprofv3 runs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RS-scored edges/sec on 1 MI355X (% HBM roofline); p50/p99 re-score latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "sbm_2k": ("SBM n=2,000, 20 communities of 100, p_in=0.05, p_out=0.001, seed 0", 20),
+    "lfr_1m": ("LFR-style n=1,000,000, degree exponent 2.5 mean 20 max 5,000, community sizes "
+               "exponent 1.5 on [50, 20,000], mixing 0.1, seed 0", 1000),
+    "lfr_20m": ("LFR-style n=20,000,000, mean degree 30, max 100,000, mixing 0.15, seed 0", 10000),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_graph(name):
+    from rsgen import cfg_lfr_1m, cfg_lfr_20m, cfg_sbm_small
+    return {"sbm_2k": cfg_sbm_small, "lfr_1m": cfg_lfr_1m, "lfr_20m": cfg_lfr_20m}[name](0)
+
+
+def kernel_bytes(c, n, nnz, s_off, k_top):
+    """Algorithmic bytes per launch of each kernel: every array the kernel must
+    touch, each element once (gathered arrays counted once at their size)."""
+    nb, ell, ellx, dp = c["n_border"], c["sum_ell"], c["sum_ell_x"], 2 * c["m_inter"]
+    w1, t1 = c["sum_work_I"], c["sum_tI"]
+    rows = (4 * n + s_off * n + 4 * n + 4 * n      # sched, off, deg, labels
+            + 4 * nnz                              # col
+            + 16 * ell                             # records: community, run start, weight
+            + 28 * n                               # ell, (p, q), own weight, a
+            + 4 * nb + 24 * (n - nb))              # border lists, zero scores of non-border
+    sagg = (nb * (4 + s_off + 12)                  # list, off, deg, ell, label
+            + 8 * ell + 4 * dp + 8 * min(n, dp)    # records scanned, foreign columns, a
+            + 8 * ellx)                            # S written
+    score = (nb * (4 + s_off + 24)                 # list, off, deg, label, a, (p, q)
+             + 4 * dp                              # u's foreign columns
+             + dp * (s_off + 16 + 28)              # w's off/ell/deg/(p,q), record key/w/S/pos
+             + 4 * w1 + 24 * t1                    # intersections, type-I lookups
+             + 24 * nb)                            # R, tI, tII
+    topk = 2 * 13 * n + 16 * 2 * k_top + 12 * k_top
+    return {"k_rows": rows, "k_sagg": sagg, "k_score": score, "topk": topk,
+            "pass": rows + sagg + score + topk}
+
+
+def copy_calibration():
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}))
+
+
+def cpu_baseline(g, k_top, budget_s=12.0):
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    times = []
+    t_end = time.perf_counter() + budget_s
+    while True:
+        t0 = time.perf_counter()
+        o = oracle.score(g, nthreads=cores)
+        oracle.topk(o["R"], k_top)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() > t_end or len(times) >= 50:
+            break
+    t = float(np.median(times))
+    return {"value": g.m / t, "unit": "edges/s", "cores": cores, "kind": "oracle",
+            "sample": f"full workload graph, {len(times)} repeats of score + top-{k_top}, median {t:.3f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lfr_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build scores one resident graph per device and "
+              "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+
+    import paper_2508_01485_amd as rs
+
+    desc, k_top = WORKLOADS[args.workload]
+    log("generating", args.workload)
+    t0 = time.perf_counter()
+    g = make_graph(args.workload)
+    log(f"generated n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream)
+    load_s = time.perf_counter() - t0
+    log(f"loaded in {load_s:.2f}s")
+
+    for _ in range(args.warmup):
+        rs.rs_score(h)
+        rs.rs_topk(h, k_top)
+    torch.cuda.synchronize()
+
+    rs.rs_set_timing(h, True)
+    rs.rs_read_timings(h)  # reset
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        rs.rs_score(h)
+        ids, sc = rs.rs_topk(h, k_top)  # waits for the stream
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    timings = rs.rs_read_timings(h)
+    rs.rs_set_timing(h, False)
+    counts = rs.rs_read_counts(h)
+    log("kernel ms/launch:", {k: round(v[0] / v[1], 4) for k, v in timings.items() if v[1]})
+
+    ms_per_step = 1000.0 * t_total / args.steps
+    value = g.m / (t_total / args.steps)
+    s_off = 8 if g.nnz > 2**31 - 1 else 4
+    kb = kernel_bytes(counts, g.n, g.nnz, s_off, k_top)
+    avg_us = {}
+    for name in ("k_rows", "k_sagg", "k_score"):
+        ms, nl = timings[name]
+        avg_us[name] = 1000.0 * ms / max(nl, 1)
+    dom = max(avg_us, key=avg_us.get)
+    achieved = kb[dom] / (avg_us[dom] * 1e-6) / 1e9
+    gpu_ms = sum(v[0] for v in timings.values()) / args.steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {desc}",
+            "n": g.n, "m": g.m, "nnz": g.nnz, "communities": int(counts["n_communities"]),
+            "mean_degree": round(g.nnz / max(g.n, 1), 3), "max_degree": int(np.diff(g.off).max()),
+            "mu_realized": round(2 * counts["m_inter"] / max(g.nnz, 1), 4), "top_k": k_top,
+            "row_offsets": f"int{8 * s_off}",
+        },
+        "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)), "p10": 1000 * float(np.percentile(lat, 10)),
+                       "p90": 1000 * float(np.percentile(lat, 90)), "p99": 1000 * float(np.percentile(lat, 99))},
+        "load_s": load_s,
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": kb[dom], "avg_us": avg_us[dom],
+        },
+        "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]},
+        "pass": {"alg_bytes": kb["pass"], "gpu_ms_per_step": gpu_ms,
+                 "alg_GBs": kb["pass"] / (gpu_ms * 1e-3) / 1e9 if gpu_ms else None},
+        "counts": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in counts.items()},
+    }
+    rs.rs_free_graph(h)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(g, k_top)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

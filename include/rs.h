@@ -1,0 +1,208 @@
+/*
+ * rs.h -- C ABI of the MI355X robust-spanner (RS) scoring library.
+ *
+ * The library scores every vertex of an undirected graph by the Robust
+ * Spanning Index of "A Parallel Algorithm for Finding Robust Spanners in
+ * Large Social Networks" (arXiv 2508.01485) and returns the highest-scoring
+ * vertices.  All compute runs in HIP kernels on one gfx950 device; this
+ * header is the only interface (plain pointers and sizes, no C++ or torch
+ * types).
+ *
+ * Conventions shared by every call
+ *   - Every function returns rs_status.  The library never aborts, never
+ *     throws across this boundary and never prints.  On any error the graph
+ *     state is unchanged; rs_last_error() returns a detail string for the
+ *     calling thread.
+ *   - Vertex ids and community labels at this boundary are always the
+ *     caller's ids.  The library may renumber internally.
+ *   - The caller owns every buffer it passes in or receives into.  The
+ *     library owns the device memory of a graph from rs_load_graph until
+ *     rs_free_graph and never keeps caller pointers.
+ *   - One rs_graph must not be used from two threads at once; distinct
+ *     graphs may be used concurrently.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rs_graph rs_graph; /* one resident graph on one device + its HIP stream */
+
+typedef enum {
+    RS_OK = 0,
+    RS_ERR_ARG = 1,   /* null pointer, negative size, bad flag or width */
+    RS_ERR_GRAPH = 2, /* not a simple undirected graph, or a negative label */
+    RS_ERR_RANGE = 3, /* an id >= n, or n / nnz too large for the offset width */
+    RS_ERR_NOMEM = 4, /* device or host allocation failed */
+    RS_ERR_HIP = 5,   /* a HIP runtime call failed (no device, launch error, ...) */
+    RS_ERR_STATE = 6  /* call out of order (e.g. rs_topk before rs_score) */
+} rs_status;
+
+/*
+ * Input graph: G = (V, E) undirected and simple, stored as CSR, plus one
+ * non-overlapping community label per vertex (Section II; the CSR layout of
+ * Section VI-A; community ids are user input, Section VI-A).
+ *   n            number of vertices, 0 <= n < 2^31
+ *   nnz          number of CSR entries = 2|E|
+ *   offset_bytes 4 (int32) or 8 (int64): element width of row_offsets
+ *   on_device    0: the three arrays are host pointers;
+ *                1: they are HIP device pointers on the current device
+ *   row_offsets  [n+1], row_offsets[0] = 0, non-decreasing, row_offsets[n] = nnz
+ *   col          [nnz] int32 neighbour ids; each row strictly ascending, no
+ *                self-loop, and (u,v) present iff (v,u) present
+ *   labels       [n] int32 community ids, any non-negative values
+ */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    int32_t offset_bytes;
+    int32_t on_device;
+    const void *row_offsets;
+    const int32_t *col;
+    const int32_t *labels;
+} rs_csr;
+
+/*
+ * rs_load_graph: validate the graph, renumber it internally (communities as
+ * contiguous id ranges, rows re-sorted), copy it to device memory and return
+ * a handle.  Returns only after the copies are complete.
+ *   hip_stream  a hipStream_t to run all of this graph's work on, or NULL for
+ *               a library-owned stream
+ *   flags       must be 0
+ * Errors: RS_ERR_ARG, RS_ERR_GRAPH (asymmetric / unsorted / duplicate / self
+ * loop / negative label), RS_ERR_RANGE, RS_ERR_NOMEM, RS_ERR_HIP.  *out is
+ * set to NULL on error.
+ */
+rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_graph **out);
+
+/*
+ * rs_score: one full scoring pass (Algorithm 1, Steps 1-3): border vertices
+ * (Step 1), the per-(vertex, community) interaction matrix of neighbour
+ * community counts and its entropy weights w_v(c) with Algorithm 2's shared
+ * terms and the global w_max (Step 2), the inter-community subgraph G', and
+ * the Robust Spanning Index of Eq. RSI for every vertex, normalized by w_max
+ * (Step 3).  Enqueued on the graph's stream; returns without waiting.
+ */
+rs_status rs_score(rs_graph *g);
+
+/*
+ * rs_topk: the k highest-scoring live vertices (Algorithm 1, Step 4), ordered
+ * by score descending, ties by the smaller caller id.  Writes
+ * min(k, live vertices) entries to the host arrays ids[k] and scores[k] and
+ * that count to *count; waits for the stream.  RS_ERR_STATE before the first
+ * rs_score.
+ */
+rs_status rs_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);
+
+/*
+ * Removal batch (the robustness disruptions of Section VII-B: random edge
+ * and vertex removal).  Host arrays: n_edges pairs (src[i], dst[i]) and
+ * n_vertices vertex ids.  Edges not in the graph are ignored and counted;
+ * repeated entries are idempotent.  A removed vertex loses all its edges,
+ * keeps its label, scores 0 and is excluded from rs_topk.
+ */
+typedef struct {
+    int64_t n_edges;
+    const int32_t *src;
+    const int32_t *dst;
+    int64_t n_vertices;
+    const int32_t *vertices;
+} rs_removals;
+
+typedef struct {
+    int64_t edges_removed;   /* distinct undirected edges deleted (including a removed vertex's edges) */
+    int64_t edges_ignored;   /* batch edge entries that named no existing edge */
+    int64_t vertices_removed;/* vertices newly removed */
+    int64_t affected;        /* vertices whose score was recomputed */
+} rs_removal_result;
+
+/*
+ * rs_apply_removals: validate the whole batch (RS_ERR_RANGE for an id >= n,
+ * RS_ERR_ARG for null arrays with non-zero counts) before mutating anything,
+ * apply it, then re-score so that every reader and rs_topk reflect the
+ * mutated graph exactly as a fresh full rs_score would.  Waits for the
+ * stream.  RS_ERR_STATE before the first rs_score.
+ */
+rs_status rs_apply_removals(rs_graph *g, const rs_removals *batch, rs_removal_result *res);
+
+/*
+ * rs_read_scores: out[n] host array, indexed by caller vertex id.
+ *   raw = 0: R(u) of Algorithm 1 (every triad term divided by w_max);
+ *   raw = 1: the sum of Eq. RSI without the w_max division (= R * w_max).
+ * Waits for the stream.
+ */
+rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw);
+
+typedef struct {
+    int64_t n;              /* vertices */
+    int64_t nnz;            /* live CSR entries (2 |E|) */
+    int64_t n_alive;        /* vertices not removed */
+    int64_t n_communities;  /* distinct labels */
+    int64_t n_border;       /* |V_b| */
+    int64_t m_inter;        /* inter-community edges = |E(G')| / 2 */
+    int64_t sum_ell;        /* stored interaction-matrix entries = sum of distinct neighbour communities */
+    int64_t sum_ell_x;      /* entries whose community is not the vertex's own */
+    int64_t sum_tI;         /* ordered type-I triads over all vertices */
+    int64_t sum_tII;        /* type-II triads over all vertices */
+    int64_t sum_work_I;     /* list elements scanned by the type-I intersections */
+    double omega_max;       /* w_max of the last pass */
+} rs_counts;
+
+/* rs_read_counts: totals of the last rs_score.  Waits for the stream. */
+rs_status rs_read_counts(rs_graph *g, rs_counts *c);
+
+/*
+ * rs_read_vertex_counts: per-vertex integer results of the last pass, host
+ * arrays of length n indexed by caller id; any pointer may be NULL.
+ *   border  1 if the vertex has a neighbour in another community (Step 1)
+ *   ell     distinct communities among its neighbours (the interaction-matrix row length)
+ *   dprime  neighbours in other communities (its degree in G')
+ *   tI, tII ordered type-I / type-II triads counted at the vertex
+ *   w_own   w_v(C(v)), the vertex's weight toward its own community (Lemma 2)
+ */
+rs_status rs_read_vertex_counts(rs_graph *g, int32_t *border, int32_t *ell, int32_t *dprime,
+                                int64_t *tI, int64_t *tII, double *w_own);
+
+/*
+ * rs_read_rows: the sparse interaction matrix of the last pass (Section
+ * VI-A), one row per vertex in caller id order and entries sorted by caller
+ * community label: row_off[n+1] (host), then comm / count / weight arrays of
+ * row_off[n] entries each.  Call first with comm == NULL to get row_off only.
+ */
+rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *count, double *weight);
+
+/*
+ * rs_read_gprime: the inter-community subgraph G' (Section VI-B: edges
+ * (u,v) in E with C(u) != C(v)) as CSR in caller ids with ascending rows:
+ * off[n+1], then col[off[n]].  Call with col == NULL to get off only.
+ */
+rs_status rs_read_gprime(rs_graph *g, int64_t *off, int32_t *col);
+
+/*
+ * Kernel timing.  rs_set_timing(g, 1) makes rs_score / rs_topk record HIP
+ * events around every kernel on the graph's stream; rs_read_timings waits
+ * for the stream, returns for each kernel id i < cap the summed
+ * milliseconds ms[i] and launch count launches[i], and resets the sums.
+ * rs_kernel_name(i) names kernel id i (NULL past the last one).
+ */
+rs_status rs_set_timing(rs_graph *g, int32_t on);
+rs_status rs_read_timings(rs_graph *g, int32_t cap, double *ms, int64_t *launches, int32_t *n_kernels);
+const char *rs_kernel_name(int32_t id);
+
+/* rs_free_graph: release all device memory of g (NULL is ignored). */
+void rs_free_graph(rs_graph *g);
+
+const char *rs_status_string(rs_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *rs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_H */

@@ -1,0 +1,276 @@
+"""MI355X robust-spanner (RS) scoring: Python binding of the C ABI in include/rs.h.
+
+Argument marshalling only: every step of the scoring pass runs in the HIP
+kernels of ``librs.so``.  The functions keep the C names.  Arrays may be numpy
+(host) or torch tensors (host or HIP device; device tensors are passed as
+device pointers).  If ``librs.so`` has not been built this package raises on
+import -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:
+    # torch ships its own HIP runtime.  Importing it first makes librs.so bind
+    # to that same runtime instead of loading a second copy, so one process
+    # has one HIP runtime and torch streams / device pointers are valid here.
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librs.so")
+
+RS_OK, RS_ERR_ARG, RS_ERR_GRAPH, RS_ERR_RANGE, RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_STATE = range(7)
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)} ({detail})")
+        self.status = status
+        self.detail = detail
+
+
+_STATUS = {0: "RS_OK", 1: "RS_ERR_ARG", 2: "RS_ERR_GRAPH", 3: "RS_ERR_RANGE", 4: "RS_ERR_NOMEM",
+           5: "RS_ERR_HIP", 6: "RS_ERR_STATE"}
+
+
+class rs_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
+                ("on_device", ctypes.c_int32), ("row_offsets", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("labels", ctypes.c_void_p)]
+
+
+class rs_removals(ctypes.Structure):
+    _fields_ = [("n_edges", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("n_vertices", ctypes.c_int64), ("vertices", ctypes.c_void_p)]
+
+
+class rs_removal_result(ctypes.Structure):
+    _fields_ = [("edges_removed", ctypes.c_int64), ("edges_ignored", ctypes.c_int64),
+                ("vertices_removed", ctypes.c_int64), ("affected", ctypes.c_int64)]
+
+
+class rs_counts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_alive", ctypes.c_int64),
+                ("n_communities", ctypes.c_int64), ("n_border", ctypes.c_int64),
+                ("m_inter", ctypes.c_int64), ("sum_ell", ctypes.c_int64), ("sum_ell_x", ctypes.c_int64),
+                ("sum_tI", ctypes.c_int64),
+                ("sum_tII", ctypes.c_int64), ("sum_work_I", ctypes.c_int64), ("omega_max", ctypes.c_double)]
+
+
+EXPORTS = [
+    "rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores", "rs_read_counts",
+    "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime", "rs_set_timing", "rs_read_timings",
+    "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
+]
+
+
+def _load_lib(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() (no fallback path exists)")
+    lib = ctypes.CDLL(path)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.rs_load_graph.argtypes = [ctypes.POINTER(rs_csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.rs_score.argtypes = [P]
+    lib.rs_topk.argtypes = [P, I64, P, P, ctypes.POINTER(I64)]
+    lib.rs_apply_removals.argtypes = [P, ctypes.POINTER(rs_removals), ctypes.POINTER(rs_removal_result)]
+    lib.rs_read_scores.argtypes = [P, P, I64, I32]
+    lib.rs_read_counts.argtypes = [P, ctypes.POINTER(rs_counts)]
+    lib.rs_read_vertex_counts.argtypes = [P, P, P, P, P, P, P]
+    lib.rs_read_rows.argtypes = [P, P, P, P, P]
+    lib.rs_read_gprime.argtypes = [P, P, P]
+    lib.rs_set_timing.argtypes = [P, I32]
+    lib.rs_read_timings.argtypes = [P, I32, P, P, ctypes.POINTER(I32)]
+    lib.rs_kernel_name.argtypes = [I32]
+    lib.rs_kernel_name.restype = ctypes.c_char_p
+    lib.rs_free_graph.argtypes = [P]
+    lib.rs_free_graph.restype = None
+    lib.rs_status_string.argtypes = [ctypes.c_int]
+    lib.rs_status_string.restype = ctypes.c_char_p
+    lib.rs_last_error.argtypes = []
+    lib.rs_last_error.restype = ctypes.c_char_p
+    for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
+                 "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
+                 "rs_set_timing", "rs_read_timings"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load_lib()
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != RS_OK:
+        raise RSError(st, where, _lib.rs_last_error().decode())
+
+
+def _ptr(a):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if a is None:
+        return None, 0, None
+    if hasattr(a, "data_ptr"):  # torch tensor
+        t = a.contiguous()
+        return t.data_ptr(), int(t.is_cuda), t
+    arr = np.ascontiguousarray(a)
+    return arr.ctypes.data, 0, arr
+
+
+class RSGraph:
+    """Handle of one resident graph (wraps ``rs_graph*``)."""
+
+    def __init__(self, handle, n, nnz):
+        self.handle = handle
+        self.n = int(n)
+        self.nnz = int(nnz)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def free(self):
+        if self.handle:
+            _lib.rs_free_graph(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rs_load_graph(row_offsets, col, labels, stream=None, flags: int = 0) -> RSGraph:
+    """Load a CSR graph + labels; ``stream`` is a hipStream_t handle (int) or a torch stream."""
+    if hasattr(row_offsets, "element_size"):
+        ob = row_offsets.element_size()
+        n = row_offsets.numel() - 1
+        nnz = col.numel()
+    else:
+        row_offsets = np.ascontiguousarray(row_offsets)
+        if row_offsets.dtype not in (np.int32, np.int64):
+            row_offsets = row_offsets.astype(np.int64)
+        ob = row_offsets.dtype.itemsize
+        n = row_offsets.size - 1
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        nnz = col.size
+    po, d0, k0 = _ptr(row_offsets)
+    pc, d1, k1 = _ptr(col)
+    pl, d2, k2 = _ptr(labels)
+    on_dev = d0
+    if n > 0 and not (d0 == d1 == d2):
+        raise ValueError("row_offsets, col and labels must all be host or all be device arrays")
+    csr = rs_csr(n, nnz, ob, on_dev, po, pc, pl)
+    s = stream
+    if s is not None and hasattr(s, "cuda_stream"):
+        s = s.cuda_stream
+    h = ctypes.c_void_p()
+    _check(_lib.rs_load_graph(ctypes.byref(csr), s, flags, ctypes.byref(h)), "rs_load_graph")
+    del k0, k1, k2
+    return RSGraph(h, n, nnz)
+
+
+def rs_score(g: RSGraph):
+    _check(_lib.rs_score(g.handle), "rs_score")
+
+
+def rs_topk(g: RSGraph, k: int):
+    ids = np.zeros(max(k, 1), np.int32)
+    sc = np.zeros(max(k, 1), np.float64)
+    cnt = ctypes.c_int64(0)
+    _check(_lib.rs_topk(g.handle, k, ids.ctypes.data, sc.ctypes.data, ctypes.byref(cnt)), "rs_topk")
+    return ids[: cnt.value].copy(), sc[: cnt.value].copy()
+
+
+def rs_apply_removals(g: RSGraph, edges=None, vertices=None) -> dict:
+    e = np.zeros((0, 2), np.int32) if edges is None else np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    v = np.zeros(0, np.int32) if vertices is None else np.ascontiguousarray(vertices, dtype=np.int32).ravel()
+    src = np.ascontiguousarray(e[:, 0])
+    dst = np.ascontiguousarray(e[:, 1])
+    b = rs_removals(e.shape[0], src.ctypes.data if e.shape[0] else None,
+                    dst.ctypes.data if e.shape[0] else None, v.size, v.ctypes.data if v.size else None)
+    r = rs_removal_result()
+    _check(_lib.rs_apply_removals(g.handle, ctypes.byref(b), ctypes.byref(r)), "rs_apply_removals")
+    return {k: getattr(r, k) for k, _ in rs_removal_result._fields_}
+
+
+def rs_read_scores(g: RSGraph, raw: bool = False):
+    out = np.zeros(max(g.n, 1), np.float64)
+    _check(_lib.rs_read_scores(g.handle, out.ctypes.data, g.n, int(raw)), "rs_read_scores")
+    return out[: g.n]
+
+
+def rs_read_counts(g: RSGraph) -> dict:
+    c = rs_counts()
+    _check(_lib.rs_read_counts(g.handle, ctypes.byref(c)), "rs_read_counts")
+    return {k: getattr(c, k) for k, _ in rs_counts._fields_}
+
+
+def rs_read_vertex_counts(g: RSGraph) -> dict:
+    nn = max(g.n, 1)
+    out = {"border": np.zeros(nn, np.int32), "ell": np.zeros(nn, np.int32), "dprime": np.zeros(nn, np.int32),
+           "tI": np.zeros(nn, np.int64), "tII": np.zeros(nn, np.int64), "w_own": np.zeros(nn)}
+    _check(_lib.rs_read_vertex_counts(g.handle, *(out[k].ctypes.data for k in
+                                                  ("border", "ell", "dprime", "tI", "tII", "w_own"))),
+           "rs_read_vertex_counts")
+    return {k: v[: g.n] for k, v in out.items()}
+
+
+def rs_read_rows(g: RSGraph):
+    off = np.zeros(g.n + 1, np.int64)
+    _check(_lib.rs_read_rows(g.handle, off.ctypes.data, None, None, None), "rs_read_rows")
+    tot = max(int(off[-1]), 1)
+    comm = np.zeros(tot, np.int32)
+    cnt = np.zeros(tot, np.int32)
+    w = np.zeros(tot)
+    _check(_lib.rs_read_rows(g.handle, off.ctypes.data, comm.ctypes.data, cnt.ctypes.data, w.ctypes.data),
+           "rs_read_rows")
+    t = int(off[-1])
+    return off, comm[:t], cnt[:t], w[:t]
+
+
+def rs_read_gprime(g: RSGraph):
+    off = np.zeros(g.n + 1, np.int64)
+    _check(_lib.rs_read_gprime(g.handle, off.ctypes.data, None), "rs_read_gprime")
+    col = np.zeros(max(int(off[-1]), 1), np.int32)
+    _check(_lib.rs_read_gprime(g.handle, off.ctypes.data, col.ctypes.data), "rs_read_gprime")
+    return off, col[: int(off[-1])]
+
+
+def rs_set_timing(g: RSGraph, on: bool = True):
+    _check(_lib.rs_set_timing(g.handle, int(on)), "rs_set_timing")
+
+
+def rs_read_timings(g: RSGraph) -> dict:
+    ms = np.zeros(64)
+    ln = np.zeros(64, np.int64)
+    nk = ctypes.c_int32(0)
+    _check(_lib.rs_read_timings(g.handle, 64, ms.ctypes.data, ln.ctypes.data, ctypes.byref(nk)), "rs_read_timings")
+    return {_lib.rs_kernel_name(i).decode(): (float(ms[i]), int(ln[i])) for i in range(nk.value)}
+
+
+def rs_kernel_name(i: int):
+    name = _lib.rs_kernel_name(i)
+    return None if name is None else name.decode()
+
+
+def rs_free_graph(g: RSGraph):
+    g.free()
+
+
+def rs_status_string(s: int) -> str:
+    return _lib.rs_status_string(s).decode()
+
+
+def rs_last_error() -> str:
+    return _lib.rs_last_error().decode()

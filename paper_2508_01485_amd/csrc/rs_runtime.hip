@@ -1,0 +1,707 @@
+// rs_runtime.hip -- host side of the RS library: the C ABI of include/rs.h.
+//
+// rs_load_graph validates the caller's CSR (a simple undirected graph,
+// Section II), renumbers it so that every community is a contiguous id range
+// (labels ascending, caller ids ascending inside a community), re-sorts the
+// rows, bins the vertices by degree for the row kernel and uploads everything
+// to device memory owned by the handle.  All later calls run kernels on the
+// graph's stream (rs_kernels.hip); the host only marshals arguments, sizes
+// launches and copies results.
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "rs_internal.h"
+
+namespace rs {
+
+static thread_local std::string g_err;
+
+rs_status fail(rs_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+rs_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return (e == hipErrorOutOfMemory) ? RS_ERR_NOMEM : RS_ERR_HIP;
+}
+
+void clear_error() { g_err.clear(); }
+
+// ------------------------------------------------------------ host threads
+template <class F>
+static void parallel_for(int64_t n, int64_t grain, F &&f) {
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 16u));
+    if (n <= grain || nt == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            int64_t s = next.fetch_add(grain);
+            if (s >= n) break;
+            f(s, std::min(n, s + grain));
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (unsigned i = 1; i < nt; ++i) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+}
+
+// ------------------------------------------------------------ allocation
+// Optional fault injection for tests of the error paths: RS_FAULT_ALLOC=N
+// makes the N-th device allocation of every rs_load_graph call fail.
+static hipError_t dev_alloc(rs_graph *g, void **p, size_t bytes) {
+    *p = nullptr;
+    const long long idx = (long long)g->allocations.size() + 1;
+    if (const char *f = std::getenv("RS_FAULT_ALLOC")) {
+        if (std::atoll(f) == idx) return hipErrorOutOfMemory;
+    }
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e == hipSuccess) g->allocations.push_back(*p);
+    return e;
+}
+
+static void release(rs_graph *g) {
+    if (!g) return;
+    for (void *p : g->allocations) (void)hipFree(p);
+    g->allocations.clear();
+    for (hipEvent_t e : g->timing.pool) (void)hipEventDestroy(e);
+    for (auto &pe : g->timing.pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    g->timing.pool.clear();
+    g->timing.pending.clear();
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    g->stream = nullptr;
+}
+
+// ------------------------------------------------------------ timing
+static hipEvent_t take_event(rs_graph *g) {
+    hipEvent_t e = nullptr;
+    if (!g->timing.pool.empty()) {
+        e = g->timing.pool.back();
+        g->timing.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+void timing_begin(rs_graph *g, int kid, hipEvent_t *ev) {
+    (void)kid;
+    *ev = nullptr;
+    if (!g->timing.on) return;
+    *ev = take_event(g);
+    if (*ev) (void)hipEventRecord(*ev, g->stream);
+}
+
+void timing_end(rs_graph *g, int kid, hipEvent_t ev) {
+    if (!g->timing.on || !ev) return;
+    hipEvent_t e2 = take_event(g);
+    if (!e2) {
+        g->timing.pool.push_back(ev);
+        return;
+    }
+    (void)hipEventRecord(e2, g->stream);
+    g->timing.pending.push_back({kid, {ev, e2}});
+}
+
+// ------------------------------------------------------------ validation
+template <class OffIn>
+static rs_status validate_graph(int64_t n, int64_t nnz, const OffIn *off, const int32_t *col, const int32_t *lab) {
+    if ((int64_t)off[0] != 0) return fail(RS_ERR_GRAPH, "row_offsets[0] != 0");
+    for (int64_t u = 0; u < n; ++u)
+        if ((int64_t)off[u + 1] < (int64_t)off[u])
+            return fail(RS_ERR_GRAPH, "row_offsets decrease at vertex " + std::to_string(u));
+    if ((int64_t)off[n] != nnz) return fail(RS_ERR_GRAPH, "row_offsets[n] != nnz");
+    for (int64_t u = 0; u < n; ++u)
+        if (lab[u] < 0) return fail(RS_ERR_GRAPH, "negative label at vertex " + std::to_string(u));
+    for (int64_t i = 0; i < nnz; ++i)
+        if (col[i] < 0 || col[i] >= n) return fail(RS_ERR_RANGE, "neighbour id out of range at entry " + std::to_string(i));
+    std::atomic<int> bad{0};
+    std::atomic<int64_t> bad_at{-1};
+    parallel_for(n, 4096, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi && !bad.load(std::memory_order_relaxed); ++u) {
+            const int64_t b = (int64_t)off[u], e = (int64_t)off[u + 1];
+            for (int64_t i = b; i < e; ++i) {
+                const int32_t v = col[i];
+                int why = 0;
+                if (v < 0 || v >= n)
+                    why = 3;
+                else if (v == u)
+                    why = 1;
+                else if (i > b && col[i - 1] >= v)
+                    why = 2;
+                else {
+                    const int32_t *rb = col + (int64_t)off[v], *re = col + (int64_t)off[v + 1];
+                    const int32_t *it = std::lower_bound(rb, re, (int32_t)u);
+                    if (it == re || *it != (int32_t)u) why = 4;
+                }
+                if (why) {
+                    int expected = 0;
+                    if (bad.compare_exchange_strong(expected, why)) bad_at.store(u);
+                    return;
+                }
+            }
+        }
+    });
+    switch (bad.load()) {
+        case 0: return RS_OK;
+        case 1: return fail(RS_ERR_GRAPH, "self-loop at vertex " + std::to_string(bad_at.load()));
+        case 2: return fail(RS_ERR_GRAPH, "row not strictly ascending (unsorted or duplicate) at vertex " +
+                                              std::to_string(bad_at.load()));
+        case 3: return fail(RS_ERR_RANGE, "neighbour id out of range in row " + std::to_string(bad_at.load()));
+        default: return fail(RS_ERR_GRAPH, "asymmetric adjacency at vertex " + std::to_string(bad_at.load()));
+    }
+}
+
+// ------------------------------------------------------------ load
+struct HostGraph {
+    std::vector<int64_t> off;   // internal offsets
+    std::vector<int32_t> col;   // internal rows
+    std::vector<int32_t> lab;   // internal community per internal vertex
+    std::vector<int32_t> new2old, old2new, comm2orig;
+    std::vector<int32_t> sched;
+    int64_t bin_lo[kRowBins + 1];
+};
+
+static int row_bin(int64_t d) {
+    for (int b = 0; b < kRowBins - 1; ++b)
+        if (d <= kRowTeam[b]) return b;
+    return kRowBins - 1;
+}
+
+template <class OffIn>
+static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const int32_t *col, const int32_t *lab,
+                                HostGraph &H) {
+    try {
+        // communities: ascending caller label -> internal id 0..k-1
+        H.comm2orig.assign(lab, lab + n);
+        std::sort(H.comm2orig.begin(), H.comm2orig.end());
+        H.comm2orig.erase(std::unique(H.comm2orig.begin(), H.comm2orig.end()), H.comm2orig.end());
+        const int64_t k = (int64_t)H.comm2orig.size();
+        std::vector<int32_t> cid(n);
+        parallel_for(n, 1 << 16, [&](int64_t lo, int64_t hi) {
+            for (int64_t v = lo; v < hi; ++v)
+                cid[v] = (int32_t)(std::lower_bound(H.comm2orig.begin(), H.comm2orig.end(), lab[v]) -
+                                   H.comm2orig.begin());
+        });
+        // vertices: counting sort by community, stable in caller id
+        std::vector<int64_t> start(k + 1, 0);
+        for (int64_t v = 0; v < n; ++v) ++start[cid[v] + 1];
+        for (int64_t c = 0; c < k; ++c) start[c + 1] += start[c];
+        H.new2old.resize(n);
+        H.old2new.resize(n);
+        H.lab.resize(n);
+        {
+            std::vector<int64_t> fill(start.begin(), start.end() - 1);
+            for (int64_t v = 0; v < n; ++v) {
+                const int64_t nv = fill[cid[v]]++;
+                H.new2old[nv] = (int32_t)v;
+                H.old2new[v] = (int32_t)nv;
+                H.lab[nv] = cid[v];
+            }
+        }
+        // rows in internal ids, sorted
+        H.off.assign(n + 1, 0);
+        for (int64_t nv = 0; nv < n; ++nv) {
+            const int64_t v = H.new2old[nv];
+            H.off[nv + 1] = H.off[nv] + ((int64_t)off[v + 1] - (int64_t)off[v]);
+        }
+        H.col.resize(nnz);
+        parallel_for(n, 1024, [&](int64_t lo, int64_t hi) {
+            for (int64_t nv = lo; nv < hi; ++nv) {
+                const int64_t v = H.new2old[nv];
+                const int64_t b = (int64_t)off[v], e = (int64_t)off[v + 1];
+                int32_t *dst = H.col.data() + H.off[nv];
+                for (int64_t i = b; i < e; ++i) dst[i - b] = H.old2new[col[i]];
+                std::sort(dst, dst + (e - b));
+            }
+        });
+        // degree bins of the row kernel, ascending internal id inside a bin
+        int64_t cnt[kRowBins] = {};
+        for (int64_t nv = 0; nv < n; ++nv) ++cnt[row_bin(H.off[nv + 1] - H.off[nv])];
+        H.bin_lo[0] = 0;
+        for (int b = 0; b < kRowBins; ++b) H.bin_lo[b + 1] = H.bin_lo[b] + cnt[b];
+        H.sched.resize(n);
+        int64_t fill[kRowBins];
+        for (int b = 0; b < kRowBins; ++b) fill[b] = H.bin_lo[b];
+        for (int64_t nv = 0; nv < n; ++nv) H.sched[fill[row_bin(H.off[nv + 1] - H.off[nv])]++] = (int32_t)nv;
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
+    }
+    return RS_OK;
+}
+
+static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
+    DeviceGraph &D = g->d;
+    D.n = n;
+    D.nnz = nnz;
+    D.k = (int32_t)H.comm2orig.size();
+    D.off64 = nnz > (int64_t)INT32_MAX;
+    const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
+    const size_t offb = D.off64 ? 8 : 4;
+    struct Req {
+        void **p;
+        size_t bytes;
+    } reqs[] = {
+        {&D.off, offb * (N + 1)},
+        {(void **)&D.deg, 4 * N},
+        {(void **)&D.col, 4 * Z},
+        {(void **)&D.lab, 4 * N},
+        {(void **)&D.new2old, 4 * N},
+        {(void **)&D.alive, N},
+        {(void **)&D.sched, 4 * N},
+        {(void **)&D.hkey, 4 * Z},
+        {(void **)&D.hpos, 4 * Z},
+        {(void **)&D.hw, 8 * Z},
+        {(void **)&D.hS, 8 * Z},
+        {(void **)&D.ell, 4 * N},
+        {(void **)&D.pq, 8 * N},
+        {(void **)&D.wown, 8 * N},
+        {(void **)&D.a, 8 * N},
+        {(void **)&D.R, 8 * N},
+        {(void **)&D.tI, 8 * N},
+        {(void **)&D.tII, 8 * N},
+        {(void **)&D.blist, 4 * N * kScoreBins},
+        {(void **)&D.ctr, sizeof(DevCounters)},
+        {(void **)&D.thist, 4 * (size_t)kTopkBins},
+        {(void **)&D.tstate, sizeof(TopkState)},
+        {(void **)&D.tfinal, sizeof(TopkKey) * N},
+        {(void **)&D.ttie, sizeof(TopkKey) * N},
+        {(void **)&D.ttie2, sizeof(TopkKey) * N},
+        {(void **)&D.tout_ids, 4 * N},
+        {(void **)&D.tout_sc, 8 * N},
+        {(void **)&D.scratch_d, 8 * N},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = dev_alloc(g, r.p, r.bytes);
+        if (e != hipSuccess) return hip_fail(e, "device allocation");
+    }
+    std::vector<int32_t> off32, deg(n);
+    for (int64_t v = 0; v < n; ++v) deg[v] = (int32_t)(H.off[v + 1] - H.off[v]);
+    const void *offsrc = H.off.data();
+    if (!D.off64) {
+        off32.resize(n + 1);
+        for (int64_t v = 0; v <= n; ++v) off32[v] = (int32_t)H.off[v];
+        offsrc = off32.data();
+    }
+    hipStream_t s = g->stream;
+    hipError_t e = hipMemcpyAsync(D.off, offsrc, offb * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(D.deg, deg.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D.col, H.col.data(), 4 * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(D.lab, H.lab.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(D.new2old, H.new2old.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(D.sched, H.sched.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "graph upload");
+    for (int b = 0; b <= kRowBins; ++b) g->row_bin_lo[b] = H.bin_lo[b];
+    g->h_new2old.swap(H.new2old);
+    g->h_old2new.swap(H.old2new);
+    g->h_comm2orig.swap(H.comm2orig);
+    g->n_alive = n;
+    return RS_OK;
+}
+
+template <class OffIn>
+static rs_status load_t(const rs_csr *csr, rs_graph *g) {
+    const int64_t n = csr->n, nnz = csr->nnz;
+    const OffIn *off = (const OffIn *)csr->row_offsets;
+    const int32_t *col = csr->col, *lab = csr->labels;
+    std::vector<OffIn> h_off;
+    std::vector<int32_t> h_col, h_lab;
+    if (csr->on_device) {
+        try {
+            h_off.resize(n + 1);
+            h_col.resize(nnz);
+            h_lab.resize(n);
+        } catch (const std::bad_alloc &) {
+            return fail(RS_ERR_NOMEM, "host staging allocation failed");
+        }
+        hipError_t e = hipMemcpy(h_off.data(), off, sizeof(OffIn) * (n + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && nnz) e = hipMemcpy(h_col.data(), col, 4 * nnz, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && n) e = hipMemcpy(h_lab.data(), lab, 4 * n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "copying the device-resident input graph");
+        off = h_off.data();
+        col = h_col.data();
+        lab = h_lab.data();
+    }
+    rs_status st = validate_graph<OffIn>(n, nnz, off, col, lab);
+    if (st != RS_OK) return st;
+    HostGraph H;
+    st = build_internal<OffIn>(n, nnz, off, col, lab, H);
+    if (st != RS_OK) return st;
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (!g->stream) {
+        e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        g->own_stream = true;
+    }
+    return upload(g, H, n, nnz);
+}
+
+template <class T>
+static hipError_t d2h(std::vector<T> &dst, const void *src, int64_t count) {
+    dst.resize(count);
+    if (!count) return hipSuccess;
+    return hipMemcpy(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost);
+}
+
+static hipError_t read_offsets(rs_graph *g, std::vector<int64_t> &off) {
+    const int64_t n = g->d.n;
+    if (g->d.off64) return d2h(off, g->d.off, n + 1);
+    std::vector<int32_t> o32;
+    hipError_t e = d2h(o32, g->d.off, n + 1);
+    off.assign(o32.begin(), o32.end());
+    return e;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *rs_status_string(rs_status s) {
+    switch (s) {
+        case RS_OK: return "RS_OK";
+        case RS_ERR_ARG: return "RS_ERR_ARG";
+        case RS_ERR_GRAPH: return "RS_ERR_GRAPH";
+        case RS_ERR_RANGE: return "RS_ERR_RANGE";
+        case RS_ERR_NOMEM: return "RS_ERR_NOMEM";
+        case RS_ERR_HIP: return "RS_ERR_HIP";
+        case RS_ERR_STATE: return "RS_ERR_STATE";
+        default: return "RS_ERR_UNKNOWN";
+    }
+}
+
+const char *rs_last_error(void) { return g_err.c_str(); }
+
+rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_graph **out) {
+    clear_error();
+    if (!out) return fail(RS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!csr) return fail(RS_ERR_ARG, "csr is NULL");
+    if (flags != 0) return fail(RS_ERR_ARG, "flags must be 0");
+    if (csr->n < 0 || csr->nnz < 0) return fail(RS_ERR_ARG, "negative n or nnz");
+    if (csr->offset_bytes != 4 && csr->offset_bytes != 8) return fail(RS_ERR_ARG, "offset_bytes must be 4 or 8");
+    if (csr->on_device != 0 && csr->on_device != 1) return fail(RS_ERR_ARG, "on_device must be 0 or 1");
+    if (!csr->row_offsets) return fail(RS_ERR_ARG, "row_offsets is NULL");
+    if (csr->n > 0 && !csr->labels) return fail(RS_ERR_ARG, "labels is NULL");
+    if (csr->nnz > 0 && !csr->col) return fail(RS_ERR_ARG, "col is NULL");
+    if (csr->n > (int64_t)INT32_MAX - 1) return fail(RS_ERR_RANGE, "n does not fit int32 vertex ids");
+    if (csr->offset_bytes == 4 && csr->nnz > (int64_t)INT32_MAX)
+        return fail(RS_ERR_RANGE, "nnz overflows 4-byte row offsets");
+    rs_graph *g = new (std::nothrow) rs_graph();
+    if (!g) return fail(RS_ERR_NOMEM, "handle allocation failed");
+    g->stream = (hipStream_t)hip_stream;  // NULL: created after validation
+    rs_status st = csr->offset_bytes == 8 ? load_t<int64_t>(csr, g) : load_t<int32_t>(csr, g);
+    if (st != RS_OK) {
+        std::string keep = g_err;
+        release(g);
+        delete g;
+        g_err = keep;
+        return st;
+    }
+    *out = g;
+    return RS_OK;
+}
+
+void rs_free_graph(rs_graph *g) {
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    release(g);
+    delete g;
+}
+
+rs_status rs_score(rs_graph *g) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    rs_status st = launch_score_pass(g);
+    if (st == RS_OK) g->scored = true;
+    return st;
+}
+
+rs_status rs_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count) {
+    clear_error();
+    if (!g || !count) return fail(RS_ERR_ARG, "graph or count is NULL");
+    if (k < 0) return fail(RS_ERR_ARG, "k < 0");
+    if (k > 0 && (!ids || !scores)) return fail(RS_ERR_ARG, "ids or scores is NULL");
+    if (!g->scored) return fail(RS_ERR_STATE, "rs_topk before rs_score");
+    int64_t cnt = 0;
+    rs_status st = launch_topk(g, k, &cnt);
+    if (st != RS_OK) return st;
+    if (cnt > 0) {
+        hipError_t e = hipMemcpyAsync(ids, g->d.tout_ids, 4 * cnt, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(scores, g->d.tout_sc, 8 * cnt, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) return hip_fail(e, "top-k copy");
+    }
+    *count = cnt;
+    return RS_OK;
+}
+
+rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result *res) {
+    clear_error();
+    if (!g || !b) return fail(RS_ERR_ARG, "graph or batch is NULL");
+    if (!g->scored) return fail(RS_ERR_STATE, "rs_apply_removals before rs_score");
+    if (b->n_edges < 0 || b->n_vertices < 0) return fail(RS_ERR_ARG, "negative batch size");
+    if (b->n_edges > 0 && (!b->src || !b->dst)) return fail(RS_ERR_ARG, "edge arrays are NULL");
+    if (b->n_vertices > 0 && !b->vertices) return fail(RS_ERR_ARG, "vertex array is NULL");
+    const int64_t n = g->d.n;
+    std::vector<int32_t> es, ed, vs;
+    try {
+        es.resize(b->n_edges);
+        ed.resize(b->n_edges);
+        vs.resize(b->n_vertices);
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host staging allocation failed");
+    }
+    for (int64_t i = 0; i < b->n_edges; ++i) {
+        const int32_t a = b->src[i], c = b->dst[i];
+        if (a < 0 || a >= n || c < 0 || c >= n) return fail(RS_ERR_RANGE, "edge endpoint out of range");
+        es[i] = g->h_old2new[a];
+        ed[i] = g->h_old2new[c];
+    }
+    for (int64_t i = 0; i < b->n_vertices; ++i) {
+        const int32_t x = b->vertices[i];
+        if (x < 0 || x >= n) return fail(RS_ERR_RANGE, "vertex id out of range");
+        vs[i] = g->h_old2new[x];
+    }
+    std::sort(vs.begin(), vs.end());
+    vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+    const int64_t m = b->n_edges, nv = (int64_t)vs.size();
+    int32_t *d_buf = nullptr;
+    unsigned long long *d_cnt = nullptr;
+    hipError_t e = hipMalloc((void **)&d_buf, 4 * (size_t)std::max<int64_t>(2 * m + nv, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_cnt, 4 * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        if (d_buf) (void)hipFree(d_buf);
+        return hip_fail(e, "removal staging");
+    }
+    if (m) e = hipMemcpyAsync(d_buf, es.data(), 4 * m, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && m) e = hipMemcpyAsync(d_buf + m, ed.data(), 4 * m, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && nv) e = hipMemcpyAsync(d_buf + 2 * m, vs.data(), 4 * nv, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long), g->stream);
+    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "removal upload");
+    if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
+    if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
+    if (st == RS_OK) st = launch_compact_rows(g);
+    if (st == RS_OK) st = launch_score_pass(g);
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    if (st == RS_OK) {
+        e = hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "removal result");
+    }
+    (void)hipFree(d_buf);
+    (void)hipFree(d_cnt);
+    if (st != RS_OK) return st;
+    g->n_alive -= (int64_t)cnt[3];
+    if (res) {
+        res->edges_removed = (int64_t)(cnt[0] + cnt[2]);
+        res->edges_ignored = m - (int64_t)cnt[0];
+        res->vertices_removed = (int64_t)cnt[3];
+        res->affected = n;
+    }
+    return RS_OK;
+}
+
+rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw) {
+    clear_error();
+    if (!g || (!out && n > 0)) return fail(RS_ERR_ARG, "graph or out is NULL");
+    if (n != g->d.n) return fail(RS_ERR_ARG, "n does not match the graph");
+    if (!g->scored) return fail(RS_ERR_STATE, "rs_read_scores before rs_score");
+    if (n == 0) return RS_OK;
+    rs_status st = launch_gather_scores(g, g->d.scratch_d, raw ? 1 : 0);
+    if (st != RS_OK) return st;
+    hipError_t e = hipMemcpyAsync(out, g->d.scratch_d, 8 * n, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? RS_OK : hip_fail(e, "score copy");
+}
+
+rs_status rs_read_counts(rs_graph *g, rs_counts *c) {
+    clear_error();
+    if (!g || !c) return fail(RS_ERR_ARG, "graph or counts is NULL");
+    DevCounters dc;
+    hipError_t e = hipMemcpyAsync(&dc, g->d.ctr, sizeof(dc), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "counter copy");
+    std::vector<int32_t> deg(g->d.n);
+    if (g->d.n) {
+        e = hipMemcpy(deg.data(), g->d.deg, 4 * g->d.n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "degree copy");
+    }
+    int64_t live = 0;
+    for (int32_t d : deg) live += d;
+    c->n = g->d.n;
+    c->nnz = live;
+    c->n_alive = g->n_alive;
+    c->n_communities = g->d.k;
+    c->n_border = (int64_t)dc.n_border;
+    c->m_inter = (int64_t)dc.sum_dprime / 2;
+    c->sum_ell = (int64_t)dc.sum_ell;
+    c->sum_ell_x = (int64_t)dc.sum_ell_x;
+    c->sum_tI = (int64_t)dc.sum_tI;
+    c->sum_tII = (int64_t)dc.sum_tII;
+    c->sum_work_I = (int64_t)dc.sum_workI;
+    double w;
+    std::memcpy(&w, &dc.wmax_bits, sizeof(w));
+    c->omega_max = w;
+    return RS_OK;
+}
+
+rs_status rs_read_vertex_counts(rs_graph *g, int32_t *border, int32_t *ell, int32_t *dprime, int64_t *tI,
+                                int64_t *tII, double *w_own) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
+    const int64_t n = g->d.n;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    std::vector<int32_t> hell, hpq, hdeg;
+    std::vector<long long> htI, htII;
+    std::vector<double> hw;
+    if (e == hipSuccess) e = d2h(hell, g->d.ell, n);
+    if (e == hipSuccess) e = d2h(hpq, g->d.pq, 2 * n);
+    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = d2h(htI, g->d.tI, n);
+    if (e == hipSuccess) e = d2h(htII, g->d.tII, n);
+    if (e == hipSuccess) e = d2h(hw, g->d.wown, n);
+    if (e != hipSuccess) return hip_fail(e, "vertex count copy");
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t x = g->h_old2new[v];
+        const int32_t dp = hdeg[x] - (hpq[2 * x + 1] - hpq[2 * x]);
+        if (border) border[v] = dp > 0;
+        if (ell) ell[v] = hell[x];
+        if (dprime) dprime[v] = dp;
+        if (tI) tI[v] = dp > 0 ? htI[x] : 0;
+        if (tII) tII[v] = dp > 0 ? htII[x] : 0;
+        if (w_own) w_own[v] = hw[x];
+    }
+    return RS_OK;
+}
+
+rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *count, double *weight) {
+    clear_error();
+    if (!g || !row_off) return fail(RS_ERR_ARG, "graph or row_off is NULL");
+    if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
+    const int64_t n = g->d.n;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    std::vector<int32_t> hell, hdeg;
+    std::vector<int64_t> off;
+    if (e == hipSuccess) e = d2h(hell, g->d.ell, n);
+    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = read_offsets(g, off);
+    if (e != hipSuccess) return hip_fail(e, "row copy");
+    row_off[0] = 0;
+    for (int64_t v = 0; v < n; ++v) row_off[v + 1] = row_off[v] + hell[g->h_old2new[v]];
+    if (!comm && !count && !weight) return RS_OK;
+    std::vector<int32_t> hkey, hpos;
+    std::vector<double> hw;
+    e = d2h(hkey, g->d.hkey, g->d.nnz);
+    if (e == hipSuccess) e = d2h(hpos, g->d.hpos, g->d.nnz);
+    if (e == hipSuccess) e = d2h(hw, g->d.hw, g->d.nnz);
+    if (e != hipSuccess) return hip_fail(e, "row copy");
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t x = g->h_old2new[v];
+        const int64_t rb = off[x];
+        const int32_t L = hell[x];
+        for (int32_t r = 0; r < L; ++r) {
+            const int64_t o = row_off[v] + r;
+            if (comm) comm[o] = g->h_comm2orig[hkey[rb + r]];
+            if (count) count[o] = ((r + 1 < L) ? hpos[rb + r + 1] : hdeg[x]) - hpos[rb + r];
+            if (weight) weight[o] = hw[rb + r];
+        }
+    }
+    return RS_OK;
+}
+
+rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
+    clear_error();
+    if (!g || !goff) return fail(RS_ERR_ARG, "graph or off is NULL");
+    if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
+    const int64_t n = g->d.n;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    std::vector<int32_t> hpq, hdeg, hcol;
+    std::vector<int64_t> off;
+    if (e == hipSuccess) e = d2h(hpq, g->d.pq, 2 * n);
+    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = read_offsets(g, off);
+    if (e != hipSuccess) return hip_fail(e, "G' copy");
+    goff[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t x = g->h_old2new[v];
+        goff[v + 1] = goff[v] + hdeg[x] - (hpq[2 * x + 1] - hpq[2 * x]);
+    }
+    if (!gcol) return RS_OK;
+    e = d2h(hcol, g->d.col, g->d.nnz);
+    if (e != hipSuccess) return hip_fail(e, "G' copy");
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t x = g->h_old2new[v];
+        const int64_t rb = off[x];
+        int64_t o = goff[v];
+        for (int32_t j = 0; j < hdeg[x]; ++j) {
+            if (j >= hpq[2 * x] && j < hpq[2 * x + 1]) continue;
+            gcol[o++] = g->h_new2old[hcol[rb + j]];
+        }
+        std::sort(gcol + goff[v], gcol + goff[v + 1]);
+    }
+    return RS_OK;
+}
+
+static const char *kKernelNames[K_COUNT] = {
+    "k_init", "k_rows", "k_sagg", "k_score", "k_topk_hist", "k_topk_find",
+    "k_topk_collect", "k_pair_rank(tie)", "k_pair_rank(final)", "k_mutate", "k_util"};
+
+const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
+
+rs_status rs_set_timing(rs_graph *g, int32_t on) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    g->timing.on = on != 0;
+    return RS_OK;
+}
+
+rs_status rs_read_timings(rs_graph *g, int32_t cap, double *ms, int64_t *launches, int32_t *n_kernels) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "timing sync");
+    for (auto &pe : g->timing.pending) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
+            g->timing.ms[pe.first] += t;
+            g->timing.launches[pe.first] += 1;
+        }
+        g->timing.pool.push_back(pe.second.first);
+        g->timing.pool.push_back(pe.second.second);
+    }
+    g->timing.pending.clear();
+    for (int i = 0; i < K_COUNT && i < cap; ++i) {
+        if (ms) ms[i] = g->timing.ms[i];
+        if (launches) launches[i] = g->timing.launches[i];
+    }
+    for (int i = 0; i < K_COUNT; ++i) {
+        g->timing.ms[i] = 0;
+        g->timing.launches[i] = 0;
+    }
+    if (n_kernels) *n_kernels = K_COUNT;
+    return RS_OK;
+}
+
+}  // extern "C"

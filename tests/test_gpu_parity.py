@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from rsgen import cfg_lfr_1m, cfg_sbm_small, from_edges, lfr, random_small, sbm
+from tests.parity import compare, gpu_run, rel_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_2508_01485_amd as m
+    return m
+
+
+def _check(g, k, name):
+    _say(f"[parity] {name}: n={g.n} nnz={g.nnz} k={k}")
+    gpu = gpu_run(g, k)
+    ora = oracle.score(g, rows=True)
+    diag = compare(g, gpu, ora, k)
+    _say(f"[parity] {name}: ok {diag}")
+    return gpu, ora, diag
+
+
+def test_k4_closed_form(rs):
+    g = from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], [7, 1, 5, 3])
+    gpu, ora, _ = _check(g, 4, "k4")
+    np.testing.assert_allclose(gpu["R"], 2 / (3 * np.log2(3)), rtol=1e-12)
+    assert list(gpu["ids"]) == [0, 1, 2, 3]
+
+
+def test_sbm_small_config(rs):
+    g = cfg_sbm_small(0)
+    _check(g, 20, "sbm n=2000")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_graphs(rs, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    g = random_small(n, float(rng.uniform(0.005, 0.3)), int(rng.integers(1, 12)), 40_000 + seed,
+                     label_values=rng.permutation(100_000)[:12] * 7)
+    _check(g, int(rng.integers(1, n + 5)), f"gnp seed={seed}")
+
+
+def test_empty_and_edgeless(rs):
+    g = from_edges(0, np.zeros((0, 2)), [])
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    rs.rs_score(h)
+    ids, sc = rs.rs_topk(h, 5)
+    assert ids.size == 0 and rs.rs_read_scores(h).size == 0
+    h.free()
+    g = from_edges(9, np.zeros((0, 2)), [3, 1, 4, 1, 5, 9, 2, 6, 5])
+    gpu, ora, _ = _check(g, 4, "edgeless")
+    assert list(gpu["ids"]) == [0, 1, 2, 3]
+
+
+def test_single_and_two_communities(rs):
+    for k in (1, 2):
+        g = random_small(120, 0.1, k, 77 + k)
+        gpu, ora, _ = _check(g, 10, f"{k} communities")
+        assert np.all(gpu["R"] == 0.0)
+
+
+def test_hubs_and_long_rows(rs):
+    """Rows longer than a wavefront (multi-chunk path) and a hub of degree > 2048."""
+    rng = np.random.default_rng(5)
+    n = 6000
+    base = random_small(n, 0.0008, 40, 55)
+    u, v = base.edges()
+    hub_edges = [(0, int(x)) for x in rng.choice(np.arange(1, n), 2500, replace=False)]
+    mid_edges = [(1, int(x)) for x in rng.choice(np.arange(2, n), 300, replace=False)]
+    e = np.concatenate([np.stack([u, v], 1), np.array(hub_edges), np.array(mid_edges)])
+    g = from_edges(n, e, base.labels)
+    _check(g, 50, "hubs")
+
+
+def test_lfr_small(rs):
+    g = lfr(30000, 20.0, 800, 0.2, seed=3, cmin=20, cmax=2000)
+    _check(g, 100, "lfr n=30000")
+
+
+def test_sbm_uneven_dense_inter(rs):
+    g = sbm([5, 40, 300, 25, 80, 2], 0.3, 0.05, 9)
+    _check(g, 30, "sbm uneven")
+
+
+def test_many_exact_ties_small_class(rs):
+    """400 disjoint K4s with the same labels: every vertex has the same score;
+    the top-k must follow caller ids (tie class smaller than the pairwise cap)."""
+    edges, labels = [], []
+    for c in range(400):
+        b = 4 * c
+        edges += [(b + i, b + j) for i in range(4) for j in range(i + 1, 4)]
+        labels += [0, 1, 2, 3]
+    g = from_edges(1600, edges, labels)
+    gpu, ora, _ = _check(g, 37, "k4 x400")
+    assert list(gpu["ids"]) == list(range(37))
+
+
+def test_many_exact_ties_refine_path(rs):
+    """A tie class larger than the pairwise ranker (5,000 K4s = 20,000 equal
+    scores) goes through the digit-by-digit refinement."""
+    edges, labels = [], []
+    for c in range(5000):
+        b = 4 * c
+        edges += [(b + i, b + j) for i in range(4) for j in range(i + 1, 4)]
+        labels += [0, 1, 2, 3]
+    g = from_edges(20000, edges, labels)
+    gpu, ora, _ = _check(g, 123, "k4 x5000")
+    assert list(gpu["ids"]) == list(range(123))
+
+
+def test_k_larger_than_nonzero_scores(rs):
+    """More requested than non-zero scores: zero-score vertices follow by id."""
+    g = random_small(200, 0.01, 6, 123)
+    gpu, ora, _ = _check(g, 200, "k=n")
+    assert gpu["ids"].size == 200
+
+
+def test_deterministic_bits(rs):
+    g = lfr(20000, 15.0, 400, 0.3, seed=11, cmin=10, cmax=500)
+    a = gpu_run(g, 50)
+    b = gpu_run(g, 50)
+    assert a["R"].tobytes() == b["R"].tobytes()
+    assert np.array_equal(a["ids"], b["ids"])
+
+
+def test_device_resident_input_and_torch_stream(rs):
+    import torch
+    g = cfg_sbm_small(1)
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    h = rs.rs_load_graph(torch.from_numpy(g.off).to(dev), torch.from_numpy(g.col).to(dev),
+                         torch.from_numpy(g.labels).to(dev), stream=s)
+    rs.rs_score(h)
+    ids, _ = rs.rs_topk(h, 20)
+    R = rs.rs_read_scores(h)
+    h.free()
+    ora = oracle.score(g)
+    rel_close(R, ora["R"], 1e-6)
+    assert list(ids) == list(oracle.topk(ora["R"], 20)[0])
+
+
+def test_removals_equal_fresh_load(rs):
+    """rs_apply_removals then reading == loading the mutated graph from scratch
+    (bit-identical scores), and both match the oracle."""
+    g = lfr(20000, 12.0, 300, 0.25, seed=21, cmin=10, cmax=400)
+    rng = np.random.default_rng(4)
+    u, v = g.edges()
+    pick = rng.choice(u.size, 500, replace=False)
+    rem_e = np.stack([u[pick], v[pick]], 1)
+    rem_e = np.concatenate([rem_e, rem_e[:20, ::-1], [[0, 0], [1, 2]]])  # repeats, reversed, absent
+    rem_v = rng.choice(g.n, 30, replace=False)
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    rs.rs_score(h)
+    res = rs.rs_apply_removals(h, edges=rem_e, vertices=rem_v)
+    R1 = rs.rs_read_scores(h)
+    ids1, _ = rs.rs_topk(h, 100)
+    h.free()
+    # the mutated graph, built on the host
+    keep = np.ones(u.size, bool)
+    keep[pick] = False
+    dead = np.zeros(g.n, bool)
+    dead[rem_v] = True
+    keep &= ~dead[u] & ~dead[v]
+    g2 = from_edges(g.n, np.stack([u[keep], v[keep]], 1), g.labels)
+    assert res["edges_removed"] == u.size - int(keep.sum())
+    assert res["vertices_removed"] == 30
+    h2 = rs.rs_load_graph(g2.off, g2.col, g2.labels)
+    rs.rs_score(h2)
+    R2 = rs.rs_read_scores(h2)
+    h2.free()
+    assert R1.tobytes() == R2.tobytes()
+    ora = oracle.score(g2)
+    rel_close(R1, ora["R"], 1e-6)
+    alive = (~dead).astype(np.uint8)
+    exp_ids, _ = oracle.topk(ora["R"], 100, alive=alive)
+    from tests.parity import topk_matches
+    topk_matches(ids1, exp_ids, ora["R"], 100, alive=alive)
+    assert not np.isin(ids1, rem_v).any()
+
+
+def test_error_paths_on_device(rs):
+    g = cfg_sbm_small(2)
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_topk(h, 5)
+    assert ei.value.status == rs.RS_ERR_STATE
+    rs.rs_score(h)
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_apply_removals(h, edges=[[0, g.n]])
+    assert ei.value.status == rs.RS_ERR_RANGE
+    before = rs.rs_read_scores(h)
+    assert rs.rs_read_scores(h).tobytes() == before.tobytes()  # unchanged after the refused batch
+    h.free()
+    os.environ["RS_FAULT_ALLOC"] = "3"
+    try:
+        with pytest.raises(rs.RSError) as ei:
+            rs.rs_load_graph(g.off, g.col, g.labels)
+        assert ei.value.status == rs.RS_ERR_NOMEM
+    finally:
+        del os.environ["RS_FAULT_ALLOC"]
+
+
+@pytest.mark.slow
+def test_lfr_1m_full_parity(rs):
+    _say("[parity] generating LFR n=1e6")
+    g = cfg_lfr_1m(0)
+    _check(g, 1000, "lfr n=1e6")
