@@ -172,13 +172,13 @@ struct HostGraph {
     std::vector<int32_t> lab;   // internal community per internal vertex
     std::vector<int32_t> new2old, old2new, comm2orig;
     std::vector<int32_t> sched;
-    int64_t bin_lo[kRowBins + 1];
+    int64_t bin_lo[kBins + 1];
 };
 
-static int row_bin(int64_t d) {
-    for (int b = 0; b < kRowBins - 1; ++b)
-        if (d <= kRowTeam[b]) return b;
-    return kRowBins - 1;
+static int degree_bin(int64_t d) {
+    for (int b = 0; b < kBins - 1; ++b)
+        if (d <= kBinMaxDeg[b]) return b;
+    return kBins - 1;
 }
 
 template <class OffIn>
@@ -228,15 +228,15 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
                 std::sort(dst, dst + (e - b));
             }
         });
-        // degree bins of the row kernel, ascending internal id inside a bin
-        int64_t cnt[kRowBins] = {};
-        for (int64_t nv = 0; nv < n; ++nv) ++cnt[row_bin(H.off[nv + 1] - H.off[nv])];
+        // degree bins, ascending internal id inside a bin
+        int64_t cnt[kBins] = {};
+        for (int64_t nv = 0; nv < n; ++nv) ++cnt[degree_bin(H.off[nv + 1] - H.off[nv])];
         H.bin_lo[0] = 0;
-        for (int b = 0; b < kRowBins; ++b) H.bin_lo[b + 1] = H.bin_lo[b] + cnt[b];
+        for (int b = 0; b < kBins; ++b) H.bin_lo[b + 1] = H.bin_lo[b] + cnt[b];
         H.sched.resize(n);
-        int64_t fill[kRowBins];
-        for (int b = 0; b < kRowBins; ++b) fill[b] = H.bin_lo[b];
-        for (int64_t nv = 0; nv < n; ++nv) H.sched[fill[row_bin(H.off[nv + 1] - H.off[nv])]++] = (int32_t)nv;
+        int64_t fill[kBins];
+        for (int b = 0; b < kBins; ++b) fill[b] = H.bin_lo[b];
+        for (int64_t nv = 0; nv < n; ++nv) H.sched[fill[degree_bin(H.off[nv + 1] - H.off[nv])]++] = (int32_t)nv;
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -251,6 +251,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     D.off64 = nnz > (int64_t)INT32_MAX;
     const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
     const size_t offb = D.off64 ? 8 : 4;
+    const int64_t n_hub = H.bin_lo[kBins] - H.bin_lo[kBins - 1];
+    g->hub_grid = (int)std::min<int64_t>(n_hub, 2048);
     struct Req {
         void **p;
         size_t bytes;
@@ -262,18 +264,15 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.new2old, 4 * N},
         {(void **)&D.alive, N},
         {(void **)&D.sched, 4 * N},
-        {(void **)&D.hkey, 4 * Z},
-        {(void **)&D.hpos, 4 * Z},
-        {(void **)&D.hw, 8 * Z},
-        {(void **)&D.hS, 8 * Z},
-        {(void **)&D.ell, 4 * N},
-        {(void **)&D.pq, 8 * N},
+        {(void **)&D.rec, sizeof(Rec) * Z},
+        {(void **)&D.meta, sizeof(VMeta) * N},
         {(void **)&D.wown, 8 * N},
         {(void **)&D.a, 8 * N},
         {(void **)&D.R, 8 * N},
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
-        {(void **)&D.blist, 4 * N * kScoreBins},
+        {(void **)&D.part_rows, sizeof(RowPart) * (kGridRows + kGridMid + (size_t)g->hub_grid)},
+        {(void **)&D.part_score, sizeof(ScorePart) * (kGridScore + kGridBig)},
         {(void **)&D.ctr, sizeof(DevCounters)},
         {(void **)&D.thist, 4 * (size_t)kTopkBins},
         {(void **)&D.tstate, sizeof(TopkState)},
@@ -283,6 +282,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.tout_ids, 4 * N},
         {(void **)&D.tout_sc, 8 * N},
         {(void **)&D.scratch_d, 8 * N},
+        {(void **)&D.scratch_u, 8 * 8},
     };
     for (auto &r : reqs) {
         hipError_t e = dev_alloc(g, r.p, r.bytes);
@@ -308,7 +308,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
-    for (int b = 0; b <= kRowBins; ++b) g->row_bin_lo[b] = H.bin_lo[b];
+    for (int b = 0; b <= kBins; ++b) g->bin_lo[b] = H.bin_lo[b];
     g->h_new2old.swap(H.new2old);
     g->h_old2new.swap(H.old2new);
     g->h_comm2orig.swap(H.comm2orig);
@@ -538,6 +538,10 @@ rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw) {
 rs_status rs_read_counts(rs_graph *g, rs_counts *c) {
     clear_error();
     if (!g || !c) return fail(RS_ERR_ARG, "graph or counts is NULL");
+    if (g->scored) {
+        const rs_status st = launch_reduce_counts(g);
+        if (st != RS_OK) return st;
+    }
     DevCounters dc;
     hipError_t e = hipMemcpyAsync(&dc, g->d.ctr, sizeof(dc), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
@@ -573,21 +577,20 @@ rs_status rs_read_vertex_counts(rs_graph *g, int32_t *border, int32_t *ell, int3
     if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
     const int64_t n = g->d.n;
     hipError_t e = hipStreamSynchronize(g->stream);
-    std::vector<int32_t> hell, hpq, hdeg;
+    std::vector<VMeta> meta;
     std::vector<long long> htI, htII;
     std::vector<double> hw;
-    if (e == hipSuccess) e = d2h(hell, g->d.ell, n);
-    if (e == hipSuccess) e = d2h(hpq, g->d.pq, 2 * n);
-    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
     if (e == hipSuccess) e = d2h(htI, g->d.tI, n);
     if (e == hipSuccess) e = d2h(htII, g->d.tII, n);
     if (e == hipSuccess) e = d2h(hw, g->d.wown, n);
     if (e != hipSuccess) return hip_fail(e, "vertex count copy");
     for (int64_t v = 0; v < n; ++v) {
+        const VMeta &m = meta[g->h_old2new[v]];
+        const int32_t dp = m.deg - (m.q - m.p);
         const int32_t x = g->h_old2new[v];
-        const int32_t dp = hdeg[x] - (hpq[2 * x + 1] - hpq[2 * x]);
         if (border) border[v] = dp > 0;
-        if (ell) ell[v] = hell[x];
+        if (ell) ell[v] = m.ell;
         if (dprime) dprime[v] = dp;
         if (tI) tI[v] = dp > 0 ? htI[x] : 0;
         if (tII) tII[v] = dp > 0 ? htII[x] : 0;
@@ -602,30 +605,27 @@ rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *co
     if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
     const int64_t n = g->d.n;
     hipError_t e = hipStreamSynchronize(g->stream);
-    std::vector<int32_t> hell, hdeg;
+    std::vector<VMeta> meta;
     std::vector<int64_t> off;
-    if (e == hipSuccess) e = d2h(hell, g->d.ell, n);
-    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
     if (e == hipSuccess) e = read_offsets(g, off);
     if (e != hipSuccess) return hip_fail(e, "row copy");
     row_off[0] = 0;
-    for (int64_t v = 0; v < n; ++v) row_off[v + 1] = row_off[v] + hell[g->h_old2new[v]];
+    for (int64_t v = 0; v < n; ++v) row_off[v + 1] = row_off[v] + meta[g->h_old2new[v]].ell;
     if (!comm && !count && !weight) return RS_OK;
-    std::vector<int32_t> hkey, hpos;
-    std::vector<double> hw;
-    e = d2h(hkey, g->d.hkey, g->d.nnz);
-    if (e == hipSuccess) e = d2h(hpos, g->d.hpos, g->d.nnz);
-    if (e == hipSuccess) e = d2h(hw, g->d.hw, g->d.nnz);
+    std::vector<Rec> rec;
+    e = d2h(rec, g->d.rec, g->d.nnz);
     if (e != hipSuccess) return hip_fail(e, "row copy");
     for (int64_t v = 0; v < n; ++v) {
         const int32_t x = g->h_old2new[v];
         const int64_t rb = off[x];
-        const int32_t L = hell[x];
-        for (int32_t r = 0; r < L; ++r) {
+        const VMeta &m = meta[x];
+        for (int32_t r = 0; r < m.ell; ++r) {
             const int64_t o = row_off[v] + r;
-            if (comm) comm[o] = g->h_comm2orig[hkey[rb + r]];
-            if (count) count[o] = ((r + 1 < L) ? hpos[rb + r + 1] : hdeg[x]) - hpos[rb + r];
-            if (weight) weight[o] = hw[rb + r];
+            const Rec &rc = rec[rb + r];
+            if (comm) comm[o] = g->h_comm2orig[rc.key];
+            if (count) count[o] = ((r + 1 < m.ell) ? rec[rb + r + 1].pos : m.deg) - rc.pos;
+            if (weight) weight[o] = rc.w;
         }
     }
     return RS_OK;
@@ -637,26 +637,27 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
     if (!g->scored) return fail(RS_ERR_STATE, "read before rs_score");
     const int64_t n = g->d.n;
     hipError_t e = hipStreamSynchronize(g->stream);
-    std::vector<int32_t> hpq, hdeg, hcol;
+    std::vector<VMeta> meta;
+    std::vector<int32_t> hcol;
     std::vector<int64_t> off;
-    if (e == hipSuccess) e = d2h(hpq, g->d.pq, 2 * n);
-    if (e == hipSuccess) e = d2h(hdeg, g->d.deg, n);
+    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
     if (e == hipSuccess) e = read_offsets(g, off);
     if (e != hipSuccess) return hip_fail(e, "G' copy");
     goff[0] = 0;
     for (int64_t v = 0; v < n; ++v) {
-        const int32_t x = g->h_old2new[v];
-        goff[v + 1] = goff[v] + hdeg[x] - (hpq[2 * x + 1] - hpq[2 * x]);
+        const VMeta &m = meta[g->h_old2new[v]];
+        goff[v + 1] = goff[v] + m.deg - (m.q - m.p);
     }
     if (!gcol) return RS_OK;
     e = d2h(hcol, g->d.col, g->d.nnz);
     if (e != hipSuccess) return hip_fail(e, "G' copy");
     for (int64_t v = 0; v < n; ++v) {
         const int32_t x = g->h_old2new[v];
+        const VMeta &m = meta[x];
         const int64_t rb = off[x];
         int64_t o = goff[v];
-        for (int32_t j = 0; j < hdeg[x]; ++j) {
-            if (j >= hpq[2 * x] && j < hpq[2 * x + 1]) continue;
+        for (int32_t j = 0; j < m.deg; ++j) {
+            if (j >= m.p && j < m.q) continue;
             gcol[o++] = g->h_new2old[hcol[rb + j]];
         }
         std::sort(gcol + goff[v], gcol + goff[v + 1]);
@@ -665,8 +666,8 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
 }
 
 static const char *kKernelNames[K_COUNT] = {
-    "k_init", "k_rows", "k_sagg", "k_score", "k_topk_hist", "k_topk_find",
-    "k_topk_collect", "k_pair_rank(tie)", "k_pair_rank(final)", "k_mutate", "k_util"};
+    "k_rows_hub", "k_rows_mid", "k_rows", "k_wmax", "k_score_small", "k_score_big", "k_topk_hist",
+    "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order"};
 
 const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
 
