@@ -44,25 +44,25 @@ def make_graph(name):
 
 
 def kernel_bytes(c, n, nnz, s_off, k_top):
-    """Algorithmic bytes per launch of each kernel: every array the kernel must
-    touch, each element once (gathered arrays counted once at their size)."""
-    nb, ell, ellx, dp = c["n_border"], c["sum_ell"], c["sum_ell_x"], 2 * c["m_inter"]
-    w1, t1 = c["sum_work_I"], c["sum_tI"]
-    rows = (4 * n + s_off * n + 4 * n + 4 * n      # sched, off, deg, labels
-            + 4 * nnz                              # col
-            + 16 * ell                             # records: community, run start, weight
-            + 28 * n                               # ell, (p, q), own weight, a
-            + 4 * nb + 24 * (n - nb))              # border lists, zero scores of non-border
-    sagg = (nb * (4 + s_off + 12)                  # list, off, deg, ell, label
-            + 8 * ell + 4 * dp + 8 * min(n, dp)    # records scanned, foreign columns, a
-            + 8 * ellx)                            # S written
-    score = (nb * (4 + s_off + 24)                 # list, off, deg, label, a, (p, q)
-             + 4 * dp                              # u's foreign columns
-             + dp * (s_off + 16 + 28)              # w's off/ell/deg/(p,q), record key/w/S/pos
-             + 4 * w1 + 24 * t1                    # intersections, type-I lookups
-             + 24 * nb)                            # R, tI, tII
-    topk = 2 * 13 * n + 16 * 2 * k_top + 12 * k_top
-    return {"k_rows": rows, "k_score": sagg + score, "topk": topk, "pass": rows + sagg + score + topk}
+    """Algorithmic bytes of one pass (B_alg): every array the method must move,
+    each element once, attributed to the kernel that moves it.  Reading G and
+    the labels, and writing the interaction-matrix rows (community, count),
+    their weights, the own weights / a_v and G', belong to the row kernel;
+    reading those back, the type-II aggregates S_w(c) (write + read), the
+    intersection lists (4 bytes per step of W1 = sum over G' edges of
+    min(d'(u), d'(w))) and writing R belong to the score kernel; top-k reads R
+    and writes K (id, score) pairs."""
+    ell, ellx, nx, w1 = c["sum_ell"], c["sum_ell_x"], 2 * c["m_inter"], c["sum_work_I"]
+    rows = ((n + 1) * s_off + 4 * nnz + 4 * n                # G and labels
+            + 8 * ell + 8 * (n + 1)                          # rows (community, count) + row pointer
+            + 8 * ell + 8 * n                                # weights, own weight / a_v
+            + 4 * nx + s_off * (n + 1))                      # G'
+    score = (8 * ell + 8 * (n + 1) + 8 * ell + 8 * n + 4 * nx + s_off * (n + 1)   # read back
+             + 2 * 8 * ellx                                  # S_w(c) write + read
+             + 4 * w1                                        # intersections
+             + 8 * n)                                        # R
+    topk = 8 * n + 12 * k_top
+    return {"k_rows": rows, "k_score": score, "topk": topk, "pass": rows + score + topk}
 
 
 def copy_calibration():
@@ -163,10 +163,7 @@ def main():
         ms, nl = timings.get(name, (0.0, 0))
         return 1000.0 * ms / nl if nl else 0.0
 
-    # kernels as the byte model groups them: the row pass (hub + regular rows)
-    # and the score pass (small + large vertices)
-    avg_us = {"k_rows": avg("k_rows") + avg("k_rows_mid") + avg("k_rows_hub"),
-              "k_score": avg("k_score_small") + avg("k_score_big")}
+    avg_us = {"k_rows": avg("k_rows"), "k_score": avg("k_score") + avg("k_score_hub")}
     dom = max(avg_us, key=avg_us.get)
     achieved = kb[dom] / (avg_us[dom] * 1e-6) / 1e9
     gpu_ms = sum(v[0] for v in timings.values()) / args.steps

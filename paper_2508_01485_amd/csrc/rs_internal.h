@@ -10,17 +10,19 @@
 //   * off[n+1] is the row capacity layout fixed at load time (OffT = int32
 //     or int64); deg[n] is the current row length (removals shrink rows in
 //     place, keeping them sorted).
-//   * The interaction matrix is stored sparse, one 16-byte record per
-//     (vertex, neighbour community) in the row's own slot range
-//     [off[v], off[v] + ell): community, first row position of that
-//     community's run, weight w_v(c).  A run's length is the next record's
-//     position minus its own (the last run ends at deg[v]).
+//   * The interaction matrix is stored sparse, one record per (vertex,
+//     neighbour community) in the row's own slot range [off[v], off[v] + ell):
+//     reckey[] holds the community (ascending within a vertex), recdat[] the
+//     first row position of that community's run, its length f and the weight
+//     w_v(c).
 //   * meta[v] = {deg, ell, p, q} of the last pass.  G' (the edges between
 //     communities) is implicit: v's foreign neighbours are the row positions
 //     outside [p, q), in ascending id order.
-//   * Vertices are grouped at load time into degree bins (sched); every
-//     kernel walks the bins with a persistent grid, so no work list is built
-//     during a pass and no kernel uses a same-address atomic.
+//   * Work is cut at load time into static tiles of consecutive vertices: row
+//     tiles bound the row capacity they cover, score tiles the number of
+//     foreign entries (removals only shrink both).  Vertices too large for a
+//     tile are hubs and get a workgroup of their own.  No kernel of a pass
+//     uses a same-address atomic; each workgroup writes its own partials.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,34 +35,28 @@
 
 namespace rs {
 
-// Degree bins (load-time degree d):
-//   A  d <= 16        rows: one thread per vertex; scores: one thread per vertex
-//   B  16 < d <= 64   rows: one thread per vertex; scores: 4 lanes per vertex
-//   C  64 < d <= 512  rows and scores: 16 lanes per vertex
-//   D  d > 512        rows: one block per vertex (streamed); scores: a wavefront
-constexpr int kBins = 4;
-constexpr int kBinMaxDeg[kBins - 1] = {16, 64, 512};
-
-constexpr int kBlock = 256;          // threads per block of the per-vertex kernels
-constexpr int kGridRows = 2048;      // persistent grid of the thread-per-vertex row kernel (multiple of 8)
-constexpr int kGridMid = 1024;       // persistent grid of the 16-lane row kernel (multiple of 8)
-constexpr int kGridScore = 2048;     // persistent grid of the small-vertex score kernel
-constexpr int kGridBig = 2048;       // persistent grid of the large-vertex score kernel
-constexpr int kCapB = 64;            // LDS staging of N'(u) for the 4-lane teams of bin B
-constexpr int kCapC = 256;           // ... 16-lane teams of bin C
-constexpr int kCapD = 1024;          // ... wavefront teams of bin D (larger lists stay in HBM)
+constexpr int kBlock = 256;          // threads per workgroup of the per-vertex kernels
+constexpr int kRowTile = 2048;       // row capacity (entries) covered by one row tile
+constexpr int kRowTileV = 512;       // vertices of one row tile
+constexpr int kScoreTileP = 256;     // foreign entries (load-time bound) of one score tile (one per thread)
+constexpr int kScoreTileV = 256;     // vertices of one score tile (one per thread)
+constexpr int kHubKeys = 4096;       // score hubs with at most this many records keep their keys in LDS
+constexpr int kHubList = 8192;       // ... and with at most this many foreign entries their foreign list
 constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
 constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise compare
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
+constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
+
+// Grid of a tiled launch: one workgroup per hub, then the tiles rounded up to
+// a multiple of the 8 XCDs.
+inline int tile_grid(int hubs, int tiles) { return hubs + 8 * ((tiles + 7) / 8); }
 
 enum KernelId {
-    K_ROWS_HUB = 0,
-    K_ROWS_MID,
-    K_ROWS,
+    K_ROWS = 0,
     K_WMAX,
+    K_SCORE_HUB,
     K_SCORE,
-    K_SCORE_BIG,
     K_TOPK_HIST,
     K_TOPK_FIND,
     K_TOPK_COLLECT,
@@ -69,10 +65,10 @@ enum KernelId {
     K_COUNT
 };
 
-struct __align__(16) Rec {
-    int key;   // community (internal id)
+struct __align__(16) RecDat {
     int pos;   // first row position of the community's run
-    double w;  // w_v(key)
+    int f;     // run length = number of neighbours in the community
+    double w;  // w_v(community)
 };
 
 struct __align__(16) VMeta {
@@ -119,6 +115,8 @@ struct TopkState {
     unsigned long long n_tie;    // tie-list fill counter
     unsigned int overflow;       // tie class too large for the pairwise ranker
     unsigned int done;           // threshold bin taken whole
+    unsigned int hist_done;      // histogram workgroups finished (the last one finds the threshold)
+    unsigned int small;          // the final order was produced by the one-workgroup sort
 };
 
 struct DeviceGraph {
@@ -131,13 +129,17 @@ struct DeviceGraph {
     int32_t *lab = nullptr;     // [n] internal community id
     int32_t *new2old = nullptr; // [n]
     uint8_t *alive = nullptr;   // [n]
-    int32_t *sched = nullptr;   // [n] vertices grouped by degree bin
-    Rec *rec = nullptr;         // [nnz] interaction-matrix records
+    int2 *rtiles = nullptr;     // row tiles: vertex ranges [x, y)
+    int32_t *rhubs = nullptr;   // vertices whose row capacity exceeds kRowTile
+    int2 *stiles = nullptr;     // score tiles
+    int32_t *shubs = nullptr;   // vertices with more than kScoreTileP foreign entries
+    int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
+    RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
     VMeta *meta = nullptr;      // [n]
     double *wown = nullptr, *a = nullptr, *R = nullptr;
     long long *tI = nullptr, *tII = nullptr;
-    RowPart *part_rows = nullptr;    // [kGridRows + kGridMid + hub blocks]
-    ScorePart *part_score = nullptr; // [kGridScore + kGridBig]
+    RowPart *part_rows = nullptr;    // [row grid]
+    ScorePart *part_score = nullptr; // [score grid]
     DevCounters *ctr = nullptr;
     // top-k
     unsigned int *thist = nullptr;  // [kTopkBins]
@@ -165,8 +167,8 @@ struct rs_graph {
     bool own_stream = false;
     bool scored = false;
     int64_t n_alive = 0;
-    int64_t bin_lo[rs::kBins + 1] = {};  // start of each degree bin in sched
-    int hub_grid = 0;                    // blocks of the hub row kernel
+    int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0;
+    int grid_rows = 0, grid_score = 0;   // hubs first, then the tiles in XCD-major order
     std::vector<int32_t> h_new2old, h_old2new, h_comm2orig;
     rs::DeviceGraph d;
     rs::Timing timing;
@@ -186,7 +188,7 @@ void timing_end(rs_graph *g, int kid, hipEvent_t ev);
 
 // Kernel launchers (rs_kernels.hip).  All enqueue on g->stream.
 rs_status launch_score_pass(rs_graph *g);
-rs_status launch_topk(rs_graph *g, int64_t k, int64_t *count);
+rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);
 rs_status launch_reduce_counts(rs_graph *g);
 rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t m,
                               unsigned long long *d_removed);

@@ -1,28 +1,23 @@
 // rs_kernels.hip -- HIP kernels of the robust-spanner scoring pass (gfx950, wave64).
 //
 // One pass (rs_score):
-//   k_rows_hub, k_rows
-//            Algorithm 1 Steps 1-2 fused, per vertex: gather the labels of the
+//   k_rows   Algorithm 1 Steps 1-2 fused, per vertex: gather the labels of the
 //            neighbours, run-length count them into interaction-matrix records
 //            (rows are community-sorted, so every community is one run),
 //            detect the border vertex, compute every record's weight with
 //            Algorithm 2's shared terms (Eq. H_optimal) and the vertex's
 //            own-community weight, and a per-block maximum for w_max.
 //   k_wmax   reduce the per-block partials (w_max and pass totals).
-//   k_score_small, k_score_big
-//            Eq. RSI per border vertex u in the per-(vertex, community)
-//            factorised form of Lemmas 1-2: the type-II triads through a
-//            foreign neighbour w contribute w_w(C(u))^(2/3) a_v for every other
-//            neighbour v of w in C(u) (a_v = cbrt(w_v(C(v)))), and the type-I
-//            triads are the common foreign neighbours of u and w, found by
-//            sorted-list search (Section IV, Step 3).  One owner per vertex,
-//            fixed summation order, no floating-point atomics.
+//   k_score  Eq. RSI per border vertex u, one lane per pair (u, w) with w a
+//            foreign neighbour, in the per-(vertex, community) factorised form
+//            of Lemmas 1-2 (Section IV, Step 3).  One owner per vertex, fixed
+//            summation order, no floating-point atomics.
 // Top-k (Algorithm 1 Step 4) is an exact radix select on the 96-bit key
 // (score bits, complement of the caller id) with 16-bit digits.
 //
-// No kernel of a pass uses a same-address global atomic: per-block results go
-// to partial arrays.  Vertex work is walked by persistent grids over static
-// degree bins, each bin split into 8 contiguous ranges, one per XCD.
+// Work is cut into static tiles of consecutive vertices (and hub vertices
+// with a workgroup each); a launch has one workgroup per tile, so the
+// hardware dispatcher balances the uneven tiles.
 #include <climits>
 
 #include "rs_internal.h"
@@ -30,80 +25,8 @@
 namespace rs {
 
 // ------------------------------------------------------------ helpers
-template <int T>
-struct Team {
-    int lane;  // lane within the team
-    int base;  // first wavefront lane of the team
-    __device__ __forceinline__ Team() {
-        const int l = (int)__lane_id();
-        lane = l & (T - 1);
-        base = l & ~(T - 1);
-    }
-    __device__ __forceinline__ unsigned long long ballot(bool p) const {
-        const unsigned long long m = __ballot(p);
-        if (T == 64) return m;
-        return (m >> base) & ((1ull << T) - 1ull);
-    }
-    template <class V>
-    __device__ __forceinline__ V bcast(V v, int src) const { return __shfl(v, src, T); }
-    template <class V>
-    __device__ __forceinline__ V up1(V v) const { return __shfl_up(v, 1, T); }
-    __device__ __forceinline__ double sum(double x) const {
-#pragma unroll
-        for (int o = T / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, T);
-        return x;
-    }
-    __device__ __forceinline__ long long sum(long long x) const {
-#pragma unroll
-        for (int o = T / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, T);
-        return x;
-    }
-    __device__ __forceinline__ int isum(int x) const {
-#pragma unroll
-        for (int o = T / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, T);
-        return x;
-    }
-    __device__ __forceinline__ double dmax(double x) const {
-#pragma unroll
-        for (int o = T / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, T));
-        return x;
-    }
-    __device__ __forceinline__ int imax(int x) const {
-#pragma unroll
-        for (int o = T / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, T));
-        return x;
-    }
-    // exclusive prefix sum over the team's lanes
-    __device__ __forceinline__ int excl_scan(int x) const {
-        int incl = x;
-#pragma unroll
-        for (int o = 1; o < T; o <<= 1) {
-            const int y = __shfl_up(incl, o, T);
-            if (lane >= o) incl += y;
-        }
-        return incl - x;
-    }
-};
-
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
-
-// Item range of this block for a bin of `cnt` items, `per` items per block
-// step: the bin is split into 8 contiguous ranges (one per XCD; blocks are
-// dealt to the XCDs round-robin, so block b runs on XCD b % 8) and the blocks
-// of an XCD stride through its range.  gridDim.x is a multiple of 8.
-struct Span {
-    long long first, hi, step;
-};
-__device__ __forceinline__ Span xcd_span(long long cnt, int per) {
-    const int x = (int)(blockIdx.x & 7u), j = (int)(blockIdx.x >> 3), nx = (int)(gridDim.x >> 3);
-    Span s;
-    const long long lo = cnt * x / 8;
-    s.hi = cnt * (x + 1) / 8;
-    s.first = lo + (long long)j * per;
-    s.step = (long long)nx * per;
-    return s;
-}
 
 // ------------------------------------------------------------ weights
 // Eq. H_optimal with Algorithm 2's shared terms: for a vertex of degree d
@@ -129,19 +52,21 @@ __device__ __forceinline__ double weight_absent(int d, double X, int ell) {
 
 __device__ __forceinline__ double flogf(int f) { return f > 1 ? (double)f * log2((double)f) : 0.0; }
 
-constexpr int kNone = 1 << 30;  // no run start in the rest of a chunk
 
-// ============================================================ row kernels
+// ============================================================ row pass
 template <typename OffT>
 struct RowArgs {
     const OffT *off;
-    const int32_t *deg, *col, *lab, *sched;
-    Rec *rec;
+    const int32_t *deg, *col, *lab;
+    const int2 *tiles;
+    const int32_t *hubs;
+    int n_tiles, n_hubs, tiles_per_xcd;
+    int32_t *reckey;
+    RecDat *recdat;
     VMeta *meta;
     double *wown, *a, *R;
     long long *tI, *tII;
     RowPart *part;
-    long long bin_lo[kBins + 1];
 };
 
 struct RowResult {
@@ -211,409 +136,289 @@ __device__ void block_reduce_row(RowAcc acc, RowPart *out) {
     }
 }
 
-// Small-value tables for the thread path (d <= kTab): log2 y, y log2 y, 1/y.
-constexpr int kTab = 64;
-struct Tables {
-    double lg[kTab + 1], fl[kTab + 1], rc[kTab + 1];
+// Tile of the grid's block b: hubs take the first blocks; the tiles follow,
+// the tiles of one XCD contiguous (blocks are dealt to the XCDs round-robin,
+// so block b runs on XCD b % 8 and consecutive tiles share that XCD's L2).
+__device__ __forceinline__ int tile_of_block(int b, int n_hubs, int per_xcd) {
+    return (b & 7) * per_xcd + ((b - n_hubs) >> 3);
+}
+
+// ------------------------------------------------------------ row tiles
+// A row tile is a run of consecutive vertices whose rows (capacity <=
+// kRowTile entries, a contiguous slice of col) are processed flat:
+//   1. every entry's neighbour label is gathered (coalesced col reads);
+//   2. an entry starts a run if it starts a row or its label differs from
+//      the previous entry's (rows are community-sorted, so each run is one
+//      interaction-matrix record); run starts are ranked with wavefront
+//      ballots and a block prefix;
+//   3. one thread per vertex walks its runs in LDS: ell, X = sum f log2 f,
+//      the own community's run and the entries below it (p, q);
+//   4. the records' weights (Eq. H_optimal) are computed flat over runs.
+// A removed entry is -1 (after compaction): such a tail forms a run that is
+// skipped.
+constexpr int kRowW = kBlock / 64;      // wavefronts per workgroup
+constexpr int kRowU = kRowTile / kBlock; // entries per thread
+constexpr int kRowM = kRowTile / 64;     // ballot words per tile
+static_assert(kRowTile % kBlock == 0 && kRowTile <= 65535, "row tile size");
+
+// Streaming state of a hub row (one workgroup).
+struct HubSeg {
+    int prev, next_prev;                     // label before the segment / of its last entry
+    int open_start, open_label, open_slot;   // run open at the segment boundary (open_start < 0: none)
+    int nruns;                               // runs started before the segment
+    double red[kRowW];
+    int ired[kRowW];
 };
-__device__ __forceinline__ void fill_tables(Tables &t) {
-    for (int i = threadIdx.x; i <= kTab; i += blockDim.x) {
-        const double x = (double)i;
-        t.lg[i] = i > 0 ? log2(x) : 0.0;
-        t.fl[i] = flogf(i);
-        t.rc[i] = i > 0 ? 1.0 / x : 0.0;
+
+struct RowTileShared {
+    HubSeg hub;
+    unsigned int bm[kRowTile / 32];      // row-start bits
+    unsigned long long mask[kRowM];      // run-start bits
+    int mbase[kRowM];                    // run starts before each mask word
+    int wlast[kRowW], wcnt[kRowW];
+    unsigned short runpos[kRowTile + 1]; // tile-local entry of each run start (+ end)
+    unsigned short runv[kRowTile];       // tile-local vertex of each run
+    int runlab[kRowTile];                // label of each run (-1: removed tail)
+    double vX[kRowTileV];
+    int vd[kRowTileV], vell[kRowTileV];
+    unsigned short vrf[kRowTileV], vo[kRowTileV];
+};
+
+__device__ __forceinline__ int run_index(const RowTileShared &S, int e) {
+    return S.mbase[e >> 6] + __popcll(S.mask[e >> 6] & ((1ull << (e & 63)) - 1ull));
+}
+
+template <typename OffT>
+__device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc &acc) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int2 tl = A.tiles[t];
+    const int v0 = tl.x, nv = tl.y - tl.x;
+    const OffT e0 = A.off[v0];
+    const int TE = (int)(A.off[tl.y] - e0);
+    for (int x = tid; x < kRowTile / 32; x += kBlock) S.bm[x] = 0u;
+    int L[kRowU];
+#pragma unroll
+    for (int i = 0; i < kRowU; ++i) {
+        const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+        L[i] = e < TE ? A.col[e0 + e] : -2;
     }
     __syncthreads();
-}
-
-// Eq. H_optimal rearranged: with Y = d - f,
-//   H = -(X - d log2 Y - f log2(f/Y)) / Y = log2 Y - (X - f log2 f) / Y.
-__device__ __forceinline__ double weight_present_t(const Tables &t, int d, double X, int ell, int f) {
-    const int L = ell - 1;
-    if (L < 2) return 0.0;
-    const int Y = d - f;
-    return (t.lg[Y] + (t.fl[f] - X) * t.rc[Y]) * (double)L;
-}
-__device__ __forceinline__ double weight_absent_t(const Tables &t, int d, double X, int ell) {
-    if (ell < 2) return 0.0;
-    return (t.lg[d] - X * t.rc[d]) * (double)ell;
-}
-
-template <int PASS, typename OffT>
-__device__ __forceinline__ void row_close_t(const RowArgs<OffT> &A, const Tables &tb, OffT rb, int d, int cv,
-                                            double X, int ell, int label, int start, int slot, int f, double &xs,
-                                            int &fown, int &pown, double &lmax) {
-    if (PASS == 1) {
-        xs += tb.fl[f];
-        if (label == cv) {
-            fown = f;
-            pown = start;
-        }
-    } else {
-        Rec rc;
-        rc.key = label;
-        rc.pos = start;
-        rc.w = weight_present_t(tb, d, X, ell, f);
-        A.rec[rb + slot] = rc;
-        lmax = fmax(lmax, rc.w);
+    for (int i = tid; i < nv; i += kBlock) {
+        const int o = (int)(A.off[v0 + i] - e0), c = (int)(A.off[v0 + i + 1] - A.off[v0 + i]);
+        if (c > 0) atomicOr(&S.bm[o >> 5], 1u << (o & 31));
     }
-}
-
-// Bins A and B (d <= 64): one thread per vertex, the row read 16 entries at
-// a time into registers.  Pass 1 counts the runs and X = sum f log2 f, pass
-// 2 re-reads the row (cache-hot) and writes the weighted records.
-template <int PASS, typename OffT>
-__device__ __forceinline__ void row_thread_pass(const RowArgs<OffT> &A, const Tables &tb, OffT rb, int d, int cv,
-                                                double X, int ell, double &xs, int &fown, int &pown, int &below,
-                                                int &nruns, double &lmax) {
-    int cur = -1, s = 0, slot = 0;
-    for (int base = 0; base < d; base += 16) {
-        int c[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) c[i] = base + i < d ? A.col[rb + base + i] : 0;
+    for (int i = 0; i < kRowU; ++i) L[i] = L[i] >= 0 ? A.lab[L[i]] : L[i];
+    if (lane == 63) S.wlast[wave] = L[kRowU - 1];
+    __syncthreads();
+    unsigned long long m[kRowU];
+    int cnt = 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            c[i] = base + i < d ? A.lab[c[i]] : INT_MAX;
-            if (PASS == 1 && base + i < d && c[i] < cv) ++below;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int pos = base + i;
-            if (pos < d) {
-                if (pos > 0 && c[i] != cur) {
-                    row_close_t<PASS>(A, tb, rb, d, cv, X, ell, cur, s, slot, pos - s, xs, fown, pown, lmax);
-                    ++slot;
-                    s = pos;
-                }
-                cur = c[i];
-            }
-        }
+    for (int i = 0; i < kRowU; ++i) {
+        const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+        int lp = __shfl_up(L[i], 1);
+        const int carry = i > 0 ? __shfl(L[i > 0 ? i - 1 : 0], 63) : (wave > 0 ? S.wlast[wave > 0 ? wave - 1 : 0] : INT_MIN);
+        if (lane == 0) lp = carry;
+        const bool rs = (S.bm[e >> 5] >> (e & 31)) & 1u;
+        m[i] = __ballot(e < TE && (rs || L[i] != lp));
+        cnt += __popcll(m[i]);
     }
-    if (d > 0) {
-        row_close_t<PASS>(A, tb, rb, d, cv, X, ell, cur, s, slot, d - s, xs, fown, pown, lmax);
-        ++slot;
-    }
-    nruns = slot;
-}
-
-template <typename OffT>
-__device__ __forceinline__ RowResult row_thread(const RowArgs<OffT> &A, const Tables &tb, OffT rb, int d, int cv) {
-    double xs = 0.0, lmax = 0.0;
-    int fown = 0, pown = 0, below = 0, nr = 0;
-    row_thread_pass<1, OffT>(A, tb, rb, d, cv, 0.0, 0, xs, fown, pown, below, nr, lmax);
-    const double X = xs;
-    const int ell = nr;
-    row_thread_pass<2, OffT>(A, tb, rb, d, cv, X, ell, xs, fown, pown, below, nr, lmax);
-    RowResult r;
-    r.ell = ell;
-    r.p = fown > 0 ? pown : below;
-    r.q = r.p + fown;
-    r.wown = fown > 0 ? weight_present_t(tb, d, X, ell, fown) : weight_absent_t(tb, d, X, ell);
-    r.lmax = fmax(lmax, r.wown);
-    return r;
-}
-
-template <int PASS, typename OffT>
-__device__ __forceinline__ void row_close_d(const RowArgs<OffT> &A, OffT rb, int d, int cv, double X, int ell,
-                                            int label, int start, int slot, int f, double &xs, int &fown, int &pown,
-                                            double &lmax) {
-    if (PASS == 1) {
-        xs += flogf(f);
-        if (label == cv) {
-            fown = f;
-            pown = start;
-        }
-    } else {
-        Rec rc;
-        rc.key = label;
-        rc.pos = start;
-        rc.w = weight_present(d, X, ell, f);
-        A.rec[rb + slot] = rc;
-        lmax = fmax(lmax, rc.w);
-    }
-}
-
-// Bin C: T lanes per vertex, the row streamed in chunks of T*U entries
-// (entry base + k*T + lane in register c[k]); run starts are team ballots and
-// the run still open at a chunk's end is carried into the next chunk.
-template <int T, int U, int PASS, typename OffT>
-__device__ __forceinline__ void row_team_pass(const RowArgs<OffT> &A, const Team<T> &tm, OffT rb, int d, int cv,
-                                              double X, int ell, double &xs, int &fown, int &pown, int &below,
-                                              int &nruns, double &lmax) {
-    constexpr int CH = T * U;
-    int open_label = -1, open_start = 0, open_slot = 0;
-    int nr = 0;
-    const unsigned long long lt = (1ull << tm.lane) - 1ull;
-    for (int base = 0; base < d; base += CH) {
-        int c[U];
+    if (lane == 0) S.wcnt[wave] = cnt;
+    __syncthreads();
+    int base = 0, total = 0;
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int i = base + k * T + tm.lane;
-            c[k] = i < d ? A.col[rb + i] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int i = base + k * T + tm.lane;
-            c[k] = i < d ? A.lab[c[k]] : INT_MAX;
-            if (PASS == 1 && i < d && c[k] < cv) ++below;
-        }
-        unsigned long long m[U];
-        int bef[U];
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int i = base + k * T + tm.lane;
-            const int last_prev = (k == 0) ? open_label : tm.bcast(c[k - 1], T - 1);
-            int pc = tm.up1(c[k]);
-            if (tm.lane == 0) pc = last_prev;
-            m[k] = tm.ballot(i < d && c[k] != pc);
-            bef[k] = cnt;
-            cnt += __popcll(m[k]);
-        }
-        const bool last_chunk = base + CH >= d;
-        int first[U + 1];
-        first[U] = last_chunk ? d - base : kNone;
-#pragma unroll
-        for (int k = U - 1; k >= 0; --k) first[k] = m[k] ? k * T + __builtin_ctzll(m[k]) : first[k + 1];
-        if (open_label >= 0 && first[0] != kNone) {
-            if (tm.lane == 0)
-                row_close_d<PASS>(A, rb, d, cv, X, ell, open_label, open_start, open_slot,
-                                  base + first[0] - open_start, xs, fown, pown, lmax);
-            open_label = -1;
-        }
-        int nl = -1, ns = 0, nsl = 0;
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            if ((m[k] >> tm.lane) & 1ull) {
-                const unsigned long long rest = (tm.lane + 1 < T) ? (m[k] >> (tm.lane + 1)) : 0ull;
-                const int nxt = rest ? k * T + tm.lane + 1 + __builtin_ctzll(rest) : first[k + 1];
-                const int slot = nr + bef[k] + __popcll(m[k] & lt);
-                if (nxt != kNone) {
-                    row_close_d<PASS>(A, rb, d, cv, X, ell, c[k], base + k * T + tm.lane, slot,
-                                      nxt - (k * T + tm.lane), xs, fown, pown, lmax);
-                } else {
-                    nl = c[k];
-                    ns = base + k * T + tm.lane;
-                    nsl = slot;
-                }
-            }
-        }
-        const unsigned long long owner = tm.ballot(nl >= 0);
-        if (owner) {
-            const int ol = __builtin_ctzll(owner);
-            open_label = tm.bcast(nl, ol);
-            open_start = tm.bcast(ns, ol);
-            open_slot = tm.bcast(nsl, ol);
-        }
-        nr += cnt;
+    for (int x = 0; x < kRowW; ++x) {
+        const int c = S.wcnt[x];
+        if (x < wave) base += c;
+        total += c;
     }
-    nruns = nr;
-}
-
-template <int T, int U, typename OffT>
-__device__ __forceinline__ RowResult row_team(const RowArgs<OffT> &A, const Team<T> &tm, OffT rb, int d, int cv) {
-    double xs = 0.0, lmax = 0.0;
-    int fown = 0, pown = -1, below = 0, nr = 0;
-    row_team_pass<T, U, 1, OffT>(A, tm, rb, d, cv, 0.0, 0, xs, fown, pown, below, nr, lmax);
-    const double X = tm.sum(xs);
-    fown = tm.imax(fown);
-    pown = tm.imax(pown);
-    below = tm.isum(below);
-    const int ell = nr;
-    row_team_pass<T, U, 2, OffT>(A, tm, rb, d, cv, X, ell, xs, fown, pown, below, nr, lmax);
-    RowResult r;
-    r.ell = ell;
-    r.p = fown > 0 ? pown : below;
-    r.q = r.p + fown;
-    r.wown = fown > 0 ? weight_present(d, X, ell, fown) : weight_absent(d, X, ell);
-    r.lmax = fmax(tm.dmax(lmax), r.wown);
-    return r;
-}
-
-template <int T, int U, typename OffT>
-__device__ __forceinline__ void rows_team_bin(const RowArgs<OffT> &A, int bin, RowAcc &acc) {
-    const Team<T> tm;
-    constexpr int per = kBlock / T;
-    const Span s = xcd_span(A.bin_lo[bin + 1] - A.bin_lo[bin], per);
-    for (long long base = s.first; base < s.hi; base += s.step) {
-        const long long it = base + threadIdx.x / T;
-        if (it < s.hi) {
-            const int v = A.sched[A.bin_lo[bin] + it];
-            const int d = A.deg[v];
-            const RowResult r = row_team<T, U, OffT>(A, tm, A.off[v], d, A.lab[v]);
-            if (tm.lane == 0) finish_row(A, v, d, r, acc);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < kRowU; ++i) {
+        const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+        if (lane == 0) {
+            S.mask[e >> 6] = m[i];
+            S.mbase[e >> 6] = base;
         }
-    }
-}
-
-// Bin C: 16 lanes per vertex.
-template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_rows_mid(RowArgs<OffT> A) {
-    RowAcc acc = {0.0, 0, 0, 0, 0};
-    rows_team_bin<16, 8, OffT>(A, 2, acc);
-    block_reduce_row(acc, &A.part[blockIdx.x]);
-}
-
-// Bins A and B: one thread per vertex.
-template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
-    __shared__ Tables tb;
-    fill_tables(tb);
-    RowAcc acc = {0.0, 0, 0, 0, 0};
-    {
-        // bins A and B are adjacent in sched: one thread per vertex
-        const Span s = xcd_span(A.bin_lo[2] - A.bin_lo[0], kBlock);
-        for (long long base = s.first; base < s.hi; base += s.step) {
-            const long long it = base + threadIdx.x;
-            if (it < s.hi) {
-                const int v = A.sched[A.bin_lo[0] + it];
-                const int d = A.deg[v];
-                const RowResult r = row_thread<OffT>(A, tb, A.off[v], d, A.lab[v]);
-                finish_row(A, v, d, r, acc);
-            }
+        if ((m[i] >> lane) & 1ull) {
+            const int r = base + __popcll(m[i] & lt);
+            S.runpos[r] = (unsigned short)e;
+            S.runlab[r] = L[i];
         }
+        base += __popcll(m[i]);
     }
-    block_reduce_row(acc, &A.part[blockIdx.x]);
+    if (tid == 0) S.runpos[total] = (unsigned short)TE;
+    __syncthreads();
+    for (int i = tid; i < nv; i += kBlock) {
+        const int v = v0 + i;
+        const int o = (int)(A.off[v] - e0);
+        const int c = (int)(A.off[v + 1] - A.off[v]);
+        const int d = A.deg[v];
+        const int cv = A.lab[v];
+        int rf = 0, re = 0;
+        if (c > 0) {
+            rf = run_index(S, o);
+            re = o + c >= TE ? total : run_index(S, o + c);
+        }
+        double X = 0.0;
+        int ell = 0, fown = 0, below = 0;
+        for (int r = rf; r < re; ++r) {
+            const int lb = S.runlab[r];
+            if (lb < 0) break;
+            const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
+            X += flogf(f);
+            ++ell;
+            S.runv[r] = (unsigned short)i;
+            if (lb == cv)
+                fown = f;
+            else if (lb < cv)
+                below += f;
+        }
+        S.vX[i] = X;
+        S.vd[i] = d;
+        S.vell[i] = ell;
+        S.vrf[i] = (unsigned short)rf;
+        S.vo[i] = (unsigned short)o;
+        RowResult res;
+        res.ell = ell;
+        res.p = below;
+        res.q = below + fown;
+        res.wown = fown > 0 ? weight_present(d, X, ell, fown) : weight_absent(d, X, ell);
+        res.lmax = res.wown;
+        finish_row(A, v, d, res, acc);
+    }
+    __syncthreads();
+    for (int r = tid; r < total; r += kBlock) {
+        const int lb = S.runlab[r];
+        if (lb < 0) continue;
+        const int i = S.runv[r];
+        const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
+        const double w = weight_present(S.vd[i], S.vX[i], S.vell[i], f);
+        const int o = S.vo[i];
+        const OffT idx = e0 + (OffT)(o + (r - (int)S.vrf[i]));
+        A.reckey[idx] = lb;
+        RecDat rd;
+        rd.pos = (int)S.runpos[r] - o;
+        rd.f = f;
+        rd.w = w;
+        A.recdat[idx] = rd;
+        acc.wmax = fmax(acc.wmax, w);
+    }
 }
 
 // ------------------------------------------------------------ hub rows
-// Bin D: one block per vertex; the row is streamed in groups of kHubG
-// entries (entry g0 + k*256 + tid in register c[k]) twice: the first pass
-// counts the runs and X, the second writes the weighted records.  A run that
-// crosses a group boundary stays open in the block's shared state.
-constexpr int kHubU = 8;
-constexpr int kHubG = kBlock * kHubU;
-constexpr int kHubW = kBlock / 64;            // wavefronts per block
-constexpr int kHubM = kHubU * kHubW;          // ballot masks per group
-
-struct HubState {
-    int prev;                                  // label of the previous group's last entry
-    int open_start, open_label, open_slot;     // run open at the group boundary (open_start < 0: none)
-    int nruns;                                 // runs started before the current group
-    int fown, pown;                            // the own community's run (pass 1)
-    int next_prev;
-};
-
-struct HubShared {
-    int lab[kHubG];
-    unsigned long long mask[kHubM];
-    int pre[kHubM + 1];
-    int first[kHubM + 1];
-    HubState st;
-    double red[kHubW];
-    int ired[kHubW];
-};
-
+// A vertex whose row capacity exceeds kRowTile gets a workgroup: its row is
+// streamed in segments of kRowTile entries with the tile's flat machinery
+// (labels, run starts by ballot, runs closed flat over LDS), twice: the first
+// pass counts the runs, X and the own run, the second writes the weighted
+// records.  The run still open at a segment's end is carried to the next.
 template <int PASS, typename OffT>
-__device__ __forceinline__ void hub_close(const RowArgs<OffT> &A, HubShared &S, OffT rb, int d, int cv, double X,
-                                          int ell, int start, int label, int slot, int f, double &xpart, double &lmax) {
+__device__ __forceinline__ void hub_run(const RowArgs<OffT> &A, OffT rb, int d, int cv, double X, int ell, int label,
+                                        int start, int f, int slot, double &xpart, int &below, int &fown,
+                                        double &lmax) {
     if (PASS == 1) {
         xpart += flogf(f);
-        if (label == cv) {
-            S.st.fown = f;
-            S.st.pown = start;
-        }
+        if (label == cv)
+            fown = f;
+        else if (label < cv)
+            below += f;
     } else {
-        Rec rc;
-        rc.key = label;
-        rc.pos = start;
-        rc.w = weight_present(d, X, ell, f);
-        A.rec[rb + slot] = rc;
-        lmax = fmax(lmax, rc.w);
+        const double w = weight_present(d, X, ell, f);
+        A.reckey[rb + slot] = label;
+        RecDat rd;
+        rd.pos = start;
+        rd.f = f;
+        rd.w = w;
+        A.recdat[rb + slot] = rd;
+        lmax = fmax(lmax, w);
     }
 }
 
 template <int PASS, typename OffT>
-__device__ void hub_stream(const RowArgs<OffT> &A, HubShared &S, OffT rb, int d, int cv, double X, int ell,
-                           double &xpart, int &below, double &lmax) {
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+__device__ void hub_pass(const RowArgs<OffT> &A, RowTileShared &S, OffT rb, int d, int cv, double X, int ell,
+                         double &xpart, int &below, int &fown, double &lmax) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    HubSeg &H = S.hub;
     if (tid == 0) {
-        S.st.prev = -1;
-        S.st.open_start = -1;
-        S.st.nruns = 0;
+        H.prev = INT_MIN;
+        H.open_start = -1;
+        H.nruns = 0;
     }
-    for (int g0 = 0; g0 < d; g0 += kHubG) {
-        int c[kHubU];
+    for (int seg0 = 0; seg0 < d; seg0 += kRowTile) {
+        const int TE = min(kRowTile, d - seg0);
+        int L[kRowU];
 #pragma unroll
-        for (int k = 0; k < kHubU; ++k) {
-            const int i = g0 + k * kBlock + tid;
-            c[k] = i < d ? A.col[rb + i] : 0;
+        for (int i = 0; i < kRowU; ++i) {
+            const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+            L[i] = e < TE ? A.col[rb + seg0 + e] : -2;
         }
 #pragma unroll
-        for (int k = 0; k < kHubU; ++k) {
-            const int i = g0 + k * kBlock + tid;
-            c[k] = i < d ? A.lab[c[k]] : INT_MAX;
-            if (PASS == 1 && i < d && c[k] < cv) ++below;
-        }
-        __syncthreads();  // previous group done with S.lab; S.st updated
+        for (int i = 0; i < kRowU; ++i) L[i] = L[i] >= 0 ? A.lab[L[i]] : L[i];
+        __syncthreads();  // the previous segment is done with S
+        if (lane == 63) S.wlast[wave] = L[kRowU - 1];
 #pragma unroll
-        for (int k = 0; k < kHubU; ++k) S.lab[k * kBlock + tid] = c[k];
+        for (int i = 0; i < kRowU; ++i)
+            if (wave * (kRowTile / kRowW) + i * 64 + lane == TE - 1) H.next_prev = L[i];
         __syncthreads();
-        const int prev = S.st.prev;
-        bool st[kHubU];
+        unsigned long long m[kRowU];
+        int cnt = 0;
 #pragma unroll
-        for (int k = 0; k < kHubU; ++k) {
-            const int li = k * kBlock + tid;
-            const int pc = li > 0 ? S.lab[li - 1] : prev;
-            st[k] = (g0 + li < d) && c[k] != pc;
-            const unsigned long long mk = __ballot(st[k]);
-            if (lane == 0) S.mask[k * kHubW + wave] = mk;
+        for (int i = 0; i < kRowU; ++i) {
+            const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+            int lp = __shfl_up(L[i], 1);
+            const int carry = i > 0 ? __shfl(L[i > 0 ? i - 1 : 0], 63) : (wave > 0 ? S.wlast[wave > 0 ? wave - 1 : 0] : H.prev);
+            if (lane == 0) lp = carry;
+            m[i] = __ballot(e < TE && L[i] != lp);
+            cnt += __popcll(m[i]);
+        }
+        if (lane == 0) S.wcnt[wave] = cnt;
+        __syncthreads();
+        int base = 0, total = 0;
+#pragma unroll
+        for (int x = 0; x < kRowW; ++x) {
+            const int c = S.wcnt[x];
+            if (x < wave) base += c;
+            total += c;
+        }
+        const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int i = 0; i < kRowU; ++i) {
+            const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+            if ((m[i] >> lane) & 1ull) {
+                const int r = base + __popcll(m[i] & lt);
+                S.runpos[r] = (unsigned short)e;
+                S.runlab[r] = L[i];
+            }
+            base += __popcll(m[i]);
+        }
+        if (tid == 0) S.runpos[total] = (unsigned short)TE;
+        __syncthreads();
+        const bool last = seg0 + TE >= d;
+        const int nr0 = H.nruns;
+        // the run carried from the previous segment closes at this segment's
+        // first run start (or at the row's end)
+        if (tid == 0 && H.open_start >= 0 && (total > 0 || last)) {
+            const int end = total > 0 ? seg0 + (int)S.runpos[0] : d;
+            hub_run<PASS, OffT>(A, rb, d, cv, X, ell, H.open_label, H.open_start, end - H.open_start, H.open_slot,
+                                xpart, below, fown, lmax);
+            H.open_start = -1;
+        }
+        const int closed = last ? total : total - 1;  // the segment's last run stays open unless the row ends
+        for (int r = tid; r < closed; r += kBlock) {
+            const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
+            hub_run<PASS, OffT>(A, rb, d, cv, X, ell, S.runlab[r], seg0 + (int)S.runpos[r], f, nr0 + r, xpart,
+                                below, fown, lmax);
         }
         __syncthreads();
         if (tid == 0) {
-            int acc = 0;
-            for (int mi = 0; mi < kHubM; ++mi) {
-                S.pre[mi] = acc;
-                acc += __popcll(S.mask[mi]);
+            if (!last && total > 0) {
+                H.open_start = seg0 + (int)S.runpos[total - 1];
+                H.open_label = S.runlab[total - 1];
+                H.open_slot = nr0 + total - 1;
             }
-            S.pre[kHubM] = acc;
-            int nxt = kNone;
-            S.first[kHubM] = kNone;
-            for (int mi = kHubM - 1; mi >= 0; --mi) {
-                if (S.mask[mi]) nxt = (mi / kHubW) * kBlock + (mi % kHubW) * 64 + __builtin_ctzll(S.mask[mi]);
-                S.first[mi] = nxt;
-            }
-            if (S.st.open_start >= 0 && S.first[0] != kNone) {
-                hub_close<PASS>(A, S, rb, d, cv, X, ell, S.st.open_start, S.st.open_label, S.st.open_slot,
-                                g0 + S.first[0] - S.st.open_start, xpart, lmax);
-                S.st.open_start = -1;
-            }
-            S.st.next_prev = S.lab[kHubG - 1];
+            H.nruns = nr0 + total;
+            H.prev = H.next_prev;
         }
-        __syncthreads();
-        const int nr0 = S.st.nruns;
-        const bool last_group = g0 + kHubG >= d;
-#pragma unroll
-        for (int k = 0; k < kHubU; ++k) {
-            if (st[k]) {
-                const int li = k * kBlock + tid;
-                const int mi = k * kHubW + wave;
-                const unsigned long long mk = S.mask[mi];
-                const unsigned long long rest = lane + 1 < 64 ? (mk >> (lane + 1)) : 0ull;
-                const int nxt = rest ? li + 1 + __builtin_ctzll(rest) : S.first[mi + 1];
-                const int slot = nr0 + S.pre[mi] + __popcll(mk & ((1ull << lane) - 1ull));
-                if (nxt != kNone)
-                    hub_close<PASS>(A, S, rb, d, cv, X, ell, g0 + li, c[k], slot, nxt - li, xpart, lmax);
-                else if (last_group)
-                    hub_close<PASS>(A, S, rb, d, cv, X, ell, g0 + li, c[k], slot, d - (g0 + li), xpart, lmax);
-                else {
-                    S.st.open_start = g0 + li;
-                    S.st.open_label = c[k];
-                    S.st.open_slot = slot;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            S.st.nruns = nr0 + S.pre[kHubM];
-            S.st.prev = S.st.next_prev;
-        }
-    }
-    __syncthreads();
-    if (tid == 0 && S.st.open_start >= 0) {
-        hub_close<PASS>(A, S, rb, d, cv, X, ell, S.st.open_start, S.st.open_label, S.st.open_slot,
-                        d - S.st.open_start, xpart, lmax);
-        S.st.open_start = -1;
     }
     __syncthreads();
 }
@@ -624,7 +429,7 @@ __device__ __forceinline__ double block_sum_d(double x, double *red) {
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     double t = 0.0;
-    for (int i = 0; i < kHubW; ++i) t += red[i];
+    for (int i = 0; i < kRowW; ++i) t += red[i];
     __syncthreads();
     return t;
 }
@@ -635,7 +440,7 @@ __device__ __forceinline__ double block_max_d(double x, double *red) {
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     double t = 0.0;
-    for (int i = 0; i < kHubW; ++i) t = fmax(t, red[i]);
+    for (int i = 0; i < kRowW; ++i) t = fmax(t, red[i]);
     __syncthreads();
     return t;
 }
@@ -646,48 +451,50 @@ __device__ __forceinline__ int block_sum_i(int x, int *red) {
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     int t = 0;
-    for (int i = 0; i < kHubW; ++i) t += red[i];
+    for (int i = 0; i < kRowW; ++i) t += red[i];
     __syncthreads();
     return t;
 }
 
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_rows_hub(RowArgs<OffT> A) {
-    __shared__ HubShared S;
-    RowAcc acc = {0.0, 0, 0, 0, 0};
-    const long long cnt = A.bin_lo[4] - A.bin_lo[3];
-    for (long long h = blockIdx.x; h < cnt; h += gridDim.x) {
-        const int v = A.sched[A.bin_lo[3] + h];
-        const OffT rb = A.off[v];
-        const int d = A.deg[v];
-        const int cv = A.lab[v];
-        if (threadIdx.x == 0) {
-            S.st.fown = 0;
-            S.st.pown = -1;
-        }
-        double xpart = 0.0, lmax = 0.0;
-        int below = 0;
-        hub_stream<1, OffT>(A, S, rb, d, cv, 0.0, 0, xpart, below, lmax);
-        const double X = block_sum_d(xpart, S.red);
-        const int nbelow = block_sum_i(below, S.ired);
-        const int ell = S.st.nruns;
-        const int fown = S.st.fown;
-        const int p = fown > 0 ? S.st.pown : nbelow;
-        __syncthreads();  // everyone has read pass 1's totals before pass 2 resets them
-        hub_stream<2, OffT>(A, S, rb, d, cv, X, ell, xpart, below, lmax);
-        const double lm = block_max_d(lmax, S.red);
-        if (threadIdx.x == 0) {
-            RowResult r;
-            r.ell = ell;
-            r.p = p;
-            r.q = p + fown;
-            r.wown = fown > 0 ? weight_present(d, X, ell, fown) : weight_absent(d, X, ell);
-            r.lmax = fmax(lm, r.wown);
-            finish_row(A, v, d, r, acc);
-        }
-        __syncthreads();
+__device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc &acc) {
+    const OffT rb = A.off[v];
+    const int d = A.deg[v];
+    const int cv = A.lab[v];
+    double xpart = 0.0, lmax = 0.0;
+    int below = 0, fown = 0;
+    hub_pass<1, OffT>(A, S, rb, d, cv, 0.0, 0, xpart, below, fown, lmax);
+    const double X = block_sum_d(xpart, S.hub.red);
+    const int p = block_sum_i(below, S.hub.ired);
+    const int fo = block_sum_i(fown, S.hub.ired);  // one thread holds the own run's length
+    const int ell = S.hub.nruns;
+    __syncthreads();  // everyone has read pass 1's totals before pass 2 resets them
+    hub_pass<2, OffT>(A, S, rb, d, cv, X, ell, xpart, below, fown, lmax);
+    const double lm = block_max_d(lmax, S.hub.red);
+    if (threadIdx.x == 0) {
+        RowResult r;
+        r.ell = ell;
+        r.p = p;
+        r.q = p + fo;
+        r.wown = fo > 0 ? weight_present(d, X, ell, fo) : weight_absent(d, X, ell);
+        r.lmax = fmax(lm, r.wown);
+        finish_row(A, v, d, r, acc);
     }
-    block_reduce_row(acc, &A.part[blockIdx.x]);
+}
+
+// Algorithm 1 Steps 1-2 for every vertex: hub rows first, then the tiles.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
+    __shared__ RowTileShared S;
+    RowAcc acc = {0.0, 0, 0, 0, 0};
+    const int b = (int)blockIdx.x;
+    if (b < A.n_hubs) {
+        hub_row(A, S, A.hubs[b], acc);
+    } else {
+        const int t = tile_of_block(b, A.n_hubs, A.tiles_per_xcd);
+        if (t < A.n_tiles) row_tile(A, S, t, acc);
+    }
+    block_reduce_row(acc, &A.part[b]);
 }
 
 // Reduce the row partials of a pass into the counters (one block).
@@ -730,91 +537,404 @@ __global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevC
     }
 }
 
-// ============================================================ score kernels
+// ============================================================ score pass
 template <typename OffT>
 struct ScoreArgs {
     const OffT *off;
-    const int32_t *col, *lab, *sched;
-    const Rec *rec;
+    const int32_t *col, *lab;
+    const int2 *tiles;
+    const int32_t *hubs;
+    int n_tiles, n_hubs, tiles_per_xcd;
+    const int32_t *reckey;
+    const RecDat *recdat;
     const VMeta *meta;
     const double *a;
     double *R;
     long long *tI, *tII;
     const DevCounters *ctr;
     ScorePart *part;
-    long long bin_lo[kBins + 1];
 };
 
-// Index of community c among the records of a vertex (c is present).
-__device__ __forceinline__ int find_rec(const Rec *rec, long long rb, int ell, int c) {
-    int lo = 0, hi = ell - 1;
+// Index of c among the n ascending keys k[0..n), or -1.  Each step reads 15
+// evenly spaced keys (independent loads) and keeps the slice between the two
+// that bracket c, so n keys take ceil(log16 n) dependent steps.
+__device__ __forceinline__ int kfind(const int32_t *k, int n, int c) {
+    int lo = 0, hi = n;
+    while (hi - lo > 16) {
+        const int st = (hi - lo + 15) >> 4;
+        int cnt = 0;
+#pragma unroll
+        for (int j = 1; j < 16; ++j) {
+            const int x = lo + j * st;
+            cnt += (x < hi && k[x] <= c) ? 1 : 0;
+        }
+        lo += cnt * st;
+        hi = min(hi, lo + st);
+    }
+    int f = -1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int x = lo + j;
+        if (x < hi && k[x] == c) f = x;
+    }
+    return f;
+}
+
+// w_x(c) for a community c present around x.
+template <typename OffT>
+__device__ __forceinline__ double weight_of(const ScoreArgs<OffT> &A, int x, int c) {
+    const long long rb = (long long)A.off[x];
+    const int s = kfind(A.reckey + rb, A.meta[x].ell, c);
+    return s >= 0 ? A.recdat[rb + s].w : 0.0;
+}
+
+// Sorted-range helpers on LDS arrays.
+__device__ __forceinline__ int lds_lower(const int *a, int lo, int hi, int x) {
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (rec[rb + mid].key < c)
+        if (a[mid] < x)
             lo = mid + 1;
         else
             hi = mid;
     }
     return lo;
 }
-
-// The foreign neighbours of x: its row minus the own-community sub-range
-// [p, q), ascending.
-struct Flist {
-    long long rb;
-    int p, h, n;
-};
-__device__ __forceinline__ Flist make_flist(long long rb, const VMeta &m) {
-    Flist f;
-    f.rb = rb;
-    f.p = m.p;
-    f.h = m.q - m.p;
-    f.n = m.deg - f.h;
-    return f;
-}
-__device__ __forceinline__ int fat(const int32_t *col, const Flist &f, int j) {
-    return col[f.rb + (j < f.p ? j : j + f.h)];
-}
-__device__ __forceinline__ bool fcontains(const int32_t *col, const Flist &f, int y) {
-    int lo = 0, hi = f.n;
+__device__ __forceinline__ int lds_upper(const int *a, int lo, int hi, int x) {
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (fat(col, f, mid) < y)
+        if (a[mid] <= x)
             lo = mid + 1;
         else
             hi = mid;
     }
-    return lo < f.n && fat(col, f, lo) == y;
+    return lo;
 }
-
-// Foreign neighbour w of u: its weight toward C(u), and the type-II triads
-// through w: the other neighbours v of w in C(u) (count F, sum of a_v).
-struct WInfo {
-    double W, S;
-    int F;
-};
-template <typename OffT>
-__device__ __forceinline__ WInfo w_info(const ScoreArgs<OffT> &A, int u, int cu, long long rbw, const VMeta &mw) {
-    const int s = find_rec(A.rec, rbw, mw.ell, cu);
-    const Rec r = A.rec[rbw + s];
-    const int e = (s + 1 < mw.ell) ? A.rec[rbw + s + 1].pos : mw.deg;
-    WInfo o;
-    o.W = r.w;
-    o.F = e - r.pos - 1;
-    double S = 0.0;
-#pragma unroll 4
-    for (int i = r.pos; i < e; ++i) {
-        const int x = A.col[rbw + i];
-        if (x != u) S += A.a[x];
+__device__ __forceinline__ bool glb_member(const int32_t *a, int lo, int hi, int x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int y = a[mid];
+        if (y < x)
+            lo = mid + 1;
+        else if (y > x)
+            hi = mid;
+        else
+            return true;
     }
-    o.S = S;
-    return o;
+    return false;
 }
 
+// The scored vertex u as seen by its pairs (u, w): its foreign neighbours,
+// grouped by community.  Tile form: the tile's pair list in LDS, where u's
+// pairs [pb, pe) hold w ascending (so communities ascending).
+struct TileU {
+    const int *w, *cw;
+    int pb, pe, nc;
+    __device__ __forceinline__ bool has(int c) const {
+        const int i = lds_lower(cw, pb, pe, c);
+        return i < pe && cw[i] == c;
+    }
+    __device__ __forceinline__ void run(int c, int &b, int &e) const {
+        b = lds_lower(cw, pb, pe, c);
+        e = lds_upper(cw, b, pe, c);
+    }
+    __device__ __forceinline__ bool member(int b, int e, int x) const {
+        const int i = lds_lower(w, b, e, x);
+        return i < e && w[i] == x;
+    }
+    __device__ __forceinline__ int at(int j) const { return w[j]; }
+    // u's whole foreign list N'(u), ascending
+    __device__ __forceinline__ int nf() const { return pe - pb; }
+    __device__ __forceinline__ int list_at(int j) const { return w[pb + j]; }
+    __device__ __forceinline__ bool in_list(int x) const {
+        const int i = lds_lower(w, pb, pe, x);
+        return i < pe && w[i] == x;
+    }
+    // iteration over the distinct communities of u's foreign neighbours
+    __device__ __forceinline__ int it_begin() const { return pb; }
+    __device__ __forceinline__ bool it_ok(int it) const { return it < pe; }
+    __device__ __forceinline__ int it_comm(int it) const { return cw[it]; }
+    __device__ __forceinline__ int it_next(int it, int c) const { return lds_upper(cw, it, pe, c); }
+};
+
+// Hub form: u's own row and records in HBM; its record keys and its foreign
+// list N'(u) (the row minus [p, p + h)) in LDS when they fit.
+struct HubU {
+    const int32_t *row;      // u's row
+    const int32_t *gkeys;    // u's record keys
+    const RecDat *gdat;      // u's record data
+    const int *skeys;        // LDS copy of the keys, or nullptr
+    const int *slist;        // LDS copy of N'(u), or nullptr
+    int ell, cu, nc, p, h, n_f;
+    __device__ __forceinline__ int nf() const { return n_f; }
+    __device__ __forceinline__ int list_at(int j) const { return slist ? slist[j] : row[j < p ? j : j + h]; }
+    __device__ __forceinline__ bool in_list(int x) const {
+        int lo = 0, hi = n_f;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int y = list_at(mid);
+            if (y < x)
+                lo = mid + 1;
+            else if (y > x)
+                hi = mid;
+            else
+                return true;
+        }
+        return false;
+    }
+    __device__ __forceinline__ int slot(int c) const {
+        if (skeys) {
+            const int i = lds_lower(skeys, 0, ell, c);
+            return (i < ell && skeys[i] == c) ? i : -1;
+        }
+        return kfind(gkeys, ell, c);
+    }
+    __device__ __forceinline__ bool has(int c) const { return c != cu && slot(c) >= 0; }
+    __device__ __forceinline__ void run(int c, int &b, int &e) const {
+        const int s = slot(c);
+        b = e = 0;
+        if (s >= 0) {
+            const RecDat r = gdat[s];
+            b = r.pos;
+            e = r.pos + r.f;
+        }
+    }
+    __device__ __forceinline__ bool member(int b, int e, int x) const { return glb_member(row, b, e, x); }
+    __device__ __forceinline__ int at(int j) const { return row[j]; }
+    // iteration over u's record keys (the caller skips the own community)
+    __device__ __forceinline__ int it_begin() const { return 0; }
+    __device__ __forceinline__ bool it_ok(int it) const { return it < ell; }
+    __device__ __forceinline__ int it_comm(int it) const { return skeys ? skeys[it] : gkeys[it]; }
+    __device__ __forceinline__ int it_next(int it, int) const { return it + 1; }
+};
+
+struct PairRes {
+    double val;
+    int t2, t1;
+    int defer;  // the list intersection of type-I was left to a wavefront
+};
+
+
+// Type-I triads of the pair (u, w) inside one community c shared by their
+// foreign neighbourhoods: v in both runs of c.  The shorter run is walked and
+// the other probed.  Each hit adds cbrt(w_w(C(u)) w_v(C(u)) w_w(c)).
+template <class UV, typename OffT>
+__device__ __forceinline__ void typeI_in(const ScoreArgs<OffT> &A, const UV &U, int cu, int c, long long ow, int sc,
+                                         double W, PairRes &out) {
+    const RecDat rc = A.recdat[ow + sc];
+    int ub, ue;
+    U.run(c, ub, ue);
+    const int nu = ue - ub;
+    if (nu <= 0) return;
+    const int32_t *wr = A.col + ow + rc.pos;
+    const bool walk_w = rc.f <= 8 * nu;
+    const int n_it = walk_w ? rc.f : nu;
+    for (int i = 0; i < n_it; ++i) {
+        int x;
+        bool hit;
+        if (walk_w) {
+            x = wr[i];
+            hit = U.member(ub, ue, x);
+        } else {
+            x = U.at(ub + i);
+            hit = glb_member(wr, 0, rc.f, x);
+        }
+        if (hit) {
+            out.t1 += 1;
+            out.val += cbrt(W * weight_of(A, x, cu) * rc.w);
+        }
+    }
+}
+
+// Type-I triads of the pair (u, w) by intersecting the whole foreign lists
+// N'(u) and N'(w) (used when u touches many communities, so that matching
+// communities first would not prune): the shorter side is walked and each
+// entry probed in the other list by binary search -- u's list in LDS (or
+// HBM for a large hub), w's list in HBM.  A common v is foreign to both, so
+// C(v) differs from C(u) and C(w).
+struct ListPlan {
+    int nu, nw, pw, hw, lv_u, lv_w;
+    bool walk_u;  // walk u's list and search w's (else walk w's, search u's)
+    int steps;    // entries to walk
+};
+
+template <class UV>
+__device__ __forceinline__ ListPlan list_plan(const UV &U, const VMeta &mw) {
+    ListPlan L;
+    L.pw = mw.p;
+    L.hw = mw.q - mw.p;
+    L.nw = mw.deg - L.hw;
+    L.nu = U.nf();
+    L.lv_w = 32 - __clz(L.nw);
+    L.lv_u = 32 - __clz(L.nu);
+    // cost of walking u's list with a search in HBM per entry vs walking w's
+    L.walk_u = (long long)L.nu * (L.lv_w + 1) < (long long)L.nw;
+    L.steps = (L.nu > 0 && L.nw > 0) ? (L.walk_u ? L.nu : L.nw) : 0;
+    return L;
+}
+
+__device__ __forceinline__ int nprime_at(const int32_t *rw, const ListPlan &L, int j) {
+    return rw[j < L.pw ? j : j + L.hw];
+}
+
+// One hit v of the pair (u, w): cbrt(w_w(C(u)) w_v(C(u)) w_w(C(v))).
 template <typename OffT>
-__device__ __forceinline__ double weight_toward(const ScoreArgs<OffT> &A, int x, int c) {
-    const long long rb = (long long)A.off[x];
-    return A.rec[rb + find_rec(A.rec, rb, A.meta[x].ell, c)].w;
+__device__ __forceinline__ double typeI_term(const ScoreArgs<OffT> &A, int v, int cu, long long ow, int ellw,
+                                             double W) {
+    const int sv = kfind(A.reckey + ow, ellw, A.lab[v]);
+    const double wwv = sv >= 0 ? A.recdat[ow + sv].w : 0.0;
+    return cbrt(W * weight_of(A, v, cu) * wwv);
+}
+
+// Walk entries [j0, j0 + span) of the plan's walked list with stride `stride`
+// (8 entries per step, interleaved searches); hits are handled in order.
+template <class UV, typename OffT>
+__device__ __forceinline__ void list_walk(const ScoreArgs<OffT> &A, const UV &U, const ListPlan &L, int cu,
+                                          long long ow, int ellw, double W, int first, int stride, double &acc,
+                                          long long &cnt) {
+    const int32_t *rw = A.col + ow;
+    for (int j0 = first; j0 < L.steps; j0 += 8 * stride) {
+        unsigned int hm = 0u;
+        int y[8], lo[8], hi[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int j = j0 + t * stride;
+            const bool ok = j < L.steps;
+            y[t] = ok ? (L.walk_u ? U.list_at(j) : nprime_at(rw, L, j)) : -1;
+            lo[t] = 0;
+            hi[t] = ok ? (L.walk_u ? L.nw : L.nu) : 0;
+        }
+        const int levels = L.walk_u ? L.lv_w : L.lv_u;
+        for (int step = 0; step <= levels; ++step) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (lo[t] < hi[t]) {
+                    const int mid = (lo[t] + hi[t]) >> 1;
+                    const int x = L.walk_u ? nprime_at(rw, L, mid) : U.list_at(mid);
+                    if (x == y[t]) {
+                        hm |= 1u << t;
+                        lo[t] = hi[t];
+                    } else if (x < y[t]) {
+                        lo[t] = mid + 1;
+                    } else {
+                        hi[t] = mid;
+                    }
+                }
+            }
+        }
+        while (hm) {
+            const int t = __builtin_ctz(hm);
+            hm &= hm - 1u;
+            const int j = j0 + t * stride;
+            const int v = L.walk_u ? U.list_at(j) : nprime_at(rw, L, j);
+            acc += typeI_term(A, v, cu, ow, ellw, W);
+            cnt += 1;
+        }
+    }
+}
+
+// Lists longer than this many walk steps are left to a whole wavefront.
+constexpr int kListLane = 32;
+
+// A deferred pair, intersected by all 64 lanes of a wavefront (the walked
+// list dealt round-robin to the lanes); the lane partials are summed in a
+// fixed tree order.
+template <class UV, typename OffT>
+__device__ __forceinline__ void list_wave(const ScoreArgs<OffT> &A, const UV &U, int cu, long long ow,
+                                          const VMeta &mw, double W, double &val, long long &cnt) {
+    const ListPlan L = list_plan(U, mw);
+    double acc = 0.0;
+    long long c = 0;
+    list_walk(A, U, L, cu, ow, mw.ell, W, (int)__lane_id(), 64, acc, c);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o);
+        c += __shfl_xor(c, o);
+    }
+    val = acc;
+    cnt = c;
+}
+
+// The terms of Eq. RSI that pass through the foreign neighbour w of u
+// (Lemmas 1-2, unnormalised weights):
+//   type-II: w_w(C(u))^(2/3) * sum of a_v over the other neighbours v of w in
+//            C(u) (a_v = cbrt(w_v(C(v)))), count f_w(C(u)) - 1;
+//   type-I : cbrt(w_w(C(u)) w_v(C(u)) w_w(C(v))) over the common foreign
+//            neighbours v of u and w outside C(w).  When u touches few
+//            communities the candidates are found community by community: a
+//            community c can hold such a v only if both u and w have
+//            neighbours in c, so the two record-key lists are matched first
+//            and only the runs of shared communities are intersected.
+template <class UV, typename OffT>
+__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, int cw, long long ow,
+                              const VMeta &mw, double &Wout) {
+    PairRes out = {0.0, 0, 0, 0};
+    const int ellw = mw.ell;
+    const int32_t *kw = A.reckey + ow;
+    int key[16];
+    int s = -1;
+    if (ellw <= 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            key[j] = j < ellw ? kw[j] : INT_MAX;
+            if (key[j] == cu) s = j;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) key[j] = INT_MAX;
+        s = kfind(kw, ellw, cu);
+    }
+    if (s < 0) return out;  // cannot happen: u is a neighbour of w
+    const RecDat rd = A.recdat[ow + s];
+    const double W = rd.w;
+    Wout = W;
+    out.t2 = rd.f - 1;
+    if (rd.f > 1) {
+        double S = 0.0;
+        const int32_t *run = A.col + ow + rd.pos;
+        for (int i = 0; i < rd.f; i += 4) {
+            int x[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[t] = i + t < rd.f ? run[i + t] : u;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (x[t] != u) S += A.a[x[t]];
+        }
+        const double c1 = cbrt(W);
+        out.val = c1 * c1 * S;
+    }
+    if (U.nc <= 1) return out;  // no foreign community of u besides C(w)
+    // u touching few communities: match communities first (walk u's
+    // communities, look each up among w's keys) and intersect only the runs
+    // of shared ones; otherwise intersect the whole foreign lists.
+    const bool by_comm = ellw <= 16 ? U.nc <= 8 : U.nc <= 4;
+    if (!by_comm) {
+        const ListPlan L = list_plan(U, mw);
+        if (L.steps > kListLane) {
+            out.defer = 1;
+            return out;
+        }
+        double acc = 0.0;
+        long long c = 0;
+        list_walk(A, U, L, cu, ow, ellw, W, 0, 1, acc, c);
+        out.val += acc;
+        out.t1 += (int)c;
+        return out;
+    }
+    for (int it = U.it_begin(); U.it_ok(it);) {
+        const int c = U.it_comm(it);
+        it = U.it_next(it, c);
+        if (c == cw || c == cu) continue;
+        int sc = -1;
+        if (ellw <= 16) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (key[j] == c) sc = j;
+        } else {
+            sc = kfind(kw, ellw, c);
+        }
+        if (sc >= 0) typeI_in(A, U, cu, c, ow, sc, W, out);
+    }
+    return out;
 }
 
 struct ScoreAcc {
@@ -831,218 +951,254 @@ __device__ __forceinline__ void score_store(const ScoreArgs<OffT> &A, int u, int
     sa.tII += cII;
 }
 
-// Membership of y in a sorted LDS column of n entries (stride kBlock).
-__device__ __forceinline__ bool lds_member(const int *colv, int n, int y) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (colv[mid * kBlock] < y)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Exclusive prefix of one int per thread over the block; total to *total.
+__device__ __forceinline__ int block_excl_scan(int x, int *ws, int &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
     }
-    return lo < n && colv[lo * kBlock] == y;
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const int c = ws[i];
+        if (i < wave) base += c;
+        total += c;
+    }
+    return base + incl - x;
 }
 
-// Bin A: one thread per vertex (d <= 16).  N'(u) is kept (ascending) in an
-// LDS column of this thread.  For every foreign neighbour w, the type-I
-// partners are N'(u) & N'(w): the shorter list is walked, the longer probed.
+// ------------------------------------------------------------ score tiles
+// A score tile is a run of <= kScoreTileV consecutive vertices with at most
+// kScoreTileP foreign entries: one thread per vertex gathers the vertex
+// facts, the pairs (u, w) are laid out flat in LDS (one lane per pair), and
+// one thread per vertex sums its pairs' terms in pair order.
+static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score tile size: one vertex and one pair per thread");
+
+struct ScoreTileShared {
+    int pb[kScoreTileV + 1];
+    long long ou[kScoreTileV];
+    int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV], nc[kScoreTileV];
+    unsigned short pu[kScoreTileP];
+    int w[kScoreTileP], cw[kScoreTileP];
+    double val[kScoreTileP];
+    int t2[kScoreTileP], t1[kScoreTileP];
+    double hW[kScoreTileP];         // deferred pairs: w_w(C(u)) ...
+    unsigned short hq[kScoreTileP]; // ... and the pair
+    int nhq;
+    int ws[kBlock / 64];
+};
+
 template <typename OffT>
-__device__ __forceinline__ void score_thread(const ScoreArgs<OffT> &A, int u, double wmax, int *colv,
-                                             ScoreAcc &sa) {
-    const VMeta mu = A.meta[u];
-    const Flist fu = make_flist((long long)A.off[u], mu);
-    if (fu.n == 0) return;
-    const int cu = A.lab[u];
-    double acc = 0.0;
-    long long cII = 0, cI = 0, work = 0;
-    for (int j0 = 0; j0 < fu.n; j0 += 4) {
-        int w[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) w[t] = j0 + t < fu.n ? fat(A.col, fu, j0 + t) : -1;
-        long long rbw[4];
-        VMeta mw[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            rbw[t] = 0;
-            mw[t].deg = mw[t].ell = mw[t].p = mw[t].q = 0;
-            if (w[t] >= 0) {
-                rbw[t] = (long long)A.off[w[t]];
-                mw[t] = A.meta[w[t]];
-            }
+__device__ void score_tile(const ScoreArgs<OffT> &A, ScoreTileShared &S, int t, double wmax, ScoreAcc &sa) {
+    const int tid = threadIdx.x;
+    const int2 tl = A.tiles[t];
+    const int v0 = tl.x, nv = tl.y - tl.x;
+    int dp = 0, deg = 0;
+    if (tid < nv) {
+        const int v = v0 + tid;
+        const VMeta m = A.meta[v];
+        deg = m.deg;
+        dp = m.deg - (m.q - m.p);
+        S.ou[tid] = (long long)A.off[v];
+        S.cu[tid] = A.lab[v];
+        S.p[tid] = m.p;
+        S.h[tid] = m.q - m.p;
+        S.nc[tid] = m.ell - (m.q > m.p ? 1 : 0);
+    }
+    int total;
+    const int pb = block_excl_scan(dp, S.ws, total);
+    if (tid < nv) {
+        S.pb[tid] = pb;
+        for (int k = pb; k < pb + dp; ++k) S.pu[k] = (unsigned short)tid;
+    }
+    if (tid == 0) {
+        S.pb[nv] = total;
+        S.nhq = 0;
+    }
+    __syncthreads();
+    // one pair per thread: its foreign neighbour w and w's row facts
+    const int k = tid;
+    long long ow = 0;
+    VMeta mw;
+    mw.deg = mw.ell = mw.p = mw.q = 0;
+    int i = 0;
+    if (k < total) {
+        i = S.pu[k];
+        const int idx = k - S.pb[i];
+        const int pos = idx < S.p[i] ? idx : idx + S.h[i];
+        const int w = A.col[S.ou[i] + pos];
+        S.w[k] = w;
+        ow = (long long)A.off[w];
+        mw = A.meta[w];
+        S.cw[k] = A.lab[w];
+        sa.workI += min(S.pb[i + 1] - S.pb[i], mw.deg - (mw.q - mw.p));
+    }
+    __syncthreads();
+    if (k < total) {
+        TileU U;
+        U.w = S.w;
+        U.cw = S.cw;
+        U.pb = S.pb[i];
+        U.pe = S.pb[i + 1];
+        U.nc = S.nc[i];
+        double W;
+        const PairRes r = score_pair(A, U, v0 + i, S.cu[i], S.w[k], S.cw[k], ow, mw, W);
+        S.val[k] = r.val;
+        S.t2[k] = r.t2;
+        S.t1[k] = r.t1;
+        if (r.defer) {
+            const int q = atomicAdd(&S.nhq, 1);
+            S.hq[q] = (unsigned short)k;
+            S.hW[q] = W;
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (w[t] >= 0) {
-                colv[(j0 + t) * kBlock] = w[t];
-                const WInfo wi = w_info(A, u, cu, rbw[t], mw[t]);
-                const double c1 = cbrt(wi.W);
-                acc += c1 * c1 * wi.S;
-                cII += wi.F;
+    }
+    __syncthreads();
+    // deferred list intersections: one wavefront per pair
+    {
+        const int wave = tid >> 6, nq = S.nhq;
+        for (int q = wave; q < nq; q += kBlock / 64) {
+            const int k = S.hq[q];
+            const int i = S.pu[k];
+            const int w = S.w[k];
+            TileU U;
+            U.w = S.w;
+            U.cw = S.cw;
+            U.pb = S.pb[i];
+            U.pe = S.pb[i + 1];
+            U.nc = S.nc[i];
+            double val;
+            long long cnt;
+            list_wave(A, U, S.cu[i], (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
+            if ((tid & 63) == 0) {
+                S.val[k] += val;
+                S.t1[k] += (int)cnt;
             }
         }
     }
-    for (int j = 0; j < fu.n; ++j) {
-        const int w = colv[j * kBlock];
-        const long long rbw = (long long)A.off[w];
-        const VMeta mw = A.meta[w];
-        const Flist fw = make_flist(rbw, mw);
-        work += min(fu.n, fw.n);
-        double Ww = -1.0;
-        if (fw.n <= fu.n) {
-            for (int t0 = 0; t0 < fw.n; t0 += 8) {
-                int y[8];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) y[t] = t0 + t < fw.n ? fat(A.col, fw, t0 + t) : -1;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    if (y[t] >= 0 && lds_member(colv, fu.n, y[t])) {
-                        if (Ww < 0.0) Ww = A.rec[rbw + find_rec(A.rec, rbw, mw.ell, cu)].w;
-                        const double Wy = weight_toward(A, y[t], cu);
-                        const double Wwy = A.rec[rbw + find_rec(A.rec, rbw, mw.ell, A.lab[y[t]])].w;
-                        acc += cbrt(Ww * Wy * Wwy);
-                        ++cI;
-                    }
-                }
-            }
-        } else {
-            for (int k = 0; k < fu.n; ++k) {
-                const int y = colv[k * kBlock];
-                if (fcontains(A.col, fw, y)) {
-                    if (Ww < 0.0) Ww = A.rec[rbw + find_rec(A.rec, rbw, mw.ell, cu)].w;
-                    const double Wy = weight_toward(A, y, cu);
-                    const double Wwy = A.rec[rbw + find_rec(A.rec, rbw, mw.ell, A.lab[y])].w;
-                    acc += cbrt(Ww * Wy * Wwy);
-                    ++cI;
-                }
-            }
+    __syncthreads();
+    if (tid < nv && dp > 0) {
+        double acc = 0.0;
+        long long c1 = 0, c2 = 0;
+        for (int k = pb; k < pb + dp; ++k) {
+            acc += S.val[k];
+            c2 += S.t2[k];
+            c1 += S.t1[k];
         }
+        score_store(A, v0 + tid, deg, acc, c1, c2, wmax, sa);
     }
-    sa.workI += work;
-    score_store(A, u, mu.deg, acc, cI, cII, wmax, sa);
 }
 
-// Bins B-D: T lanes per vertex.  N'(u) is staged in LDS when it fits (CAP).
-// The foreign neighbours w are dealt to the lanes in chunks of T; each lane
-// computes w's weight and type-II sum, then the chunk's type-I searches are
-// flattened over the team: item t of w iterates the shorter of N'(u), N'(w)
-// and probes the other.
-template <int T, int CAP, typename OffT>
-__device__ __forceinline__ void score_team(const ScoreArgs<OffT> &A, const Team<T> &tm, int u, const VMeta &mu,
-                                           const Flist &fu, double wmax, const int *nl, ScoreAcc &sa) {
+// ------------------------------------------------------------ score hubs
+// A vertex with more than kScoreTileP foreign entries gets a workgroup of its
+// own kernel; its record keys and foreign list are staged in LDS when they
+// fit, and its pairs are taken kBlock at a time and summed in a fixed tree
+// order.
+struct ScoreHubShared {
+    int keys[kHubKeys];
+    int list[kHubList];
+    double red[kBlock / 64];
+    long long ired[2][kBlock / 64];
+    double hW[kBlock], dval[kBlock];  // deferred pairs of a chunk, by lane
+    int hw[kBlock], dcnt[kBlock];
+    unsigned char hq[kBlock];
+    int nhq;
+};
+
+template <typename OffT>
+__device__ void score_hub(const ScoreArgs<OffT> &A, ScoreHubShared &S, int u, double wmax, ScoreAcc &sa) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const VMeta m = A.meta[u];
+    const long long ou = (long long)A.off[u];
     const int cu = A.lab[u];
-    const bool staged = fu.n <= CAP;
+    const int h = m.q - m.p;
+    const int dp = m.deg - h;
+    const bool lk = m.ell <= kHubKeys, ll = dp <= kHubList;
+    if (lk)
+        for (int j = tid; j < m.ell; j += kBlock) S.keys[j] = A.reckey[ou + j];
+    if (ll)
+        for (int j = tid; j < dp; j += kBlock) S.list[j] = A.col[ou + (j < m.p ? j : j + h)];
+    __syncthreads();
+    HubU U;
+    U.row = A.col + ou;
+    U.gkeys = A.reckey + ou;
+    U.gdat = A.recdat + ou;
+    U.skeys = lk ? S.keys : nullptr;
+    U.slist = ll ? S.list : nullptr;
+    U.ell = m.ell;
+    U.cu = cu;
+    U.nc = m.ell - (h > 0 ? 1 : 0);
+    U.p = m.p;
+    U.h = h;
+    U.n_f = dp;
     double acc = 0.0;
-    long long cI = 0, cII = 0, work = 0;
-    for (int jb = 0; jb < fu.n; jb += T) {
-        const int j = jb + tm.lane;
-        const bool has = j < fu.n;
-        Flist fw;
-        fw.rb = 0;
-        fw.p = fw.h = fw.n = 0;
-        double W = 0.0;
-        int wl = 0;
-        if (has) {
-            const int w = staged ? nl[j] : fat(A.col, fu, j);
-            const long long rbw = (long long)A.off[w];
+    long long c1 = 0, c2 = 0;
+    for (int k0 = 0; k0 < dp; k0 += kBlock) {
+        const int k = k0 + tid;
+        if (tid == 0) S.nhq = 0;
+        __syncthreads();
+        PairRes r = {0.0, 0, 0, 0};
+        if (k < dp) {
+            const int w = ll ? S.list[k] : A.col[ou + (k < m.p ? k : k + h)];
+            const long long ow = (long long)A.off[w];
             const VMeta mw = A.meta[w];
-            fw = make_flist(rbw, mw);
-            const WInfo wi = w_info(A, u, cu, rbw, mw);
-            W = wi.W;
-            const double c1 = cbrt(W);
-            acc += c1 * c1 * wi.S;
-            cII += wi.F;
-            wl = mw.ell;
+            const int cw = A.lab[w];
+            sa.workI += min(dp, mw.deg - (mw.q - mw.p));
+            double W;
+            r = score_pair(A, U, u, cu, w, cw, ow, mw, W);
+            if (r.defer) {
+                const int q = atomicAdd(&S.nhq, 1);
+                S.hq[q] = (unsigned char)tid;
+                S.hW[q] = W;
+                S.hw[q] = w;
+            }
         }
-        // type-I: flattened over the chunk
-        const int myw = has ? min(fu.n, fw.n) : 0;
-        const int ex = tm.excl_scan(myw);
-        const int total = tm.isum(myw);
-        work += myw;
-        for (int b = 0; b < total; b += T) {
-            const int it = b + tm.lane;
-            // owner: the largest lane whose exclusive prefix is <= it
-            int lo = 0;
+        __syncthreads();
+        {
+            const int nq = S.nhq;
+            for (int q = wave; q < nq; q += kBlock / 64) {
+                const int w = S.hw[q];
+                double val;
+                long long cnt;
+                list_wave(A, U, cu, (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
+                if (lane == 0) {
+                    S.dval[S.hq[q]] = val;
+                    S.dcnt[S.hq[q]] = (int)cnt;
+                }
+            }
+        }
+        __syncthreads();
+        if (r.defer) {
+            r.val += S.dval[tid];
+            r.t1 += S.dcnt[tid];
+        }
+        double x = r.val;
+        long long y1 = r.t1, y2 = r.t2;
 #pragma unroll
-            for (int step = T / 2; step > 0; step >>= 1) {
-                const int cand = lo + step;
-                const int e = tm.bcast(ex, cand);
-                if (e <= it) lo = cand;
-            }
-            const int o = lo;
-            const int t = it - tm.bcast(ex, o);
-            Flist fo;
-            fo.rb = tm.bcast(fw.rb, o);
-            fo.p = tm.bcast(fw.p, o);
-            fo.h = tm.bcast(fw.h, o);
-            fo.n = tm.bcast(fw.n, o);
-            const double oW = tm.bcast(W, o);
-            const int owl = tm.bcast(wl, o);
-            if (it < total) {
-                int y;
-                bool found;
-                if (fo.n <= fu.n) {
-                    y = fat(A.col, fo, t);
-                    if (staged) {
-                        int l2 = 0, h2 = fu.n;
-                        while (l2 < h2) {
-                            const int mid = (l2 + h2) >> 1;
-                            if (nl[mid] < y)
-                                l2 = mid + 1;
-                            else
-                                h2 = mid;
-                        }
-                        found = l2 < fu.n && nl[l2] == y;
-                    } else {
-                        found = fcontains(A.col, fu, y);
-                    }
-                } else {
-                    y = staged ? nl[t] : fat(A.col, fu, t);
-                    found = fcontains(A.col, fo, y);
-                }
-                if (found) {
-                    const double Wv = weight_toward(A, y, cu);
-                    const double Wwv = A.rec[fo.rb + find_rec(A.rec, fo.rb, owl, A.lab[y])].w;
-                    acc += cbrt(oW * Wv * Wwv);
-                    ++cI;
-                }
-            }
+        for (int o = 32; o > 0; o >>= 1) {
+            x += __shfl_xor(x, o);
+            y1 += __shfl_xor(y1, o);
+            y2 += __shfl_xor(y2, o);
         }
-    }
-    acc = tm.sum(acc);
-    cI = tm.sum(cI);
-    cII = tm.sum(cII);
-    if (tm.lane == 0) score_store(A, u, mu.deg, acc, cI, cII, wmax, sa);
-    sa.workI += work;
-}
-
-template <int T, int CAP, typename OffT>
-__device__ __forceinline__ void score_team_bin(const ScoreArgs<OffT> &A, int bin, double wmax, int *lds,
-                                               ScoreAcc &sa) {
-    const Team<T> tm;
-    const int teams = (int)blockDim.x / T;
-    const Span s = xcd_span(A.bin_lo[bin + 1] - A.bin_lo[bin], teams);
-    int *nl = lds + (threadIdx.x / T) * CAP;
-    for (long long base = s.first; base < s.hi; base += s.step) {
-        const long long it = base + threadIdx.x / T;
-        const bool has = it < s.hi;
-        int u = 0;
-        VMeta mu;
-        mu.deg = mu.ell = mu.p = mu.q = 0;
-        Flist fu;
-        fu.rb = 0;
-        fu.p = fu.h = fu.n = 0;
-        if (has) {
-            u = A.sched[A.bin_lo[bin] + it];
-            mu = A.meta[u];
-            fu = make_flist((long long)A.off[u], mu);
-            if (fu.n <= CAP)
-                for (int j = tm.lane; j < fu.n; j += T) nl[j] = fat(A.col, fu, j);
+        if (lane == 0) {
+            S.red[wave] = x;
+            S.ired[0][wave] = y1;
+            S.ired[1][wave] = y2;
         }
         __syncthreads();
-        if (has && fu.n > 0) score_team<T, CAP, OffT>(A, tm, u, mu, fu, wmax, nl, sa);
+        for (int i = 0; i < kBlock / 64; ++i) {
+            acc += S.red[i];
+            c1 += S.ired[0][i];
+            c2 += S.ired[1][i];
+        }
         __syncthreads();
     }
+    if (tid == 0 && dp > 0) score_store(A, u, m.deg, acc, c1, c2, wmax, sa);
 }
 
 __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
@@ -1071,32 +1227,27 @@ __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
     }
 }
 
-// Bins A (one thread per vertex) and B (4 lanes per vertex).
+// Algorithm 1 Step 3 (Eq. RSI) for every border vertex of a score tile.
+// Partials go after the hub kernel's.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_score_small(ScoreArgs<OffT> A) {
-    __shared__ int lds[16 * kBlock];  // bin A: 16-entry column per thread; bin B: kCapB entries per team
+__global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
+    __shared__ ScoreTileShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0, 0};
-    score_team_bin<4, kCapB, OffT>(A, 1, wmax, lds, sa);
-    {
-        const Span s = xcd_span(A.bin_lo[1] - A.bin_lo[0], kBlock);
-        for (long long base = s.first; base < s.hi; base += s.step) {
-            const long long it = base + threadIdx.x;
-            if (it < s.hi) score_thread<OffT>(A, A.sched[A.bin_lo[0] + it], wmax, lds + threadIdx.x, sa);
-        }
-    }
-    block_reduce_score(sa, &A.part[blockIdx.x]);
+    const int b = (int)blockIdx.x;
+    const int t = tile_of_block(b, 0, A.tiles_per_xcd);
+    if (t < A.n_tiles) score_tile(A, S, t, wmax, sa);
+    block_reduce_score(sa, &A.part[A.n_hubs + b]);
 }
 
-// Bins C (16 lanes per vertex) and D (a wavefront per vertex).
+// ... and for every score hub (one workgroup each).
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_score_big(ScoreArgs<OffT> A) {
-    __shared__ int lds[16 * kBlock];  // bin C: 16 teams x kCapC; bin D: 4 teams x kCapD
+__global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
+    __shared__ ScoreHubShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0, 0};
-    score_team_bin<64, kCapD, OffT>(A, 3, wmax, lds, sa);
-    score_team_bin<16, kCapC, OffT>(A, 2, wmax, lds, sa);
-    block_reduce_score(sa, &A.part[kGridScore + blockIdx.x]);
+    score_hub(A, S, A.hubs[blockIdx.x], wmax, sa);
+    block_reduce_score(sa, &A.part[blockIdx.x]);
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, int np, DevCounters *c) {
@@ -1141,41 +1292,40 @@ static rs_status score_pass_t(rs_graph *g) {
     A.deg = D.deg;
     A.col = D.col;
     A.lab = D.lab;
-    A.sched = D.sched;
-    A.rec = D.rec;
+    A.tiles = D.rtiles;
+    A.hubs = D.rhubs;
+    A.n_tiles = g->n_rtiles;
+    A.n_hubs = g->n_rhubs;
+    A.tiles_per_xcd = (g->n_rtiles + 7) / 8;
+    A.reckey = D.reckey;
+    A.recdat = D.recdat;
     A.meta = D.meta;
     A.wown = D.wown;
     A.a = D.a;
     A.R = D.R;
     A.tI = D.tI;
     A.tII = D.tII;
-    for (int b = 0; b <= kBins; ++b) A.bin_lo[b] = g->bin_lo[b];
-    // partials: [k_rows | k_rows_mid | k_rows_hub]
-    if (g->hub_grid > 0) {
-        A.part = D.part_rows + kGridRows + kGridMid;
-        timing_begin(g, K_ROWS_HUB, &ev);
-        hipLaunchKernelGGL(k_rows_hub<OffT>, dim3(g->hub_grid), dim3(kBlock), 0, g->stream, A);
-        timing_end(g, K_ROWS_HUB, ev);
-    }
-    A.part = D.part_rows + kGridRows;
-    timing_begin(g, K_ROWS_MID, &ev);
-    hipLaunchKernelGGL(k_rows_mid<OffT>, dim3(kGridMid), dim3(kBlock), 0, g->stream, A);
-    timing_end(g, K_ROWS_MID, ev);
     A.part = D.part_rows;
-    timing_begin(g, K_ROWS, &ev);
-    hipLaunchKernelGGL(k_rows<OffT>, dim3(kGridRows), dim3(kBlock), 0, g->stream, A);
-    timing_end(g, K_ROWS, ev);
+    if (g->grid_rows > 0) {
+        timing_begin(g, K_ROWS, &ev);
+        hipLaunchKernelGGL(k_rows<OffT>, dim3(g->grid_rows), dim3(kBlock), 0, g->stream, A);
+        timing_end(g, K_ROWS, ev);
+    }
     timing_begin(g, K_WMAX, &ev);
-    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.part_rows, kGridRows + kGridMid + g->hub_grid,
-                       D.ctr);
+    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.part_rows, g->grid_rows, D.ctr);
     timing_end(g, K_WMAX, ev);
 
     ScoreArgs<OffT> S;
     S.off = (const OffT *)D.off;
     S.col = D.col;
     S.lab = D.lab;
-    S.sched = D.sched;
-    S.rec = D.rec;
+    S.tiles = D.stiles;
+    S.hubs = D.shubs;
+    S.n_tiles = g->n_stiles;
+    S.n_hubs = g->n_shubs;
+    S.tiles_per_xcd = (g->n_stiles + 7) / 8;
+    S.reckey = D.reckey;
+    S.recdat = D.recdat;
     S.meta = D.meta;
     S.a = D.a;
     S.R = D.R;
@@ -1183,13 +1333,16 @@ static rs_status score_pass_t(rs_graph *g) {
     S.tII = D.tII;
     S.ctr = D.ctr;
     S.part = D.part_score;
-    for (int b = 0; b <= kBins; ++b) S.bin_lo[b] = g->bin_lo[b];
-    timing_begin(g, K_SCORE, &ev);
-    hipLaunchKernelGGL(k_score_small<OffT>, dim3(kGridScore), dim3(kBlock), 0, g->stream, S);
-    timing_end(g, K_SCORE, ev);
-    timing_begin(g, K_SCORE_BIG, &ev);
-    hipLaunchKernelGGL(k_score_big<OffT>, dim3(kGridBig), dim3(kBlock), 0, g->stream, S);
-    timing_end(g, K_SCORE_BIG, ev);
+    if (g->n_shubs > 0) {
+        timing_begin(g, K_SCORE_HUB, &ev);
+        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(g->n_shubs), dim3(kBlock), 0, g->stream, S);
+        timing_end(g, K_SCORE_HUB, ev);
+    }
+    if (g->grid_score > g->n_shubs) {
+        timing_begin(g, K_SCORE, &ev);
+        hipLaunchKernelGGL(k_score<OffT>, dim3(g->grid_score - g->n_shubs), dim3(kBlock), 0, g->stream, S);
+        timing_end(g, K_SCORE, ev);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "score pass launch");
     return RS_OK;
@@ -1200,8 +1353,7 @@ rs_status launch_score_pass(rs_graph *g) {
 }
 
 rs_status launch_reduce_counts(rs_graph *g) {
-    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, g->d.part_score, kGridScore + kGridBig,
-                       g->d.ctr);
+    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, g->d.part_score, g->grid_score, g->d.ctr);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "reduce launch");
 }
@@ -1230,12 +1382,71 @@ __device__ __forceinline__ TopkKey make_key(const double *R, const int32_t *new2
     return k;
 }
 
+// Threshold search over the 65,536-bin histogram by one workgroup of kBlock
+// threads: thread t owns 256 bins, descending with t; the block prefix of
+// the per-thread totals finds the bin where the count from the top reaches
+// st->take.  Records the threshold in st and clears the histogram.
+__device__ void topk_find_block(unsigned int *hist, TopkState *st, int level, long long *s_scan) {
+    constexpr int kPer = kTopkBins / kBlock;
+    const int t = threadIdx.x;
+    const long long need = st->take;
+    const int base = kTopkBins - kPer * (t + 1);
+    const uint4 *h4 = (const uint4 *)(hist + base);
+    long long mine = 0;
+#pragma unroll 8
+    for (int i = 0; i < kPer / 4; ++i) {
+        const uint4 x = h4[i];
+        mine += (long long)x.x + x.y + x.z + x.w;
+    }
+    s_scan[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const long long x = t >= o ? s_scan[t - o] : 0;
+        __syncthreads();
+        s_scan[t] += x;
+        __syncthreads();
+    }
+    const long long incl = s_scan[t];
+    const long long excl = incl - mine;
+    const long long total = s_scan[kBlock - 1];
+    if (excl < need && need <= incl) {
+        long long cum = excl;
+        for (int i = kPer - 1; i >= 0; --i) {
+            const long long h = hist[base + i];
+            if (cum + h >= need) {
+                st->digit = (unsigned int)level;
+                st->thresh = (unsigned int)(base + i);
+                st->above += cum;
+                st->take = need - cum;
+                st->binsize = h;
+                st->done = (need - cum == h) ? 1u : 0u;
+                break;
+            }
+            cum += h;
+        }
+    }
+    if (t == 0 && !(need > 0 && total >= need)) {  // cannot happen for need <= live keys: take all
+        st->digit = (unsigned int)level;
+        st->thresh = 0;
+        st->take = 0;
+        st->binsize = 0;
+        st->done = 1u;
+    }
+    __syncthreads();
+    uint4 *w4 = (uint4 *)(hist + base);
+#pragma unroll 8
+    for (int i = 0; i < kPer / 4; ++i) w4[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Level-0 histogram: each block counts a contiguous chunk (< 2^16 keys) in an
 // LDS histogram of 16-bit counters packed two per word, then adds its
-// non-zero bins to the global histogram.
+// non-zero bins to the global histogram.  The last block to finish resets
+// the selection state for k and finds the threshold bin.
 __global__ __launch_bounds__(kBlock) void k_topk_hist(const double *R, const int32_t *new2old, const uint8_t *alive,
-                                                      long long n, long long chunk, unsigned int *hist) {
+                                                      long long n, long long chunk, unsigned int *hist,
+                                                      TopkState *st, long long k) {
     __shared__ unsigned int sh[kTopkBins / 2];
+    __shared__ int s_last;
     for (int i = threadIdx.x; i < kTopkBins / 2; i += kBlock) sh[i] = 0u;
     __syncthreads();
     const long long lo = (long long)blockIdx.x * chunk;
@@ -1252,6 +1463,28 @@ __global__ __launch_bounds__(kBlock) void k_topk_hist(const double *R, const int
         if (x & 0xffffu) atomicAdd(&hist[2 * i], x & 0xffffu);
         if (x >> 16) atomicAdd(&hist[2 * i + 1], x >> 16);
     }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1 ? 1 : 0;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+        st->k = k;
+        st->digit = 0;
+        st->thresh = 0;
+        st->above = 0;
+        st->take = k;
+        st->binsize = 0;
+        st->n_final = 0;
+        st->n_tie = 0;
+        st->overflow = 0;
+        st->done = 0;
+        st->hist_done = 0;
+        st->small = 0;
+    }
+    __syncthreads();
+    topk_find_block(hist, st, 0, (long long *)sh);
 }
 
 // Histogram of digit j over a key list (refinement of a large tie class).
@@ -1492,19 +1725,54 @@ __global__ __launch_bounds__(kBlock) void k_final_rank(const TopkKey *fin, long 
     }
 }
 
-__global__ void k_topk_setup(TopkState *st, long long k) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->k = k;
-        st->digit = 0;
-        st->thresh = 0;
-        st->above = 0;
-        st->take = k;
-        st->binsize = 0;
-        st->n_final = 0;
-        st->n_tie = 0;
-        st->overflow = 0;
-        st->done = 0;
+// Common case: the final list plus the threshold bin hold at most
+// kSmallCap keys.  One block loads both into LDS, bitonic-sorts them
+// (descending) and writes the first keff; keys are unique (the id is part of
+// the key), so the order is exact.  Otherwise it leaves the work to the
+// general path.
+__global__ __launch_bounds__(1024) void k_topk_small(TopkState *st, const TopkKey *fin, const TopkKey *tie,
+                                                     long long keff, const double *R, const int32_t *new2old,
+                                                     int32_t *out_ids, double *out_sc) {
+    __shared__ TopkKey s[kSmallCap];
+    const long long nf = (long long)st->n_final;
+    const long long nt = st->done ? 0 : (long long)st->n_tie;
+    const long long total = nf + nt;
+    if (total > kSmallCap || total < keff) return;
+    int n2 = 1;
+    while (n2 < total) n2 <<= 1;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        if (i < nf) {
+            s[i] = fin[i];
+        } else if (i < total) {
+            s[i] = tie[i - nf];
+        } else {
+            s[i].hi = 0;
+            s[i].lo = 0;  // below every real key (a real key has lo >= 2^31)
+            s[i].v = -1;
+        }
     }
+    __syncthreads();
+    for (int kk = 2; kk <= n2; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool desc = (i & kk) == 0;
+                    const TopkKey x = s[i], y = s[l];
+                    if (desc ? key_gt(y, x) : key_gt(x, y)) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < keff; i += blockDim.x) {
+        out_ids[i] = new2old[s[i].v];
+        out_sc[i] = R[s[i].v];
+    }
+    if (threadIdx.x == 0) st->small = 1u;
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int count) {
@@ -1533,7 +1801,13 @@ static rs_status final_order(rs_graph *g, long long keff) {
     return e == hipSuccess ? RS_OK : hip_fail(e, "top-k order launch");
 }
 
-rs_status launch_topk(rs_graph *g, int64_t k, int64_t *count) {
+static hipError_t copy_out(rs_graph *g, long long keff, int32_t *ids, double *scores) {
+    hipError_t e = hipMemcpyAsync(ids, g->d.tout_ids, 4 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(scores, g->d.tout_sc, 8 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
+    return e;
+}
+
+rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count) {
     DeviceGraph &D = g->d;
     const long long keff = k < g->n_alive ? k : g->n_alive;
     *count = keff;
@@ -1543,63 +1817,72 @@ rs_status launch_topk(rs_graph *g, int64_t k, int64_t *count) {
     if (chunk < 4096) chunk = 4096;
     if (chunk > kHistChunk) chunk = kHistChunk;
     const int grid_h = (int)((D.n + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_topk_setup, dim3(1), dim3(64), 0, g->stream, D.tstate, keff);
     timing_begin(g, K_TOPK_HIST, &ev);
     hipLaunchKernelGGL(k_topk_hist, dim3(grid_h), dim3(kBlock), 0, g->stream, D.R, D.new2old, D.alive, D.n, chunk,
-                       D.thist);
+                       D.thist, D.tstate, keff);
     timing_end(g, K_TOPK_HIST, ev);
-    timing_begin(g, K_TOPK_FIND, &ev);
-    hipLaunchKernelGGL(k_topk_find, dim3(1), dim3(1024), 0, g->stream, D.thist, D.tstate, 0);
-    timing_end(g, K_TOPK_FIND, ev);
     timing_begin(g, K_TOPK_COLLECT, &ev);
     hipLaunchKernelGGL(k_topk_collect, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.R,
                        D.new2old, D.alive, D.n, D.tstate, D.tfinal, D.ttie);
     timing_end(g, K_TOPK_COLLECT, ev);
+    timing_begin(g, K_TOPK_RANK, &ev);
+    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, g->stream, D.tstate, D.tfinal, D.ttie, keff, D.R,
+                       D.new2old, D.tout_ids, D.tout_sc);
+    timing_end(g, K_TOPK_RANK, ev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "top-k launch");
+    TopkState st;
+    e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = copy_out(g, keff, ids, scores);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "top-k state read");
+    if (st.small) return RS_OK;
+
+    // General path: rank the tie class pairwise, then order the final list.
     timing_begin(g, K_TOPK_TIE, &ev);
     hipLaunchKernelGGL(k_tie_rank, dim3(kTieCap / kBlock), dim3(kBlock), 0, g->stream, D.ttie, D.tstate, D.tfinal);
     timing_end(g, K_TOPK_TIE, ev);
     rs_status rs_st = final_order(g, keff);
     if (rs_st != RS_OK) return rs_st;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "top-k launch");
-
-    TopkState st;
     e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "top-k state read");
-    if (!st.overflow) return RS_OK;
-
-    // A tie class larger than the pairwise ranker: refine it digit by digit.
-    // The final list already holds the keys above the tie class.
-    unsigned long long *cnt = D.scratch_u;  // [0] current list size, [1] next list size
-    TopkKey *cur = D.ttie, *nxt = D.ttie2;
-    e = hipMemcpyAsync(cnt, &D.tstate->n_tie, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
-    for (int j = 1; j <= 5 && e == hipSuccess; ++j) {
-        unsigned long long cur_n = 0;
-        e = hipMemcpyAsync(&cur_n, cnt, sizeof(cur_n), hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-        if (e != hipSuccess) break;
-        const int grid_l = grid_for((long long)cur_n, kBlock, 4096);
-        hipLaunchKernelGGL(k_list_hist, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, j, D.thist);
-        hipLaunchKernelGGL(k_topk_find, dim3(1), dim3(1024), 0, g->stream, D.thist, D.tstate, j);
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, cnt + 1, 1);
-        hipLaunchKernelGGL(k_list_collect, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, D.tstate, D.tfinal,
-                           nxt, cnt + 1);
-        e = hipMemcpyAsync(cnt, cnt + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-        if (e != hipSuccess) break;
-        TopkKey *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        if (st.done) break;
+    if (st.overflow) {
+        // A tie class larger than the pairwise ranker: refine it digit by
+        // digit.  The final list already holds the keys above the tie class.
+        unsigned long long *cnt = D.scratch_u;  // [0] current list size, [1] next list size
+        TopkKey *cur = D.ttie, *nxt = D.ttie2;
+        e = hipMemcpyAsync(cnt, &D.tstate->n_tie, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
+        for (int j = 1; j <= 5 && e == hipSuccess; ++j) {
+            unsigned long long cur_n = 0;
+            e = hipMemcpyAsync(&cur_n, cnt, sizeof(cur_n), hipMemcpyDeviceToHost, g->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+            if (e != hipSuccess) break;
+            const int grid_l = grid_for((long long)cur_n, kBlock, 4096);
+            hipLaunchKernelGGL(k_list_hist, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, j, D.thist);
+            timing_begin(g, K_TOPK_FIND, &ev);
+            hipLaunchKernelGGL(k_topk_find, dim3(1), dim3(1024), 0, g->stream, D.thist, D.tstate, j);
+            timing_end(g, K_TOPK_FIND, ev);
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, cnt + 1, 1);
+            hipLaunchKernelGGL(k_list_collect, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, D.tstate,
+                               D.tfinal, nxt, cnt + 1);
+            e = hipMemcpyAsync(cnt, cnt + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+            if (e != hipSuccess) break;
+            TopkKey *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            if (st.done) break;
+        }
+        if (e == hipSuccess) e = hipMemsetAsync(&D.tstate->overflow, 0, sizeof(unsigned int), g->stream);
+        if (e != hipSuccess) return hip_fail(e, "top-k refine");
+        rs_st = final_order(g, keff);
+        if (rs_st != RS_OK) return rs_st;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(&D.tstate->overflow, 0, sizeof(unsigned int), g->stream);
-    if (e != hipSuccess) return hip_fail(e, "top-k refine");
-    rs_st = final_order(g, keff);
-    if (rs_st != RS_OK) return rs_st;
-    e = hipStreamSynchronize(g->stream);
-    return e == hipSuccess ? RS_OK : hip_fail(e, "top-k refine");
+    e = copy_out(g, keff, ids, scores);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? RS_OK : hip_fail(e, "top-k copy");
 }
 
 // ============================================================ removals
@@ -1675,7 +1958,9 @@ __global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *
     }
 }
 
-// Squeeze the marked entries out of every row (order kept), updating deg.
+// Squeeze the marked entries out of every row (order kept), updating deg;
+// the freed tail of the row's capacity is set to -1, which the row tiles
+// read as "no entry".
 template <typename OffT>
 __global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, long long n) {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
@@ -1686,6 +1971,7 @@ __global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, long long
             const int x = col[rb + j];
             if (x >= 0) col[rb + (w++)] = x;
         }
+        for (int j = w; j < d; ++j) col[rb + j] = -1;
         deg[v] = w;
     }
 }

@@ -171,14 +171,33 @@ struct HostGraph {
     std::vector<int32_t> col;   // internal rows
     std::vector<int32_t> lab;   // internal community per internal vertex
     std::vector<int32_t> new2old, old2new, comm2orig;
-    std::vector<int32_t> sched;
-    int64_t bin_lo[kBins + 1];
+    std::vector<int2> rtiles, stiles;
+    std::vector<int32_t> rhubs, shubs;
 };
 
-static int degree_bin(int64_t d) {
-    for (int b = 0; b < kBins - 1; ++b)
-        if (d <= kBinMaxDeg[b]) return b;
-    return kBins - 1;
+// Greedy cut of the vertex sequence into tiles of consecutive vertices: a
+// tile closes when the next vertex would push its weight past wcap or its
+// vertex count past vcap.  A vertex heavier than wcap is a hub.
+static void cut_tiles(int64_t n, const std::vector<int64_t> &weight, int64_t wcap, int64_t vcap,
+                      std::vector<int2> &tiles, std::vector<int32_t> &hubs) {
+    int64_t lo = 0, w = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t x = weight[v];
+        if (x > wcap) {
+            if (v > lo) tiles.push_back(make_int2((int)lo, (int)v));
+            hubs.push_back((int32_t)v);
+            lo = v + 1;
+            w = 0;
+            continue;
+        }
+        if (w + x > wcap || v - lo == vcap) {
+            tiles.push_back(make_int2((int)lo, (int)v));
+            lo = v;
+            w = 0;
+        }
+        w += x;
+    }
+    if (n > lo) tiles.push_back(make_int2((int)lo, (int)n));
 }
 
 template <class OffIn>
@@ -228,15 +247,20 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
                 std::sort(dst, dst + (e - b));
             }
         });
-        // degree bins, ascending internal id inside a bin
-        int64_t cnt[kBins] = {};
-        for (int64_t nv = 0; nv < n; ++nv) ++cnt[degree_bin(H.off[nv + 1] - H.off[nv])];
-        H.bin_lo[0] = 0;
-        for (int b = 0; b < kBins; ++b) H.bin_lo[b + 1] = H.bin_lo[b] + cnt[b];
-        H.sched.resize(n);
-        int64_t fill[kBins];
-        for (int b = 0; b < kBins; ++b) fill[b] = H.bin_lo[b];
-        for (int64_t nv = 0; nv < n; ++nv) H.sched[fill[degree_bin(H.off[nv + 1] - H.off[nv])]++] = (int32_t)nv;
+        // tiles: row tiles bound the row capacity, score tiles the foreign
+        // entries (own-community neighbours form the id range of the community)
+        std::vector<int64_t> cap(n), fgn(n);
+        parallel_for(n, 4096, [&](int64_t lo, int64_t hi) {
+            for (int64_t nv = lo; nv < hi; ++nv) {
+                const int32_t *b = H.col.data() + H.off[nv], *e = H.col.data() + H.off[nv + 1];
+                const int32_t c = H.lab[nv];
+                const int64_t own = std::lower_bound(b, e, (int32_t)start[c + 1]) - std::lower_bound(b, e, (int32_t)start[c]);
+                cap[nv] = e - b;
+                fgn[nv] = (e - b) - own;
+            }
+        });
+        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtiles, H.rhubs);
+        cut_tiles(n, fgn, kScoreTileP, kScoreTileV, H.stiles, H.shubs);
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -251,8 +275,14 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     D.off64 = nnz > (int64_t)INT32_MAX;
     const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
     const size_t offb = D.off64 ? 8 : 4;
-    const int64_t n_hub = H.bin_lo[kBins] - H.bin_lo[kBins - 1];
-    g->hub_grid = (int)std::min<int64_t>(n_hub, 2048);
+    g->n_rtiles = (int)H.rtiles.size();
+    g->n_rhubs = (int)H.rhubs.size();
+    g->n_stiles = (int)H.stiles.size();
+    g->n_shubs = (int)H.shubs.size();
+    g->grid_rows = tile_grid(g->n_rhubs, g->n_rtiles);
+    g->grid_score = tile_grid(g->n_shubs, g->n_stiles);
+    const size_t nrt = std::max<size_t>(H.rtiles.size(), 1), nrh = std::max<size_t>(H.rhubs.size(), 1);
+    const size_t nst = std::max<size_t>(H.stiles.size(), 1), nsh = std::max<size_t>(H.shubs.size(), 1);
     struct Req {
         void **p;
         size_t bytes;
@@ -263,16 +293,20 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.lab, 4 * N},
         {(void **)&D.new2old, 4 * N},
         {(void **)&D.alive, N},
-        {(void **)&D.sched, 4 * N},
-        {(void **)&D.rec, sizeof(Rec) * Z},
+        {(void **)&D.rtiles, sizeof(int2) * nrt},
+        {(void **)&D.rhubs, 4 * nrh},
+        {(void **)&D.stiles, sizeof(int2) * nst},
+        {(void **)&D.shubs, 4 * nsh},
+        {(void **)&D.reckey, 4 * Z},
+        {(void **)&D.recdat, sizeof(RecDat) * Z},
         {(void **)&D.meta, sizeof(VMeta) * N},
         {(void **)&D.wown, 8 * N},
         {(void **)&D.a, 8 * N},
         {(void **)&D.R, 8 * N},
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
-        {(void **)&D.part_rows, sizeof(RowPart) * (kGridRows + kGridMid + (size_t)g->hub_grid)},
-        {(void **)&D.part_score, sizeof(ScorePart) * (kGridScore + kGridBig)},
+        {(void **)&D.part_rows, sizeof(RowPart) * std::max(g->grid_rows, 1)},
+        {(void **)&D.part_score, sizeof(ScorePart) * std::max(g->grid_score, 1)},
         {(void **)&D.ctr, sizeof(DevCounters)},
         {(void **)&D.thist, 4 * (size_t)kTopkBins},
         {(void **)&D.tstate, sizeof(TopkState)},
@@ -302,13 +336,20 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (e == hipSuccess && nnz) e = hipMemcpyAsync(D.col, H.col.data(), 4 * nnz, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && n) e = hipMemcpyAsync(D.lab, H.lab.data(), 4 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && n) e = hipMemcpyAsync(D.new2old, H.new2old.data(), 4 * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && n) e = hipMemcpyAsync(D.sched, H.sched.data(), 4 * n, hipMemcpyHostToDevice, s);
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    put(D.rtiles, H.rtiles.data(), sizeof(int2) * H.rtiles.size());
+    put(D.rhubs, H.rhubs.data(), 4 * H.rhubs.size());
+    put(D.stiles, H.stiles.data(), sizeof(int2) * H.stiles.size());
+    put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.tstate, 0, sizeof(TopkState), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * std::max(g->grid_score, 1), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
-    for (int b = 0; b <= kBins; ++b) g->bin_lo[b] = H.bin_lo[b];
     g->h_new2old.swap(H.new2old);
     g->h_old2new.swap(H.old2new);
     g->h_comm2orig.swap(H.comm2orig);
@@ -444,14 +485,8 @@ rs_status rs_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t 
     if (k > 0 && (!ids || !scores)) return fail(RS_ERR_ARG, "ids or scores is NULL");
     if (!g->scored) return fail(RS_ERR_STATE, "rs_topk before rs_score");
     int64_t cnt = 0;
-    rs_status st = launch_topk(g, k, &cnt);
+    rs_status st = launch_topk(g, k, ids, scores, &cnt);
     if (st != RS_OK) return st;
-    if (cnt > 0) {
-        hipError_t e = hipMemcpyAsync(ids, g->d.tout_ids, 4 * cnt, hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(scores, g->d.tout_sc, 8 * cnt, hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-        if (e != hipSuccess) return hip_fail(e, "top-k copy");
-    }
     *count = cnt;
     return RS_OK;
 }
@@ -613,8 +648,10 @@ rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *co
     row_off[0] = 0;
     for (int64_t v = 0; v < n; ++v) row_off[v + 1] = row_off[v] + meta[g->h_old2new[v]].ell;
     if (!comm && !count && !weight) return RS_OK;
-    std::vector<Rec> rec;
-    e = d2h(rec, g->d.rec, g->d.nnz);
+    std::vector<int32_t> key;
+    std::vector<RecDat> dat;
+    e = d2h(key, g->d.reckey, g->d.nnz);
+    if (e == hipSuccess) e = d2h(dat, g->d.recdat, g->d.nnz);
     if (e != hipSuccess) return hip_fail(e, "row copy");
     for (int64_t v = 0; v < n; ++v) {
         const int32_t x = g->h_old2new[v];
@@ -622,10 +659,9 @@ rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *co
         const VMeta &m = meta[x];
         for (int32_t r = 0; r < m.ell; ++r) {
             const int64_t o = row_off[v] + r;
-            const Rec &rc = rec[rb + r];
-            if (comm) comm[o] = g->h_comm2orig[rc.key];
-            if (count) count[o] = ((r + 1 < m.ell) ? rec[rb + r + 1].pos : m.deg) - rc.pos;
-            if (weight) weight[o] = rc.w;
+            if (comm) comm[o] = g->h_comm2orig[key[rb + r]];
+            if (count) count[o] = dat[rb + r].f;
+            if (weight) weight[o] = dat[rb + r].w;
         }
     }
     return RS_OK;
@@ -666,8 +702,7 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
 }
 
 static const char *kKernelNames[K_COUNT] = {
-    "k_rows_hub", "k_rows_mid", "k_rows", "k_wmax", "k_score_small", "k_score_big", "k_topk_hist",
-    "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order"};
+    "k_rows", "k_wmax", "k_score_hub", "k_score", "k_topk_hist", "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order"};
 
 const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
 

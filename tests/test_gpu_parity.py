@@ -102,6 +102,22 @@ def test_hub_runs_cross_stream_groups(rs):
     _check(g, 40, "hub runs")
 
 
+def test_score_hub_beyond_lds_staging(rs):
+    """Two hubs whose foreign lists (> 8,192 entries) and record keys (> 4,096
+    communities) exceed what a score-hub workgroup stages in LDS, so their
+    pairs read u's side from HBM; the hubs are adjacent (hub-hub pairs)."""
+    rng = np.random.default_rng(8)
+    n = 15000
+    labels = rng.integers(0, 7000, n)
+    base = random_small(n, 0.0002, 5, 88)
+    u, v = base.edges()
+    hubs = [(0, int(x)) for x in rng.choice(np.arange(1, n), 12000, replace=False)]
+    hubs += [(1, int(x)) for x in rng.choice(np.arange(2, n), 9500, replace=False)]
+    hubs += [(0, 1)]
+    g = from_edges(n, np.concatenate([np.stack([u, v], 1), np.array(hubs)]), labels)
+    _check(g, 60, "score hubs beyond LDS")
+
+
 def test_lfr_small(rs):
     g = lfr(30000, 20.0, 800, 0.2, seed=3, cmin=20, cmax=2000)
     _check(g, 100, "lfr n=30000")
