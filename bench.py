@@ -65,6 +65,38 @@ def kernel_bytes(c, n, nnz, s_off, k_top):
     return {"k_rows": rows, "k_score": score, "topk": topk, "pass": rows + score + topk}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_01485_amd", "csrc", "rs_kernels.hip")
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the same counter
+    reads for a plain device copy of known size), or None when there is none
+    or the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("<!-- traffic "):
+                rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+    if not rec or rec.get("source_sha") != kernel_source_sha():
+        return None
+    k = rec["kernels"].get(kernel)
+    if not k:
+        return None
+    fetch = k["fetch_kib"] * 1024.0 * rec["copy_bytes"] / (rec["copy_fetch_kib"] * 1024.0)
+    write = k["write_kib"] * 1024.0 * rec["copy_bytes"] / (rec["copy_write_kib"] * 1024.0)
+    return fetch + write
+
+
 def copy_calibration():
     import torch
     nbytes = 1 << 30
@@ -192,7 +224,7 @@ def main():
         "load_s": load_s,
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom),
             "bytes_per_launch": kb[dom], "avg_us": avg_us[dom],
         },
         "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]},

@@ -40,8 +40,8 @@ constexpr int kRowTile = 2048;       // row capacity (entries) covered by one ro
 constexpr int kRowTileV = 512;       // vertices of one row tile
 constexpr int kScoreTileP = 256;     // foreign entries (load-time bound) of one score tile (one per thread)
 constexpr int kScoreTileV = 256;     // vertices of one score tile (one per thread)
-constexpr int kHubKeys = 4096;       // score hubs with at most this many records keep their keys in LDS
-constexpr int kHubList = 8192;       // ... and with at most this many foreign entries their foreign list
+constexpr int kHubKeys = 1024;       // score hubs with at most this many records keep their keys in LDS
+constexpr int kHubList = 2048;       // ... and with at most this many foreign entries their foreign list
 constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
 constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise compare
@@ -75,12 +75,23 @@ struct __align__(16) VMeta {
     int deg, ell, p, q;
 };
 
+// A row tile: vertices [v0, v1) whose rows occupy entries [e0, e0 + te).
+struct __align__(16) RowTile {
+    long long e0;
+    int v0, v1, te, pad;
+};
+
 // Per-block partial results of the row kernels (no atomics).
 struct RowPart {
     unsigned long long wmax_bits, n_border, sum_dprime, sum_ell, sum_ell_x, pad[3];
 };
 struct ScorePart {
     unsigned long long tI, tII, workI, pad;
+};
+// Partial sum of one chunk of a score hub's pairs.
+struct HubPart {
+    double raw;
+    long long tI, tII, pad;
 };
 
 // Totals of a pass, reduced from the partials.
@@ -129,10 +140,14 @@ struct DeviceGraph {
     int32_t *lab = nullptr;     // [n] internal community id
     int32_t *new2old = nullptr; // [n]
     uint8_t *alive = nullptr;   // [n]
-    int2 *rtiles = nullptr;     // row tiles: vertex ranges [x, y)
+    RowTile *rtiles = nullptr;  // row tiles
     int32_t *rhubs = nullptr;   // vertices whose row capacity exceeds kRowTile
     int2 *stiles = nullptr;     // score tiles
     int32_t *shubs = nullptr;   // vertices with more than kScoreTileP foreign entries
+    int32_t *shub_first = nullptr;  // [hubs + 1] first chunk of each score hub
+    int2 *shub_chunk = nullptr;     // [chunks] (hub, chunk index within the hub)
+    HubPart *hub_part = nullptr;    // [chunks] chunk partials
+    unsigned int *hub_cnt = nullptr;  // [hubs] chunks finished in the current pass
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
     VMeta *meta = nullptr;      // [n]
@@ -167,7 +182,8 @@ struct rs_graph {
     bool own_stream = false;
     bool scored = false;
     int64_t n_alive = 0;
-    int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0;
+    int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0, n_schunks = 0;
+    int n_schunks_lds = 0;               // chunks of hubs whose foreign list fits in LDS (listed first)
     int grid_rows = 0, grid_score = 0;   // hubs first, then the tiles in XCD-major order
     std::vector<int32_t> h_new2old, h_old2new, h_comm2orig;
     rs::DeviceGraph d;

@@ -52,13 +52,41 @@ __device__ __forceinline__ double weight_absent(int d, double X, int ell) {
 
 __device__ __forceinline__ double flogf(int f) { return f > 1 ? (double)f * log2((double)f) : 0.0; }
 
+// The same terms with small arguments (<= kTab) read from LDS tables of
+// log2 y, y log2 y and 1/y (most run lengths and degrees are small).
+constexpr int kTab = 64;
+struct Tables {
+    double lg[kTab + 1], fl[kTab + 1], rc[kTab + 1];
+};
+__device__ __forceinline__ void fill_tables(Tables &t) {
+    for (int i = threadIdx.x; i <= kTab; i += blockDim.x) {
+        const double x = (double)i;
+        t.lg[i] = i > 0 ? log2(x) : 0.0;
+        t.fl[i] = flogf(i);
+        t.rc[i] = i > 0 ? 1.0 / x : 0.0;
+    }
+}
+__device__ __forceinline__ double flogf_t(const Tables &t, int f) { return f <= kTab ? t.fl[f] : flogf(f); }
+__device__ __forceinline__ double weight_present_t(const Tables &t, int d, double X, int ell, int f) {
+    const int L = ell - 1;
+    if (L < 2) return 0.0;
+    const int Y = d - f;
+    if (Y <= kTab) return (t.lg[Y] + (flogf_t(t, f) - X) * t.rc[Y]) * (double)L;
+    return weight_present(d, X, ell, f);
+}
+__device__ __forceinline__ double weight_absent_t(const Tables &t, int d, double X, int ell) {
+    if (ell < 2) return 0.0;
+    if (d <= kTab) return (t.lg[d] - X * t.rc[d]) * (double)ell;
+    return weight_absent(d, X, ell);
+}
+
 
 // ============================================================ row pass
 template <typename OffT>
 struct RowArgs {
     const OffT *off;
     const int32_t *deg, *col, *lab;
-    const int2 *tiles;
+    const RowTile *tiles;
     const int32_t *hubs;
     int n_tiles, n_hubs, tiles_per_xcd;
     int32_t *reckey;
@@ -159,7 +187,7 @@ __device__ __forceinline__ int tile_of_block(int b, int n_hubs, int per_xcd) {
 constexpr int kRowW = kBlock / 64;      // wavefronts per workgroup
 constexpr int kRowU = kRowTile / kBlock; // entries per thread
 constexpr int kRowM = kRowTile / 64;     // ballot words per tile
-static_assert(kRowTile % kBlock == 0 && kRowTile <= 65535, "row tile size");
+static_assert(kRowTile % kBlock == 0 && kRowTile <= 65535 && kRowTileV % kBlock == 0, "row tile size");
 
 // Streaming state of a hub row (one workgroup).
 struct HubSeg {
@@ -172,6 +200,7 @@ struct HubSeg {
 
 struct RowTileShared {
     HubSeg hub;
+    Tables tab;
     unsigned int bm[kRowTile / 32];      // row-start bits
     unsigned long long mask[kRowM];      // run-start bits
     int mbase[kRowM];                    // run starts before each mask word
@@ -190,25 +219,41 @@ __device__ __forceinline__ int run_index(const RowTileShared &S, int e) {
 
 template <typename OffT>
 __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc &acc) {
+    constexpr int kVU = kRowTileV / kBlock;  // vertices per thread
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int2 tl = A.tiles[t];
-    const int v0 = tl.x, nv = tl.y - tl.x;
-    const OffT e0 = A.off[v0];
-    const int TE = (int)(A.off[tl.y] - e0);
+    const RowTile tl = A.tiles[t];
+    const int v0 = tl.v0, nv = tl.v1 - tl.v0;
+    const OffT e0 = (OffT)tl.e0;
+    const int TE = tl.te;
     for (int x = tid; x < kRowTile / 32; x += kBlock) S.bm[x] = 0u;
+    fill_tables(S.tab);
+    // the tile's entries and the facts of this thread's vertices, all
+    // independent loads issued together
     int L[kRowU];
 #pragma unroll
     for (int i = 0; i < kRowU; ++i) {
         const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
         L[i] = e < TE ? A.col[e0 + e] : -2;
     }
-    __syncthreads();
-    for (int i = tid; i < nv; i += kBlock) {
-        const int o = (int)(A.off[v0 + i] - e0), c = (int)(A.off[v0 + i + 1] - A.off[v0 + i]);
-        if (c > 0) atomicOr(&S.bm[o >> 5], 1u << (o & 31));
+    int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU];
+#pragma unroll
+    for (int j = 0; j < kVU; ++j) {
+        const int i = tid + j * kBlock;
+        vo[j] = vc[j] = vdeg[j] = vlab[j] = 0;
+        if (i < nv) {
+            const OffT a0 = A.off[v0 + i], a1 = A.off[v0 + i + 1];
+            vo[j] = (int)(a0 - e0);
+            vc[j] = (int)(a1 - a0);
+            vdeg[j] = A.deg[v0 + i];
+            vlab[j] = A.lab[v0 + i];
+        }
     }
 #pragma unroll
     for (int i = 0; i < kRowU; ++i) L[i] = L[i] >= 0 ? A.lab[L[i]] : L[i];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kVU; ++j)
+        if (vc[j] > 0) atomicOr(&S.bm[vo[j] >> 5], 1u << (vo[j] & 31));
     if (lane == 63) S.wlast[wave] = L[kRowU - 1];
     __syncthreads();
     unsigned long long m[kRowU];
@@ -249,12 +294,11 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
     }
     if (tid == 0) S.runpos[total] = (unsigned short)TE;
     __syncthreads();
-    for (int i = tid; i < nv; i += kBlock) {
-        const int v = v0 + i;
-        const int o = (int)(A.off[v] - e0);
-        const int c = (int)(A.off[v + 1] - A.off[v]);
-        const int d = A.deg[v];
-        const int cv = A.lab[v];
+#pragma unroll
+    for (int j = 0; j < kVU; ++j) {
+        const int i = tid + j * kBlock;
+        if (i >= nv) continue;
+        const int o = vo[j], c = vc[j], d = vdeg[j], cv = vlab[j];
         int rf = 0, re = 0;
         if (c > 0) {
             rf = run_index(S, o);
@@ -266,7 +310,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
             const int lb = S.runlab[r];
             if (lb < 0) break;
             const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
-            X += flogf(f);
+            X += flogf_t(S.tab, f);
             ++ell;
             S.runv[r] = (unsigned short)i;
             if (lb == cv)
@@ -283,9 +327,9 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         res.ell = ell;
         res.p = below;
         res.q = below + fown;
-        res.wown = fown > 0 ? weight_present(d, X, ell, fown) : weight_absent(d, X, ell);
+        res.wown = fown > 0 ? weight_present_t(S.tab, d, X, ell, fown) : weight_absent_t(S.tab, d, X, ell);
         res.lmax = res.wown;
-        finish_row(A, v, d, res, acc);
+        finish_row(A, v0 + i, d, res, acc);
     }
     __syncthreads();
     for (int r = tid; r < total; r += kBlock) {
@@ -293,7 +337,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         if (lb < 0) continue;
         const int i = S.runv[r];
         const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
-        const double w = weight_present(S.vd[i], S.vX[i], S.vell[i], f);
+        const double w = weight_present_t(S.tab, S.vd[i], S.vX[i], S.vell[i], f);
         const int o = S.vo[i];
         const OffT idx = e0 + (OffT)(o + (r - (int)S.vrf[i]));
         A.reckey[idx] = lb;
@@ -545,6 +589,11 @@ struct ScoreArgs {
     const int2 *tiles;
     const int32_t *hubs;
     int n_tiles, n_hubs, tiles_per_xcd;
+    const int32_t *hub_first;
+    const int2 *hub_chunk;
+    int n_chunks, n_chunks_lds;
+    HubPart *hub_part;
+    unsigned int *hub_cnt;
     const int32_t *reckey;
     const RecDat *recdat;
     const VMeta *meta;
@@ -973,232 +1022,341 @@ __device__ __forceinline__ int block_excl_scan(int x, int *ws, int &total) {
     return base + incl - x;
 }
 
-// ------------------------------------------------------------ score tiles
-// A score tile is a run of <= kScoreTileV consecutive vertices with at most
-// kScoreTileP foreign entries: one thread per vertex gathers the vertex
-// facts, the pairs (u, w) are laid out flat in LDS (one lane per pair), and
-// one thread per vertex sums its pairs' terms in pair order.
-static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score tile size: one vertex and one pair per thread");
+// Store a hub chunk's partial; the chunk finishing last adds the partials
+// of the hub in chunk order and writes its score (one thread).
+template <typename OffT>
+__device__ void hub_finish(const ScoreArgs<OffT> &A, const double *red, const long long (*ired)[kBlock / 64], int hub,
+                           int chunk, int u, int deg, int dp, double wmax, ScoreAcc &sa) {
+    const int first = A.hub_first[hub], nch = A.hub_first[hub + 1] - first;
+    HubPart hp;
+    hp.raw = 0.0;
+    hp.tI = hp.tII = 0;
+    hp.pad = 0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+        hp.raw += red[i];
+        hp.tI += ired[0][i];
+        hp.tII += ired[1][i];
+    }
+    A.hub_part[first + chunk] = hp;
+    __threadfence();
+    if (atomicAdd(&A.hub_cnt[hub], 1u) == (unsigned int)(nch - 1)) {
+        __threadfence();
+        double acc = 0.0;
+        long long c1 = 0, c2 = 0;
+        for (int c = 0; c < nch; ++c) {
+            const HubPart q = A.hub_part[first + c];
+            acc += q.raw;
+            c1 += q.tI;
+            c2 += q.tII;
+        }
+        A.hub_cnt[hub] = 0u;
+        if (dp > 0) score_store(A, u, deg, acc, c1, c2, wmax, sa);
+    }
+}
 
-struct ScoreTileShared {
-    int pb[kScoreTileV + 1];
+// ------------------------------------------------------------ score units
+// A score unit is either a tile -- <= kScoreTileV consecutive vertices with
+// at most kScoreTileP foreign entries -- or one chunk of kScoreTileP pairs of
+// a score hub whose foreign list fits in LDS.  Either way the foreign
+// neighbours w of the unit's vertices are laid out in LDS with their
+// communities (a vertex's entries ascending, hence grouped by community),
+// one lane takes one pair (u, w), pairs whose list intersection is long are
+// handed to a whole wavefront, and the pair terms are summed in a fixed
+// order: per vertex in pair order for a tile, in a tree over the chunk for
+// a hub (the chunk that finishes last adds the chunk partials in order).
+static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: one vertex and one pair per thread");
+
+struct ScoreUnitShared {
+    int w[kHubList], cw[kHubList];   // foreign neighbours and their communities
+    int pb[kScoreTileV + 1];         // tile: first pair of each vertex
     long long ou[kScoreTileV];
     int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV], nc[kScoreTileV];
-    unsigned short pu[kScoreTileP];
-    int w[kScoreTileP], cw[kScoreTileP];
-    double val[kScoreTileP];
-    int t2[kScoreTileP], t1[kScoreTileP];
-    double hW[kScoreTileP];         // deferred pairs: w_w(C(u)) ...
-    unsigned short hq[kScoreTileP]; // ... and the pair
+    unsigned short pu[kScoreTileP];  // tile: vertex of each pair
+    double val[kBlock];              // the lane's pair terms
+    int t2[kBlock], t1[kBlock];
+    double hW[kBlock];               // deferred pairs: w_w(C(u)) ...
+    unsigned char hq[kBlock];        // ... and the lane
     int nhq;
     int ws[kBlock / 64];
+    double red[kBlock / 64];
+    long long ired[2][kBlock / 64];
 };
 
 template <typename OffT>
-__device__ void score_tile(const ScoreArgs<OffT> &A, ScoreTileShared &S, int t, double wmax, ScoreAcc &sa) {
-    const int tid = threadIdx.x;
-    const int2 tl = A.tiles[t];
-    const int v0 = tl.x, nv = tl.y - tl.x;
-    int dp = 0, deg = 0;
-    if (tid < nv) {
-        const int v = v0 + tid;
-        const VMeta m = A.meta[v];
-        deg = m.deg;
-        dp = m.deg - (m.q - m.p);
-        S.ou[tid] = (long long)A.off[v];
-        S.cu[tid] = A.lab[v];
-        S.p[tid] = m.p;
-        S.h[tid] = m.q - m.p;
-        S.nc[tid] = m.ell - (m.q > m.p ? 1 : 0);
+__device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hub_unit, int idx, double wmax,
+                           ScoreAcc &sa) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // ---- prologue: lay out the unit's pairs
+    int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;  // tile
+    int hub = 0, chunk = 0, hu = 0, hdeg = 0, hdp = 0, hnc = 0, hcu = 0;  // hub chunk
+    if (hub_unit) {
+        const int2 hc = A.hub_chunk[idx];
+        hub = hc.x;
+        chunk = hc.y;
+        hu = A.hubs[hub];
+        const VMeta m = A.meta[hu];
+        const long long ou = (long long)A.off[hu];
+        const int h = m.q - m.p;
+        hdeg = m.deg;
+        hdp = m.deg - h;  // <= the load-time count, which fits kHubList
+        hnc = m.ell - (h > 0 ? 1 : 0);
+        hcu = A.lab[hu];
+        for (int j = tid; j < hdp; j += kBlock) {
+            const int x = A.col[ou + (j < m.p ? j : j + h)];
+            S.w[j] = x;
+            S.cw[j] = A.lab[x];
+        }
+        total = min(kBlock, max(0, hdp - chunk * kBlock));
+        if (tid == 0) S.nhq = 0;
+        __syncthreads();
+    } else {
+        const int2 tl = A.tiles[idx];
+        v0 = tl.x;
+        nv = tl.y - tl.x;
+        if (tid < nv) {
+            const int v = v0 + tid;
+            const VMeta m = A.meta[v];
+            deg = m.deg;
+            dp = m.deg - (m.q - m.p);
+            S.ou[tid] = (long long)A.off[v];
+            S.cu[tid] = A.lab[v];
+            S.p[tid] = m.p;
+            S.h[tid] = m.q - m.p;
+            S.nc[tid] = m.ell - (m.q > m.p ? 1 : 0);
+        }
+        pb = block_excl_scan(dp, S.ws, total);
+        if (tid < nv) {
+            S.pb[tid] = pb;
+            for (int k = pb; k < pb + dp; ++k) S.pu[k] = (unsigned short)tid;
+        }
+        if (tid == 0) {
+            S.pb[nv] = total;
+            S.nhq = 0;
+        }
+        __syncthreads();
+        if (tid < total) {
+            const int i = S.pu[tid];
+            const int j = tid - S.pb[i];
+            const int x = A.col[S.ou[i] + (j < S.p[i] ? j : j + S.h[i])];
+            S.w[tid] = x;
+            S.cw[tid] = A.lab[x];
+        }
+        __syncthreads();
     }
-    int total;
-    const int pb = block_excl_scan(dp, S.ws, total);
-    if (tid < nv) {
-        S.pb[tid] = pb;
-        for (int k = pb; k < pb + dp; ++k) S.pu[k] = (unsigned short)tid;
-    }
-    if (tid == 0) {
-        S.pb[nv] = total;
-        S.nhq = 0;
-    }
-    __syncthreads();
-    // one pair per thread: its foreign neighbour w and w's row facts
-    const int k = tid;
-    long long ow = 0;
-    VMeta mw;
-    mw.deg = mw.ell = mw.p = mw.q = 0;
-    int i = 0;
-    if (k < total) {
-        i = S.pu[k];
-        const int idx = k - S.pb[i];
-        const int pos = idx < S.p[i] ? idx : idx + S.h[i];
-        const int w = A.col[S.ou[i] + pos];
-        S.w[k] = w;
-        ow = (long long)A.off[w];
-        mw = A.meta[w];
-        S.cw[k] = A.lab[w];
-        sa.workI += min(S.pb[i + 1] - S.pb[i], mw.deg - (mw.q - mw.p));
-    }
-    __syncthreads();
-    if (k < total) {
-        TileU U;
-        U.w = S.w;
-        U.cw = S.cw;
+    // ---- the lane's pair
+    const bool has = tid < total;
+    int k = 0;
+    TileU U;
+    U.w = S.w;
+    U.cw = S.cw;
+    int u = 0, cu = 0;
+    if (hub_unit) {
+        k = chunk * kBlock + tid;
+        U.pb = 0;
+        U.pe = hdp;
+        U.nc = hnc;
+        u = hu;
+        cu = hcu;
+    } else {
+        k = tid;
+        const int i = has ? S.pu[tid] : 0;
         U.pb = S.pb[i];
         U.pe = S.pb[i + 1];
         U.nc = S.nc[i];
+        u = v0 + i;
+        cu = S.cu[i];
+    }
+    PairRes r = {0.0, 0, 0, 0};
+    if (has) {
+        const int w = S.w[k];
+        const long long ow = (long long)A.off[w];
+        const VMeta mw = A.meta[w];
+        sa.workI += min(U.pe - U.pb, mw.deg - (mw.q - mw.p));
         double W;
-        const PairRes r = score_pair(A, U, v0 + i, S.cu[i], S.w[k], S.cw[k], ow, mw, W);
-        S.val[k] = r.val;
-        S.t2[k] = r.t2;
-        S.t1[k] = r.t1;
+        r = score_pair(A, U, u, cu, w, S.cw[k], ow, mw, W);
         if (r.defer) {
             const int q = atomicAdd(&S.nhq, 1);
-            S.hq[q] = (unsigned short)k;
+            S.hq[q] = (unsigned char)tid;
             S.hW[q] = W;
         }
     }
+    S.val[tid] = r.val;
+    S.t2[tid] = r.t2;
+    S.t1[tid] = r.t1;
     __syncthreads();
-    // deferred list intersections: one wavefront per pair
+    // ---- deferred list intersections: one wavefront per pair
     {
-        const int wave = tid >> 6, nq = S.nhq;
+        const int nq = S.nhq;
         for (int q = wave; q < nq; q += kBlock / 64) {
-            const int k = S.hq[q];
-            const int i = S.pu[k];
-            const int w = S.w[k];
-            TileU U;
-            U.w = S.w;
-            U.cw = S.cw;
-            U.pb = S.pb[i];
-            U.pe = S.pb[i + 1];
-            U.nc = S.nc[i];
+            const int l = S.hq[q];
+            TileU V;
+            V.w = S.w;
+            V.cw = S.cw;
+            int kk, vcu;
+            if (hub_unit) {
+                kk = chunk * kBlock + l;
+                V.pb = 0;
+                V.pe = hdp;
+                V.nc = hnc;
+                vcu = hcu;
+            } else {
+                kk = l;
+                const int i = S.pu[l];
+                V.pb = S.pb[i];
+                V.pe = S.pb[i + 1];
+                V.nc = S.nc[i];
+                vcu = S.cu[i];
+            }
+            const int w = S.w[kk];
             double val;
             long long cnt;
-            list_wave(A, U, S.cu[i], (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
-            if ((tid & 63) == 0) {
-                S.val[k] += val;
-                S.t1[k] += (int)cnt;
+            list_wave(A, V, vcu, (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
+            if (lane == 0) {
+                S.val[l] += val;
+                S.t1[l] += (int)cnt;
             }
         }
     }
     __syncthreads();
-    if (tid < nv && dp > 0) {
-        double acc = 0.0;
-        long long c1 = 0, c2 = 0;
-        for (int k = pb; k < pb + dp; ++k) {
-            acc += S.val[k];
-            c2 += S.t2[k];
-            c1 += S.t1[k];
+    // ---- epilogue: sums in a fixed order
+    if (!hub_unit) {
+        if (tid < nv && dp > 0) {
+            double acc = 0.0;
+            long long c1 = 0, c2 = 0;
+            for (int q = pb; q < pb + dp; ++q) {
+                acc += S.val[q];
+                c2 += S.t2[q];
+                c1 += S.t1[q];
+            }
+            score_store(A, v0 + tid, deg, acc, c1, c2, wmax, sa);
         }
-        score_store(A, v0 + tid, deg, acc, c1, c2, wmax, sa);
+        return;
     }
+    double x = S.val[tid];
+    long long y1 = S.t1[tid], y2 = S.t2[tid];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o);
+        y1 += __shfl_xor(y1, o);
+        y2 += __shfl_xor(y2, o);
+    }
+    if (lane == 0) {
+        S.red[wave] = x;
+        S.ired[0][wave] = y1;
+        S.ired[1][wave] = y2;
+    }
+    __syncthreads();
+    if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, hu, hdeg, hdp, wmax, sa);
 }
 
 // ------------------------------------------------------------ score hubs
-// A vertex with more than kScoreTileP foreign entries gets a workgroup of its
-// own kernel; its record keys and foreign list are staged in LDS when they
-// fit, and its pairs are taken kBlock at a time and summed in a fixed tree
-// order.
-struct ScoreHubShared {
-    int keys[kHubKeys];
-    int list[kHubList];
+// A vertex with more than kScoreTileP foreign entries is a score hub: its
+// pairs are cut into chunks of kScoreTileP, one workgroup per chunk (so a
+// hub's work spreads over the chip).  A chunk sums its pairs in a fixed
+// tree order and stores a partial; the chunk that finishes last (a
+// device-scope counter per hub) adds the partials in chunk order and writes
+// the score.  A hub whose foreign list fits in LDS stages it with its
+// communities and runs in the tile kernel with the tile view of u; larger
+// hubs read u's side from HBM in a kernel of their own.
+struct HubChunkShared {
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
-    double hW[kBlock], dval[kBlock];  // deferred pairs of a chunk, by lane
+    double hW[kBlock], dval[kBlock];  // deferred pairs of the chunk, by lane
     int hw[kBlock], dcnt[kBlock];
     unsigned char hq[kBlock];
-    int nhq;
+    int nhq, last;
+};
+
+template <class UV, typename OffT>
+__device__ void hub_chunk_run(const ScoreArgs<OffT> &A, const UV &U, HubChunkShared &C, int hub, int chunk, int u,
+                              int cu, int deg, int dp, double wmax, ScoreAcc &sa) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k = chunk * kScoreTileP + tid;
+    PairRes r = {0.0, 0, 0, 0};
+    if (k < dp) {
+        const int w = U.list_at(k);
+        const long long ow = (long long)A.off[w];
+        const VMeta mw = A.meta[w];
+        const int cw = A.lab[w];
+        sa.workI += min(dp, mw.deg - (mw.q - mw.p));
+        double W;
+        r = score_pair(A, U, u, cu, w, cw, ow, mw, W);
+        if (r.defer) {
+            const int q = atomicAdd(&C.nhq, 1);
+            C.hq[q] = (unsigned char)tid;
+            C.hW[q] = W;
+            C.hw[q] = w;
+        }
+    }
+    __syncthreads();
+    {
+        const int nq = C.nhq;
+        for (int q = wave; q < nq; q += kBlock / 64) {
+            const int w = C.hw[q];
+            double val;
+            long long cnt;
+            list_wave(A, U, cu, (long long)A.off[w], A.meta[w], C.hW[q], val, cnt);
+            if (lane == 0) {
+                C.dval[C.hq[q]] = val;
+                C.dcnt[C.hq[q]] = (int)cnt;
+            }
+        }
+    }
+    __syncthreads();
+    if (r.defer) {
+        r.val += C.dval[tid];
+        r.t1 += C.dcnt[tid];
+    }
+    double x = r.val;
+    long long y1 = r.t1, y2 = r.t2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o);
+        y1 += __shfl_xor(y1, o);
+        y2 += __shfl_xor(y2, o);
+    }
+    if (lane == 0) {
+        C.red[wave] = x;
+        C.ired[0][wave] = y1;
+        C.ired[1][wave] = y2;
+    }
+    __syncthreads();
+    if (tid == 0) hub_finish(A, C.red, C.ired, hub, chunk, u, deg, dp, wmax, sa);
+}
+
+constexpr int kBigKeys = 4096;  // record keys staged in LDS for the HBM-side hubs
+struct ScoreHubBigShared {
+    int keys[kBigKeys];
+    HubChunkShared c;
 };
 
 template <typename OffT>
-__device__ void score_hub(const ScoreArgs<OffT> &A, ScoreHubShared &S, int u, double wmax, ScoreAcc &sa) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, int hub, int chunk, double wmax,
+                              ScoreAcc &sa) {
+    const int tid = threadIdx.x;
+    const int u = A.hubs[hub];
     const VMeta m = A.meta[u];
     const long long ou = (long long)A.off[u];
-    const int cu = A.lab[u];
     const int h = m.q - m.p;
     const int dp = m.deg - h;
-    const bool lk = m.ell <= kHubKeys, ll = dp <= kHubList;
+    const bool lk = m.ell <= kBigKeys;
     if (lk)
         for (int j = tid; j < m.ell; j += kBlock) S.keys[j] = A.reckey[ou + j];
-    if (ll)
-        for (int j = tid; j < dp; j += kBlock) S.list[j] = A.col[ou + (j < m.p ? j : j + h)];
+    if (tid == 0) S.c.nhq = 0;
     __syncthreads();
     HubU U;
     U.row = A.col + ou;
     U.gkeys = A.reckey + ou;
     U.gdat = A.recdat + ou;
     U.skeys = lk ? S.keys : nullptr;
-    U.slist = ll ? S.list : nullptr;
+    U.slist = nullptr;
     U.ell = m.ell;
-    U.cu = cu;
+    U.cu = A.lab[u];
     U.nc = m.ell - (h > 0 ? 1 : 0);
     U.p = m.p;
     U.h = h;
     U.n_f = dp;
-    double acc = 0.0;
-    long long c1 = 0, c2 = 0;
-    for (int k0 = 0; k0 < dp; k0 += kBlock) {
-        const int k = k0 + tid;
-        if (tid == 0) S.nhq = 0;
-        __syncthreads();
-        PairRes r = {0.0, 0, 0, 0};
-        if (k < dp) {
-            const int w = ll ? S.list[k] : A.col[ou + (k < m.p ? k : k + h)];
-            const long long ow = (long long)A.off[w];
-            const VMeta mw = A.meta[w];
-            const int cw = A.lab[w];
-            sa.workI += min(dp, mw.deg - (mw.q - mw.p));
-            double W;
-            r = score_pair(A, U, u, cu, w, cw, ow, mw, W);
-            if (r.defer) {
-                const int q = atomicAdd(&S.nhq, 1);
-                S.hq[q] = (unsigned char)tid;
-                S.hW[q] = W;
-                S.hw[q] = w;
-            }
-        }
-        __syncthreads();
-        {
-            const int nq = S.nhq;
-            for (int q = wave; q < nq; q += kBlock / 64) {
-                const int w = S.hw[q];
-                double val;
-                long long cnt;
-                list_wave(A, U, cu, (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
-                if (lane == 0) {
-                    S.dval[S.hq[q]] = val;
-                    S.dcnt[S.hq[q]] = (int)cnt;
-                }
-            }
-        }
-        __syncthreads();
-        if (r.defer) {
-            r.val += S.dval[tid];
-            r.t1 += S.dcnt[tid];
-        }
-        double x = r.val;
-        long long y1 = r.t1, y2 = r.t2;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            x += __shfl_xor(x, o);
-            y1 += __shfl_xor(y1, o);
-            y2 += __shfl_xor(y2, o);
-        }
-        if (lane == 0) {
-            S.red[wave] = x;
-            S.ired[0][wave] = y1;
-            S.ired[1][wave] = y2;
-        }
-        __syncthreads();
-        for (int i = 0; i < kBlock / 64; ++i) {
-            acc += S.red[i];
-            c1 += S.ired[0][i];
-            c2 += S.ired[1][i];
-        }
-        __syncthreads();
-    }
-    if (tid == 0 && dp > 0) score_store(A, u, m.deg, acc, c1, c2, wmax, sa);
+    hub_chunk_run(A, U, S.c, hub, chunk, u, U.cu, m.deg, dp, wmax, sa);
 }
 
 __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
@@ -1227,27 +1385,30 @@ __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
     }
 }
 
-// Algorithm 1 Step 3 (Eq. RSI) for every border vertex of a score tile.
-// Partials go after the hub kernel's.
+// Algorithm 1 Step 3 (Eq. RSI) for every border vertex of the tiles and of
+// the LDS-sized score hubs (their chunks first, so they start early).
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
-    __shared__ ScoreTileShared S;
+    __shared__ ScoreUnitShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0, 0};
     const int b = (int)blockIdx.x;
-    const int t = tile_of_block(b, 0, A.tiles_per_xcd);
-    if (t < A.n_tiles) score_tile(A, S, t, wmax, sa);
-    block_reduce_score(sa, &A.part[A.n_hubs + b]);
+    const bool hub_unit = b < A.n_chunks_lds;
+    const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
+    if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax, sa);
+    block_reduce_score(sa, &A.part[b]);
 }
 
-// ... and for every score hub (one workgroup each).
+// ... and of the hubs too large for LDS (chunks n_chunks_lds ...); partials
+// after the tile kernel's.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
-    __shared__ ScoreHubShared S;
+__global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int part0) {
+    __shared__ ScoreHubBigShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0, 0};
-    score_hub(A, S, A.hubs[blockIdx.x], wmax, sa);
-    block_reduce_score(sa, &A.part[blockIdx.x]);
+    const int2 hc = A.hub_chunk[A.n_chunks_lds + blockIdx.x];
+    score_hub_big(A, S, hc.x, hc.y, wmax, sa);
+    block_reduce_score(sa, &A.part[part0 + blockIdx.x]);
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, int np, DevCounters *c) {
@@ -1324,6 +1485,12 @@ static rs_status score_pass_t(rs_graph *g) {
     S.n_tiles = g->n_stiles;
     S.n_hubs = g->n_shubs;
     S.tiles_per_xcd = (g->n_stiles + 7) / 8;
+    S.hub_first = D.shub_first;
+    S.hub_chunk = D.shub_chunk;
+    S.n_chunks = g->n_schunks;
+    S.n_chunks_lds = g->n_schunks_lds;
+    S.hub_part = D.hub_part;
+    S.hub_cnt = D.hub_cnt;
     S.reckey = D.reckey;
     S.recdat = D.recdat;
     S.meta = D.meta;
@@ -1333,14 +1500,16 @@ static rs_status score_pass_t(rs_graph *g) {
     S.tII = D.tII;
     S.ctr = D.ctr;
     S.part = D.part_score;
-    if (g->n_shubs > 0) {
+    const int n_big = g->n_schunks - g->n_schunks_lds;
+    const int grid_main = g->grid_score - n_big;
+    if (n_big > 0) {
         timing_begin(g, K_SCORE_HUB, &ev);
-        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(g->n_shubs), dim3(kBlock), 0, g->stream, S);
+        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(n_big), dim3(kBlock), 0, g->stream, S, grid_main);
         timing_end(g, K_SCORE_HUB, ev);
     }
-    if (g->grid_score > g->n_shubs) {
+    if (grid_main > 0) {
         timing_begin(g, K_SCORE, &ev);
-        hipLaunchKernelGGL(k_score<OffT>, dim3(g->grid_score - g->n_shubs), dim3(kBlock), 0, g->stream, S);
+        hipLaunchKernelGGL(k_score<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
         timing_end(g, K_SCORE, ev);
     }
     const hipError_t e = hipGetLastError();
@@ -1387,16 +1556,24 @@ __device__ __forceinline__ TopkKey make_key(const double *R, const int32_t *new2
 // the per-thread totals finds the bin where the count from the top reaches
 // st->take.  Records the threshold in st and clears the histogram.
 __device__ void topk_find_block(unsigned int *hist, TopkState *st, int level, long long *s_scan) {
-    constexpr int kPer = kTopkBins / kBlock;
+    constexpr int kPer = kTopkBins / kBlock;  // 256 bins per thread
+    constexpr int kGrp = 16;                  // bins per group
     const int t = threadIdx.x;
     const long long need = st->take;
     const int base = kTopkBins - kPer * (t + 1);
     const uint4 *h4 = (const uint4 *)(hist + base);
+    unsigned int gs[kPer / kGrp];
     long long mine = 0;
-#pragma unroll 8
-    for (int i = 0; i < kPer / 4; ++i) {
-        const uint4 x = h4[i];
-        mine += (long long)x.x + x.y + x.z + x.w;
+#pragma unroll
+    for (int g = 0; g < kPer / kGrp; ++g) {
+        unsigned int x = 0;
+#pragma unroll
+        for (int i = 0; i < kGrp / 4; ++i) {
+            const uint4 y = h4[g * (kGrp / 4) + i];
+            x += y.x + y.y + y.z + y.w;
+        }
+        gs[g] = x;
+        mine += x;
     }
     s_scan[t] = mine;
     __syncthreads();
@@ -1410,19 +1587,41 @@ __device__ void topk_find_block(unsigned int *hist, TopkState *st, int level, lo
     const long long excl = incl - mine;
     const long long total = s_scan[kBlock - 1];
     if (excl < need && need <= incl) {
+        // the group, from the top of this thread's range, then the bin
         long long cum = excl;
-        for (int i = kPer - 1; i >= 0; --i) {
-            const long long h = hist[base + i];
-            if (cum + h >= need) {
-                st->digit = (unsigned int)level;
-                st->thresh = (unsigned int)(base + i);
-                st->above += cum;
-                st->take = need - cum;
-                st->binsize = h;
-                st->done = (need - cum == h) ? 1u : 0u;
-                break;
+        int gsel = 0;
+        bool found = false;
+#pragma unroll
+        for (int g = kPer / kGrp - 1; g >= 0; --g) {
+            if (!found) {
+                if (cum + gs[g] >= need) {
+                    gsel = g;
+                    found = true;
+                } else {
+                    cum += gs[g];
+                }
             }
-            cum += h;
+        }
+        unsigned int hb[kGrp];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) hb[i] = hist[base + gsel * kGrp + i];
+        bool done = false;
+#pragma unroll
+        for (int i = kGrp - 1; i >= 0; --i) {
+            if (!done) {
+                const long long h = hb[i];
+                if (cum + h >= need) {
+                    st->digit = (unsigned int)level;
+                    st->thresh = (unsigned int)(base + gsel * kGrp + i);
+                    st->above += cum;
+                    st->take = need - cum;
+                    st->binsize = h;
+                    st->done = (need - cum == h) ? 1u : 0u;
+                    done = true;
+                } else {
+                    cum += h;
+                }
+            }
         }
     }
     if (t == 0 && !(need > 0 && total >= need)) {  // cannot happen for need <= live keys: take all

@@ -171,8 +171,10 @@ struct HostGraph {
     std::vector<int32_t> col;   // internal rows
     std::vector<int32_t> lab;   // internal community per internal vertex
     std::vector<int32_t> new2old, old2new, comm2orig;
-    std::vector<int2> rtiles, stiles;
-    std::vector<int32_t> rhubs, shubs;
+    std::vector<int2> rtv, stiles, schunk;
+    std::vector<RowTile> rtiles;
+    std::vector<int32_t> rhubs, shubs, sfirst;
+    int n_chunks_lds = 0;
 };
 
 // Greedy cut of the vertex sequence into tiles of consecutive vertices: a
@@ -259,8 +261,28 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
                 fgn[nv] = (e - b) - own;
             }
         });
-        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtiles, H.rhubs);
+        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs);
+        H.rtiles.resize(H.rtv.size());
+        for (size_t t = 0; t < H.rtv.size(); ++t) {
+            RowTile &rt = H.rtiles[t];
+            rt.v0 = H.rtv[t].x;
+            rt.v1 = H.rtv[t].y;
+            rt.e0 = H.off[rt.v0];
+            rt.te = (int)(H.off[rt.v1] - H.off[rt.v0]);
+            rt.pad = 0;
+        }
         cut_tiles(n, fgn, kScoreTileP, kScoreTileV, H.stiles, H.shubs);
+        // a score hub's pairs are processed kScoreTileP at a time, one chunk per workgroup
+        // hubs whose foreign list fits in LDS are listed (and chunked) first
+        std::stable_partition(H.shubs.begin(), H.shubs.end(), [&](int32_t v) { return fgn[v] <= kHubList; });
+        H.sfirst.assign(1, 0);
+        H.n_chunks_lds = 0;
+        for (size_t h = 0; h < H.shubs.size(); ++h) {
+            const int64_t nch = (fgn[H.shubs[h]] + kScoreTileP - 1) / kScoreTileP;
+            for (int64_t c = 0; c < nch; ++c) H.schunk.push_back(make_int2((int)h, (int)c));
+            H.sfirst.push_back((int32_t)H.schunk.size());
+            if (fgn[H.shubs[h]] <= kHubList) H.n_chunks_lds = (int)H.schunk.size();
+        }
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -279,8 +301,11 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     g->n_rhubs = (int)H.rhubs.size();
     g->n_stiles = (int)H.stiles.size();
     g->n_shubs = (int)H.shubs.size();
+    g->n_schunks = (int)H.schunk.size();
+    g->n_schunks_lds = H.n_chunks_lds;
     g->grid_rows = tile_grid(g->n_rhubs, g->n_rtiles);
-    g->grid_score = tile_grid(g->n_shubs, g->n_stiles);
+    g->grid_score = tile_grid(g->n_schunks, g->n_stiles);
+    const size_t nch = std::max<size_t>(H.schunk.size(), 1);
     const size_t nrt = std::max<size_t>(H.rtiles.size(), 1), nrh = std::max<size_t>(H.rhubs.size(), 1);
     const size_t nst = std::max<size_t>(H.stiles.size(), 1), nsh = std::max<size_t>(H.shubs.size(), 1);
     struct Req {
@@ -293,10 +318,14 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.lab, 4 * N},
         {(void **)&D.new2old, 4 * N},
         {(void **)&D.alive, N},
-        {(void **)&D.rtiles, sizeof(int2) * nrt},
+        {(void **)&D.rtiles, sizeof(RowTile) * nrt},
         {(void **)&D.rhubs, 4 * nrh},
         {(void **)&D.stiles, sizeof(int2) * nst},
         {(void **)&D.shubs, 4 * nsh},
+        {(void **)&D.shub_first, 4 * (nsh + 1)},
+        {(void **)&D.shub_chunk, sizeof(int2) * nch},
+        {(void **)&D.hub_part, sizeof(HubPart) * nch},
+        {(void **)&D.hub_cnt, 4 * nsh},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
         {(void **)&D.meta, sizeof(VMeta) * N},
@@ -339,10 +368,13 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     auto put = [&](void *dst, const void *src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     };
-    put(D.rtiles, H.rtiles.data(), sizeof(int2) * H.rtiles.size());
+    put(D.rtiles, H.rtiles.data(), sizeof(RowTile) * H.rtiles.size());
     put(D.rhubs, H.rhubs.data(), 4 * H.rhubs.size());
     put(D.stiles, H.stiles.data(), sizeof(int2) * H.stiles.size());
     put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
+    put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
+    put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
+    if (e == hipSuccess) e = hipMemsetAsync(D.hub_cnt, 0, 4 * nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
