@@ -18,6 +18,11 @@
 //   * meta[v] = {deg, ell, p, q} of the last pass.  G' (the edges between
 //     communities) is implicit: v's foreign neighbours are the row positions
 //     outside [p, q), in ascending id order.
+//   * Out-lists orient G': vertices are ranked by (load-time foreign degree,
+//     id), and out(v) lists v's foreign neighbours of higher rank.  Every
+//     triangle of G' is {u, x, y} with y in out(x) for exactly one ordering of
+//     its other two vertices, and the lists are short (a hub's foreign
+//     neighbours are mostly of lower rank).  Removals tombstone entries (~id).
 //   * Work is cut at load time into static tiles of consecutive vertices: row
 //     tiles bound the row capacity they cover, score tiles the number of
 //     foreign entries (removals only shrink both).  Vertices too large for a
@@ -41,7 +46,7 @@ constexpr int kRowTileV = 512;       // vertices of one row tile
 constexpr int kScoreTileP = 256;     // foreign entries (load-time bound) of one score tile (one per thread)
 constexpr int kScoreTileV = 256;     // vertices of one score tile (one per thread)
 constexpr int kHubKeys = 1024;       // score hubs with at most this many records keep their keys in LDS
-constexpr int kHubList = 2048;       // ... and with at most this many foreign entries their foreign list
+constexpr int kHubList = 1024;       // score hubs with at most this many foreign entries stage them in LDS
 constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
 constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise compare
@@ -148,6 +153,8 @@ struct DeviceGraph {
     int2 *shub_chunk = nullptr;     // [chunks] (hub, chunk index within the hub)
     HubPart *hub_part = nullptr;    // [chunks] chunk partials
     unsigned int *hub_cnt = nullptr;  // [hubs] chunks finished in the current pass
+    int64_t *oo = nullptr;      // [n+1] out-list offsets
+    int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
     VMeta *meta = nullptr;      // [n]

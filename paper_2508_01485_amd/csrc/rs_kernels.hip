@@ -594,6 +594,8 @@ struct ScoreArgs {
     int n_chunks, n_chunks_lds;
     HubPart *hub_part;
     unsigned int *hub_cnt;
+    const int64_t *oo;
+    const int32_t *outl;
     const int32_t *reckey;
     const RecDat *recdat;
     const VMeta *meta;
@@ -629,14 +631,6 @@ __device__ __forceinline__ int kfind(const int32_t *k, int n, int c) {
     return f;
 }
 
-// w_x(c) for a community c present around x.
-template <typename OffT>
-__device__ __forceinline__ double weight_of(const ScoreArgs<OffT> &A, int x, int c) {
-    const long long rb = (long long)A.off[x];
-    const int s = kfind(A.reckey + rb, A.meta[x].ell, c);
-    return s >= 0 ? A.recdat[rb + s].w : 0.0;
-}
-
 // Sorted-range helpers on LDS arrays.
 __device__ __forceinline__ int lds_lower(const int *a, int lo, int hi, int x) {
     while (lo < hi) {
@@ -648,74 +642,25 @@ __device__ __forceinline__ int lds_lower(const int *a, int lo, int hi, int x) {
     }
     return lo;
 }
-__device__ __forceinline__ int lds_upper(const int *a, int lo, int hi, int x) {
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] <= x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-__device__ __forceinline__ bool glb_member(const int32_t *a, int lo, int hi, int x) {
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int y = a[mid];
-        if (y < x)
-            lo = mid + 1;
-        else if (y > x)
-            hi = mid;
-        else
-            return true;
-    }
-    return false;
-}
-
-// The scored vertex u as seen by its pairs (u, w): its foreign neighbours,
-// grouped by community.  Tile form: the tile's pair list in LDS, where u's
-// pairs [pb, pe) hold w ascending (so communities ascending).
+// The scored vertex u as seen by its pairs (u, w): its foreign list N'(u),
+// ascending.  Tile form: u's entries [pb, pe) of the unit's LDS list.
 struct TileU {
-    const int *w, *cw;
-    int pb, pe, nc;
-    __device__ __forceinline__ bool has(int c) const {
-        const int i = lds_lower(cw, pb, pe, c);
-        return i < pe && cw[i] == c;
-    }
-    __device__ __forceinline__ void run(int c, int &b, int &e) const {
-        b = lds_lower(cw, pb, pe, c);
-        e = lds_upper(cw, b, pe, c);
-    }
-    __device__ __forceinline__ bool member(int b, int e, int x) const {
-        const int i = lds_lower(w, b, e, x);
-        return i < e && w[i] == x;
-    }
-    __device__ __forceinline__ int at(int j) const { return w[j]; }
-    // u's whole foreign list N'(u), ascending
+    const int *w;
+    int pb, pe;
     __device__ __forceinline__ int nf() const { return pe - pb; }
     __device__ __forceinline__ int list_at(int j) const { return w[pb + j]; }
     __device__ __forceinline__ bool in_list(int x) const {
         const int i = lds_lower(w, pb, pe, x);
         return i < pe && w[i] == x;
     }
-    // iteration over the distinct communities of u's foreign neighbours
-    __device__ __forceinline__ int it_begin() const { return pb; }
-    __device__ __forceinline__ bool it_ok(int it) const { return it < pe; }
-    __device__ __forceinline__ int it_comm(int it) const { return cw[it]; }
-    __device__ __forceinline__ int it_next(int it, int c) const { return lds_upper(cw, it, pe, c); }
 };
 
-// Hub form: u's own row and records in HBM; its record keys and its foreign
-// list N'(u) (the row minus [p, p + h)) in LDS when they fit.
+// Hub form: u's row in HBM (the foreign list is the row minus [p, p + h)).
 struct HubU {
-    const int32_t *row;      // u's row
-    const int32_t *gkeys;    // u's record keys
-    const RecDat *gdat;      // u's record data
-    const int *skeys;        // LDS copy of the keys, or nullptr
-    const int *slist;        // LDS copy of N'(u), or nullptr
-    int ell, cu, nc, p, h, n_f;
+    const int32_t *row;
+    int p, h, n_f;
     __device__ __forceinline__ int nf() const { return n_f; }
-    __device__ __forceinline__ int list_at(int j) const { return slist ? slist[j] : row[j < p ? j : j + h]; }
+    __device__ __forceinline__ int list_at(int j) const { return row[j < p ? j : j + h]; }
     __device__ __forceinline__ bool in_list(int x) const {
         int lo = 0, hi = n_f;
         while (lo < hi) {
@@ -730,258 +675,82 @@ struct HubU {
         }
         return false;
     }
-    __device__ __forceinline__ int slot(int c) const {
-        if (skeys) {
-            const int i = lds_lower(skeys, 0, ell, c);
-            return (i < ell && skeys[i] == c) ? i : -1;
-        }
-        return kfind(gkeys, ell, c);
-    }
-    __device__ __forceinline__ bool has(int c) const { return c != cu && slot(c) >= 0; }
-    __device__ __forceinline__ void run(int c, int &b, int &e) const {
-        const int s = slot(c);
-        b = e = 0;
-        if (s >= 0) {
-            const RecDat r = gdat[s];
-            b = r.pos;
-            e = r.pos + r.f;
-        }
-    }
-    __device__ __forceinline__ bool member(int b, int e, int x) const { return glb_member(row, b, e, x); }
-    __device__ __forceinline__ int at(int j) const { return row[j]; }
-    // iteration over u's record keys (the caller skips the own community)
-    __device__ __forceinline__ int it_begin() const { return 0; }
-    __device__ __forceinline__ bool it_ok(int it) const { return it < ell; }
-    __device__ __forceinline__ int it_comm(int it) const { return skeys ? skeys[it] : gkeys[it]; }
-    __device__ __forceinline__ int it_next(int it, int) const { return it + 1; }
 };
 
 struct PairRes {
     double val;
     int t2, t1;
-    int defer;  // the list intersection of type-I was left to a wavefront
 };
 
-
-// Type-I triads of the pair (u, w) inside one community c shared by their
-// foreign neighbourhoods: v in both runs of c.  The shorter run is walked and
-// the other probed.  Each hit adds cbrt(w_w(C(u)) w_v(C(u)) w_w(c)).
-template <class UV, typename OffT>
-__device__ __forceinline__ void typeI_in(const ScoreArgs<OffT> &A, const UV &U, int cu, int c, long long ow, int sc,
-                                         double W, PairRes &out) {
-    const RecDat rc = A.recdat[ow + sc];
-    int ub, ue;
-    U.run(c, ub, ue);
-    const int nu = ue - ub;
-    if (nu <= 0) return;
-    const int32_t *wr = A.col + ow + rc.pos;
-    const bool walk_w = rc.f <= 8 * nu;
-    const int n_it = walk_w ? rc.f : nu;
-    for (int i = 0; i < n_it; ++i) {
-        int x;
-        bool hit;
-        if (walk_w) {
-            x = wr[i];
-            hit = U.member(ub, ue, x);
-        } else {
-            x = U.at(ub + i);
-            hit = glb_member(wr, 0, rc.f, x);
-        }
-        if (hit) {
-            out.t1 += 1;
-            out.val += cbrt(W * weight_of(A, x, cu) * rc.w);
-        }
-    }
-}
-
-// Type-I triads of the pair (u, w) by intersecting the whole foreign lists
-// N'(u) and N'(w) (used when u touches many communities, so that matching
-// communities first would not prune): the shorter side is walked and each
-// entry probed in the other list by binary search -- u's list in LDS (or
-// HBM for a large hub), w's list in HBM.  A common v is foreign to both, so
-// C(v) differs from C(u) and C(w).
-struct ListPlan {
-    int nu, nw, pw, hw, lv_u, lv_w;
-    bool walk_u;  // walk u's list and search w's (else walk w's, search u's)
-    int steps;    // entries to walk
-};
-
-template <class UV>
-__device__ __forceinline__ ListPlan list_plan(const UV &U, const VMeta &mw) {
-    ListPlan L;
-    L.pw = mw.p;
-    L.hw = mw.q - mw.p;
-    L.nw = mw.deg - L.hw;
-    L.nu = U.nf();
-    L.lv_w = 32 - __clz(L.nw);
-    L.lv_u = 32 - __clz(L.nu);
-    // cost of walking u's list with a search in HBM per entry vs walking w's
-    L.walk_u = (long long)L.nu * (L.lv_w + 1) < (long long)L.nw;
-    L.steps = (L.nu > 0 && L.nw > 0) ? (L.walk_u ? L.nu : L.nw) : 0;
-    return L;
-}
-
-__device__ __forceinline__ int nprime_at(const int32_t *rw, const ListPlan &L, int j) {
-    return rw[j < L.pw ? j : j + L.hw];
-}
-
-// One hit v of the pair (u, w): cbrt(w_w(C(u)) w_v(C(u)) w_w(C(v))).
-template <typename OffT>
-__device__ __forceinline__ double typeI_term(const ScoreArgs<OffT> &A, int v, int cu, long long ow, int ellw,
-                                             double W) {
-    const int sv = kfind(A.reckey + ow, ellw, A.lab[v]);
-    const double wwv = sv >= 0 ? A.recdat[ow + sv].w : 0.0;
-    return cbrt(W * weight_of(A, v, cu) * wwv);
-}
-
-// Walk entries [j0, j0 + span) of the plan's walked list with stride `stride`
-// (8 entries per step, interleaved searches); hits are handled in order.
-template <class UV, typename OffT>
-__device__ __forceinline__ void list_walk(const ScoreArgs<OffT> &A, const UV &U, const ListPlan &L, int cu,
-                                          long long ow, int ellw, double W, int first, int stride, double &acc,
-                                          long long &cnt) {
-    const int32_t *rw = A.col + ow;
-    for (int j0 = first; j0 < L.steps; j0 += 8 * stride) {
-        unsigned int hm = 0u;
-        int y[8], lo[8], hi[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int j = j0 + t * stride;
-            const bool ok = j < L.steps;
-            y[t] = ok ? (L.walk_u ? U.list_at(j) : nprime_at(rw, L, j)) : -1;
-            lo[t] = 0;
-            hi[t] = ok ? (L.walk_u ? L.nw : L.nu) : 0;
-        }
-        const int levels = L.walk_u ? L.lv_w : L.lv_u;
-        for (int step = 0; step <= levels; ++step) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (lo[t] < hi[t]) {
-                    const int mid = (lo[t] + hi[t]) >> 1;
-                    const int x = L.walk_u ? nprime_at(rw, L, mid) : U.list_at(mid);
-                    if (x == y[t]) {
-                        hm |= 1u << t;
-                        lo[t] = hi[t];
-                    } else if (x < y[t]) {
-                        lo[t] = mid + 1;
-                    } else {
-                        hi[t] = mid;
-                    }
-                }
-            }
-        }
-        while (hm) {
-            const int t = __builtin_ctz(hm);
-            hm &= hm - 1u;
-            const int j = j0 + t * stride;
-            const int v = L.walk_u ? U.list_at(j) : nprime_at(rw, L, j);
-            acc += typeI_term(A, v, cu, ow, ellw, W);
-            cnt += 1;
-        }
-    }
-}
-
-// Lists longer than this many walk steps are left to a whole wavefront.
-constexpr int kListLane = 32;
-
-// A deferred pair, intersected by all 64 lanes of a wavefront (the walked
-// list dealt round-robin to the lanes); the lane partials are summed in a
-// fixed tree order.
-template <class UV, typename OffT>
-__device__ __forceinline__ void list_wave(const ScoreArgs<OffT> &A, const UV &U, int cu, long long ow,
-                                          const VMeta &mw, double W, double &val, long long &cnt) {
-    const ListPlan L = list_plan(U, mw);
-    double acc = 0.0;
-    long long c = 0;
-    list_walk(A, U, L, cu, ow, mw.ell, W, (int)__lane_id(), 64, acc, c);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        acc += __shfl_xor(acc, o);
-        c += __shfl_xor(c, o);
-    }
-    val = acc;
-    cnt = c;
-}
 
 // The terms of Eq. RSI that pass through the foreign neighbour w of u
 // (Lemmas 1-2, unnormalised weights):
 //   type-II: w_w(C(u))^(2/3) * sum of a_v over the other neighbours v of w in
 //            C(u) (a_v = cbrt(w_v(C(v)))), count f_w(C(u)) - 1;
-//   type-I : cbrt(w_w(C(u)) w_v(C(u)) w_w(C(v))) over the common foreign
-//            neighbours v of u and w outside C(w).  When u touches few
-//            communities the candidates are found community by community: a
-//            community c can hold such a v only if both u and w have
-//            neighbours in c, so the two record-key lists are matched first
-//            and only the runs of shared communities are intersected.
+//   type-I : the triangles {u, w, y} of G' with y in out(w) -- each triangle
+//            at u is found by exactly one of its two pairs -- each adding
+//            both ordered triads (w, y) and (y, w):
+//              cbrt(w_y(C(u)) w_w(C(y)) w_w(C(u))) + cbrt(w_w(C(u)) w_y(C(w)) w_y(C(u))).
 template <class UV, typename OffT>
 __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, int cw, long long ow,
-                              const VMeta &mw, double &Wout) {
-    PairRes out = {0.0, 0, 0, 0};
+                              const VMeta &mw, long long o0, long long o1) {
+    PairRes out = {0.0, 0, 0};
     const int ellw = mw.ell;
     const int32_t *kw = A.reckey + ow;
-    int key[16];
     int s = -1;
     if (ellw <= 16) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            key[j] = j < ellw ? kw[j] : INT_MAX;
-            if (key[j] == cu) s = j;
+            const int key = j < ellw ? kw[j] : INT_MAX;
+            if (key == cu) s = j;
         }
     } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) key[j] = INT_MAX;
         s = kfind(kw, ellw, cu);
     }
     if (s < 0) return out;  // cannot happen: u is a neighbour of w
     const RecDat rd = A.recdat[ow + s];
     const double W = rd.w;
-    Wout = W;
     out.t2 = rd.f - 1;
     if (rd.f > 1) {
         double S = 0.0;
         const int32_t *run = A.col + ow + rd.pos;
-        for (int i = 0; i < rd.f; i += 4) {
-            int x[4];
+        for (int i = 0; i < rd.f; i += 8) {
+            int x[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) x[t] = i + t < rd.f ? run[i + t] : u;
+            for (int t = 0; t < 8; ++t) x[t] = i + t < rd.f ? run[i + t] : u;
+            double av[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (x[t] != u) S += A.a[x[t]];
+            for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.a[x[t]] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) S += av[t];
         }
         const double c1 = cbrt(W);
         out.val = c1 * c1 * S;
     }
-    if (U.nc <= 1) return out;  // no foreign community of u besides C(w)
-    // u touching few communities: match communities first (walk u's
-    // communities, look each up among w's keys) and intersect only the runs
-    // of shared ones; otherwise intersect the whole foreign lists.
-    const bool by_comm = ellw <= 16 ? U.nc <= 8 : U.nc <= 4;
-    if (!by_comm) {
-        const ListPlan L = list_plan(U, mw);
-        if (L.steps > kListLane) {
-            out.defer = 1;
-            return out;
-        }
-        double acc = 0.0;
-        long long c = 0;
-        list_walk(A, U, L, cu, ow, ellw, W, 0, 1, acc, c);
-        out.val += acc;
-        out.t1 += (int)c;
-        return out;
-    }
-    for (int it = U.it_begin(); U.it_ok(it);) {
-        const int c = U.it_comm(it);
-        it = U.it_next(it, c);
-        if (c == cw || c == cu) continue;
-        int sc = -1;
-        if (ellw <= 16) {
+    for (long long j0 = o0; j0 < o1; j0 += 4) {
+        int y[4];
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (key[j] == c) sc = j;
-        } else {
-            sc = kfind(kw, ellw, c);
+        for (int t = 0; t < 4; ++t) y[t] = j0 + t < o1 ? A.outl[j0 + t] : -1;
+        unsigned int hm = 0u;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (y[t] >= 0 && U.in_list(y[t])) hm |= 1u << t;
+        while (hm) {
+            const int t = __builtin_ctz(hm);
+            hm &= hm - 1u;
+            const int v = A.outl[j0 + t];
+            const int cv = A.lab[v];
+            const long long ov = (long long)A.off[v];
+            const int ellv = A.meta[v].ell;
+            const int s1 = kfind(A.reckey + ov, ellv, cu);
+            const int s2 = kfind(A.reckey + ov, ellv, cw);
+            const int s3 = kfind(kw, ellw, cv);
+            const double w_vu = s1 >= 0 ? A.recdat[ov + s1].w : 0.0;
+            const double w_vw = s2 >= 0 ? A.recdat[ov + s2].w : 0.0;
+            const double w_wv = s3 >= 0 ? A.recdat[ow + s3].w : 0.0;
+            out.val += cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
+            out.t1 += 2;
         }
-        if (sc >= 0) typeI_in(A, U, cu, c, ow, sc, W, out);
     }
     return out;
 }
@@ -1058,37 +827,51 @@ __device__ void hub_finish(const ScoreArgs<OffT> &A, const double *red, const lo
 // A score unit is either a tile -- <= kScoreTileV consecutive vertices with
 // at most kScoreTileP foreign entries -- or one chunk of kScoreTileP pairs of
 // a score hub whose foreign list fits in LDS.  Either way the foreign
-// neighbours w of the unit's vertices are laid out in LDS with their
-// communities (a vertex's entries ascending, hence grouped by community),
-// one lane takes one pair (u, w), pairs whose list intersection is long are
-// handed to a whole wavefront, and the pair terms are summed in a fixed
-// order: per vertex in pair order for a tile, in a tree over the chunk for
-// a hub (the chunk that finishes last adds the chunk partials in order).
+// neighbours w of the unit's vertices are laid out in LDS (a vertex's
+// entries ascending), one lane takes one pair (u, w), and the pair terms are
+// summed in a fixed order: per vertex in pair order for a tile, in a tree
+// over the chunk for a hub (the chunk that finishes last adds the chunk
+// partials in order).
 static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: one vertex and one pair per thread");
 
 struct ScoreUnitShared {
-    int w[kHubList], cw[kHubList];   // foreign neighbours and their communities
+    int w[kHubList];                 // foreign neighbours
     int pb[kScoreTileV + 1];         // tile: first pair of each vertex
     long long ou[kScoreTileV];
-    int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV], nc[kScoreTileV];
+    int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV];
     unsigned short pu[kScoreTileP];  // tile: vertex of each pair
     double val[kBlock];              // the lane's pair terms
     int t2[kBlock], t1[kBlock];
-    double hW[kBlock];               // deferred pairs: w_w(C(u)) ...
-    unsigned char hq[kBlock];        // ... and the lane
-    int nhq;
     int ws[kBlock / 64];
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
 };
 
+// A hub chunk's partial: block tree sum of the lanes' terms (thread 0 gets it).
+__device__ __forceinline__ void chunk_tree(double x, long long y1, long long y2, double *red,
+                                           long long (*ired)[kBlock / 64]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o);
+        y1 += __shfl_xor(y1, o);
+        y2 += __shfl_xor(y2, o);
+    }
+    if (lane == 0) {
+        red[wave] = x;
+        ired[0][wave] = y1;
+        ired[1][wave] = y2;
+    }
+    __syncthreads();
+}
+
 template <typename OffT>
 __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hub_unit, int idx, double wmax,
                            ScoreAcc &sa) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     // ---- prologue: lay out the unit's pairs
-    int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;  // tile
-    int hub = 0, chunk = 0, hu = 0, hdeg = 0, hdp = 0, hnc = 0, hcu = 0;  // hub chunk
+    int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;    // tile
+    int hub = 0, chunk = 0, hu = 0, hdeg = 0, hdp = 0, hcu = 0;  // hub chunk
     if (hub_unit) {
         const int2 hc = A.hub_chunk[idx];
         hub = hc.x;
@@ -1099,15 +882,9 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         const int h = m.q - m.p;
         hdeg = m.deg;
         hdp = m.deg - h;  // <= the load-time count, which fits kHubList
-        hnc = m.ell - (h > 0 ? 1 : 0);
         hcu = A.lab[hu];
-        for (int j = tid; j < hdp; j += kBlock) {
-            const int x = A.col[ou + (j < m.p ? j : j + h)];
-            S.w[j] = x;
-            S.cw[j] = A.lab[x];
-        }
+        for (int j = tid; j < hdp; j += kBlock) S.w[j] = A.col[ou + (j < m.p ? j : j + h)];
         total = min(kBlock, max(0, hdp - chunk * kBlock));
-        if (tid == 0) S.nhq = 0;
         __syncthreads();
     } else {
         const int2 tl = A.tiles[idx];
@@ -1122,104 +899,56 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             S.cu[tid] = A.lab[v];
             S.p[tid] = m.p;
             S.h[tid] = m.q - m.p;
-            S.nc[tid] = m.ell - (m.q > m.p ? 1 : 0);
         }
         pb = block_excl_scan(dp, S.ws, total);
         if (tid < nv) {
             S.pb[tid] = pb;
             for (int k = pb; k < pb + dp; ++k) S.pu[k] = (unsigned short)tid;
         }
-        if (tid == 0) {
-            S.pb[nv] = total;
-            S.nhq = 0;
-        }
+        if (tid == 0) S.pb[nv] = total;
         __syncthreads();
         if (tid < total) {
             const int i = S.pu[tid];
             const int j = tid - S.pb[i];
-            const int x = A.col[S.ou[i] + (j < S.p[i] ? j : j + S.h[i])];
-            S.w[tid] = x;
-            S.cw[tid] = A.lab[x];
+            S.w[tid] = A.col[S.ou[i] + (j < S.p[i] ? j : j + S.h[i])];
         }
         __syncthreads();
     }
     // ---- the lane's pair
     const bool has = tid < total;
-    int k = 0;
-    TileU U;
-    U.w = S.w;
-    U.cw = S.cw;
-    int u = 0, cu = 0;
-    if (hub_unit) {
-        k = chunk * kBlock + tid;
-        U.pb = 0;
-        U.pe = hdp;
-        U.nc = hnc;
-        u = hu;
-        cu = hcu;
-    } else {
-        k = tid;
-        const int i = has ? S.pu[tid] : 0;
-        U.pb = S.pb[i];
-        U.pe = S.pb[i + 1];
-        U.nc = S.nc[i];
-        u = v0 + i;
-        cu = S.cu[i];
-    }
-    PairRes r = {0.0, 0, 0, 0};
+    PairRes r = {0.0, 0, 0};
     if (has) {
+        TileU U;
+        U.w = S.w;
+        int k, u, cu;
+        if (hub_unit) {
+            k = chunk * kBlock + tid;
+            U.pb = 0;
+            U.pe = hdp;
+            u = hu;
+            cu = hcu;
+        } else {
+            k = tid;
+            const int i = S.pu[tid];
+            U.pb = S.pb[i];
+            U.pe = S.pb[i + 1];
+            u = v0 + i;
+            cu = S.cu[i];
+        }
         const int w = S.w[k];
         const long long ow = (long long)A.off[w];
         const VMeta mw = A.meta[w];
+        const int cw = A.lab[w];
+        const long long o0 = A.oo[w], o1 = A.oo[w + 1];
         sa.workI += min(U.pe - U.pb, mw.deg - (mw.q - mw.p));
-        double W;
-        r = score_pair(A, U, u, cu, w, S.cw[k], ow, mw, W);
-        if (r.defer) {
-            const int q = atomicAdd(&S.nhq, 1);
-            S.hq[q] = (unsigned char)tid;
-            S.hW[q] = W;
-        }
+        r = score_pair(A, U, u, cu, w, cw, ow, mw, o0, o1);
     }
-    S.val[tid] = r.val;
-    S.t2[tid] = r.t2;
-    S.t1[tid] = r.t1;
-    __syncthreads();
-    // ---- deferred list intersections: one wavefront per pair
-    {
-        const int nq = S.nhq;
-        for (int q = wave; q < nq; q += kBlock / 64) {
-            const int l = S.hq[q];
-            TileU V;
-            V.w = S.w;
-            V.cw = S.cw;
-            int kk, vcu;
-            if (hub_unit) {
-                kk = chunk * kBlock + l;
-                V.pb = 0;
-                V.pe = hdp;
-                V.nc = hnc;
-                vcu = hcu;
-            } else {
-                kk = l;
-                const int i = S.pu[l];
-                V.pb = S.pb[i];
-                V.pe = S.pb[i + 1];
-                V.nc = S.nc[i];
-                vcu = S.cu[i];
-            }
-            const int w = S.w[kk];
-            double val;
-            long long cnt;
-            list_wave(A, V, vcu, (long long)A.off[w], A.meta[w], S.hW[q], val, cnt);
-            if (lane == 0) {
-                S.val[l] += val;
-                S.t1[l] += (int)cnt;
-            }
-        }
-    }
-    __syncthreads();
     // ---- epilogue: sums in a fixed order
     if (!hub_unit) {
+        S.val[tid] = r.val;
+        S.t2[tid] = r.t2;
+        S.t1[tid] = r.t1;
+        __syncthreads();
         if (tid < nv && dp > 0) {
             double acc = 0.0;
             long long c1 = 0, c2 = 0;
@@ -1232,102 +961,14 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         }
         return;
     }
-    double x = S.val[tid];
-    long long y1 = S.t1[tid], y2 = S.t2[tid];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        x += __shfl_xor(x, o);
-        y1 += __shfl_xor(y1, o);
-        y2 += __shfl_xor(y2, o);
-    }
-    if (lane == 0) {
-        S.red[wave] = x;
-        S.ired[0][wave] = y1;
-        S.ired[1][wave] = y2;
-    }
-    __syncthreads();
+    chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
     if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, hu, hdeg, hdp, wmax, sa);
 }
 
-// ------------------------------------------------------------ score hubs
-// A vertex with more than kScoreTileP foreign entries is a score hub: its
-// pairs are cut into chunks of kScoreTileP, one workgroup per chunk (so a
-// hub's work spreads over the chip).  A chunk sums its pairs in a fixed
-// tree order and stores a partial; the chunk that finishes last (a
-// device-scope counter per hub) adds the partials in chunk order and writes
-// the score.  A hub whose foreign list fits in LDS stages it with its
-// communities and runs in the tile kernel with the tile view of u; larger
-// hubs read u's side from HBM in a kernel of their own.
-struct HubChunkShared {
+// A hub whose foreign list exceeds kHubList: u's list is read from HBM.
+struct ScoreHubBigShared {
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
-    double hW[kBlock], dval[kBlock];  // deferred pairs of the chunk, by lane
-    int hw[kBlock], dcnt[kBlock];
-    unsigned char hq[kBlock];
-    int nhq, last;
-};
-
-template <class UV, typename OffT>
-__device__ void hub_chunk_run(const ScoreArgs<OffT> &A, const UV &U, HubChunkShared &C, int hub, int chunk, int u,
-                              int cu, int deg, int dp, double wmax, ScoreAcc &sa) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k = chunk * kScoreTileP + tid;
-    PairRes r = {0.0, 0, 0, 0};
-    if (k < dp) {
-        const int w = U.list_at(k);
-        const long long ow = (long long)A.off[w];
-        const VMeta mw = A.meta[w];
-        const int cw = A.lab[w];
-        sa.workI += min(dp, mw.deg - (mw.q - mw.p));
-        double W;
-        r = score_pair(A, U, u, cu, w, cw, ow, mw, W);
-        if (r.defer) {
-            const int q = atomicAdd(&C.nhq, 1);
-            C.hq[q] = (unsigned char)tid;
-            C.hW[q] = W;
-            C.hw[q] = w;
-        }
-    }
-    __syncthreads();
-    {
-        const int nq = C.nhq;
-        for (int q = wave; q < nq; q += kBlock / 64) {
-            const int w = C.hw[q];
-            double val;
-            long long cnt;
-            list_wave(A, U, cu, (long long)A.off[w], A.meta[w], C.hW[q], val, cnt);
-            if (lane == 0) {
-                C.dval[C.hq[q]] = val;
-                C.dcnt[C.hq[q]] = (int)cnt;
-            }
-        }
-    }
-    __syncthreads();
-    if (r.defer) {
-        r.val += C.dval[tid];
-        r.t1 += C.dcnt[tid];
-    }
-    double x = r.val;
-    long long y1 = r.t1, y2 = r.t2;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        x += __shfl_xor(x, o);
-        y1 += __shfl_xor(y1, o);
-        y2 += __shfl_xor(y2, o);
-    }
-    if (lane == 0) {
-        C.red[wave] = x;
-        C.ired[0][wave] = y1;
-        C.ired[1][wave] = y2;
-    }
-    __syncthreads();
-    if (tid == 0) hub_finish(A, C.red, C.ired, hub, chunk, u, deg, dp, wmax, sa);
-}
-
-constexpr int kBigKeys = 4096;  // record keys staged in LDS for the HBM-side hubs
-struct ScoreHubBigShared {
-    int keys[kBigKeys];
-    HubChunkShared c;
 };
 
 template <typename OffT>
@@ -1339,24 +980,24 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     const long long ou = (long long)A.off[u];
     const int h = m.q - m.p;
     const int dp = m.deg - h;
-    const bool lk = m.ell <= kBigKeys;
-    if (lk)
-        for (int j = tid; j < m.ell; j += kBlock) S.keys[j] = A.reckey[ou + j];
-    if (tid == 0) S.c.nhq = 0;
-    __syncthreads();
+    const int cu = A.lab[u];
     HubU U;
     U.row = A.col + ou;
-    U.gkeys = A.reckey + ou;
-    U.gdat = A.recdat + ou;
-    U.skeys = lk ? S.keys : nullptr;
-    U.slist = nullptr;
-    U.ell = m.ell;
-    U.cu = A.lab[u];
-    U.nc = m.ell - (h > 0 ? 1 : 0);
     U.p = m.p;
     U.h = h;
     U.n_f = dp;
-    hub_chunk_run(A, U, S.c, hub, chunk, u, U.cu, m.deg, dp, wmax, sa);
+    const int k = chunk * kScoreTileP + tid;
+    PairRes r = {0.0, 0, 0};
+    if (k < dp) {
+        const int w = U.list_at(k);
+        const long long ow = (long long)A.off[w];
+        const VMeta mw = A.meta[w];
+        const int cw = A.lab[w];
+        sa.workI += min(dp, mw.deg - (mw.q - mw.p));
+        r = score_pair(A, U, u, cu, w, cw, ow, mw, A.oo[w], A.oo[w + 1]);
+    }
+    chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
+    if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, u, m.deg, dp, wmax, sa);
 }
 
 __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
@@ -1491,6 +1132,8 @@ static rs_status score_pass_t(rs_graph *g) {
     S.n_chunks_lds = g->n_schunks_lds;
     S.hub_part = D.hub_part;
     S.hub_cnt = D.hub_cnt;
+    S.oo = D.oo;
+    S.outl = D.outl;
     S.reckey = D.reckey;
     S.recdat = D.recdat;
     S.meta = D.meta;
@@ -2105,26 +1748,46 @@ __device__ __forceinline__ long long find_entry(const OffT *off, const int32_t *
     return -1;
 }
 
+// The out-lists that a removal must update.
+struct OutLists {
+    const int32_t *lab;
+    const int64_t *oo;
+    int32_t *outl;
+};
+
+// Tombstone y in out(x), if there; returns whether it was found.
+__device__ __forceinline__ bool out_drop(const OutLists &O, int x, int y) {
+    for (long long j = O.oo[x]; j < O.oo[x + 1]; ++j)
+        if (O.outl[j] == y) {
+            O.outl[j] = ~y;
+            return true;
+        }
+    return false;
+}
+
 // Delete the undirected edge {a, b}; the entry in the row of min(a, b) is
-// the owner and decides which request wins.  Returns 1 if deleted here.
+// the owner and decides which request wins.  Returns 1 if deleted here.  A
+// deleted edge between communities also leaves the out-list that holds it.
 template <typename OffT>
-__device__ __forceinline__ int delete_edge(const OffT *off, const int32_t *deg, int32_t *col, int a, int b) {
+__device__ __forceinline__ int delete_edge(const OffT *off, const int32_t *deg, int32_t *col, const OutLists &O,
+                                           int a, int b) {
     const int x = min(a, b), y = max(a, b);
     const long long e = find_entry(off, deg, col, x, y);
     if (e < 0) return 0;
     if (atomicCAS(&col[e], y, ~y) != y) return 0;
     const long long f = find_entry(off, deg, col, y, x);
     if (f >= 0) col[f] = ~x;
+    if (O.lab[x] != O.lab[y] && !out_drop(O, x, y)) out_drop(O, y, x);
     return 1;
 }
 
 template <typename OffT>
-__global__ void k_remove_edges(const OffT *off, const int32_t *deg, int32_t *col, const int32_t *src,
+__global__ void k_remove_edges(const OffT *off, const int32_t *deg, int32_t *col, OutLists O, const int32_t *src,
                                const int32_t *dst, long long m, unsigned long long *removed) {
     unsigned long long cnt = 0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
         const int a = src[i], b = dst[i];
-        if (a != b) cnt += (unsigned long long)delete_edge(off, deg, col, a, b);
+        if (a != b) cnt += (unsigned long long)delete_edge(off, deg, col, O, a, b);
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
     if (__lane_id() == 0 && cnt) atomicAdd(removed, cnt);
@@ -2133,7 +1796,7 @@ __global__ void k_remove_edges(const OffT *off, const int32_t *deg, int32_t *col
 // One wavefront per removed vertex: delete every incident edge, then mark the
 // vertex dead.  removed[0] counts edges, removed[1] newly dead vertices.
 template <typename OffT>
-__global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *col, uint8_t *alive,
+__global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *col, OutLists O, uint8_t *alive,
                                   const int32_t *verts, long long nv, unsigned long long *removed) {
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
@@ -2144,7 +1807,7 @@ __global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *
         unsigned long long cnt = 0;
         for (int j = (int)__lane_id(); j < d; j += 64) {
             const int y = col[rb + j];
-            if (y >= 0) cnt += (unsigned long long)delete_edge(off, deg, col, x, y);
+            if (y >= 0) cnt += (unsigned long long)delete_edge(off, deg, col, O, x, y);
         }
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
         if (__lane_id() == 0) {
@@ -2175,16 +1838,25 @@ __global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, long long
     }
 }
 
+static OutLists out_lists(rs_graph *g) {
+    OutLists O;
+    O.lab = g->d.lab;
+    O.oo = g->d.oo;
+    O.outl = g->d.outl;
+    return O;
+}
+
 rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t m,
                               unsigned long long *d_removed) {
     if (m <= 0) return RS_OK;
     const int grid = grid_for(m, 256, 4096);
     if (g->d.off64)
         hipLaunchKernelGGL(k_remove_edges<long long>, dim3(grid), dim3(256), 0, g->stream,
-                           (const long long *)g->d.off, g->d.deg, g->d.col, d_src, d_dst, (long long)m, d_removed);
+                           (const long long *)g->d.off, g->d.deg, g->d.col, out_lists(g), d_src, d_dst, (long long)m,
+                           d_removed);
     else
         hipLaunchKernelGGL(k_remove_edges<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, d_src, d_dst, (long long)m, d_removed);
+                           g->d.deg, g->d.col, out_lists(g), d_src, d_dst, (long long)m, d_removed);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "remove edges launch");
 }
@@ -2194,11 +1866,11 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
     const int grid = grid_for(nv, 4, 4096);
     if (g->d.off64)
         hipLaunchKernelGGL(k_remove_vertices<long long>, dim3(grid), dim3(256), 0, g->stream,
-                           (const long long *)g->d.off, g->d.deg, g->d.col, g->d.alive, d_verts, (long long)nv,
-                           d_removed);
+                           (const long long *)g->d.off, g->d.deg, g->d.col, out_lists(g), g->d.alive, d_verts,
+                           (long long)nv, d_removed);
     else
         hipLaunchKernelGGL(k_remove_vertices<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, g->d.alive, d_verts, (long long)nv, d_removed);
+                           g->d.deg, g->d.col, out_lists(g), g->d.alive, d_verts, (long long)nv, d_removed);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "remove vertices launch");
 }

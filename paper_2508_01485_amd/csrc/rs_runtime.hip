@@ -173,6 +173,8 @@ struct HostGraph {
     std::vector<int32_t> new2old, old2new, comm2orig;
     std::vector<int2> rtv, stiles, schunk;
     std::vector<RowTile> rtiles;
+    std::vector<int64_t> oo;
+    std::vector<int32_t> outl;
     std::vector<int32_t> rhubs, shubs, sfirst;
     int n_chunks_lds = 0;
 };
@@ -261,6 +263,31 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
                 fgn[nv] = (e - b) - own;
             }
         });
+        // out-lists: foreign neighbours of higher rank (foreign degree, id)
+        H.oo.assign(n + 1, 0);
+        auto higher = [&](int64_t x, int32_t y) { return fgn[y] > fgn[x] || (fgn[y] == fgn[x] && y > x); };
+        auto foreign = [&](int64_t x, int32_t y) { return H.lab[y] != H.lab[x]; };
+        parallel_for(n, 4096, [&](int64_t lo, int64_t hi) {
+            for (int64_t x = lo; x < hi; ++x) {
+                int64_t c = 0;
+                for (int64_t j = H.off[x]; j < H.off[x + 1]; ++j) {
+                    const int32_t y = H.col[j];
+                    if (foreign(x, y) && higher(x, y)) ++c;
+                }
+                H.oo[x + 1] = c;
+            }
+        });
+        for (int64_t x = 0; x < n; ++x) H.oo[x + 1] += H.oo[x];
+        H.outl.resize(H.oo[n]);
+        parallel_for(n, 4096, [&](int64_t lo, int64_t hi) {
+            for (int64_t x = lo; x < hi; ++x) {
+                int64_t o = H.oo[x];
+                for (int64_t j = H.off[x]; j < H.off[x + 1]; ++j) {
+                    const int32_t y = H.col[j];
+                    if (foreign(x, y) && higher(x, y)) H.outl[o++] = y;
+                }
+            }
+        });
         cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs);
         H.rtiles.resize(H.rtv.size());
         for (size_t t = 0; t < H.rtv.size(); ++t) {
@@ -326,6 +353,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.shub_chunk, sizeof(int2) * nch},
         {(void **)&D.hub_part, sizeof(HubPart) * nch},
         {(void **)&D.hub_cnt, 4 * nsh},
+        {(void **)&D.oo, 8 * (N + 1)},
+        {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
         {(void **)&D.meta, sizeof(VMeta) * N},
@@ -373,6 +402,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     put(D.stiles, H.stiles.data(), sizeof(int2) * H.stiles.size());
     put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
     put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
+    put(D.oo, H.oo.data(), 8 * H.oo.size());
+    put(D.outl, H.outl.data(), 4 * H.outl.size());
     put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.hub_cnt, 0, 4 * nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);

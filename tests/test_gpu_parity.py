@@ -103,9 +103,10 @@ def test_hub_runs_cross_stream_groups(rs):
 
 
 def test_score_hub_beyond_lds_staging(rs):
-    """Two hubs whose foreign lists (> 8,192 entries) and record keys (> 4,096
-    communities) exceed what a score-hub workgroup stages in LDS, so their
-    pairs read u's side from HBM; the hubs are adjacent (hub-hub pairs)."""
+    """Two adjacent hubs (hub-hub pairs) with foreign lists of ~10,000 entries
+    and > 4,096 distinct neighbour communities: too large for a score unit's
+    LDS list, so their chunks read u's side from HBM; keys beyond one 16-key
+    read take the multi-level search."""
     rng = np.random.default_rng(8)
     n = 15000
     labels = rng.integers(0, 7000, n)
@@ -188,8 +189,9 @@ def test_device_resident_input_and_torch_stream(rs):
 def test_removals_equal_fresh_load(rs):
     """rs_apply_removals then reading == loading the mutated graph from scratch,
     and both match the oracle.  Integer results are identical; scores agree to
-    1e-12 relative (a vertex keeps the lane team of its load-time degree, so
-    its floating-point summation order can differ from a fresh load's)."""
+    1e-12 relative (the tiles and out-list orientation are fixed at load time,
+    so a vertex's floating-point summation order can differ from a fresh
+    load's)."""
     g = lfr(20000, 12.0, 300, 0.25, seed=21, cmin=10, cmax=400)
     rng = np.random.default_rng(4)
     u, v = g.edges()
@@ -230,6 +232,47 @@ def test_removals_equal_fresh_load(rs):
     from tests.parity import topk_matches
     topk_matches(ids1, exp_ids, ora["R"], 100, alive=alive)
     assert not np.isin(ids1, rem_v).any()
+
+
+def test_removals_on_triangle_rich_hubs(rs):
+    """Removals that delete edges between communities of a triangle-rich graph
+    with hubs (so oriented out-lists lose entries), including a hub vertex,
+    then re-score: equal to the oracle on the mutated graph."""
+    rng = np.random.default_rng(12)
+    n = 3000
+    labels = rng.integers(0, 60, n)
+    base = random_small(n, 0.004, 5, 91)
+    u, v = base.edges()
+    hubs = [(h, int(x)) for h in range(4) for x in rng.choice(np.arange(4, n), 900, replace=False)]
+    hubs += [(0, 1), (0, 2), (1, 2), (2, 3)]
+    g = from_edges(n, np.concatenate([np.stack([u, v], 1), np.array(hubs)]), labels)
+    gu, gv = g.edges()
+    cross = np.nonzero(labels[gu] != labels[gv])[0]
+    pick = rng.choice(cross, 400, replace=False)
+    rem_e = np.concatenate([np.stack([gu[pick], gv[pick]], 1), [[0, 1], [1, 2]]])
+    rem_v = np.array([3, 17, 2999])
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    rs.rs_score(h)
+    rs.rs_apply_removals(h, edges=rem_e, vertices=rem_v)
+    R1 = rs.rs_read_scores(h)
+    c1 = rs.rs_read_vertex_counts(h)
+    ids1, _ = rs.rs_topk(h, 50)
+    h.free()
+    keep = np.ones(gu.size, bool)
+    ekey = set(map(tuple, np.sort(rem_e, 1).tolist()))
+    keep &= np.array([(a, b) not in ekey for a, b in zip(gu.tolist(), gv.tolist())])
+    dead = np.zeros(n, bool)
+    dead[rem_v] = True
+    keep &= ~dead[gu] & ~dead[gv]
+    g2 = from_edges(n, np.stack([gu[keep], gv[keep]], 1), labels)
+    ora = oracle.score(g2)
+    rel_close(R1, ora["R"], 1e-6)
+    assert np.array_equal(c1["tI"], ora["tI"]) and np.array_equal(c1["tII"], ora["tII"])
+    assert int(ora["tI"].sum()) > 0
+    alive = (~dead).astype(np.uint8)
+    exp_ids, _ = oracle.topk(ora["R"], 50, alive=alive)
+    from tests.parity import topk_matches
+    topk_matches(ids1, exp_ids, ora["R"], 50, alive=alive)
 
 
 def test_error_paths_on_device(rs):
