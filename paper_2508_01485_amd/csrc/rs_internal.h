@@ -131,8 +131,7 @@ struct TopkState {
     unsigned long long n_tie;    // tie-list fill counter
     unsigned int overflow;       // tie class too large for the pairwise ranker
     unsigned int done;           // threshold bin taken whole
-    unsigned int hist_done;      // histogram workgroups finished (the last one finds the threshold)
-    unsigned int small;          // the final order was produced by the one-workgroup sort
+    unsigned int small;          // spare
 };
 
 struct DeviceGraph {
@@ -165,11 +164,13 @@ struct DeviceGraph {
     DevCounters *ctr = nullptr;
     // top-k
     unsigned int *thist = nullptr;  // [kTopkBins]
+    unsigned int *thist_c = nullptr;  // [256] coarse histogram (sums of 256 bins)
     TopkState *tstate = nullptr;
     TopkKey *tfinal = nullptr, *ttie = nullptr, *ttie2 = nullptr;  // [n] each
     int32_t *tout_ids = nullptr;
     double *tout_sc = nullptr;
     double *scratch_d = nullptr;    // [n] doubles (readers)
+    char *tblk = nullptr;           // [16 + 16 n] top-k output block: flag | ids | scores
     unsigned long long *scratch_u = nullptr;  // [8] small counters
 };
 
@@ -196,6 +197,9 @@ struct rs_graph {
     rs::DeviceGraph d;
     rs::Timing timing;
     std::vector<void *> allocations;
+    // pinned host buffer of the common top-k path: [flag | ids | scores]
+    void *hpin = nullptr;
+    int64_t hpin_cap = 0;
 };
 
 namespace rs {

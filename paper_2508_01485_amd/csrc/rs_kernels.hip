@@ -19,6 +19,7 @@
 // with a workgroup each); a launch has one workgroup per tile, so the
 // hardware dispatcher balances the uneven tiles.
 #include <climits>
+#include <cstring>
 
 #include "rs_internal.h"
 
@@ -526,32 +527,30 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
     }
 }
 
-// Algorithm 1 Steps 1-2 for every vertex: hub rows first, then the tiles.
-template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
-    __shared__ RowTileShared S;
-    RowAcc acc = {0.0, 0, 0, 0, 0};
-    const int b = (int)blockIdx.x;
-    if (b < A.n_hubs) {
-        hub_row(A, S, A.hubs[b], acc);
-    } else {
-        const int t = tile_of_block(b, A.n_hubs, A.tiles_per_xcd);
-        if (t < A.n_tiles) row_tile(A, S, t, acc);
-    }
-    block_reduce_row(acc, &A.part[b]);
-}
-
-// Reduce the row partials of a pass into the counters (one block).
-__global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevCounters *c) {
-    __shared__ unsigned long long s[5][16];
+// Reduce the row partials of a pass into the counters (one workgroup; the
+// loads of four partials per thread are in flight together).
+__device__ void reduce_row_parts(const RowPart *part, int np, DevCounters *c) {
+    __shared__ unsigned long long s[5][kBlock / 64];
     unsigned long long w = 0, nb = 0, dp = 0, ell = 0, ellx = 0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        const RowPart p = part[i];
-        w = max(w, p.wmax_bits);
-        nb += p.n_border;
-        dp += p.sum_dprime;
-        ell += p.sum_ell;
-        ellx += p.sum_ell_x;
+    for (int i0 = threadIdx.x; i0 < np; i0 += 4 * kBlock) {
+        RowPart q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = i0 + j * kBlock;
+            if (i < np) {
+                q[j] = part[i];
+            } else {
+                q[j] = RowPart{};
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w = max(w, q[j].wmax_bits);
+            nb += q[j].n_border;
+            dp += q[j].sum_dprime;
+            ell += q[j].sum_ell;
+            ellx += q[j].sum_ell_x;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         w = max(w, (unsigned long long)__shfl_xor(w, o));
@@ -569,8 +568,9 @@ __global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevC
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        DevCounters r = {};
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        DevCounters r = *c;
+        r.wmax_bits = r.n_border = r.sum_dprime = r.sum_ell = r.sum_ell_x = 0;
+        for (int i = 0; i < kBlock / 64; ++i) {
             r.wmax_bits = max(r.wmax_bits, s[0][i]);
             r.n_border += s[1][i];
             r.sum_dprime += s[2][i];
@@ -579,6 +579,52 @@ __global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevC
         }
         *c = r;
     }
+}
+
+// Algorithm 1 Steps 1-2 for every vertex: hub rows first, then the tiles.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
+    __shared__ RowTileShared S;
+    RowAcc acc = {0.0, 0, 0, 0, 0};
+    const int b = (int)blockIdx.x;
+    if (b < A.n_hubs) {
+        hub_row(A, S, A.hubs[b], acc);
+    } else {
+        const int t = tile_of_block(b, A.n_hubs, A.tiles_per_xcd);
+        if (t < A.n_tiles) row_tile(A, S, t, acc);
+    }
+    block_reduce_row(acc, &A.part[b]);
+}
+
+// w_max of a pass from the row partials (one workgroup of 1024 threads, the
+// loads of eight partials per thread in flight together); the other row
+// totals are reduced when the counters are read.
+__global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevCounters *c) {
+    __shared__ unsigned long long s[16];
+    unsigned long long w = 0;
+    for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 1024) {
+        unsigned long long q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = i0 + j * 1024;
+            q[j] = i < np ? part[i].wmax_bits : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w = max(w, q[j]);
+    }
+    for (int o = 32; o > 0; o >>= 1) w = max(w, (unsigned long long)__shfl_xor(w, o));
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0;
+        for (int i = 0; i < 16; ++i) m = max(m, s[i]);
+        c->wmax_bits = m;
+    }
+}
+
+// All row totals of the last pass (for the counter readers).
+__global__ __launch_bounds__(kBlock) void k_reduce_rows(const RowPart *part, int np, DevCounters *c) {
+    reduce_row_parts(part, np, c);
 }
 
 // ============================================================ score pass
@@ -1084,6 +1130,10 @@ __global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, in
     }
 }
 
+__global__ void k_zero_u64(unsigned long long *p, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
+}
+
 // ------------------------------------------------------------ pass launcher
 template <typename OffT>
 static rs_status score_pass_t(rs_graph *g) {
@@ -1165,6 +1215,7 @@ rs_status launch_score_pass(rs_graph *g) {
 }
 
 rs_status launch_reduce_counts(rs_graph *g) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, g->stream, g->d.part_rows, g->grid_rows, g->d.ctr);
     hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, g->d.part_score, g->grid_score, g->d.ctr);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "reduce launch");
@@ -1194,110 +1245,30 @@ __device__ __forceinline__ TopkKey make_key(const double *R, const int32_t *new2
     return k;
 }
 
-// Threshold search over the 65,536-bin histogram by one workgroup of kBlock
-// threads: thread t owns 256 bins, descending with t; the block prefix of
-// the per-thread totals finds the bin where the count from the top reaches
-// st->take.  Records the threshold in st and clears the histogram.
-__device__ void topk_find_block(unsigned int *hist, TopkState *st, int level, long long *s_scan) {
-    constexpr int kPer = kTopkBins / kBlock;  // 256 bins per thread
-    constexpr int kGrp = 16;                  // bins per group
-    const int t = threadIdx.x;
-    const long long need = st->take;
-    const int base = kTopkBins - kPer * (t + 1);
-    const uint4 *h4 = (const uint4 *)(hist + base);
-    unsigned int gs[kPer / kGrp];
-    long long mine = 0;
-#pragma unroll
-    for (int g = 0; g < kPer / kGrp; ++g) {
-        unsigned int x = 0;
-#pragma unroll
-        for (int i = 0; i < kGrp / 4; ++i) {
-            const uint4 y = h4[g * (kGrp / 4) + i];
-            x += y.x + y.y + y.z + y.w;
-        }
-        gs[g] = x;
-        mine += x;
-    }
-    s_scan[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
-        const long long x = t >= o ? s_scan[t - o] : 0;
-        __syncthreads();
-        s_scan[t] += x;
-        __syncthreads();
-    }
-    const long long incl = s_scan[t];
-    const long long excl = incl - mine;
-    const long long total = s_scan[kBlock - 1];
-    if (excl < need && need <= incl) {
-        // the group, from the top of this thread's range, then the bin
-        long long cum = excl;
-        int gsel = 0;
-        bool found = false;
-#pragma unroll
-        for (int g = kPer / kGrp - 1; g >= 0; --g) {
-            if (!found) {
-                if (cum + gs[g] >= need) {
-                    gsel = g;
-                    found = true;
-                } else {
-                    cum += gs[g];
-                }
-            }
-        }
-        unsigned int hb[kGrp];
-#pragma unroll
-        for (int i = 0; i < kGrp; ++i) hb[i] = hist[base + gsel * kGrp + i];
-        bool done = false;
-#pragma unroll
-        for (int i = kGrp - 1; i >= 0; --i) {
-            if (!done) {
-                const long long h = hb[i];
-                if (cum + h >= need) {
-                    st->digit = (unsigned int)level;
-                    st->thresh = (unsigned int)(base + gsel * kGrp + i);
-                    st->above += cum;
-                    st->take = need - cum;
-                    st->binsize = h;
-                    st->done = (need - cum == h) ? 1u : 0u;
-                    done = true;
-                } else {
-                    cum += h;
-                }
-            }
-        }
-    }
-    if (t == 0 && !(need > 0 && total >= need)) {  // cannot happen for need <= live keys: take all
-        st->digit = (unsigned int)level;
-        st->thresh = 0;
-        st->take = 0;
-        st->binsize = 0;
-        st->done = 1u;
-    }
-    __syncthreads();
-    uint4 *w4 = (uint4 *)(hist + base);
-#pragma unroll 8
-    for (int i = 0; i < kPer / 4; ++i) w4[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 // Level-0 histogram: each block counts a contiguous chunk (< 2^16 keys) in an
 // LDS histogram of 16-bit counters packed two per word, then adds its
-// non-zero bins to the global histogram.  The last block to finish resets
-// the selection state for k and finds the threshold bin.
+// non-zero bins to the global histogram, and its sums of 256 consecutive
+// bins to a 256-bin coarse histogram.
 __global__ __launch_bounds__(kBlock) void k_topk_hist(const double *R, const int32_t *new2old, const uint8_t *alive,
                                                       long long n, long long chunk, unsigned int *hist,
-                                                      TopkState *st, long long k) {
+                                                      unsigned int *coarse) {
     __shared__ unsigned int sh[kTopkBins / 2];
-    __shared__ int s_last;
     for (int i = threadIdx.x; i < kTopkBins / 2; i += kBlock) sh[i] = 0u;
     __syncthreads();
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    for (long long v = lo + threadIdx.x; v < hi; v += kBlock) {
-        if (alive[v]) {
-            const unsigned int dig = key_digit(make_key(R, new2old, (int)v), 0);
-            atomicAdd(&sh[dig >> 1], 1u << ((dig & 1u) * 16u));
+    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += 8 * kBlock) {
+        unsigned int dig[8];
+        bool ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long v = v0 + (long long)j * kBlock;
+            ok[j] = v < hi && alive[v];
+            dig[j] = ok[j] ? key_digit(make_key(R, new2old, (int)v), 0) : 0u;
         }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (ok[j]) atomicAdd(&sh[dig[j] >> 1], 1u << ((dig[j] & 1u) * 16u));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kTopkBins / 2; i += kBlock) {
@@ -1305,28 +1276,85 @@ __global__ __launch_bounds__(kBlock) void k_topk_hist(const double *R, const int
         if (x & 0xffffu) atomicAdd(&hist[2 * i], x & 0xffffu);
         if (x >> 16) atomicAdd(&hist[2 * i + 1], x >> 16);
     }
-    __threadfence();
+    // coarse histogram: thread t sums fine bins [256 t, 256 t + 256) (words
+    // [128 t, 128 t + 128), visited in a skewed order to spread LDS banks)
+    static_assert(kTopkBins == 256 * kBlock, "one coarse bin per thread");
+    unsigned int cs = 0;
+    for (int j = 0; j < 128; ++j) {
+        const unsigned int x = sh[128 * threadIdx.x + ((j + threadIdx.x) & 127)];
+        cs += (x & 0xffffu) + (x >> 16);
+    }
+    if (cs) atomicAdd(&coarse[threadIdx.x], cs);
+}
+
+// Level-0 threshold (one workgroup): reset the selection state for k, find
+// the coarse bin where the count from the top reaches k, then the fine bin
+// inside it; clear the coarse histogram (the collect kernel clears the fine
+// one).
+__device__ __forceinline__ long long block_incl_scan_ll(long long x, long long *ws) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1 ? 1 : 0;
+    long long base = 0;
+    for (int i = 0; i < wave; ++i) base += ws[i];
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (threadIdx.x == 0) {
+    return base + x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_topk_find0(unsigned int *hist, unsigned int *coarse, TopkState *st,
+                                                       long long k) {
+    __shared__ long long ws[kBlock / 64];
+    __shared__ long long s_total;
+    __shared__ int s_c;
+    __shared__ long long s_above;
+    const int t = threadIdx.x;
+    // descending bins: thread t holds coarse bin 255 - t
+    const long long mc = coarse[kBlock - 1 - t];
+    const long long ic = block_incl_scan_ll(mc, ws);
+    if (t == kBlock - 1) s_total = ic;
+    if (ic - mc < k && k <= ic) {
+        s_c = kBlock - 1 - t;
+        s_above = ic - mc;
+    }
+    coarse[kBlock - 1 - t] = 0u;
+    __syncthreads();
+    if (s_total < k) {  // cannot happen for k <= live keys: take all
+        if (t == 0) {
+            st->k = k;
+            st->digit = 0;
+            st->thresh = 0;
+            st->above = 0;
+            st->take = 0;
+            st->binsize = 0;
+            st->n_final = 0;
+            st->n_tie = 0;
+            st->overflow = 0;
+            st->done = 1u;
+        }
+        return;
+    }
+    const int c = s_c;
+    const long long above_c = s_above;
+    const unsigned int bin = (unsigned int)(256 * c + 255 - t);
+    const long long mf = hist[bin];
+    const long long inf = above_c + block_incl_scan_ll(mf, ws);
+    if (inf - mf < k && k <= inf) {
         st->k = k;
         st->digit = 0;
-        st->thresh = 0;
-        st->above = 0;
-        st->take = k;
-        st->binsize = 0;
+        st->thresh = bin;
+        st->above = inf - mf;
+        st->take = k - (inf - mf);
+        st->binsize = mf;
         st->n_final = 0;
         st->n_tie = 0;
         st->overflow = 0;
-        st->done = 0;
-        st->hist_done = 0;
-        st->small = 0;
+        st->done = (k == inf) ? 1u : 0u;
     }
-    __syncthreads();
-    topk_find_block(hist, st, 0, (long long *)sh);
 }
 
 // Histogram of digit j over a key list (refinement of a large tie class).
@@ -1413,9 +1441,13 @@ __device__ __forceinline__ void block_push(TopkKey *list, unsigned long long *co
 }
 
 __global__ __launch_bounds__(kBlock) void k_topk_collect(const double *R, const int32_t *new2old, const uint8_t *alive,
-                                                         long long n, TopkState *st, TopkKey *fin, TopkKey *tie) {
+                                                         long long n, TopkState *st, TopkKey *fin, TopkKey *tie,
+                                                         unsigned int *hist) {
     __shared__ unsigned int s_cnt[kBlock / 64];
     __shared__ unsigned long long s_base;
+    // the fine histogram is no longer needed: clear it for the next call
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < kTopkBins / 4; i += gridDim.x * kBlock)
+        ((uint4 *)hist)[i] = make_uint4(0u, 0u, 0u, 0u);
     const unsigned int th = st->thresh;
     const bool done = st->done != 0u;
     for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
@@ -1567,58 +1599,164 @@ __global__ __launch_bounds__(kBlock) void k_final_rank(const TopkKey *fin, long 
     }
 }
 
+// 8-bit digit d (0..9) of a key below its first 16 bits: hi bits 47..0,
+// then lo bits 31..0.
+__device__ __forceinline__ unsigned int key_byte(unsigned long long hi, unsigned int lo, int d) {
+    return d < 6 ? (unsigned int)(hi >> (40 - 8 * d)) & 0xffu : (lo >> (24 - 8 * (d - 6))) & 0xffu;
+}
+
 // Common case: the final list plus the threshold bin hold at most
-// kSmallCap keys.  One block loads both into LDS, bitonic-sorts them
-// (descending) and writes the first keff; keys are unique (the id is part of
-// the key), so the order is exact.  Otherwise it leaves the work to the
-// general path.
-__global__ __launch_bounds__(1024) void k_topk_small(TopkState *st, const TopkKey *fin, const TopkKey *tie,
+// kSmallCap keys.  One block loads them into LDS, radix-selects the `take`
+// largest keys of the threshold bin with 8-bit digits (LDS histograms), and
+// bitonic-sorts the keff selected keys (descending; keys are unique since the
+// id is part of the key, so the order is exact).  flag = 1 if done here, 0
+// if the general path must run.
+__global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const TopkKey *fin, const TopkKey *tie,
                                                      long long keff, const double *R, const int32_t *new2old,
-                                                     int32_t *out_ids, double *out_sc) {
-    __shared__ TopkKey s[kSmallCap];
-    const long long nf = (long long)st->n_final;
-    const long long nt = st->done ? 0 : (long long)st->n_tie;
-    const long long total = nf + nt;
-    if (total > kSmallCap || total < keff) return;
-    int n2 = 1;
-    while (n2 < total) n2 <<= 1;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                                                     int32_t *out_ids, double *out_sc, unsigned int *flag) {
+    __shared__ TopkKey s[kSmallCap], s2[kSmallCap];
+    __shared__ unsigned char mark[kSmallCap];  // 1 in, 0 out, 2 undecided
+    __shared__ unsigned int hcount[256];
+    __shared__ int s_bin, s_above, s_wsum[16];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const long long nfl = (long long)st->n_final;
+    const long long ntl = st->done ? 0 : (long long)st->n_tie;
+    if (nfl + ntl > kSmallCap || nfl + ntl < keff) {
+        if (tid == 0) *flag = 0u;
+        return;
+    }
+    const int nf = (int)nfl, total = (int)(nfl + ntl), kf = (int)keff;
+    for (int i = tid; i < total; i += nthr) {
         if (i < nf) {
             s[i] = fin[i];
-        } else if (i < total) {
-            s[i] = tie[i - nf];
+            mark[i] = 1;
         } else {
-            s[i].hi = 0;
-            s[i].lo = 0;  // below every real key (a real key has lo >= 2^31)
-            s[i].v = -1;
+            s[i] = tie[i - nf];
+            mark[i] = 2;
         }
     }
+    int need = kf - nf;  // threshold-bin keys still to take (uniform)
     __syncthreads();
-    for (int kk = 2; kk <= n2; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool desc = (i & kk) == 0;
-                    const TopkKey x = s[i], y = s[l];
-                    if (desc ? key_gt(y, x) : key_gt(x, y)) {
-                        s[i] = y;
-                        s[l] = x;
-                    }
-                }
+    for (int d = 0; d < 10 && need > 0; ++d) {
+        for (int i = tid; i < 256; i += nthr) hcount[i] = 0u;
+        __syncthreads();
+        for (int i = nf + tid; i < total; i += nthr)
+            if (mark[i] == 2) atomicAdd(&hcount[key_byte(s[i].hi, s[i].lo, d)], 1u);
+        __syncthreads();
+        {
+            // descending bins: thread t < 256 holds bin 255 - t
+            const int mine = tid < 256 ? (int)hcount[255 - tid] : 0;
+            int incl = mine;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if ((tid & 63) >= o) incl += y;
+            }
+            if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
+            __syncthreads();
+            for (int w = 0; w < (tid >> 6); ++w) incl += s_wsum[w];
+            if (tid < 256 && incl - mine < need && need <= incl) {
+                s_bin = 255 - tid;
+                s_above = incl - mine;
             }
             __syncthreads();
         }
+        const int b = s_bin, above = s_above;
+        const bool whole = above + (int)hcount[b] == need;
+        for (int i = nf + tid; i < total; i += nthr) {
+            if (mark[i] == 2) {
+                const unsigned int dg = key_byte(s[i].hi, s[i].lo, d);
+                mark[i] = (dg > (unsigned int)b || (dg == (unsigned int)b && whole)) ? 1 : (dg < (unsigned int)b ? 0 : 2);
+            }
+        }
+        need = whole ? 0 : need - above;
+        __syncthreads();
     }
-    for (int i = threadIdx.x; i < keff; i += blockDim.x) {
-        out_ids[i] = new2old[s[i].v];
-        out_sc[i] = R[s[i].v];
+    // compact the selected keys (in index order) into s2
+    const int per = (total + nthr - 1) / nthr;
+    const int i0 = tid * per;
+    int cnt = 0;
+    for (int i = i0; i < min(total, i0 + per); ++i) cnt += mark[i] == 1 ? 1 : 0;
+    int incl = cnt;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
     }
-    if (threadIdx.x == 0) st->small = 1u;
-}
-
-__global__ void k_zero_u64(unsigned long long *p, int count) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += s_wsum[w];
+    int pos = base + incl - cnt;
+    for (int i = i0; i < min(total, i0 + per); ++i)
+        if (mark[i] == 1) s2[pos++] = s[i];
+    int n2 = 1;
+    while (n2 < kf) n2 <<= 1;
+    __syncthreads();
+    if (n2 <= 1024) {
+        // one key per thread; partners inside a wavefront are exchanged by
+        // shuffles, the others through LDS
+        TopkKey me;
+        me.hi = 0;
+        me.lo = 0;  // padding: below every real key (a real key has lo >= 2^31)
+        me.v = -1;
+        if (tid < kf) me = s2[tid];
+        for (int kk = 2; kk <= n2; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                TopkKey o;
+                if (j >= 64) {
+                    __syncthreads();
+                    if (tid < n2) s2[tid] = me;
+                    __syncthreads();
+                    if (tid < n2) o = s2[tid ^ j];
+                } else {
+                    o.hi = (unsigned long long)__shfl_xor((long long)me.hi, j);
+                    o.lo = (unsigned int)__shfl_xor((int)me.lo, j);
+                    o.v = __shfl_xor(me.v, j);
+                }
+                if (tid < n2) {
+                    const bool desc = (tid & kk) == 0;
+                    const bool lower = tid < (tid ^ j);
+                    // the lower index keeps the larger key in a descending run
+                    const bool take_o = (lower == desc) ? key_gt(o, me) : key_gt(me, o);
+                    if (take_o) me = o;
+                }
+            }
+        }
+        if (tid < kf) {
+            out_ids[tid] = new2old[me.v];
+            out_sc[tid] = R[me.v];
+        }
+    } else {
+        for (int i = kf + tid; i < n2; i += nthr) {
+            s2[i].hi = 0;
+            s2[i].lo = 0;
+            s2[i].v = -1;
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= n2; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < n2; i += nthr) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const bool desc = (i & kk) == 0;
+                        const TopkKey x = s2[i], y = s2[l];
+                        if (desc ? key_gt(y, x) : key_gt(x, y)) {
+                            s2[i] = y;
+                            s2[l] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < kf; i += nthr) {
+            out_ids[i] = new2old[s2[i].v];
+            out_sc[i] = R[s2[i].v];
+        }
+    }
+    if (tid == 0) *flag = 1u;
 }
 
 static inline int grid_for(long long items, int per_block, int cap) {
@@ -1661,24 +1799,44 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     const int grid_h = (int)((D.n + chunk - 1) / chunk);
     timing_begin(g, K_TOPK_HIST, &ev);
     hipLaunchKernelGGL(k_topk_hist, dim3(grid_h), dim3(kBlock), 0, g->stream, D.R, D.new2old, D.alive, D.n, chunk,
-                       D.thist, D.tstate, keff);
+                       D.thist, D.thist_c);
     timing_end(g, K_TOPK_HIST, ev);
+    timing_begin(g, K_TOPK_FIND, &ev);
+    hipLaunchKernelGGL(k_topk_find0, dim3(1), dim3(kBlock), 0, g->stream, D.thist, D.thist_c, D.tstate, keff);
+    timing_end(g, K_TOPK_FIND, ev);
     timing_begin(g, K_TOPK_COLLECT, &ev);
     hipLaunchKernelGGL(k_topk_collect, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.R,
-                       D.new2old, D.alive, D.n, D.tstate, D.tfinal, D.ttie);
+                       D.new2old, D.alive, D.n, D.tstate, D.tfinal, D.ttie, D.thist);
     timing_end(g, K_TOPK_COLLECT, ev);
+    // common path: one workgroup ranks the candidates into a compact device
+    // block [flag | ids | scores], copied once into pinned host memory
+    if (g->hpin_cap < keff) {
+        if (g->hpin) (void)hipHostFree(g->hpin);
+        g->hpin = nullptr;
+        g->hpin_cap = 0;
+        const hipError_t ea = hipHostMalloc(&g->hpin, 16 + 16 * (size_t)keff, hipHostMallocDefault);
+        if (ea != hipSuccess) {
+            g->hpin = nullptr;
+            return hip_fail(ea, "pinned top-k buffer");
+        }
+        g->hpin_cap = keff;
+    }
+    const size_t sc_off = 16 + ((4 * (size_t)keff + 7) & ~(size_t)7);
+    char *dblk = D.tblk;
     timing_begin(g, K_TOPK_RANK, &ev);
     hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, g->stream, D.tstate, D.tfinal, D.ttie, keff, D.R,
-                       D.new2old, D.tout_ids, D.tout_sc);
+                       D.new2old, (int32_t *)(dblk + 16), (double *)(dblk + sc_off), (unsigned int *)dblk);
     timing_end(g, K_TOPK_RANK, ev);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "top-k launch");
-    TopkState st;
-    e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = copy_out(g, keff, ids, scores);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->hpin, dblk, sc_off + 8 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return hip_fail(e, "top-k state read");
-    if (st.small) return RS_OK;
+    if (e != hipSuccess) return hip_fail(e, "top-k");
+    if (*(const unsigned int *)g->hpin) {
+        memcpy(ids, (const char *)g->hpin + 16, 4 * (size_t)keff);
+        memcpy(scores, (const char *)g->hpin + sc_off, 8 * (size_t)keff);
+        return RS_OK;
+    }
+    TopkState st;
 
     // General path: rank the tie class pairwise, then order the final list.
     timing_begin(g, K_TOPK_TIE, &ev);

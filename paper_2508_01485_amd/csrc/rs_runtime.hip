@@ -74,6 +74,9 @@ static void release(rs_graph *g) {
     if (!g) return;
     for (void *p : g->allocations) (void)hipFree(p);
     g->allocations.clear();
+    if (g->hpin) (void)hipHostFree(g->hpin);
+    g->hpin = nullptr;
+    g->hpin_cap = 0;
     for (hipEvent_t e : g->timing.pool) (void)hipEventDestroy(e);
     for (auto &pe : g->timing.pending) {
         (void)hipEventDestroy(pe.second.first);
@@ -367,6 +370,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.part_score, sizeof(ScorePart) * std::max(g->grid_score, 1)},
         {(void **)&D.ctr, sizeof(DevCounters)},
         {(void **)&D.thist, 4 * (size_t)kTopkBins},
+        {(void **)&D.thist_c, 4 * 256},
         {(void **)&D.tstate, sizeof(TopkState)},
         {(void **)&D.tfinal, sizeof(TopkKey) * N},
         {(void **)&D.ttie, sizeof(TopkKey) * N},
@@ -374,6 +378,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.tout_ids, 4 * N},
         {(void **)&D.tout_sc, 8 * N},
         {(void **)&D.scratch_d, 8 * N},
+        {(void **)&D.tblk, 16 + 16 * N},
         {(void **)&D.scratch_u, 8 * 8},
     };
     for (auto &r : reqs) {
@@ -408,6 +413,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (e == hipSuccess) e = hipMemsetAsync(D.hub_cnt, 0, 4 * nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.thist_c, 0, 4 * 256, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
     if (e == hipSuccess) e = hipMemsetAsync(D.tstate, 0, sizeof(TopkState), s);
     if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * std::max(g->grid_score, 1), s);
