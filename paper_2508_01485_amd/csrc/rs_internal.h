@@ -80,6 +80,21 @@ struct __align__(16) VMeta {
     int deg, ell, p, q;
 };
 
+// Everything a pass needs about a vertex as a neighbour, in one 64-byte
+// card (one memory line for a gathered neighbour): the static row and
+// out-list ranges and community, and the last pass's row facts, a_v and the
+// first record keys (INT_MAX past ell).
+struct __align__(64) VCard {
+    long long off;  // row start
+    long long oo;   // out-list start
+    VMeta m;        // {deg, ell, p, q} of the last pass
+    int on;         // out-list length (tombstones included)
+    int lab;        // community
+    double a;       // cbrt(own-community weight) of the last pass
+    int key[4];     // first record keys of the last pass
+};
+static_assert(sizeof(VCard) == 64, "one card per 64 bytes");
+
 // A row tile: vertices [v0, v1) whose rows occupy entries [e0, e0 + te).
 struct __align__(16) RowTile {
     long long e0;
@@ -156,8 +171,8 @@ struct DeviceGraph {
     int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
-    VMeta *meta = nullptr;      // [n]
-    double *wown = nullptr, *a = nullptr, *R = nullptr;
+    VCard *card = nullptr;      // [n]
+    double *wown = nullptr, *R = nullptr;
     long long *tI = nullptr, *tII = nullptr;
     RowPart *part_rows = nullptr;    // [row grid]
     ScorePart *part_score = nullptr; // [score grid]

@@ -92,8 +92,9 @@ struct RowArgs {
     int n_tiles, n_hubs, tiles_per_xcd;
     int32_t *reckey;
     RecDat *recdat;
-    VMeta *meta;
-    double *wown, *a, *R;
+    VCard *card;
+    const int64_t *oo;
+    double *wown, *R;
     long long *tI, *tII;
     RowPart *part;
 };
@@ -108,18 +109,29 @@ struct RowAcc {
     unsigned long long nb, dp, ell, ellx;
 };
 
+// The vertex's row facts of this pass: its card (row facts, a_v, first four
+// record keys k4), own weight, and zero scores for a non-border vertex.
 template <typename OffT>
-__device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d, const RowResult &r, RowAcc &acc) {
+__device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d, const RowResult &r, int4 k4,
+                                           long long off, long long oo, int on, int lab, RowAcc &acc) {
     const int fown = r.q - r.p;
     const int dprime = d - fown;
-    VMeta m;
-    m.deg = d;
-    m.ell = r.ell;
-    m.p = r.p;
-    m.q = r.q;
-    A.meta[v] = m;
+    VCard c;  // written whole: one aligned 64-byte store, no partial lines
+    c.off = off;
+    c.oo = oo;
+    c.m.deg = d;
+    c.m.ell = r.ell;
+    c.m.p = r.p;
+    c.m.q = r.q;
+    c.on = on;
+    c.lab = lab;
+    c.a = cbrt(r.wown);
+    c.key[0] = k4.x;
+    c.key[1] = k4.y;
+    c.key[2] = k4.z;
+    c.key[3] = k4.w;
+    A.card[v] = c;
     A.wown[v] = r.wown;
-    A.a[v] = cbrt(r.wown);
     acc.wmax = fmax(acc.wmax, r.lmax);
     acc.ell += (unsigned long long)r.ell;
     acc.ellx += (unsigned long long)(r.ell - (fown > 0 ? 1 : 0));
@@ -236,17 +248,21 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
         L[i] = e < TE ? A.col[e0 + e] : -2;
     }
-    int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU];
+    int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU], von[kVU];
+    long long voo[kVU];
 #pragma unroll
     for (int j = 0; j < kVU; ++j) {
         const int i = tid + j * kBlock;
-        vo[j] = vc[j] = vdeg[j] = vlab[j] = 0;
+        vo[j] = vc[j] = vdeg[j] = vlab[j] = von[j] = 0;
+        voo[j] = 0;
         if (i < nv) {
             const OffT a0 = A.off[v0 + i], a1 = A.off[v0 + i + 1];
             vo[j] = (int)(a0 - e0);
             vc[j] = (int)(a1 - a0);
             vdeg[j] = A.deg[v0 + i];
             vlab[j] = A.lab[v0 + i];
+            voo[j] = A.oo[v0 + i];
+            von[j] = (int)(A.oo[v0 + i + 1] - voo[j]);
         }
     }
 #pragma unroll
@@ -330,7 +346,12 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         res.q = below + fown;
         res.wown = fown > 0 ? weight_present_t(S.tab, d, X, ell, fown) : weight_absent_t(S.tab, d, X, ell);
         res.lmax = res.wown;
-        finish_row(A, v0 + i, d, res, acc);
+        int4 k4;  // the first record keys: the labels of the first valid runs
+        k4.x = ell > 0 ? S.runlab[rf] : INT_MAX;
+        k4.y = ell > 1 ? S.runlab[rf + 1] : INT_MAX;
+        k4.z = ell > 2 ? S.runlab[rf + 2] : INT_MAX;
+        k4.w = ell > 3 ? S.runlab[rf + 3] : INT_MAX;
+        finish_row(A, v0 + i, d, res, k4, (long long)e0 + o, voo[j], von[j], cv, acc);
     }
     __syncthreads();
     for (int r = tid; r < total; r += kBlock) {
@@ -515,7 +536,7 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
     const int ell = S.hub.nruns;
     __syncthreads();  // everyone has read pass 1's totals before pass 2 resets them
     hub_pass<2, OffT>(A, S, rb, d, cv, X, ell, xpart, below, fown, lmax);
-    const double lm = block_max_d(lmax, S.hub.red);
+    const double lm = block_max_d(lmax, S.hub.red);  // (its barriers order pass 2's record writes)
     if (threadIdx.x == 0) {
         RowResult r;
         r.ell = ell;
@@ -523,7 +544,12 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
         r.q = p + fo;
         r.wown = fo > 0 ? weight_present(d, X, ell, fo) : weight_absent(d, X, ell);
         r.lmax = fmax(lm, r.wown);
-        finish_row(A, v, d, r, acc);
+        int4 k4;
+        k4.x = ell > 0 ? A.reckey[rb + 0] : INT_MAX;
+        k4.y = ell > 1 ? A.reckey[rb + 1] : INT_MAX;
+        k4.z = ell > 2 ? A.reckey[rb + 2] : INT_MAX;
+        k4.w = ell > 3 ? A.reckey[rb + 3] : INT_MAX;
+        finish_row(A, v, d, r, k4, (long long)rb, A.oo[v], (int)(A.oo[v + 1] - A.oo[v]), cv, acc);
     }
 }
 
@@ -640,12 +666,10 @@ struct ScoreArgs {
     int n_chunks, n_chunks_lds;
     HubPart *hub_part;
     unsigned int *hub_cnt;
-    const int64_t *oo;
     const int32_t *outl;
     const int32_t *reckey;
     const RecDat *recdat;
-    const VMeta *meta;
-    const double *a;
+    const VCard *card;
     double *R;
     long long *tI, *tII;
     const DevCounters *ctr;
@@ -737,22 +761,24 @@ struct PairRes {
 //            at u is found by exactly one of its two pairs -- each adding
 //            both ordered triads (w, y) and (y, w):
 //              cbrt(w_y(C(u)) w_w(C(y)) w_w(C(u))) + cbrt(w_w(C(u)) w_y(C(w)) w_y(C(u))).
-template <class UV, typename OffT>
-__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, int cw, long long ow,
-                              const VMeta &mw, long long o0, long long o1) {
-    PairRes out = {0.0, 0, 0};
-    const int ellw = mw.ell;
-    const int32_t *kw = A.reckey + ow;
-    int s = -1;
-    if (ellw <= 16) {
+// Slot of community c among a vertex's record keys: the card's first four
+// keys, else a 16-ary search of the key array (-1 if absent).
+__device__ __forceinline__ int card_find(const VCard &c, const int32_t *reckey, int x) {
+    if (c.m.ell <= 4) {
+        int sl = -1;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int key = j < ellw ? kw[j] : INT_MAX;
-            if (key == cu) s = j;
-        }
-    } else {
-        s = kfind(kw, ellw, cu);
+        for (int j = 0; j < 4; ++j)
+            if (c.key[j] == x) sl = j;
+        return sl;
     }
+    return kfind(reckey + c.off, c.m.ell, x);
+}
+
+template <class UV, typename OffT>
+__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, const VCard &cw_) {
+    PairRes out = {0.0, 0, 0};
+    const long long ow = cw_.off;
+    const int s = card_find(cw_, A.reckey, cu);
     if (s < 0) return out;  // cannot happen: u is a neighbour of w
     const RecDat rd = A.recdat[ow + s];
     const double W = rd.w;
@@ -766,13 +792,14 @@ __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int 
             for (int t = 0; t < 8; ++t) x[t] = i + t < rd.f ? run[i + t] : u;
             double av[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.a[x[t]] : 0.0;
+            for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.card[x[t]].a : 0.0;
 #pragma unroll
             for (int t = 0; t < 8; ++t) S += av[t];
         }
         const double c1 = cbrt(W);
         out.val = c1 * c1 * S;
     }
+    const long long o0 = cw_.oo, o1 = cw_.oo + cw_.on;
     for (long long j0 = o0; j0 < o1; j0 += 4) {
         int y[4];
 #pragma unroll
@@ -785,14 +812,12 @@ __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int 
             const int t = __builtin_ctz(hm);
             hm &= hm - 1u;
             const int v = A.outl[j0 + t];
-            const int cv = A.lab[v];
-            const long long ov = (long long)A.off[v];
-            const int ellv = A.meta[v].ell;
-            const int s1 = kfind(A.reckey + ov, ellv, cu);
-            const int s2 = kfind(A.reckey + ov, ellv, cw);
-            const int s3 = kfind(kw, ellw, cv);
-            const double w_vu = s1 >= 0 ? A.recdat[ov + s1].w : 0.0;
-            const double w_vw = s2 >= 0 ? A.recdat[ov + s2].w : 0.0;
+            const VCard cv = A.card[v];
+            const int s1 = card_find(cv, A.reckey, cu);
+            const int s2 = card_find(cv, A.reckey, cw_.lab);
+            const int s3 = card_find(cw_, A.reckey, cv.lab);
+            const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
+            const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
             const double w_wv = s3 >= 0 ? A.recdat[ow + s3].w : 0.0;
             out.val += cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
             out.t1 += 2;
@@ -923,12 +948,13 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         hub = hc.x;
         chunk = hc.y;
         hu = A.hubs[hub];
-        const VMeta m = A.meta[hu];
-        const long long ou = (long long)A.off[hu];
+        const VCard ch = A.card[hu];
+        const VMeta m = ch.m;
+        const long long ou = ch.off;
         const int h = m.q - m.p;
         hdeg = m.deg;
         hdp = m.deg - h;  // <= the load-time count, which fits kHubList
-        hcu = A.lab[hu];
+        hcu = ch.lab;
         for (int j = tid; j < hdp; j += kBlock) S.w[j] = A.col[ou + (j < m.p ? j : j + h)];
         total = min(kBlock, max(0, hdp - chunk * kBlock));
         __syncthreads();
@@ -938,11 +964,12 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         nv = tl.y - tl.x;
         if (tid < nv) {
             const int v = v0 + tid;
-            const VMeta m = A.meta[v];
+            const VCard cv = A.card[v];
+            const VMeta m = cv.m;
             deg = m.deg;
             dp = m.deg - (m.q - m.p);
-            S.ou[tid] = (long long)A.off[v];
-            S.cu[tid] = A.lab[v];
+            S.ou[tid] = cv.off;
+            S.cu[tid] = cv.lab;
             S.p[tid] = m.p;
             S.h[tid] = m.q - m.p;
         }
@@ -982,12 +1009,9 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             cu = S.cu[i];
         }
         const int w = S.w[k];
-        const long long ow = (long long)A.off[w];
-        const VMeta mw = A.meta[w];
-        const int cw = A.lab[w];
-        const long long o0 = A.oo[w], o1 = A.oo[w + 1];
-        sa.workI += min(U.pe - U.pb, mw.deg - (mw.q - mw.p));
-        r = score_pair(A, U, u, cu, w, cw, ow, mw, o0, o1);
+        const VCard cw = A.card[w];
+        sa.workI += min(U.pe - U.pb, cw.m.deg - (cw.m.q - cw.m.p));
+        r = score_pair(A, U, u, cu, w, cw);
     }
     // ---- epilogue: sums in a fixed order
     if (!hub_unit) {
@@ -1022,11 +1046,12 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
                               ScoreAcc &sa) {
     const int tid = threadIdx.x;
     const int u = A.hubs[hub];
-    const VMeta m = A.meta[u];
-    const long long ou = (long long)A.off[u];
+    const VCard cu_ = A.card[u];
+    const VMeta m = cu_.m;
+    const long long ou = cu_.off;
     const int h = m.q - m.p;
     const int dp = m.deg - h;
-    const int cu = A.lab[u];
+    const int cu = cu_.lab;
     HubU U;
     U.row = A.col + ou;
     U.p = m.p;
@@ -1036,11 +1061,9 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     PairRes r = {0.0, 0, 0};
     if (k < dp) {
         const int w = U.list_at(k);
-        const long long ow = (long long)A.off[w];
-        const VMeta mw = A.meta[w];
-        const int cw = A.lab[w];
-        sa.workI += min(dp, mw.deg - (mw.q - mw.p));
-        r = score_pair(A, U, u, cu, w, cw, ow, mw, A.oo[w], A.oo[w + 1]);
+        const VCard cw = A.card[w];
+        sa.workI += min(dp, cw.m.deg - (cw.m.q - cw.m.p));
+        r = score_pair(A, U, u, cu, w, cw);
     }
     chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
     if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, u, m.deg, dp, wmax, sa);
@@ -1151,9 +1174,9 @@ static rs_status score_pass_t(rs_graph *g) {
     A.tiles_per_xcd = (g->n_rtiles + 7) / 8;
     A.reckey = D.reckey;
     A.recdat = D.recdat;
-    A.meta = D.meta;
+    A.card = D.card;
+    A.oo = D.oo;
     A.wown = D.wown;
-    A.a = D.a;
     A.R = D.R;
     A.tI = D.tI;
     A.tII = D.tII;
@@ -1182,12 +1205,10 @@ static rs_status score_pass_t(rs_graph *g) {
     S.n_chunks_lds = g->n_schunks_lds;
     S.hub_part = D.hub_part;
     S.hub_cnt = D.hub_cnt;
-    S.oo = D.oo;
     S.outl = D.outl;
     S.reckey = D.reckey;
     S.recdat = D.recdat;
-    S.meta = D.meta;
-    S.a = D.a;
+    S.card = D.card;
     S.R = D.R;
     S.tI = D.tI;
     S.tII = D.tII;

@@ -360,9 +360,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
-        {(void **)&D.meta, sizeof(VMeta) * N},
+        {(void **)&D.card, sizeof(VCard) * N},
         {(void **)&D.wown, 8 * N},
-        {(void **)&D.a, 8 * N},
         {(void **)&D.R, 8 * N},
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
@@ -408,6 +407,22 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
     put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
     put(D.oo, H.oo.data(), 8 * H.oo.size());
+    std::vector<VCard> cards;
+    try {
+        cards.resize(n);
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host allocation failed while building vertex cards");
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        VCard &c = cards[v];
+        memset(&c, 0, sizeof(c));
+        c.off = H.off[v];
+        c.oo = H.oo[v];
+        c.on = (int)(H.oo[v + 1] - H.oo[v]);
+        c.lab = H.lab[v];
+    }
+    put(D.card, cards.data(), sizeof(VCard) * cards.size());
+    if (e == hipSuccess && n) e = hipStreamSynchronize(s);  // the host cards must outlive the copy
     put(D.outl, H.outl.data(), 4 * H.outl.size());
     put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.hub_cnt, 0, 4 * nsh, s);
@@ -462,6 +477,19 @@ static rs_status load_t(const rs_csr *csr, rs_graph *g) {
         g->own_stream = true;
     }
     return upload(g, H, n, nnz);
+}
+
+template <class T>
+static hipError_t d2h(std::vector<T> &dst, const void *src, int64_t count);
+
+// The last pass's row facts {deg, ell, p, q} of every vertex (internal ids).
+static hipError_t read_meta(rs_graph *g, std::vector<VMeta> &meta) {
+    std::vector<VCard> cards;
+    const hipError_t e = d2h(cards, g->d.card, g->d.n);
+    if (e != hipSuccess) return e;
+    meta.resize(cards.size());
+    for (size_t v = 0; v < cards.size(); ++v) meta[v] = cards[v].m;
+    return hipSuccess;
 }
 
 template <class T>
@@ -684,7 +712,7 @@ rs_status rs_read_vertex_counts(rs_graph *g, int32_t *border, int32_t *ell, int3
     std::vector<VMeta> meta;
     std::vector<long long> htI, htII;
     std::vector<double> hw;
-    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
+    if (e == hipSuccess) e = read_meta(g, meta);
     if (e == hipSuccess) e = d2h(htI, g->d.tI, n);
     if (e == hipSuccess) e = d2h(htII, g->d.tII, n);
     if (e == hipSuccess) e = d2h(hw, g->d.wown, n);
@@ -711,7 +739,7 @@ rs_status rs_read_rows(rs_graph *g, int64_t *row_off, int32_t *comm, int32_t *co
     hipError_t e = hipStreamSynchronize(g->stream);
     std::vector<VMeta> meta;
     std::vector<int64_t> off;
-    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
+    if (e == hipSuccess) e = read_meta(g, meta);
     if (e == hipSuccess) e = read_offsets(g, off);
     if (e != hipSuccess) return hip_fail(e, "row copy");
     row_off[0] = 0;
@@ -745,7 +773,7 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
     std::vector<VMeta> meta;
     std::vector<int32_t> hcol;
     std::vector<int64_t> off;
-    if (e == hipSuccess) e = d2h(meta, g->d.meta, n);
+    if (e == hipSuccess) e = read_meta(g, meta);
     if (e == hipSuccess) e = read_offsets(g, off);
     if (e != hipSuccess) return hip_fail(e, "G' copy");
     goff[0] = 0;
