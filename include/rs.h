@@ -72,11 +72,15 @@ typedef struct {
  * a handle.  Returns only after the copies are complete.
  *   hip_stream  a hipStream_t to run all of this graph's work on, or NULL for
  *               a library-owned stream
- *   flags       must be 0
+ *   flags       0, or RS_LOAD_WIDE_OFFSETS: keep 64-bit edge offsets on the
+ *               device even when nnz fits 32 bits (they are used anyway when
+ *               nnz > INT32_MAX; the flag lets small graphs run that form)
  * Errors: RS_ERR_ARG, RS_ERR_GRAPH (asymmetric / unsorted / duplicate / self
  * loop / negative label), RS_ERR_RANGE, RS_ERR_NOMEM, RS_ERR_HIP.  *out is
  * set to NULL on error.
  */
+#define RS_LOAD_WIDE_OFFSETS 1u
+
 rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_graph **out);
 
 /*

@@ -25,6 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librs.so")
 
 RS_OK, RS_ERR_ARG, RS_ERR_GRAPH, RS_ERR_RANGE, RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_STATE = range(7)
+RS_LOAD_WIDE_OFFSETS = 1  # 64-bit device edge offsets even when nnz fits 32 bits
 
 
 class RSError(RuntimeError):

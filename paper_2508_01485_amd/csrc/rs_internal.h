@@ -204,6 +204,7 @@ struct rs_graph {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool scored = false;
+    bool wide_offsets = false;  // 64-bit device edge offsets even for nnz <= INT32_MAX
     int64_t n_alive = 0;
     int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0, n_schunks = 0;
     int n_schunks_lds = 0;               // chunks of hubs whose foreign list fits in LDS (listed first)

@@ -324,7 +324,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     D.n = n;
     D.nnz = nnz;
     D.k = (int32_t)H.comm2orig.size();
-    D.off64 = nnz > (int64_t)INT32_MAX;
+    D.off64 = nnz > (int64_t)INT32_MAX || g->wide_offsets;
     const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
     const size_t offb = D.off64 ? 8 : 4;
     g->n_rtiles = (int)H.rtiles.size();
@@ -535,7 +535,7 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     if (!out) return fail(RS_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!csr) return fail(RS_ERR_ARG, "csr is NULL");
-    if (flags != 0) return fail(RS_ERR_ARG, "flags must be 0");
+    if ((flags & ~RS_LOAD_WIDE_OFFSETS) != 0) return fail(RS_ERR_ARG, "unknown flags");
     if (csr->n < 0 || csr->nnz < 0) return fail(RS_ERR_ARG, "negative n or nnz");
     if (csr->offset_bytes != 4 && csr->offset_bytes != 8) return fail(RS_ERR_ARG, "offset_bytes must be 4 or 8");
     if (csr->on_device != 0 && csr->on_device != 1) return fail(RS_ERR_ARG, "on_device must be 0 or 1");
@@ -548,6 +548,7 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     rs_graph *g = new (std::nothrow) rs_graph();
     if (!g) return fail(RS_ERR_NOMEM, "handle allocation failed");
     g->stream = (hipStream_t)hip_stream;  // NULL: created after validation
+    g->wide_offsets = (flags & RS_LOAD_WIDE_OFFSETS) != 0;
     rs_status st = csr->offset_bytes == 8 ? load_t<int64_t>(csr, g) : load_t<int32_t>(csr, g);
     if (st != RS_OK) {
         std::string keep = g_err;

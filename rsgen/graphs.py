@@ -22,9 +22,46 @@ available here):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
+
+_PAR_MIN = 1 << 22  # arrays shorter than this are sorted in one call
+
+
+def _sort_keys(x, hi: int):
+    """Ascending copy of non-negative int64 keys below ``hi`` (same result as
+    ``np.sort``).  Large arrays are split into 64 value ranges by a stable
+    radix pass on the top key bits and the ranges are sorted in threads."""
+    x = np.asarray(x, dtype=np.int64)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    if x.size < _PAR_MIN or threads == 1 or hi <= 64:
+        return np.sort(x)
+    shift = max(0, int(hi - 1).bit_length() - 6)
+    bucket = (x >> shift).astype(np.uint8)
+    cnt = np.bincount(bucket, minlength=64)
+    order = np.argsort(bucket, kind="stable")
+    del bucket
+    xs = x[order]
+    del order
+    ends = np.cumsum(cnt)
+    starts = ends - cnt
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda i: xs[starts[i]:ends[i]].sort(), range(64)))
+    return xs
+
+
+def _unique_keys(x, hi: int):
+    """Sorted distinct values of non-negative int64 keys below ``hi``."""
+    s = _sort_keys(x, hi)
+    if s.size < 2:
+        return s
+    keep = np.empty(s.size, dtype=bool)
+    keep[0] = True
+    np.not_equal(s[1:], s[:-1], out=keep[1:])
+    return s[keep]
 
 
 @dataclass
@@ -63,14 +100,13 @@ def canonical_csr(n: int, u, v):
     a = np.minimum(u, v)
     b = np.maximum(u, v)
     del u, v, keep
-    key = np.unique(a * n + b)
+    key = _unique_keys(a * n + b, n * n)
     del a, b
     a = key // n
     b = key - a * n
     del key
-    both = np.concatenate([a * n + b, b * n + a])
+    both = _sort_keys(np.concatenate([a * n + b, b * n + a]), n * n)
     del a, b
-    both.sort()
     src = both // n
     dst = (both - src * n).astype(np.int32)
     del both
@@ -203,7 +239,11 @@ def _pair_internal(rng, stubs, comm):
         return np.zeros(0, np.int64)
     n = comm.size
     stubs = stubs[rng.permutation(stubs.size)]
-    stubs = stubs[np.argsort(comm[stubs], kind="stable")]
+    key = comm[stubs]
+    if comm.size and int(comm.max()) < 65536:
+        key = key.astype(np.uint16)  # the stable sort of 16-bit keys is a radix sort
+    stubs = stubs[np.argsort(key, kind="stable")]
+    del key
     sc = comm[stubs]
     gstart = np.flatnonzero(np.r_[True, sc[1:] != sc[:-1]])
     glen = np.diff(np.r_[gstart, sc.size])
@@ -237,17 +277,19 @@ def _union_keys(keys, add, n):
     """Sorted union of edge-key sets (duplicates dropped)."""
     if add.size == 0:
         return keys
-    add = np.unique(add)
-    if keys.size:
-        pos = np.searchsorted(keys, add)
-        pos = np.minimum(pos, keys.size - 1)
-        add = add[keys[pos] != add]
-    return np.union1d(keys, add) if keys.size else add
+    add = _unique_keys(add, n * n)
+    if keys.size == 0:
+        return add
+    pos = np.searchsorted(keys, add)
+    pos_c = np.minimum(pos, keys.size - 1)
+    new = keys[pos_c] != add
+    # both sorted and disjoint: insert the new keys at their positions
+    return np.insert(keys, pos[new], add[new])
 
 
 def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
         tau1: float = 2.5, tau2: float = 1.5, cmin: int = 50, cmax: int = 20000,
-        ext_rounds: int = 12, repair_rounds: int = 4) -> Graph:
+        ext_rounds: int = 12, repair_rounds: int = 4, log=None) -> Graph:
     """LFR-style graph.
 
     Steps: (1) degrees i.i.d. as floor(X), X from the power law x^-tau1 on
@@ -263,8 +305,10 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
     community, external stubs uniformly at random across the graph with
     same-community pairs rejected and redrawn for a bounded number of rounds;
     (7) self-loops and multi-edges are removed; (8) vertex ids and community
-    ids are randomly permuted.  Realised statistics go to ``meta``.
+    ids are randomly permuted.  Realised statistics go to ``meta``.  ``log``,
+    if given, is called with a short message after each stage.
     """
+    say = log if log is not None else (lambda msg: None)
     rng = np.random.default_rng(seed)
     x0 = _solve_x0(mean_deg, max_deg, tau1)
     deg = _floor_powerlaw(rng, n, x0, max_deg, tau1)
@@ -304,10 +348,13 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
     k_in = k_in - over
     k_ext = k_ext + over
 
+    say(f"lfr: degrees and {nc} communities drawn")
     keys = _union_keys(np.zeros(0, np.int64),
                        _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), k_in), comm), n)
+    say(f"lfr: {keys.size} internal edges paired")
     ext_keys, left = _pair_external(rng, np.repeat(np.arange(n, dtype=np.int64), k_ext), comm, ext_rounds)
     keys = _union_keys(keys, ext_keys, n)
+    say(f"lfr: {keys.size} edges after external pairing")
     # repair rounds: stubs lost to self-loops / multi-edges are paired again
     for _ in range(repair_rounds):
         a = keys // n
@@ -323,12 +370,15 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
         add = _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), def_in), comm)
         add_e, _ = _pair_external(rng, np.repeat(np.arange(n, dtype=np.int64), def_ext), comm, ext_rounds)
         keys = _union_keys(keys, np.concatenate([add, add_e]), n)
+        say(f"lfr: {keys.size} edges after a repair round")
     u = keys // n
     v = keys - u * n
     del keys
     off, col = canonical_csr(n, u, v)
     del u, v
+    say("lfr: CSR built")
     off, col, labels = _relabel(rng, n, off, col, comm.astype(np.int32))
+    say("lfr: ids permuted")
     g = Graph(n, off, col, labels, meta={
         "kind": "lfr", "seed": seed, "n": n, "mean_deg_target": mean_deg, "max_deg": max_deg,
         "mu_target": mu, "x_min": x0, "communities": int(nc)})
@@ -383,12 +433,12 @@ def cfg_sbm_small(seed: int = 0) -> Graph:
     return sbm([100] * 20, 0.05, 0.001, seed)
 
 
-def cfg_lfr_1m(seed: int = 0) -> Graph:
+def cfg_lfr_1m(seed: int = 0, log=None) -> Graph:
     """LFR-style: n=1e6, degree law exponent 2.5, mean 20, max 5,000, sizes
     exponent 1.5 on [50, 20,000], mixing 0.1."""
-    return lfr(1_000_000, 20.0, 5000, 0.1, seed)
+    return lfr(1_000_000, 20.0, 5000, 0.1, seed, log=log)
 
 
-def cfg_lfr_20m(seed: int = 0) -> Graph:
+def cfg_lfr_20m(seed: int = 0, log=None) -> Graph:
     """LFR-style: n=2e7, mean degree 30, max 100,000, mixing 0.15 (same size law)."""
-    return lfr(20_000_000, 30.0, 100_000, 0.15, seed)
+    return lfr(20_000_000, 30.0, 100_000, 0.15, seed, log=log)

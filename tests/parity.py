@@ -15,9 +15,9 @@ W_REL = 1e-9     # weights: closed form of Eq. H_optimal vs the direct entropy s
 TIE_REL = 1e-9
 
 
-def gpu_run(g, k, stream=None):
+def gpu_run(g, k, stream=None, flags=0):
     import paper_2508_01485_amd as rs
-    h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream)
+    h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream, flags=flags)
     try:
         rs.rs_score(h)
         ids, sc = rs.rs_topk(h, k)

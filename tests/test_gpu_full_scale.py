@@ -1,0 +1,81 @@
+"""Parity at the LFR-style n=2e7 (~290M edges) size, in the launch form the
+benchmark times: every per-vertex integer (border, ell, d') and the own
+weight for all 2e7 vertices against the oracle's rows; R, tI and tII on
+sampled vertices (random ones, the highest-degree ones and the returned
+top ids) against the oracle's per-vertex scores; the top-k list checked by
+properties that hold at any size.
+
+Generating the graph takes several minutes of host time, so the test runs
+only when RS_FULL_SCALE=1 is set.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from rsgen import cfg_lfr_20m
+from tests.parity import rel_close
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("RS_FULL_SCALE") != "1",
+                                 reason="full-scale case (minutes of graph generation): set RS_FULL_SCALE=1")]
+
+K = 10_000
+
+
+def _say(*a):
+    print("[full-scale]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def test_lfr_20m_sampled_parity():
+    import paper_2508_01485_amd as rs
+    import torch
+
+    g = cfg_lfr_20m(0, log=_say)
+    _say(f"graph n={g.n} m={g.m} nnz={g.nnz}")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream)
+    try:
+        rs.rs_score(h)
+        ids, sc = rs.rs_topk(h, K)
+        R = rs.rs_read_scores(h)
+        vc = rs.rs_read_vertex_counts(h)
+        cnt = rs.rs_read_counts(h)
+    finally:
+        h.free()
+    _say("GPU pass done")
+
+    # top-k by properties: sorted (R desc, id asc), scores are R, nothing left out
+    assert ids.size == min(K, g.n)
+    assert np.array_equal(sc, R[ids])
+    order = np.lexsort((ids, -sc))
+    assert np.array_equal(order, np.arange(ids.size))
+    rest = np.ones(g.n, bool)
+    rest[ids] = False
+    last_s, last_id = sc[-1], ids[-1]
+    assert not np.any(R[rest] > last_s)
+    assert not np.any((R[rest] == last_s) & (np.flatnonzero(rest) < last_id))
+
+    # oracle: every row (so all per-vertex integers and weights), scores on a sample
+    rng = np.random.default_rng(2024)
+    deg = np.diff(g.off)
+    sample = np.unique(np.concatenate([rng.choice(g.n, 4000, replace=False),
+                                       np.argsort(-deg, kind="stable")[:200], ids[:300]]))
+    _say(f"oracle on {sample.size} sampled vertices")
+    ora = oracle.score(g, subset=sample, nthreads=16)
+    _say("oracle done")
+    assert np.array_equal(vc["border"].astype(np.uint8), ora["border"])
+    assert np.array_equal(vc["ell"], ora["ell"])
+    assert np.array_equal(vc["dprime"], ora["dprime"])
+    rel_close(vc["w_own"], ora["w_own"], 1e-9)
+    assert cnt["n_border"] == ora["n_border"]
+    assert cnt["m_inter"] == ora["m_inter"]
+    assert abs(cnt["omega_max"] - ora["omega_max"]) <= 1e-12 * ora["omega_max"]
+    assert np.array_equal(vc["tI"][sample], ora["tI"][sample])
+    assert np.array_equal(vc["tII"][sample], ora["tII"][sample])
+    rel_close(R[sample], ora["R"][sample], 1e-6)
+    _say(f"ok: {sample.size} sampled scores, all {g.n} rows")

@@ -23,9 +23,9 @@ def rs():
     return m
 
 
-def _check(g, k, name):
-    _say(f"[parity] {name}: n={g.n} nnz={g.nnz} k={k}")
-    gpu = gpu_run(g, k)
+def _check(g, k, name, flags=0):
+    _say(f"[parity] {name}: n={g.n} nnz={g.nnz} k={k} flags={flags}")
+    gpu = gpu_run(g, k, flags=flags)
     ora = oracle.score(g, rows=True)
     diag = compare(g, gpu, ora, k)
     _say(f"[parity] {name}: ok {diag}")
@@ -117,6 +117,46 @@ def test_score_hub_beyond_lds_staging(rs):
     hubs += [(0, 1)]
     g = from_edges(n, np.concatenate([np.stack([u, v], 1), np.array(hubs)]), labels)
     _check(g, 60, "score hubs beyond LDS")
+
+
+def test_wide_offsets_path(rs):
+    """The 64-bit edge-offset kernels (used for nnz > 2^31) on small graphs:
+    row hubs, score hubs beyond LDS staging, a triangle-rich LFR graph and
+    removals; integer results bit-identical to the 32-bit form."""
+    rng = np.random.default_rng(31)
+    n = 9000
+    labels = rng.integers(0, 3000, n)
+    base = random_small(n, 0.0005, 5, 131)
+    u, v = base.edges()
+    hubs = [(0, int(x)) for x in rng.choice(np.arange(1, n), 6000, replace=False)]
+    hubs += [(1, int(x)) for x in rng.choice(np.arange(2, n), 2600, replace=False)]
+    hubs += [(0, 1)]
+    g1 = from_edges(n, np.concatenate([np.stack([u, v], 1), np.array(hubs)]), labels)
+    g2 = lfr(20000, 16.0, 600, 0.2, seed=13, cmin=20, cmax=1500)
+    for name, g, k in (("hubs", g1, 40), ("lfr n=20000", g2, 100)):
+        wide, _, _ = _check(g, k, f"wide offsets, {name}", flags=rs.RS_LOAD_WIDE_OFFSETS)
+        narrow = gpu_run(g, k)
+        for key in ("border", "ell", "dprime", "tI", "tII", "ids"):
+            assert np.array_equal(wide[key], narrow[key]), key
+        rel_close(wide["R"], narrow["R"], 1e-12)
+    # removals on the wide form equal a fresh load of the mutated graph
+    gu, gv = g2.edges()
+    pick = rng.choice(gu.size, 300, replace=False)
+    h = rs.rs_load_graph(g2.off, g2.col, g2.labels, flags=rs.RS_LOAD_WIDE_OFFSETS)
+    rs.rs_score(h)
+    rs.rs_apply_removals(h, edges=np.stack([gu[pick], gv[pick]], 1), vertices=[5, 77])
+    c1 = rs.rs_read_vertex_counts(h)
+    R1 = rs.rs_read_scores(h)
+    h.free()
+    keep = np.ones(gu.size, bool)
+    keep[pick] = False
+    dead = np.zeros(g2.n, bool)
+    dead[[5, 77]] = True
+    keep &= ~dead[gu] & ~dead[gv]
+    g3 = from_edges(g2.n, np.stack([gu[keep], gv[keep]], 1), g2.labels)
+    ora = oracle.score(g3)
+    rel_close(R1, ora["R"], 1e-6)
+    assert np.array_equal(c1["tI"], ora["tI"]) and np.array_equal(c1["tII"], ora["tII"])
 
 
 def test_lfr_small(rs):
