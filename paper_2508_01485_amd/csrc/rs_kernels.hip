@@ -1258,54 +1258,85 @@ __device__ __forceinline__ unsigned int key_digit(const TopkKey &k, int j) {
     }
 }
 
-__device__ __forceinline__ TopkKey make_key(const double *R, const int32_t *new2old, int v) {
-    TopkKey k;
-    k.hi = dbits(R[v]) & 0x7fffffffffffffffull;  // scores are >= 0; never rank a -0.0 first
-    k.lo = 0xffffffffu - (unsigned int)new2old[v];
-    k.v = v;
-    return k;
+// A vertex's ranking key is (score bits, 0xffffffff - caller id), compared
+// as one 96-bit number.  Scores are >= 0; the sign bit is cleared so that a
+// -0.0 could never rank first.
+__device__ __forceinline__ unsigned long long score_bits(double r) {
+    return dbits(r) & 0x7fffffffffffffffull;
 }
 
-// Level-0 histogram: each block counts a contiguous chunk (< 2^16 keys) in an
-// LDS histogram of 16-bit counters packed two per word, then adds its
-// non-zero bins to the global histogram, and its sums of 256 consecutive
-// bins to a 256-bin coarse histogram.
-__global__ __launch_bounds__(kBlock) void k_topk_hist(const double *R, const int32_t *new2old, const uint8_t *alive,
-                                                      long long n, long long chunk, unsigned int *hist,
-                                                      unsigned int *coarse) {
-    __shared__ unsigned int sh[kTopkBins / 2];
-    for (int i = threadIdx.x; i < kTopkBins / 2; i += kBlock) sh[i] = 0u;
+// Level-0 digit: the top 16 bits of the key (score bits only).
+__device__ __forceinline__ unsigned int digit0_of(double r) { return (unsigned int)(score_bits(r) >> 48); }
+
+// Level-0 histogram: each block (1024 threads) counts a contiguous chunk
+// (< 2^16 keys) in an LDS histogram of 16-bit counters packed two per word
+// (digit 0, which holds every zero score, is counted in registers), then adds
+// its non-zero bins to the global histogram, and its sums of 256 consecutive
+// bins to a 256-bin coarse histogram.  Few large blocks keep the number of
+// global atomics (one per non-zero bin per block) small.
+constexpr int kHistThreads = 1024;
+__global__ __launch_bounds__(kHistThreads) void k_topk_hist(const double *R, const uint8_t *alive, long long n,
+                                                            long long chunk, unsigned int *hist,
+                                                            unsigned int *coarse) {
+    __shared__ uint4 sh4[kTopkBins / 8];
+    __shared__ unsigned int s_zero[kHistThreads / 64];
+    unsigned int *sh = (unsigned int *)sh4;
+    for (int i = threadIdx.x; i < kTopkBins / 8; i += kHistThreads) sh4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += 8 * kBlock) {
-        unsigned int dig[8];
-        bool ok[8];
+    unsigned int zeros = 0;
+    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += 8 * kHistThreads) {
+        double r[8];
+        uint8_t al[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const long long v = v0 + (long long)j * kBlock;
-            ok[j] = v < hi && alive[v];
-            dig[j] = ok[j] ? key_digit(make_key(R, new2old, (int)v), 0) : 0u;
+        for (int j = 0; j < 8; ++j) {  // independent loads, all in flight together
+            const long long v = v0 + (long long)j * kHistThreads;
+            r[j] = v < hi ? R[v] : 0.0;
+            al[j] = v < hi ? alive[v] : (uint8_t)0;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (ok[j]) atomicAdd(&sh[dig[j] >> 1], 1u << ((dig[j] & 1u) * 16u));
+        for (int j = 0; j < 8; ++j) {
+            if (!al[j]) continue;
+            const unsigned int dig = digit0_of(r[j]);
+            if (dig == 0u)
+                ++zeros;
+            else
+                atomicAdd(&sh[dig >> 1], 1u << ((dig & 1u) * 16u));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) zeros += __shfl_xor(zeros, o);
+    if ((threadIdx.x & 63) == 0) s_zero[threadIdx.x >> 6] = zeros;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int z = 0;
+        for (int w = 0; w < kHistThreads / 64; ++w) z += s_zero[w];
+        sh[0] += z;  // bin 0 is the low half of word 0 (z < 2^16: the chunk is smaller)
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kTopkBins / 2; i += kBlock) {
-        const unsigned int x = sh[i];
-        if (x & 0xffffu) atomicAdd(&hist[2 * i], x & 0xffffu);
-        if (x >> 16) atomicAdd(&hist[2 * i + 1], x >> 16);
+    for (int i = threadIdx.x; i < kTopkBins / 8; i += kHistThreads) {
+        const uint4 x = sh4[i];
+        const unsigned int w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (w[t] & 0xffffu) atomicAdd(&hist[8 * i + 2 * t], w[t] & 0xffffu);
+            if (w[t] >> 16) atomicAdd(&hist[8 * i + 2 * t + 1], w[t] >> 16);
+        }
     }
-    // coarse histogram: thread t sums fine bins [256 t, 256 t + 256) (words
-    // [128 t, 128 t + 128), visited in a skewed order to spread LDS banks)
-    static_assert(kTopkBins == 256 * kBlock, "one coarse bin per thread");
-    unsigned int cs = 0;
-    for (int j = 0; j < 128; ++j) {
-        const unsigned int x = sh[128 * threadIdx.x + ((j + threadIdx.x) & 127)];
-        cs += (x & 0xffffu) + (x >> 16);
+    // coarse histogram: thread t < 256 sums fine bins [256 t, 256 t + 256)
+    // (16-byte words [32 t, 32 t + 32), visited in a skewed order to spread
+    // LDS banks)
+    static_assert(kTopkBins == 256 * 256, "256 coarse bins of 256 fine bins");
+    if (threadIdx.x < 256) {
+        unsigned int cs = 0;
+        for (int j = 0; j < 32; ++j) {
+            const uint4 x = sh4[32 * threadIdx.x + ((j + threadIdx.x) & 31)];
+            cs += (x.x & 0xffffu) + (x.x >> 16) + (x.y & 0xffffu) + (x.y >> 16) + (x.z & 0xffffu) + (x.z >> 16) +
+                  (x.w & 0xffffu) + (x.w >> 16);
+        }
+        if (cs) atomicAdd(&coarse[threadIdx.x], cs);
     }
-    if (cs) atomicAdd(&coarse[threadIdx.x], cs);
 }
 
 // Level-0 threshold (one workgroup): reset the selection state for k, find
@@ -1461,33 +1492,71 @@ __device__ __forceinline__ void block_push(TopkKey *list, unsigned long long *co
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_topk_collect(const double *R, const int32_t *new2old, const uint8_t *alive,
-                                                         long long n, TopkState *st, TopkKey *fin, TopkKey *tie,
-                                                         unsigned int *hist) {
-    __shared__ unsigned int s_cnt[kBlock / 64];
-    __shared__ unsigned long long s_base;
+// Level-0 collect: keys above the threshold bin go to the final list, keys in
+// it to the tie list.  Each block (1024 threads) scans one contiguous chunk
+// and stages its keys in LDS, then reserves room in each list with one atomic
+// (keys beyond the staging capacity are reserved one by one).
+constexpr int kCollThreads = 1024;
+constexpr int kCollStage = 2048;  // staged keys per list and block
+__global__ __launch_bounds__(kCollThreads) void k_topk_collect(const double *R, const int32_t *new2old,
+                                                               const uint8_t *alive, long long n, long long chunk,
+                                                               TopkState *st, TopkKey *fin, TopkKey *tie,
+                                                               unsigned int *hist) {
+    __shared__ TopkKey sf[kCollStage], stl[kCollStage];
+    __shared__ unsigned int s_nf, s_nt;
+    __shared__ unsigned long long s_bf, s_bt;
     // the fine histogram is no longer needed: clear it for the next call
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < kTopkBins / 4; i += gridDim.x * kBlock)
+    for (int i = blockIdx.x * kCollThreads + threadIdx.x; i < kTopkBins / 4; i += gridDim.x * kCollThreads)
         ((uint4 *)hist)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (threadIdx.x == 0) {
+        s_nf = 0u;
+        s_nt = 0u;
+    }
+    __syncthreads();
     const unsigned int th = st->thresh;
     const bool done = st->done != 0u;
-    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
-        const long long v = base + threadIdx.x;
-        const bool act = v < n && alive[v];
-        TopkKey k;
-        k.hi = 0;
-        k.lo = 0;
-        k.v = -1;
-        unsigned int dig = 0;
-        if (act) {
-            k = make_key(R, new2old, (int)v);
-            dig = key_digit(k, 0);
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    constexpr int kPer = 8;  // keys per thread per step, loads all in flight together
+    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += (long long)kPer * kCollThreads) {
+        double r[kPer];
+        uint8_t al[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const long long v = v0 + (long long)j * kCollThreads;
+            r[j] = v < hi ? R[v] : 0.0;
+            al[j] = v < hi ? alive[v] : (uint8_t)0;
         }
-        const bool to_final = act && (dig > th || (dig == th && done));
-        const bool to_tie = act && dig == th && !done;
-        if (__syncthreads_or(to_final)) block_push(fin, &st->n_final, to_final, k, s_cnt, &s_base);
-        if (__syncthreads_or(to_tie)) block_push(tie, &st->n_tie, to_tie, k, s_cnt, &s_base);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (!al[j]) continue;
+            const unsigned int dig = digit0_of(r[j]);
+            const bool f = dig > th || (dig == th && done);
+            const bool t = dig == th && !done;
+            if (!f && !t) continue;
+            const long long v = v0 + (long long)j * kCollThreads;
+            TopkKey k;
+            k.hi = score_bits(r[j]);
+            k.lo = 0xffffffffu - (unsigned int)new2old[v];
+            k.v = (int)v;
+            const unsigned int i = atomicAdd(f ? &s_nf : &s_nt, 1u);
+            if (i < (unsigned int)kCollStage)
+                (f ? sf : stl)[i] = k;
+            else if (f)
+                fin[atomicAdd(&st->n_final, 1ull)] = k;
+            else
+                tie[atomicAdd(&st->n_tie, 1ull)] = k;
+        }
     }
+    __syncthreads();
+    const unsigned int cf = min(s_nf, (unsigned int)kCollStage), ct = min(s_nt, (unsigned int)kCollStage);
+    if (threadIdx.x == 0) {
+        if (cf) s_bf = atomicAdd(&st->n_final, (unsigned long long)cf);
+        if (ct) s_bt = atomicAdd(&st->n_tie, (unsigned long long)ct);
+    }
+    __syncthreads();
+    for (unsigned int i = threadIdx.x; i < cf; i += kCollThreads) fin[s_bf + i] = sf[i];
+    for (unsigned int i = threadIdx.x; i < ct; i += kCollThreads) tie[s_bt + i] = stl[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_list_collect(const TopkKey *list, const unsigned long long *count,
@@ -1632,6 +1701,80 @@ __device__ __forceinline__ unsigned int key_byte(unsigned long long hi, unsigned
 // bitonic-sorts the keff selected keys (descending; keys are unique since the
 // id is part of the key, so the order is exact).  flag = 1 if done here, 0
 // if the general path must run.
+static_assert(kSmallCap <= 4 * 1024, "the final sort holds at most four keys per thread");
+// Bitonic sort, descending, of the n2 (a power of two, >= E) keys of s2, by
+// all threads of the block; the first kf go out.  Thread t < n2 / E holds
+// positions [E t, E t + E): pairs closer than E are exchanged in registers,
+// pairs within a wavefront by shuffles, the others through LDS.  Only the key
+// moves: id and score are recovered from it (key = (score bits, 0xffffffff -
+// caller id), scores >= +0).
+template <int E>
+__device__ __forceinline__ void sort_desc_keys(TopkKey *s2, int n2, int kf, int32_t *out_ids, double *out_sc) {
+    const int tid = threadIdx.x;
+    const int T = n2 / E;
+    const bool part = tid < T;
+    TopkKey x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = part ? s2[E * tid + e] : s2[0];
+    for (int kk = 2; kk <= n2; kk <<= 1) {
+        for (int j = kk >> 1; j >= E; j >>= 1) {
+            const int tj = j / E;  // partner thread distance
+            const bool desc = ((E * tid) & kk) == 0;
+            const bool lower = (tid & tj) == 0;
+            if (tj >= 64) {
+                __syncthreads();
+                if (part) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) s2[E * tid + e] = x[e];
+                }
+                __syncthreads();
+                if (part) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const TopkKey o = s2[E * (tid ^ tj) + e];
+                        if ((lower == desc) ? key_gt(o, x[e]) : key_gt(x[e], o)) x[e] = o;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    TopkKey o;
+                    o.hi = (unsigned long long)__shfl_xor((long long)x[e].hi, tj);
+                    o.lo = (unsigned int)__shfl_xor((int)x[e].lo, tj);
+                    o.v = x[e].v;
+                    if (part && ((lower == desc) ? key_gt(o, x[e]) : key_gt(x[e], o))) x[e] = o;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = E / 2; j >= 1; j >>= 1) {
+            if (j >= kk) continue;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int f = e ^ j;
+                if (f <= e) continue;
+                // positions e < f of one thread; the lower keeps the larger key in a descending run
+                const bool desc = ((E * tid + e) & kk) == 0;
+                if (desc ? key_gt(x[f], x[e]) : key_gt(x[e], x[f])) {
+                    const TopkKey y = x[e];
+                    x[e] = x[f];
+                    x[f] = y;
+                }
+            }
+        }
+    }
+    if (part) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = E * tid + e;
+            if (p < kf) {
+                out_ids[p] = (int32_t)(0xffffffffu - x[e].lo);
+                out_sc[p] = __longlong_as_double((long long)x[e].hi);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const TopkKey *fin, const TopkKey *tie,
                                                      long long keff, const double *R, const int32_t *new2old,
                                                      int32_t *out_ids, double *out_sc, unsigned int *flag) {
@@ -1647,16 +1790,23 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
         return;
     }
     const int nf = (int)nfl, total = (int)(nfl + ntl), kf = (int)keff;
+    int pk = 1, pt = 1;
+    while (pk < kf) pk <<= 1;
+    while (pt < total) pt <<= 1;
+    // when every candidate fits the sort the kf selected keys need anyway,
+    // sort them all and skip the selection
+    const bool sort_all = pt == pk;
+    const int nsel = sort_all ? total : kf;
     for (int i = tid; i < total; i += nthr) {
         if (i < nf) {
             s[i] = fin[i];
             mark[i] = 1;
         } else {
             s[i] = tie[i - nf];
-            mark[i] = 2;
+            mark[i] = sort_all ? 1 : 2;
         }
     }
-    int need = kf - nf;  // threshold-bin keys still to take (uniform)
+    int need = sort_all ? 0 : kf - nf;  // threshold-bin keys still to take (uniform)
     __syncthreads();
     for (int d = 0; d < 10 && need > 0; ++d) {
         for (int i = tid; i < 256; i += nthr) hcount[i] = 0u;
@@ -1712,71 +1862,19 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
     int pos = base + incl - cnt;
     for (int i = i0; i < min(total, i0 + per); ++i)
         if (mark[i] == 1) s2[pos++] = s[i];
-    int n2 = 1;
-    while (n2 < kf) n2 <<= 1;
-    __syncthreads();
-    if (n2 <= 1024) {
-        // one key per thread; partners inside a wavefront are exchanged by
-        // shuffles, the others through LDS
-        TopkKey me;
-        me.hi = 0;
-        me.lo = 0;  // padding: below every real key (a real key has lo >= 2^31)
-        me.v = -1;
-        if (tid < kf) me = s2[tid];
-        for (int kk = 2; kk <= n2; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                TopkKey o;
-                if (j >= 64) {
-                    __syncthreads();
-                    if (tid < n2) s2[tid] = me;
-                    __syncthreads();
-                    if (tid < n2) o = s2[tid ^ j];
-                } else {
-                    o.hi = (unsigned long long)__shfl_xor((long long)me.hi, j);
-                    o.lo = (unsigned int)__shfl_xor((int)me.lo, j);
-                    o.v = __shfl_xor(me.v, j);
-                }
-                if (tid < n2) {
-                    const bool desc = (tid & kk) == 0;
-                    const bool lower = tid < (tid ^ j);
-                    // the lower index keeps the larger key in a descending run
-                    const bool take_o = (lower == desc) ? key_gt(o, me) : key_gt(me, o);
-                    if (take_o) me = o;
-                }
-            }
-        }
-        if (tid < kf) {
-            out_ids[tid] = new2old[me.v];
-            out_sc[tid] = R[me.v];
-        }
-    } else {
-        for (int i = kf + tid; i < n2; i += nthr) {
-            s2[i].hi = 0;
-            s2[i].lo = 0;
-            s2[i].v = -1;
-        }
-        __syncthreads();
-        for (int kk = 2; kk <= n2; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int i = tid; i < n2; i += nthr) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const bool desc = (i & kk) == 0;
-                        const TopkKey x = s2[i], y = s2[l];
-                        if (desc ? key_gt(y, x) : key_gt(x, y)) {
-                            s2[i] = y;
-                            s2[l] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int i = tid; i < kf; i += nthr) {
-            out_ids[i] = new2old[s2[i].v];
-            out_sc[i] = R[s2[i].v];
-        }
+    const int n2 = sort_all ? pt : pk;
+    for (int i = nsel + tid; i < n2; i += nthr) {  // padding: below every real key (lo >= 2^31)
+        s2[i].hi = 0;
+        s2[i].lo = 0;
+        s2[i].v = -1;
     }
+    __syncthreads();
+    if (n2 <= 1024)
+        sort_desc_keys<1>(s2, n2, kf, out_ids, out_sc);
+    else if (n2 <= 2048)
+        sort_desc_keys<2>(s2, n2, kf, out_ids, out_sc);
+    else
+        sort_desc_keys<4>(s2, n2, kf, out_ids, out_sc);
     if (tid == 0) *flag = 1u;
 }
 
@@ -1814,20 +1912,22 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     *count = keff;
     if (keff <= 0) return RS_OK;
     hipEvent_t ev;
-    long long chunk = (D.n + 255) / 256;
-    if (chunk < 4096) chunk = 4096;
+    long long chunk = (D.n + 63) / 64;  // about 64 blocks, each < 2^16 keys
+    if (chunk < 16384) chunk = 16384;
     if (chunk > kHistChunk) chunk = kHistChunk;
     const int grid_h = (int)((D.n + chunk - 1) / chunk);
     timing_begin(g, K_TOPK_HIST, &ev);
-    hipLaunchKernelGGL(k_topk_hist, dim3(grid_h), dim3(kBlock), 0, g->stream, D.R, D.new2old, D.alive, D.n, chunk,
+    hipLaunchKernelGGL(k_topk_hist, dim3(grid_h), dim3(kHistThreads), 0, g->stream, D.R, D.alive, D.n, chunk,
                        D.thist, D.thist_c);
     timing_end(g, K_TOPK_HIST, ev);
     timing_begin(g, K_TOPK_FIND, &ev);
     hipLaunchKernelGGL(k_topk_find0, dim3(1), dim3(kBlock), 0, g->stream, D.thist, D.thist_c, D.tstate, keff);
     timing_end(g, K_TOPK_FIND, ev);
     timing_begin(g, K_TOPK_COLLECT, &ev);
-    hipLaunchKernelGGL(k_topk_collect, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.R,
-                       D.new2old, D.alive, D.n, D.tstate, D.tfinal, D.ttie, D.thist);
+    long long cchunk = (D.n + 255) / 256;  // 64 to 256 blocks
+    if (cchunk < 16384) cchunk = 16384;
+    hipLaunchKernelGGL(k_topk_collect, dim3((int)((D.n + cchunk - 1) / cchunk)), dim3(kCollThreads), 0, g->stream,
+                       D.R, D.new2old, D.alive, D.n, cchunk, D.tstate, D.tfinal, D.ttie, D.thist);
     timing_end(g, K_TOPK_COLLECT, ev);
     // common path: one workgroup ranks the candidates into a compact device
     // block [flag | ids | scores], copied once into pinned host memory

@@ -164,6 +164,25 @@ def test_lfr_small(rs):
     _check(g, 100, "lfr n=30000")
 
 
+def test_topk_sort_widths(rs):
+    """Top-k sizes whose final sort holds one, two and four keys per thread
+    (k above 1,024 and 2,048), plus one beyond the single-block sort."""
+    g = lfr(30000, 20.0, 800, 0.2, seed=4, cmin=20, cmax=2000)
+    ora = oracle.score(g)
+    from tests.parity import topk_matches
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    try:
+        rs.rs_score(h)
+        for k in (700, 1100, 2100, 3500, 6000):
+            ids, sc = rs.rs_topk(h, k)
+            exp_ids, _ = oracle.topk(ora["R"], k)
+            used = topk_matches(ids, exp_ids, ora["R"], k)
+            _say(f"[parity] top-{k}: ok, {used} near-tie positions")
+            rel_close(sc, ora["R"][ids], 1e-6)
+    finally:
+        h.free()
+
+
 def test_sbm_uneven_dense_inter(rs):
     g = sbm([5, 40, 300, 25, 80, 2], 0.3, 0.05, 9)
     _check(g, 30, "sbm uneven")
