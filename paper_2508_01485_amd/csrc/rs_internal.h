@@ -67,6 +67,7 @@ enum KernelId {
     K_TOPK_COLLECT,
     K_TOPK_TIE,
     K_TOPK_RANK,
+    K_HUB_SUM,
     K_COUNT
 };
 
@@ -166,7 +167,6 @@ struct DeviceGraph {
     int32_t *shub_first = nullptr;  // [hubs + 1] first chunk of each score hub
     int2 *shub_chunk = nullptr;     // [chunks] (hub, chunk index within the hub)
     HubPart *hub_part = nullptr;    // [chunks] chunk partials
-    unsigned int *hub_cnt = nullptr;  // [hubs] chunks finished in the current pass
     int64_t *oo = nullptr;      // [n+1] out-list offsets
     int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
@@ -175,6 +175,7 @@ struct DeviceGraph {
     double *wown = nullptr, *R = nullptr;
     long long *tI = nullptr, *tII = nullptr;
     RowPart *part_rows = nullptr;    // [row grid]
+    unsigned long long *wmax_part = nullptr;  // [row grid] w_max bits per block
     ScorePart *part_score = nullptr; // [score grid]
     DevCounters *ctr = nullptr;
     // top-k

@@ -7,11 +7,14 @@
 //            detect the border vertex, compute every record's weight with
 //            Algorithm 2's shared terms (Eq. H_optimal) and the vertex's
 //            own-community weight, and a per-block maximum for w_max.
-//   k_wmax   reduce the per-block partials (w_max and pass totals).
+//   k_wmax   reduce the per-block maxima to w_max (the other pass totals are
+//            reduced when a reader asks).
 //   k_score  Eq. RSI per border vertex u, one lane per pair (u, w) with w a
 //            foreign neighbour, in the per-(vertex, community) factorised form
 //            of Lemmas 1-2 (Section IV, Step 3).  One owner per vertex, fixed
-//            summation order, no floating-point atomics.
+//            summation order, no floating-point atomics.  Hubs too large for
+//            LDS staging run in k_score_hub; k_hub_sum adds each hub's chunk
+//            partials.
 // Top-k (Algorithm 1 Step 4) is an exact radix select on the 96-bit key
 // (score bits, complement of the caller id) with 16-bit digits.
 //
@@ -97,6 +100,7 @@ struct RowArgs {
     double *wown, *R;
     long long *tI, *tII;
     RowPart *part;
+    unsigned long long *wmax_part;  // [grid] w_max bits of each block (dense copy for k_wmax)
 };
 
 struct RowResult {
@@ -145,7 +149,7 @@ __device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d,
     }
 }
 
-__device__ void block_reduce_row(RowAcc acc, RowPart *out) {
+__device__ void block_reduce_row(RowAcc acc, RowPart *out, unsigned long long *wmax_out) {
     __shared__ unsigned long long s_u[5][kBlock / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -174,6 +178,7 @@ __device__ void block_reduce_row(RowAcc acc, RowPart *out) {
             p.sum_ell_x += s_u[4][i];
         }
         *out = p;
+        *wmax_out = p.wmax_bits;
     }
 }
 
@@ -619,13 +624,13 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
         const int t = tile_of_block(b, A.n_hubs, A.tiles_per_xcd);
         if (t < A.n_tiles) row_tile(A, S, t, acc);
     }
-    block_reduce_row(acc, &A.part[b]);
+    block_reduce_row(acc, &A.part[b], &A.wmax_part[b]);
 }
 
-// w_max of a pass from the row partials (one workgroup of 1024 threads, the
-// loads of eight partials per thread in flight together); the other row
-// totals are reduced when the counters are read.
-__global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevCounters *c) {
+// w_max of a pass from the dense per-block maxima of the row kernel (one
+// workgroup of 1024 threads, eight loads per thread in flight together); the
+// other row totals are reduced only when a reader asks for them.
+__global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, int np, DevCounters *c) {
     __shared__ unsigned long long s[16];
     unsigned long long w = 0;
     for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 1024) {
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(1024) void k_wmax(const RowPart *part, int np, DevC
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int i = i0 + j * 1024;
-            q[j] = i < np ? part[i].wmax_bits : 0ull;
+            q[j] = i < np ? wpart[i] : 0ull;
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) w = max(w, q[j]);
@@ -665,7 +670,6 @@ struct ScoreArgs {
     const int2 *hub_chunk;
     int n_chunks, n_chunks_lds;
     HubPart *hub_part;
-    unsigned int *hub_cnt;
     const int32_t *outl;
     const int32_t *reckey;
     const RecDat *recdat;
@@ -725,25 +729,48 @@ struct TileU {
     }
 };
 
-// Hub form: u's row in HBM (the foreign list is the row minus [p, p + h)).
+// Hub form: u's foreign list in HBM (the row minus [p, p + h)).  Every
+// stride-th entry is staged in LDS (samp, ns entries), so a membership probe
+// is a binary search in LDS followed by a 16-ary search of one stride-long
+// block in HBM.
+constexpr int kHubSamp = 2048;  // LDS samples of a big hub's foreign list
 struct HubU {
     const int32_t *row;
     int p, h, n_f;
+    const int *samp;
+    int ns, stride;
     __device__ __forceinline__ int nf() const { return n_f; }
     __device__ __forceinline__ int list_at(int j) const { return row[j < p ? j : j + h]; }
     __device__ __forceinline__ bool in_list(int x) const {
-        int lo = 0, hi = n_f;
+        // last sample <= x
+        int lo = 0, hi = ns;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            const int y = list_at(mid);
-            if (y < x)
+            if (samp[mid] <= x)
                 lo = mid + 1;
-            else if (y > x)
-                hi = mid;
             else
-                return true;
+                hi = mid;
         }
-        return false;
+        if (lo == 0) return false;  // below the first entry
+        int b = (lo - 1) * stride, e = min(n_f, b + stride);
+        while (e - b > 16) {
+            const int st = (e - b + 15) >> 4;
+            int cnt = 0;
+#pragma unroll
+            for (int j = 1; j < 16; ++j) {
+                const int y = b + j * st;
+                cnt += (y < e && list_at(y) <= x) ? 1 : 0;
+            }
+            b += cnt * st;
+            e = min(e, b + st);
+        }
+        bool f = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int y = b + j;
+            if (y < e && list_at(y) == x) f = true;
+        }
+        return f;
     }
 };
 
@@ -830,10 +857,15 @@ struct ScoreAcc {
     long long tI, tII, workI;
 };
 
+// R of Algorithm 1: the raw sum over w_max and d(d-1); 0 when d < 2 or w_max = 0.
+__device__ __forceinline__ double score_value(double acc, int d, double wmax) {
+    return (d >= 2 && wmax > 0.0) ? acc / wmax / (double)((long long)d * (d - 1)) : 0.0;
+}
+
 template <typename OffT>
 __device__ __forceinline__ void score_store(const ScoreArgs<OffT> &A, int u, int d, double acc, long long cI,
                                             long long cII, double wmax, ScoreAcc &sa) {
-    A.R[u] = (d >= 2 && wmax > 0.0) ? acc / wmax / (double)((long long)d * (d - 1)) : 0.0;
+    A.R[u] = score_value(acc, d, wmax);
     A.tI[u] = cI;
     A.tII[u] = cII;
     sa.tI += cI;
@@ -864,10 +896,13 @@ __device__ __forceinline__ int block_excl_scan(int x, int *ws, int &total) {
 
 // Store a hub chunk's partial; the chunk finishing last adds the partials
 // of the hub in chunk order and writes its score (one thread).
+// A hub chunk's partial (its pair terms and counts, summed over the block in a
+// fixed tree order) goes to its slot; k_hub_sum adds the chunks of each hub in
+// chunk order once the score kernels are done.  The chunk's counts also go to
+// the block totals.
 template <typename OffT>
-__device__ void hub_finish(const ScoreArgs<OffT> &A, const double *red, const long long (*ired)[kBlock / 64], int hub,
-                           int chunk, int u, int deg, int dp, double wmax, ScoreAcc &sa) {
-    const int first = A.hub_first[hub], nch = A.hub_first[hub + 1] - first;
+__device__ void hub_chunk_store(const ScoreArgs<OffT> &A, const double *red, const long long (*ired)[kBlock / 64],
+                                int hub, int chunk, ScoreAcc &sa) {
     HubPart hp;
     hp.raw = 0.0;
     hp.tI = hp.tII = 0;
@@ -877,21 +912,9 @@ __device__ void hub_finish(const ScoreArgs<OffT> &A, const double *red, const lo
         hp.tI += ired[0][i];
         hp.tII += ired[1][i];
     }
-    A.hub_part[first + chunk] = hp;
-    __threadfence();
-    if (atomicAdd(&A.hub_cnt[hub], 1u) == (unsigned int)(nch - 1)) {
-        __threadfence();
-        double acc = 0.0;
-        long long c1 = 0, c2 = 0;
-        for (int c = 0; c < nch; ++c) {
-            const HubPart q = A.hub_part[first + c];
-            acc += q.raw;
-            c1 += q.tI;
-            c2 += q.tII;
-        }
-        A.hub_cnt[hub] = 0u;
-        if (dp > 0) score_store(A, u, deg, acc, c1, c2, wmax, sa);
-    }
+    A.hub_part[A.hub_first[hub] + chunk] = hp;
+    sa.tI += hp.tI;
+    sa.tII += hp.tII;
 }
 
 // ------------------------------------------------------------ score units
@@ -901,8 +924,8 @@ __device__ void hub_finish(const ScoreArgs<OffT> &A, const double *red, const lo
 // neighbours w of the unit's vertices are laid out in LDS (a vertex's
 // entries ascending), one lane takes one pair (u, w), and the pair terms are
 // summed in a fixed order: per vertex in pair order for a tile, in a tree
-// over the chunk for a hub (the chunk that finishes last adds the chunk
-// partials in order).
+// over the chunk for a hub (k_hub_sum then adds a hub's chunk partials in a
+// fixed order).
 static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: one vertex and one pair per thread");
 
 struct ScoreUnitShared {
@@ -942,7 +965,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
     const int tid = threadIdx.x;
     // ---- prologue: lay out the unit's pairs
     int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;    // tile
-    int hub = 0, chunk = 0, hu = 0, hdeg = 0, hdp = 0, hcu = 0;  // hub chunk
+    int hub = 0, chunk = 0, hu = 0, hdp = 0, hcu = 0;  // hub chunk
     if (hub_unit) {
         const int2 hc = A.hub_chunk[idx];
         hub = hc.x;
@@ -952,7 +975,6 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         const VMeta m = ch.m;
         const long long ou = ch.off;
         const int h = m.q - m.p;
-        hdeg = m.deg;
         hdp = m.deg - h;  // <= the load-time count, which fits kHubList
         hcu = ch.lab;
         for (int j = tid; j < hdp; j += kBlock) S.w[j] = A.col[ou + (j < m.p ? j : j + h)];
@@ -1032,13 +1054,14 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         return;
     }
     chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
-    if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, hu, hdeg, hdp, wmax, sa);
+    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
 
 // A hub whose foreign list exceeds kHubList: u's list is read from HBM.
 struct ScoreHubBigShared {
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
+    int samp[kHubSamp];
 };
 
 template <typename OffT>
@@ -1057,6 +1080,11 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     U.p = m.p;
     U.h = h;
     U.n_f = dp;
+    U.stride = max(64, (dp + kHubSamp - 1) / kHubSamp);
+    U.ns = (dp + U.stride - 1) / U.stride;
+    U.samp = S.samp;
+    for (int j = tid; j < U.ns; j += kBlock) S.samp[j] = U.list_at(j * U.stride);
+    __syncthreads();
     const int k = chunk * kScoreTileP + tid;
     PairRes r = {0.0, 0, 0};
     if (k < dp) {
@@ -1066,7 +1094,7 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
         r = score_pair(A, U, u, cu, w, cw);
     }
     chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
-    if (tid == 0) hub_finish(A, S.red, S.ired, hub, chunk, u, m.deg, dp, wmax, sa);
+    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
 
 __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
@@ -1119,6 +1147,42 @@ __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int par
     const int2 hc = A.hub_chunk[A.n_chunks_lds + blockIdx.x];
     score_hub_big(A, S, hc.x, hc.y, wmax, sa);
     block_reduce_score(sa, &A.part[part0 + blockIdx.x]);
+}
+
+// Each hub's score from its chunk partials (one wavefront per hub: lane l
+// sums chunks l, l + 64, ... in order, then a fixed shuffle tree).  A hub
+// whose foreign list became empty keeps the zeros the row pass wrote.
+__global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const int32_t *hub_first,
+                                                    const HubPart *hub_part, int n_hubs, const VCard *card,
+                                                    const DevCounters *ctr, double *R, long long *tI,
+                                                    long long *tII) {
+    const int hub = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (hub >= n_hubs) return;
+    const int first = hub_first[hub], nch = hub_first[hub + 1] - first;
+    double acc = 0.0;
+    long long c1 = 0, c2 = 0;
+    for (int c = lane; c < nch; c += 64) {
+        const HubPart q = hub_part[first + c];
+        acc += q.raw;
+        c1 += q.tI;
+        c2 += q.tII;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o);
+        c1 += __shfl_xor(c1, o);
+        c2 += __shfl_xor(c2, o);
+    }
+    if (lane == 0) {
+        const int u = hubs[hub];
+        const VMeta m = card[u].m;
+        if (m.deg - (m.q - m.p) > 0) {
+            R[u] = score_value(acc, m.deg, bitsd(ctr->wmax_bits));
+            tI[u] = c1;
+            tII[u] = c2;
+        }
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, int np, DevCounters *c) {
@@ -1181,13 +1245,14 @@ static rs_status score_pass_t(rs_graph *g) {
     A.tI = D.tI;
     A.tII = D.tII;
     A.part = D.part_rows;
+    A.wmax_part = D.wmax_part;
     if (g->grid_rows > 0) {
         timing_begin(g, K_ROWS, &ev);
         hipLaunchKernelGGL(k_rows<OffT>, dim3(g->grid_rows), dim3(kBlock), 0, g->stream, A);
         timing_end(g, K_ROWS, ev);
     }
     timing_begin(g, K_WMAX, &ev);
-    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.part_rows, g->grid_rows, D.ctr);
+    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.wmax_part, g->grid_rows, D.ctr);
     timing_end(g, K_WMAX, ev);
 
     ScoreArgs<OffT> S;
@@ -1204,7 +1269,6 @@ static rs_status score_pass_t(rs_graph *g) {
     S.n_chunks = g->n_schunks;
     S.n_chunks_lds = g->n_schunks_lds;
     S.hub_part = D.hub_part;
-    S.hub_cnt = D.hub_cnt;
     S.outl = D.outl;
     S.reckey = D.reckey;
     S.recdat = D.recdat;
@@ -1225,6 +1289,13 @@ static rs_status score_pass_t(rs_graph *g) {
         timing_begin(g, K_SCORE, &ev);
         hipLaunchKernelGGL(k_score<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
         timing_end(g, K_SCORE, ev);
+    }
+    if (g->n_shubs > 0) {
+        timing_begin(g, K_HUB_SUM, &ev);
+        hipLaunchKernelGGL(k_hub_sum, dim3((g->n_shubs + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                           g->stream, D.shubs, D.shub_first, D.hub_part, g->n_shubs, D.card, D.ctr, D.R, D.tI,
+                           D.tII);
+        timing_end(g, K_HUB_SUM, ev);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "score pass launch");

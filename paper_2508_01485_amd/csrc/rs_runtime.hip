@@ -355,7 +355,6 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.shub_first, 4 * (nsh + 1)},
         {(void **)&D.shub_chunk, sizeof(int2) * nch},
         {(void **)&D.hub_part, sizeof(HubPart) * nch},
-        {(void **)&D.hub_cnt, 4 * nsh},
         {(void **)&D.oo, 8 * (N + 1)},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
@@ -366,6 +365,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
         {(void **)&D.part_rows, sizeof(RowPart) * std::max(g->grid_rows, 1)},
+        {(void **)&D.wmax_part, 8 * (size_t)std::max(g->grid_rows, 1)},
         {(void **)&D.part_score, sizeof(ScorePart) * std::max(g->grid_score, 1)},
         {(void **)&D.ctr, sizeof(DevCounters)},
         {(void **)&D.thist, 4 * (size_t)kTopkBins},
@@ -425,7 +425,6 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (e == hipSuccess && n) e = hipStreamSynchronize(s);  // the host cards must outlive the copy
     put(D.outl, H.outl.data(), 4 * H.outl.size());
     put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
-    if (e == hipSuccess) e = hipMemsetAsync(D.hub_cnt, 0, 4 * nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist_c, 0, 4 * 256, s);
@@ -800,7 +799,8 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
 }
 
 static const char *kKernelNames[K_COUNT] = {
-    "k_rows", "k_wmax", "k_score_hub", "k_score", "k_topk_hist", "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order"};
+    "k_rows", "k_wmax", "k_score_hub", "k_score", "k_topk_hist", "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order",
+    "k_hub_sum"};
 
 const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
 

@@ -16,4 +16,5 @@ from .graphs import (  # noqa: F401
     cfg_lfr_1m,
     cfg_lfr_20m,
     graph_stats,
+    cached,
 )

@@ -53,6 +53,21 @@ def _sort_keys(x, hi: int):
     return xs
 
 
+def _take(a, idx):
+    """``a[idx]`` for a 1-D array and an index array; large gathers run in
+    threads over index chunks (same result)."""
+    idx = np.asarray(idx)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    if idx.size < _PAR_MIN or threads == 1:
+        return a[idx]
+    out = np.empty(idx.size, dtype=a.dtype)
+    bounds = np.linspace(0, idx.size, 4 * threads + 1).astype(np.int64)
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda i: np.take(a, idx[bounds[i]:bounds[i + 1]], out=out[bounds[i]:bounds[i + 1]]),
+                    range(4 * threads)))
+    return out
+
+
 def _unique_keys(x, hi: int):
     """Sorted distinct values of non-negative int64 keys below ``hi``."""
     s = _sort_keys(x, hi)
@@ -90,8 +105,9 @@ class Graph:
         return src[keep], dst[keep]
 
 
-def canonical_csr(n: int, u, v):
+def canonical_csr(n: int, u, v, say=None):
     """Symmetrise, drop self-loops and duplicates, sort rows; return (off, col)."""
+    say = say if say is not None else (lambda msg: None)
     u = np.asarray(u, dtype=np.int64).ravel()
     v = np.asarray(v, dtype=np.int64).ravel()
     keep = u != v
@@ -102,11 +118,13 @@ def canonical_csr(n: int, u, v):
     del u, v, keep
     key = _unique_keys(a * n + b, n * n)
     del a, b
+    say(f"csr: {key.size} distinct edges")
     a = key // n
     b = key - a * n
     del key
     both = _sort_keys(np.concatenate([a * n + b, b * n + a]), n * n)
     del a, b
+    say(f"csr: {both.size} entries sorted")
     src = both // n
     dst = (both - src * n).astype(np.int32)
     del both
@@ -116,12 +134,12 @@ def canonical_csr(n: int, u, v):
     return off, dst
 
 
-def _relabel(rng, n, off, col, labels):
+def _relabel(rng, n, off, col, labels, say=None):
     """Randomly permute vertex ids and community ids (keeps the graph isomorphic)."""
     perm = rng.permutation(n).astype(np.int64)  # old -> new
     src = np.repeat(perm, np.diff(off))
-    dst = perm[col.astype(np.int64)]
-    off2, col2 = canonical_csr(n, src, dst)
+    dst = _take(perm, col)
+    off2, col2 = canonical_csr(n, src, dst, say)
     lab_new = np.empty(n, dtype=np.int64)
     lab_new[perm] = labels
     uniq = np.unique(lab_new)
@@ -233,18 +251,23 @@ def _floor_powerlaw(rng, size, x0, hi, expo):
     return np.minimum(np.floor(x), hi).astype(np.int64)
 
 
-def _pair_internal(rng, stubs, comm):
+def _pair_internal(rng, stubs, comm, say=None):
     """Pair stubs uniformly at random inside each community; return edge keys (a<b)."""
+    say = say if say is not None else (lambda msg: None)
     if stubs.size < 2:
         return np.zeros(0, np.int64)
     n = comm.size
-    stubs = stubs[rng.permutation(stubs.size)]
-    key = comm[stubs]
+    stubs = _take(stubs, rng.permutation(stubs.size))
+    say(f"lfr: {stubs.size} internal stubs shuffled")
+    key = _take(comm, stubs)
     if comm.size and int(comm.max()) < 65536:
         key = key.astype(np.uint16)  # the stable sort of 16-bit keys is a radix sort
-    stubs = stubs[np.argsort(key, kind="stable")]
+    order = np.argsort(key, kind="stable")
     del key
-    sc = comm[stubs]
+    say("lfr: internal stubs ordered by community")
+    stubs = _take(stubs, order)
+    del order
+    sc = _take(comm, stubs)
     gstart = np.flatnonzero(np.r_[True, sc[1:] != sc[:-1]])
     glen = np.diff(np.r_[gstart, sc.size])
     pos = np.arange(sc.size) - np.repeat(gstart, glen)
@@ -350,7 +373,7 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
 
     say(f"lfr: degrees and {nc} communities drawn")
     keys = _union_keys(np.zeros(0, np.int64),
-                       _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), k_in), comm), n)
+                       _pair_internal(rng, np.repeat(np.arange(n, dtype=np.int64), k_in), comm, say), n)
     say(f"lfr: {keys.size} internal edges paired")
     ext_keys, left = _pair_external(rng, np.repeat(np.arange(n, dtype=np.int64), k_ext), comm, ext_rounds)
     keys = _union_keys(keys, ext_keys, n)
@@ -359,7 +382,7 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
     for _ in range(repair_rounds):
         a = keys // n
         b = keys - a * n
-        same = comm[a] == comm[b]
+        same = _take(comm, a) == _take(comm, b)
         r_in = np.bincount(a[same], minlength=n) + np.bincount(b[same], minlength=n)
         r_ext = np.bincount(a[~same], minlength=n) + np.bincount(b[~same], minlength=n)
         del a, b, same
@@ -374,10 +397,10 @@ def lfr(n: int, mean_deg: float, max_deg: int, mu: float, seed: int,
     u = keys // n
     v = keys - u * n
     del keys
-    off, col = canonical_csr(n, u, v)
+    off, col = canonical_csr(n, u, v, say)
     del u, v
     say("lfr: CSR built")
-    off, col, labels = _relabel(rng, n, off, col, comm.astype(np.int32))
+    off, col, labels = _relabel(rng, n, off, col, comm.astype(np.int32), say)
     say("lfr: ids permuted")
     g = Graph(n, off, col, labels, meta={
         "kind": "lfr", "seed": seed, "n": n, "mean_deg_target": mean_deg, "max_deg": max_deg,
@@ -422,6 +445,34 @@ def graph_stats(g: Graph) -> dict:
         "mu_real": inter / g.m if g.m else 0.0,
         "communities_real": int(np.unique(g.labels).size) if g.n else 0,
     }
+
+
+def cached(name: str, make, cache_dir=None, log=None) -> Graph:
+    """The graph ``name`` from ``cache_dir`` if an earlier call stored it there,
+    else ``make()``, stored there.  ``cache_dir`` defaults to the environment
+    variable RS_GRAPH_CACHE; without one nothing is cached.  Arrays are plain
+    .npy files (loaded without pickle) and the metadata is JSON."""
+    import json
+    cache_dir = cache_dir if cache_dir is not None else os.environ.get("RS_GRAPH_CACHE", "")
+    say = log if log is not None else (lambda msg: None)
+    if not cache_dir:
+        return make()
+    base = os.path.join(cache_dir, name)
+    parts = ("off", "col", "labels")
+    if all(os.path.exists(f"{base}.{p}.npy") for p in parts) and os.path.exists(f"{base}.json"):
+        arr = {p: np.load(f"{base}.{p}.npy", allow_pickle=False) for p in parts}
+        with open(f"{base}.json") as f:
+            meta = json.load(f)
+        say(f"graph {name} loaded from {cache_dir}")
+        return Graph(int(arr["off"].size - 1), arr["off"], arr["col"], arr["labels"], meta=meta)
+    g = make()
+    os.makedirs(cache_dir, exist_ok=True)
+    for p in parts:
+        np.save(f"{base}.{p}.npy", getattr(g, p), allow_pickle=False)
+    with open(f"{base}.json", "w") as f:
+        json.dump(g.meta, f)
+    say(f"graph {name} stored in {cache_dir}")
+    return g
 
 
 # Named workloads.  Sizes follow the benchmark configurations: a small SBM the

@@ -56,3 +56,33 @@ def test_lfr_statistics_small():
     deg = np.diff(g.off)
     # heavy tail: the top 1 % of degrees sits far above the mean
     assert np.percentile(deg, 99) > 4 * deg.mean()
+
+
+def test_graph_cache_round_trip(tmp_path):
+    from rsgen import cached
+    calls = []
+
+    def make():
+        calls.append(1)
+        return lfr(3000, 10.0, 100, 0.2, seed=5, cmin=20, cmax=300)
+
+    g1 = cached("lfr3k", make, cache_dir=str(tmp_path))
+    g2 = cached("lfr3k", make, cache_dir=str(tmp_path))
+    assert len(calls) == 1
+    for a, b in ((g1.off, g2.off), (g1.col, g2.col), (g1.labels, g2.labels)):
+        assert a.dtype == b.dtype and np.array_equal(a, b)
+    assert g2.meta["m_real"] == g1.meta["m_real"]
+    g3 = cached("lfr3k", make, cache_dir="")  # no cache directory: always generated
+    assert len(calls) == 2 and np.array_equal(g3.col, g1.col)
+
+
+def test_large_array_helpers_match_numpy():
+    """The threaded sort / gather helpers give numpy's own results."""
+    from rsgen.graphs import _sort_keys, _take, _unique_keys
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 10**12, 5_000_000)
+    assert np.array_equal(_sort_keys(x, 10**12), np.sort(x))
+    y = rng.integers(0, 1000, 5_000_000)
+    assert np.array_equal(_unique_keys(y, 1000), np.unique(y))
+    idx = rng.integers(0, x.size, 5_000_000)
+    assert np.array_equal(_take(x, idx), x[idx])

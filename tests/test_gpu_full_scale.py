@@ -6,7 +6,8 @@ top ids) against the oracle's per-vertex scores; the top-k list checked by
 properties that hold at any size.
 
 Generating the graph takes several minutes of host time, so the test runs
-only when RS_FULL_SCALE=1 is set.
+only when RS_FULL_SCALE=1 is set (with RS_GRAPH_CACHE set, a graph stored by
+an earlier run, e.g. of the benchmark, is reused).
 """
 import os
 import sys
@@ -15,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from rsgen import cfg_lfr_20m
+from rsgen import cached, cfg_lfr_20m
 from tests.parity import rel_close
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow,
@@ -34,7 +35,7 @@ def test_lfr_20m_sampled_parity():
     import paper_2508_01485_amd as rs
     import torch
 
-    g = cfg_lfr_20m(0, log=_say)
+    g = cached("lfr_20m_seed0", lambda: cfg_lfr_20m(0, log=_say), log=_say)
     _say(f"graph n={g.n} m={g.m} nnz={g.nnz}")
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
