@@ -23,6 +23,13 @@
 //     triangle of G' is {u, x, y} with y in out(x) for exactly one ordering of
 //     its other two vertices, and the lists are short (a hub's foreign
 //     neighbours are mostly of lower rank).  Removals tombstone entries (~id).
+//   * Pair facts: every foreign row entry e = (w, u) gets prec[e], written by
+//     w's row pass: w_w(C(u)) and the run of C(u) in w's row.  The G' entries
+//     (u, w) of u have link slots [goff[u], goff[u + 1]) in foreign-list order
+//     (goff is the prefix of the load-time foreign degrees; removals only
+//     shrink the lists): plink[s] = the index of the reverse entry (w, u) and
+//     w's out-list range.  The score pass reads u's links as one contiguous
+//     stream and each pair's facts with one independent load.
 //   * Work is cut at load time into static tiles of consecutive vertices: row
 //     tiles bound the row capacity they cover, score tiles the number of
 //     foreign entries (removals only shrink both).  Vertices too large for a
@@ -52,6 +59,7 @@ constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (
 constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise compare
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
+constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
 
 // Grid of a tiled launch: one workgroup per hub, then the tiles rounded up to
 // a multiple of the 8 XCDs.
@@ -81,18 +89,35 @@ struct __align__(16) VMeta {
     int deg, ell, p, q;
 };
 
-// Everything a pass needs about a vertex as a neighbour, in one 64-byte
-// card (one memory line for a gathered neighbour): the static row and
-// out-list ranges and community, and the last pass's row facts, a_v and the
-// first record keys (INT_MAX past ell).
+// Everything a pass needs about a vertex, in one 64-byte card (one memory
+// line for a gathered vertex): the static row start, pair-slot start and
+// community, and the last pass's row facts, a_v and the first record keys
+// (INT_MAX past ell).
 struct __align__(64) VCard {
-    long long off;  // row start
-    long long oo;   // out-list start
-    VMeta m;        // {deg, ell, p, q} of the last pass
-    int on;         // out-list length (tombstones included)
-    int lab;        // community
-    double a;       // cbrt(own-community weight) of the last pass
-    int key[4];     // first record keys of the last pass
+    long long off;   // row start
+    long long goff;  // first pair slot
+    VMeta m;         // {deg, ell, p, q} of the last pass
+    int pad;
+    int lab;         // community
+    double a;        // cbrt(own-community weight) of the last pass
+    int key[4];      // first record keys of the last pass
+};
+
+// The facts of the pair (u, w) at w's row entry (w, u), written by w's row
+// pass: w_w(C(u)), the length f of C(u)'s run in w's row and the distance
+// from the entry back to the run's first entry.
+struct __align__(16) PairRec {
+    double w;
+    int f;
+    int back;
+};
+
+// A link slot (u, w): the index of the row entry (w, u) and w's out-list
+// range (tombstones included).
+struct __align__(16) PairLink {
+    long long e;
+    int oo;
+    int on;
 };
 static_assert(sizeof(VCard) == 64, "one card per 64 bytes");
 
@@ -107,7 +132,7 @@ struct RowPart {
     unsigned long long wmax_bits, n_border, sum_dprime, sum_ell, sum_ell_x, pad[3];
 };
 struct ScorePart {
-    unsigned long long tI, tII, workI, pad;
+    unsigned long long tI, tII;
 };
 // Partial sum of one chunk of a score hub's pairs.
 struct HubPart {
@@ -168,6 +193,11 @@ struct DeviceGraph {
     int2 *shub_chunk = nullptr;     // [chunks] (hub, chunk index within the hub)
     HubPart *hub_part = nullptr;    // [chunks] chunk partials
     int64_t *oo = nullptr;      // [n+1] out-list offsets
+    int64_t *goff = nullptr;    // [n+1] pair-slot offsets
+    PairRec *prec = nullptr;    // [nnz] pair facts at foreign row entries
+    PairLink *plink = nullptr;  // [link slots]
+    int32_t *cstart = nullptr;  // [k+1] first internal id of each community
+    unsigned long long *wpart = nullptr;  // [kWorkBlocks] partials of the on-demand W1 count
     int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
@@ -239,6 +269,7 @@ rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *
 rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv,
                                  unsigned long long *d_removed_edges);
 rs_status launch_compact_rows(rs_graph *g);
+rs_status launch_links(rs_graph *g);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);
 

@@ -96,7 +96,8 @@ struct RowArgs {
     int32_t *reckey;
     RecDat *recdat;
     VCard *card;
-    const int64_t *oo;
+    const int64_t *goff;
+    PairRec *prec;     // pair facts at the foreign row entries, written by this pass
     double *wown, *R;
     long long *tI, *tII;
     RowPart *part;
@@ -117,17 +118,17 @@ struct RowAcc {
 // record keys k4), own weight, and zero scores for a non-border vertex.
 template <typename OffT>
 __device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d, const RowResult &r, int4 k4,
-                                           long long off, long long oo, int on, int lab, RowAcc &acc) {
+                                           long long off, long long goff, int lab, RowAcc &acc) {
     const int fown = r.q - r.p;
     const int dprime = d - fown;
     VCard c;  // written whole: one aligned 64-byte store, no partial lines
     c.off = off;
-    c.oo = oo;
+    c.goff = goff;
     c.m.deg = d;
     c.m.ell = r.ell;
     c.m.p = r.p;
     c.m.q = r.q;
-    c.on = on;
+    c.pad = 0;
     c.lab = lab;
     c.a = cbrt(r.wown);
     c.key[0] = k4.x;
@@ -227,7 +228,7 @@ struct RowTileShared {
     unsigned short runv[kRowTile];       // tile-local vertex of each run
     int runlab[kRowTile];                // label of each run (-1: removed tail)
     double vX[kRowTileV];
-    int vd[kRowTileV], vell[kRowTileV];
+    int vd[kRowTileV], vell[kRowTileV], vlab[kRowTileV];
     unsigned short vrf[kRowTileV], vo[kRowTileV];
 };
 
@@ -253,21 +254,20 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
         L[i] = e < TE ? A.col[e0 + e] : -2;
     }
-    int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU], von[kVU];
-    long long voo[kVU];
+    int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU];
+    long long vgo[kVU];
 #pragma unroll
     for (int j = 0; j < kVU; ++j) {
         const int i = tid + j * kBlock;
-        vo[j] = vc[j] = vdeg[j] = vlab[j] = von[j] = 0;
-        voo[j] = 0;
+        vo[j] = vc[j] = vdeg[j] = vlab[j] = 0;
+        vgo[j] = 0;
         if (i < nv) {
             const OffT a0 = A.off[v0 + i], a1 = A.off[v0 + i + 1];
             vo[j] = (int)(a0 - e0);
             vc[j] = (int)(a1 - a0);
             vdeg[j] = A.deg[v0 + i];
             vlab[j] = A.lab[v0 + i];
-            voo[j] = A.oo[v0 + i];
-            von[j] = (int)(A.oo[v0 + i + 1] - voo[j]);
+            vgo[j] = A.goff[v0 + i];
         }
     }
 #pragma unroll
@@ -342,6 +342,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         }
         S.vX[i] = X;
         S.vd[i] = d;
+        S.vlab[i] = cv;
         S.vell[i] = ell;
         S.vrf[i] = (unsigned short)rf;
         S.vo[i] = (unsigned short)o;
@@ -356,7 +357,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         k4.y = ell > 1 ? S.runlab[rf + 1] : INT_MAX;
         k4.z = ell > 2 ? S.runlab[rf + 2] : INT_MAX;
         k4.w = ell > 3 ? S.runlab[rf + 3] : INT_MAX;
-        finish_row(A, v0 + i, d, res, k4, (long long)e0 + o, voo[j], von[j], cv, acc);
+        finish_row(A, v0 + i, d, res, k4, (long long)e0 + o, vgo[j], cv, acc);
     }
     __syncthreads();
     for (int r = tid; r < total; r += kBlock) {
@@ -374,6 +375,21 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         rd.w = w;
         A.recdat[idx] = rd;
         acc.wmax = fmax(acc.wmax, w);
+    }
+    // pair facts at the foreign entries: entry (w, u) gets the record of
+    // C(u) in w's row (contiguous writes along the runs)
+    for (int e = tid; e < TE; e += kBlock) {
+        const int r = run_index(S, e) + (int)((S.mask[e >> 6] >> (e & 63)) & 1ull) - 1;
+        const int lb = S.runlab[r];
+        if (lb < 0) continue;  // removed tail
+        const int i = S.runv[r];
+        if (lb == S.vlab[i]) continue;  // own community
+        const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
+        PairRec pr;
+        pr.w = weight_present_t(S.tab, S.vd[i], S.vX[i], S.vell[i], f);
+        pr.f = f;
+        pr.back = e - (int)S.runpos[r];
+        A.prec[e0 + e] = pr;
     }
 }
 
@@ -393,14 +409,15 @@ __device__ __forceinline__ void hub_run(const RowArgs<OffT> &A, OffT rb, int d, 
             fown = f;
         else if (label < cv)
             below += f;
-    } else {
-        const double w = weight_present(d, X, ell, f);
         A.reckey[rb + slot] = label;
         RecDat rd;
         rd.pos = start;
         rd.f = f;
-        rd.w = w;
+        rd.w = 0.0;  // set by the second pass, once X and ell are known
         A.recdat[rb + slot] = rd;
+    } else {
+        const double w = weight_present(d, X, ell, f);
+        A.recdat[rb + slot].w = w;
         lmax = fmax(lmax, w);
     }
 }
@@ -466,6 +483,31 @@ __device__ void hub_pass(const RowArgs<OffT> &A, RowTileShared &S, OffT rb, int 
         __syncthreads();
         const bool last = seg0 + TE >= d;
         const int nr0 = H.nruns;
+        if (PASS == 2) {
+            // pair facts at this segment's foreign entries: the entry's run
+            // (the one carried in, or the last run start at or before it)
+            // and that run's record from the first pass
+#pragma unroll
+            for (int i = 0; i < kRowU; ++i) {
+                const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
+                if (e >= TE || L[i] < 0 || L[i] == cv) continue;
+                int lo = 0, hi = total;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((int)S.runpos[mid] <= e)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                const int slot = lo == 0 ? H.open_slot : nr0 + lo - 1;
+                const RecDat rd = A.recdat[rb + slot];
+                PairRec pr;
+                pr.w = weight_present(d, X, ell, rd.f);
+                pr.f = rd.f;
+                pr.back = seg0 + e - rd.pos;
+                A.prec[rb + seg0 + e] = pr;
+            }
+        }
         // the run carried from the previous segment closes at this segment's
         // first run start (or at the row's end)
         if (tid == 0 && H.open_start >= 0 && (total > 0 || last)) {
@@ -554,7 +596,7 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
         k4.y = ell > 1 ? A.reckey[rb + 1] : INT_MAX;
         k4.z = ell > 2 ? A.reckey[rb + 2] : INT_MAX;
         k4.w = ell > 3 ? A.reckey[rb + 3] : INT_MAX;
-        finish_row(A, v, d, r, k4, (long long)rb, A.oo[v], (int)(A.oo[v + 1] - A.oo[v]), cv, acc);
+        finish_row(A, v, d, r, k4, (long long)rb, A.goff[v], cv, acc);
     }
 }
 
@@ -674,6 +716,8 @@ struct ScoreArgs {
     const int32_t *reckey;
     const RecDat *recdat;
     const VCard *card;
+    const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
+    const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
     double *R;
     long long *tI, *tII;
     const DevCounters *ctr;
@@ -801,22 +845,32 @@ __device__ __forceinline__ int card_find(const VCard &c, const int32_t *reckey, 
     return kfind(reckey + c.off, c.m.ell, x);
 }
 
+// The terms of one pair (u, w), w a foreign neighbour of u, from the pair's
+// facts (w_w(C(u)) = W and the run of C(u) in w's row, at w's entry for u)
+// and its link (that entry, w's out-list):
+//   type II (Lemma 2): W^(2/3) times the sum of a_v over the other members of
+//     that run (v in C(u), v adjacent to w; counted whether or not v ~ u);
+//   type I: every v in w's out-list that is also a foreign neighbour of u
+//     closes the G' triangle {u, w, v}; its two ordered triads (w, v) and
+//     (v, w) add cbrt(w_v(C(u)) w_w(C(v)) W) + cbrt(W w_v(C(w)) w_v(C(u))).
 template <class UV, typename OffT>
-__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, const VCard &cw_) {
+__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, const PairRec &pr,
+                              const PairLink &pl) {
     PairRes out = {0.0, 0, 0};
-    const long long ow = cw_.off;
-    const int s = card_find(cw_, A.reckey, cu);
-    if (s < 0) return out;  // cannot happen: u is a neighbour of w
-    const RecDat rd = A.recdat[ow + s];
-    const double W = rd.w;
-    out.t2 = rd.f - 1;
-    if (rd.f > 1) {
+    const double W = pr.w;
+    out.t2 = pr.f - 1;
+    // the out-list's first entries load together with the run below
+    const int o0 = pl.oo, o1 = pl.oo + pl.on;
+    int y[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) y[t] = o0 + t < o1 ? A.outl[o0 + t] : -1;
+    if (pr.f > 1) {
         double S = 0.0;
-        const int32_t *run = A.col + ow + rd.pos;
-        for (int i = 0; i < rd.f; i += 8) {
+        const int32_t *run = A.col + (pl.e - pr.back);
+        for (int i = 0; i < pr.f; i += 8) {
             int x[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) x[t] = i + t < rd.f ? run[i + t] : u;
+            for (int t = 0; t < 8; ++t) x[t] = i + t < pr.f ? run[i + t] : u;
             double av[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.card[x[t]].a : 0.0;
@@ -826,11 +880,11 @@ __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int 
         const double c1 = cbrt(W);
         out.val = c1 * c1 * S;
     }
-    const long long o0 = cw_.oo, o1 = cw_.oo + cw_.on;
-    for (long long j0 = o0; j0 < o1; j0 += 4) {
-        int y[4];
+    for (int j0 = o0; j0 < o1; j0 += 4) {
+        if (j0 > o0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) y[t] = j0 + t < o1 ? A.outl[j0 + t] : -1;
+            for (int t = 0; t < 4; ++t) y[t] = j0 + t < o1 ? A.outl[j0 + t] : -1;
+        }
         unsigned int hm = 0u;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -840,12 +894,13 @@ __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int 
             hm &= hm - 1u;
             const int v = A.outl[j0 + t];
             const VCard cv = A.card[v];
+            const VCard cw = A.card[w];
             const int s1 = card_find(cv, A.reckey, cu);
-            const int s2 = card_find(cv, A.reckey, cw_.lab);
-            const int s3 = card_find(cw_, A.reckey, cv.lab);
+            const int s2 = card_find(cv, A.reckey, cw.lab);
+            const int s3 = card_find(cw, A.reckey, cv.lab);
             const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
             const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
-            const double w_wv = s3 >= 0 ? A.recdat[ow + s3].w : 0.0;
+            const double w_wv = s3 >= 0 ? A.recdat[cw.off + s3].w : 0.0;
             out.val += cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
             out.t1 += 2;
         }
@@ -854,7 +909,7 @@ __device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int 
 }
 
 struct ScoreAcc {
-    long long tI, tII, workI;
+    long long tI, tII;
 };
 
 // R of Algorithm 1: the raw sum over w_max and d(d-1); 0 when d < 2 or w_max = 0.
@@ -931,7 +986,7 @@ static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: 
 struct ScoreUnitShared {
     int w[kHubList];                 // foreign neighbours
     int pb[kScoreTileV + 1];         // tile: first pair of each vertex
-    long long ou[kScoreTileV];
+    long long ou[kScoreTileV], go[kScoreTileV];  // tile: row start and first pair slot of each vertex
     int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV];
     unsigned short pu[kScoreTileP];  // tile: vertex of each pair
     double val[kBlock];              // the lane's pair terms
@@ -966,6 +1021,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
     // ---- prologue: lay out the unit's pairs
     int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;    // tile
     int hub = 0, chunk = 0, hu = 0, hdp = 0, hcu = 0;  // hub chunk
+    long long hgo = 0;
     if (hub_unit) {
         const int2 hc = A.hub_chunk[idx];
         hub = hc.x;
@@ -977,6 +1033,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         const int h = m.q - m.p;
         hdp = m.deg - h;  // <= the load-time count, which fits kHubList
         hcu = ch.lab;
+        hgo = ch.goff;
         for (int j = tid; j < hdp; j += kBlock) S.w[j] = A.col[ou + (j < m.p ? j : j + h)];
         total = min(kBlock, max(0, hdp - chunk * kBlock));
         __syncthreads();
@@ -991,6 +1048,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             deg = m.deg;
             dp = m.deg - (m.q - m.p);
             S.ou[tid] = cv.off;
+            S.go[tid] = cv.goff;
             S.cu[tid] = cv.lab;
             S.p[tid] = m.p;
             S.h[tid] = m.q - m.p;
@@ -1016,12 +1074,14 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         TileU U;
         U.w = S.w;
         int k, u, cu;
+        long long slot;
         if (hub_unit) {
             k = chunk * kBlock + tid;
             U.pb = 0;
             U.pe = hdp;
             u = hu;
             cu = hcu;
+            slot = hgo + k;
         } else {
             k = tid;
             const int i = S.pu[tid];
@@ -1029,11 +1089,12 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             U.pe = S.pb[i + 1];
             u = v0 + i;
             cu = S.cu[i];
+            slot = S.go[i] + (tid - U.pb);
         }
         const int w = S.w[k];
-        const VCard cw = A.card[w];
-        sa.workI += min(U.pe - U.pb, cw.m.deg - (cw.m.q - cw.m.p));
-        r = score_pair(A, U, u, cu, w, cw);
+        const PairLink pl = A.plink[slot];
+        const PairRec pr = A.prec[pl.e];
+        r = score_pair(A, U, u, cu, w, pr, pl);
     }
     // ---- epilogue: sums in a fixed order
     if (!hub_unit) {
@@ -1089,27 +1150,25 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     PairRes r = {0.0, 0, 0};
     if (k < dp) {
         const int w = U.list_at(k);
-        const VCard cw = A.card[w];
-        sa.workI += min(dp, cw.m.deg - (cw.m.q - cw.m.p));
-        r = score_pair(A, U, u, cu, w, cw);
+        const PairLink pl = A.plink[cu_.goff + k];
+        const PairRec pr = A.prec[pl.e];
+        r = score_pair(A, U, u, cu, w, pr, pl);
     }
     chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
     if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
 
 __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
-    __shared__ unsigned long long s_u[3][16];
+    __shared__ unsigned long long s_u[2][16];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         sa.tI += __shfl_xor(sa.tI, o);
         sa.tII += __shfl_xor(sa.tII, o);
-        sa.workI += __shfl_xor(sa.workI, o);
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_u[0][w] = (unsigned long long)sa.tI;
         s_u[1][w] = (unsigned long long)sa.tII;
-        s_u[2][w] = (unsigned long long)sa.workI;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1117,7 +1176,6 @@ __device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
             p.tI += s_u[0][i];
             p.tII += s_u[1][i];
-            p.workI += s_u[2][i];
         }
         *out = p;
     }
@@ -1129,7 +1187,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
     __shared__ ScoreUnitShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    ScoreAcc sa = {0, 0, 0};
+    ScoreAcc sa = {0, 0};
     const int b = (int)blockIdx.x;
     const bool hub_unit = b < A.n_chunks_lds;
     const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
@@ -1143,7 +1201,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int part0) {
     __shared__ ScoreHubBigShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    ScoreAcc sa = {0, 0, 0};
+    ScoreAcc sa = {0, 0};
     const int2 hc = A.hub_chunk[A.n_chunks_lds + blockIdx.x];
     score_hub_big(A, S, hc.x, hc.y, wmax, sa);
     block_reduce_score(sa, &A.part[part0 + blockIdx.x]);
@@ -1186,36 +1244,142 @@ __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const i
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, int np, DevCounters *c) {
-    __shared__ unsigned long long s[3][16];
-    unsigned long long a = 0, b = 0, w = 0;
+    __shared__ unsigned long long s[2][16];
+    unsigned long long a = 0, b = 0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         a += part[i].tI;
         b += part[i].tII;
-        w += part[i].workI;
     }
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);
         b += __shfl_xor(b, o);
-        w += __shfl_xor(w, o);
     }
     if ((threadIdx.x & 63) == 0) {
         s[0][threadIdx.x >> 6] = a;
         s[1][threadIdx.x >> 6] = b;
-        s[2][threadIdx.x >> 6] = w;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long x = 0, y = 0, z = 0;
+        unsigned long long x = 0, y = 0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
             x += s[0][i];
             y += s[1][i];
-            z += s[2][i];
         }
         c->sum_tI = x;
         c->sum_tII = y;
+    }
+}
+
+// W1 = sum over G' pairs (u, w) of min(d'(u), d'(w)), the list elements a
+// merge intersection would scan (reported for the algorithmic-byte count;
+// computed when a reader asks, from the last pass's row facts).  One
+// wavefront per vertex; per-block partials in wpart.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_work_I(const OffT *off, const int32_t *col, const VCard *card, long long n,
+                                                   unsigned long long *wpart) {
+    __shared__ unsigned long long s[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long acc = 0;
+    for (long long x = (long long)blockIdx.x * (kBlock / 64) + wave; x < n; x += (long long)gridDim.x * (kBlock / 64)) {
+        const VMeta m = card[x].m;
+        const int dpx = m.deg - (m.q - m.p);
+        if (dpx == 0) continue;
+        const OffT rb = off[x];
+        for (int j = lane; j < m.deg; j += 64) {
+            if (j >= m.p && j < m.q) continue;
+            const VMeta my = card[col[rb + j]].m;
+            acc += (unsigned long long)min(dpx, my.deg - (my.q - my.p));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) s[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / 64; ++i) t += s[i];
+        wpart[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_work(const unsigned long long *wpart, DevCounters *c) {
+    __shared__ unsigned long long s[kBlock / 64];
+    unsigned long long t = 0;
+    for (int i = threadIdx.x; i < kWorkBlocks; i += kBlock) t += wpart[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long z = 0;
+        for (int i = 0; i < kBlock / 64; ++i) z += s[i];
         c->sum_workI = z;
     }
 }
+
+// ------------------------------------------------------------ link slots
+// For a row entry e = (x, y) with y foreign to x: plink[goff[x] + k] = {the
+// index of the entry (y, x), y's out-list range}, k = y's index among x's
+// foreign entries (x's row without its own-community id range).  Rows are
+// sorted, so positions are binary searches.  Run at load and after removals
+// (compaction shifts rows).
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_links(const OffT *off, const int32_t *deg, const int32_t *col,
+                                                  const int32_t *lab, const int32_t *cstart, const int64_t *goff,
+                                                  const int64_t *oo, long long n, long long nnz, PairLink *plink) {
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (long long)gridDim.x * kBlock) {
+        // the row owning e: the last x with off[x] <= e (its capacity is > 0)
+        long long lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const long long mid = (lo + hi) >> 1;
+            if ((long long)off[mid] <= e)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int x = (int)lo;
+        const int j = (int)(e - (long long)off[x]);
+        if (j >= deg[x]) continue;  // removed tail
+        const int y = col[e];
+        const int cx = lab[x];
+        if (lab[y] == cx) continue;  // own community
+        // first position in a's row (length da) holding an id >= key
+        auto lower = [&](int a, int da, int key) {
+            const int32_t *row = col + off[a];
+            int l = 0, h = da;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (row[mid] < key)
+                    l = mid + 1;
+                else
+                    h = mid;
+            }
+            return l;
+        };
+        const int dx = deg[x];
+        int kx = j;
+        if (y >= cstart[cx + 1]) kx -= lower(x, dx, cstart[cx + 1]) - lower(x, dx, cstart[cx]);
+        PairLink pl;
+        pl.e = (long long)off[y] + lower(y, deg[y], x);
+        pl.oo = (int)oo[y];
+        pl.on = (int)(oo[y + 1] - oo[y]);
+        plink[goff[x] + kx] = pl;
+    }
+}
+
+template <typename OffT>
+static rs_status links_t(rs_graph *g) {
+    DeviceGraph &D = g->d;
+    if (D.nnz == 0) return RS_OK;
+    const long long grid = std::min<long long>((D.nnz + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_links<OffT>, dim3((int)grid), dim3(kBlock), 0, g->stream, (const OffT *)D.off, D.deg,
+                       D.col, D.lab, D.cstart, D.goff, D.oo, (long long)D.n, (long long)D.nnz, D.plink);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "link-slot launch");
+}
+
+rs_status launch_links(rs_graph *g) { return g->d.off64 ? links_t<long long>(g) : links_t<int32_t>(g); }
+
 
 __global__ void k_zero_u64(unsigned long long *p, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
@@ -1239,7 +1403,8 @@ static rs_status score_pass_t(rs_graph *g) {
     A.reckey = D.reckey;
     A.recdat = D.recdat;
     A.card = D.card;
-    A.oo = D.oo;
+    A.goff = D.goff;
+    A.prec = D.prec;
     A.wown = D.wown;
     A.R = D.R;
     A.tI = D.tI;
@@ -1273,6 +1438,8 @@ static rs_status score_pass_t(rs_graph *g) {
     S.reckey = D.reckey;
     S.recdat = D.recdat;
     S.card = D.card;
+    S.prec = D.prec;
+    S.plink = D.plink;
     S.R = D.R;
     S.tI = D.tI;
     S.tII = D.tII;
@@ -1307,8 +1474,16 @@ rs_status launch_score_pass(rs_graph *g) {
 }
 
 rs_status launch_reduce_counts(rs_graph *g) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, g->stream, g->d.part_rows, g->grid_rows, g->d.ctr);
-    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, g->d.part_score, g->grid_score, g->d.ctr);
+    DeviceGraph &D = g->d;
+    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, g->stream, D.part_rows, g->grid_rows, D.ctr);
+    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, D.part_score, g->grid_score, D.ctr);
+    if (D.off64)
+        hipLaunchKernelGGL(k_work_I<long long>, dim3(kWorkBlocks), dim3(kBlock), 0, g->stream,
+                           (const long long *)D.off, D.col, D.card, (long long)D.n, D.wpart);
+    else
+        hipLaunchKernelGGL(k_work_I<int32_t>, dim3(kWorkBlocks), dim3(kBlock), 0, g->stream, (const int32_t *)D.off,
+                           D.col, D.card, (long long)D.n, D.wpart);
+    hipLaunchKernelGGL(k_reduce_work, dim3(1), dim3(kBlock), 0, g->stream, D.wpart, D.ctr);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "reduce launch");
 }

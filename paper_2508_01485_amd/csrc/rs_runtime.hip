@@ -176,8 +176,8 @@ struct HostGraph {
     std::vector<int32_t> new2old, old2new, comm2orig;
     std::vector<int2> rtv, stiles, schunk;
     std::vector<RowTile> rtiles;
-    std::vector<int64_t> oo;
-    std::vector<int32_t> outl;
+    std::vector<int64_t> oo, goff;
+    std::vector<int32_t> outl, cstart;
     std::vector<int32_t> rhubs, shubs, sfirst;
     int n_chunks_lds = 0;
 };
@@ -291,6 +291,13 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
                 }
             }
         });
+        // link slots: u's foreign entries in row order (the links themselves
+        // are built on the device)
+        H.goff.assign(n + 1, 0);
+        for (int64_t x = 0; x < n; ++x) H.goff[x + 1] = H.goff[x] + fgn[x];
+        if (H.oo[n] > (int64_t)INT32_MAX) return fail(RS_ERR_RANGE, "out-lists exceed 32-bit offsets");
+        H.cstart.resize(k + 1);
+        for (int64_t c = 0; c <= k; ++c) H.cstart[c] = (int32_t)start[c];
         cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs);
         H.rtiles.resize(H.rtv.size());
         for (size_t t = 0; t < H.rtv.size(); ++t) {
@@ -356,6 +363,11 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.shub_chunk, sizeof(int2) * nch},
         {(void **)&D.hub_part, sizeof(HubPart) * nch},
         {(void **)&D.oo, 8 * (N + 1)},
+        {(void **)&D.goff, 8 * (N + 1)},
+        {(void **)&D.prec, sizeof(PairRec) * Z},
+        {(void **)&D.plink, sizeof(PairLink) * std::max<size_t>((size_t)H.goff[n], 1)},
+        {(void **)&D.cstart, 4 * H.cstart.size()},
+        {(void **)&D.wpart, 8 * (size_t)kWorkBlocks},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
@@ -407,6 +419,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
     put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
     put(D.oo, H.oo.data(), 8 * H.oo.size());
+    put(D.goff, H.goff.data(), 8 * H.goff.size());
+    put(D.cstart, H.cstart.data(), 4 * H.cstart.size());
     std::vector<VCard> cards;
     try {
         cards.resize(n);
@@ -417,8 +431,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         VCard &c = cards[v];
         memset(&c, 0, sizeof(c));
         c.off = H.off[v];
-        c.oo = H.oo[v];
-        c.on = (int)(H.oo[v + 1] - H.oo[v]);
+        c.goff = H.goff[v];
         c.lab = H.lab[v];
     }
     put(D.card, cards.data(), sizeof(VCard) * cards.size());
@@ -433,6 +446,10 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * std::max(g->grid_score, 1), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
+    const rs_status rst = launch_links(g);  // each G' entry's reverse entry and out-list range
+    if (rst != RS_OK) return rst;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pair-slot map");
     g->h_new2old.swap(H.new2old);
     g->h_old2new.swap(H.old2new);
     g->h_comm2orig.swap(H.comm2orig);
@@ -634,6 +651,7 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
     if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
     if (st == RS_OK) st = launch_compact_rows(g);
+    if (st == RS_OK) st = launch_links(g);
     if (st == RS_OK) st = launch_score_pass(g);
     unsigned long long cnt[4] = {0, 0, 0, 0};
     if (st == RS_OK) {
