@@ -121,15 +121,21 @@ typedef struct {
     int64_t edges_removed;   /* distinct undirected edges deleted (including a removed vertex's edges) */
     int64_t edges_ignored;   /* batch edge entries that named no existing edge */
     int64_t vertices_removed;/* vertices newly removed */
-    int64_t affected;        /* vertices whose score was recomputed */
+    int64_t affected;        /* vertices whose score depends on the removed edges (re-scored) */
 } rs_removal_result;
 
 /*
  * rs_apply_removals: validate the whole batch (RS_ERR_RANGE for an id >= n,
  * RS_ERR_ARG for null arrays with non-zero counts) before mutating anything,
  * apply it, then re-score so that every reader and rs_topk reflect the
- * mutated graph exactly as a fresh full rs_score would.  Waits for the
- * stream.  RS_ERR_STATE before the first rs_score.
+ * mutated graph exactly as a fresh full rs_score would (bit for bit).  The
+ * re-score is incremental: rows are recomputed only for the endpoints of
+ * removed edges, and scores only for the vertices that depend on them (the
+ * endpoints, their neighbours in other communities, and the members of an
+ * endpoint's community adjacent to those neighbours); if w_max moves, every
+ * score is rescaled.  This follows the removal model of the experiments
+ * (Section V).  Waits for the stream.  RS_ERR_STATE before the first
+ * rs_score.
  */
 rs_status rs_apply_removals(rs_graph *g, const rs_removals *batch, rs_removal_result *res);
 

@@ -61,6 +61,13 @@ constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
 
+// Vertex marks of an incremental re-score (after removals).
+constexpr unsigned int kRowChanged = 1u;   // the row lost entries
+constexpr unsigned int kAffected = 2u;     // the score must be recomputed
+constexpr unsigned int kNearChanged = 4u;  // a neighbour's row changed: links move
+// Counters of an incremental re-score (ictr[]).
+enum IncCounter { kIcChanged = 0, kIcLinkRows, kIcRows, kIcMain, kIcBig, kIcAffected, kIcWmaxOld, kIcCount };
+
 // Grid of a tiled launch: one workgroup per hub, then the tiles rounded up to
 // a multiple of the 8 XCDs.
 inline int tile_grid(int hubs, int tiles) { return hubs + 8 * ((tiles + 7) / 8); }
@@ -198,11 +205,20 @@ struct DeviceGraph {
     PairLink *plink = nullptr;  // [link slots]
     int32_t *cstart = nullptr;  // [k+1] first internal id of each community
     unsigned long long *wpart = nullptr;  // [kWorkBlocks] partials of the on-demand W1 count
+    // incremental re-score
+    unsigned int *vmark = nullptr;          // [n] kRowChanged | kAffected | kNearChanged
+    int32_t *vrowb = nullptr;               // [n] row block of each vertex
+    int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
+    uint8_t *rflag = nullptr, *sflag = nullptr, *hflag = nullptr;  // unit flags
+    int32_t *elist = nullptr, *llist = nullptr;                   // [n] changed rows, rows whose links move
+    int32_t *rlist = nullptr, *slist = nullptr, *hlist = nullptr; // block lists
+    unsigned long long *ictr = nullptr;     // [kIcCount]
     int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
     VCard *card = nullptr;      // [n]
     double *wown = nullptr, *R = nullptr;
+    double *raw = nullptr;      // [n] Eq. RSI sums before the w_max and d(d-1) division
     long long *tI = nullptr, *tII = nullptr;
     RowPart *part_rows = nullptr;    // [row grid]
     unsigned long long *wmax_part = nullptr;  // [row grid] w_max bits per block
@@ -262,6 +278,19 @@ void timing_end(rs_graph *g, int kid, hipEvent_t ev);
 
 // Kernel launchers (rs_kernels.hip).  All enqueue on g->stream.
 rs_status launch_score_pass(rs_graph *g);
+// An incremental pass: the row blocks, the main score blocks and the big-hub
+// chunks to rerun (indices of the full launches), then w_max from every
+// block's partial and, if it moved from *wmax_old, every score rescaled.
+struct PassLists {
+    const int *rows;
+    int n_rows;
+    const int *main;
+    int n_main;
+    const int *big;
+    int n_big;
+    const unsigned long long *wmax_old;
+};
+rs_status launch_score_lists(rs_graph *g, const PassLists &inc);
 rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);
 rs_status launch_reduce_counts(rs_graph *g);
 rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t m,
@@ -270,6 +299,7 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
                                  unsigned long long *d_removed_edges);
 rs_status launch_compact_rows(rs_graph *g);
 rs_status launch_links(rs_graph *g);
+rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);
 

@@ -29,6 +29,15 @@
 namespace rs {
 
 // ------------------------------------------------------------ helpers
+// Blocks for a grid-stride loop over `items`: one per per_block items, at
+// least 1 and at most cap.
+static inline int grid_for(long long items, int per_block, int cap) {
+    long long g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -98,7 +107,8 @@ struct RowArgs {
     VCard *card;
     const int64_t *goff;
     PairRec *prec;     // pair facts at the foreign row entries, written by this pass
-    double *wown, *R;
+    const int *blist;  // incremental pass: the blocks to run (else every block)
+    double *wown, *R, *raw;
     long long *tI, *tII;
     RowPart *part;
     unsigned long long *wmax_part;  // [grid] w_max bits of each block (dense copy for k_wmax)
@@ -145,6 +155,7 @@ __device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d,
         acc.dp += (unsigned long long)dprime;
     } else {
         A.R[v] = 0.0;
+        A.raw[v] = 0.0;
         A.tI[v] = 0;
         A.tII[v] = 0;
     }
@@ -659,7 +670,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
     __shared__ RowTileShared S;
     RowAcc acc = {0.0, 0, 0, 0, 0};
-    const int b = (int)blockIdx.x;
+    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
     if (b < A.n_hubs) {
         hub_row(A, S, A.hubs[b], acc);
     } else {
@@ -718,7 +729,8 @@ struct ScoreArgs {
     const VCard *card;
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
-    double *R;
+    const int *blist;       // incremental pass: the blocks to run (else every block)
+    double *R, *raw;
     long long *tI, *tII;
     const DevCounters *ctr;
     ScorePart *part;
@@ -921,6 +933,7 @@ template <typename OffT>
 __device__ __forceinline__ void score_store(const ScoreArgs<OffT> &A, int u, int d, double acc, long long cI,
                                             long long cII, double wmax, ScoreAcc &sa) {
     A.R[u] = score_value(acc, d, wmax);
+    A.raw[u] = acc;
     A.tI[u] = cI;
     A.tII[u] = cII;
     sa.tI += cI;
@@ -1188,7 +1201,7 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
     __shared__ ScoreUnitShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0};
-    const int b = (int)blockIdx.x;
+    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
     const bool hub_unit = b < A.n_chunks_lds;
     const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
     if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax, sa);
@@ -1202,9 +1215,10 @@ __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int par
     __shared__ ScoreHubBigShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
     ScoreAcc sa = {0, 0};
-    const int2 hc = A.hub_chunk[A.n_chunks_lds + blockIdx.x];
+    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
+    const int2 hc = A.hub_chunk[A.n_chunks_lds + b];
     score_hub_big(A, S, hc.x, hc.y, wmax, sa);
-    block_reduce_score(sa, &A.part[part0 + blockIdx.x]);
+    block_reduce_score(sa, &A.part[part0 + b]);
 }
 
 // Each hub's score from its chunk partials (one wavefront per hub: lane l
@@ -1212,8 +1226,8 @@ __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int par
 // whose foreign list became empty keeps the zeros the row pass wrote.
 __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const int32_t *hub_first,
                                                     const HubPart *hub_part, int n_hubs, const VCard *card,
-                                                    const DevCounters *ctr, double *R, long long *tI,
-                                                    long long *tII) {
+                                                    const DevCounters *ctr, double *R, double *raw,
+                                                    long long *tI, long long *tII) {
     const int hub = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (hub >= n_hubs) return;
@@ -1237,6 +1251,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const i
         const VMeta m = card[u].m;
         if (m.deg - (m.q - m.p) > 0) {
             R[u] = score_value(acc, m.deg, bitsd(ctr->wmax_bits));
+            raw[u] = acc;
             tI[u] = c1;
             tII[u] = c2;
         }
@@ -1324,47 +1339,85 @@ __global__ __launch_bounds__(kBlock) void k_reduce_work(const unsigned long long
 // sorted, so positions are binary searches.  Run at load and after removals
 // (compaction shifts rows).
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_links(const OffT *off, const int32_t *deg, const int32_t *col,
-                                                  const int32_t *lab, const int32_t *cstart, const int64_t *goff,
-                                                  const int64_t *oo, long long n, long long nnz, PairLink *plink) {
+struct LinkArgs {
+    const OffT *off;
+    const int32_t *deg, *col, *lab, *cstart;
+    const int64_t *goff, *oo;
+    PairLink *plink;
+};
+
+// The link of x's row entry j (if it is a current foreign entry).
+template <typename OffT>
+__device__ __forceinline__ void link_entry(const LinkArgs<OffT> &L, int x, int j) {
+    if (j >= L.deg[x]) return;  // removed tail
+    const int y = L.col[(long long)L.off[x] + j];
+    const int cx = L.lab[x];
+    if (L.lab[y] == cx) return;  // own community
+    // first position in a's row (length da) holding an id >= key
+    auto lower = [&](int a, int da, int key) {
+        const int32_t *row = L.col + L.off[a];
+        int l = 0, h = da;
+        while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (row[mid] < key)
+                l = mid + 1;
+            else
+                h = mid;
+        }
+        return l;
+    };
+    const int dx = L.deg[x];
+    int kx = j;
+    if (y >= L.cstart[cx + 1]) kx -= lower(x, dx, L.cstart[cx + 1]) - lower(x, dx, L.cstart[cx]);
+    PairLink pl;
+    pl.e = (long long)L.off[y] + lower(y, L.deg[y], x);
+    pl.oo = (int)L.oo[y];
+    pl.on = (int)(L.oo[y + 1] - L.oo[y]);
+    L.plink[L.goff[x] + kx] = pl;
+}
+
+// Every entry (at load): the owning row is the last x with off[x] <= e.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_links(LinkArgs<OffT> L, long long n, long long nnz) {
     for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (long long)gridDim.x * kBlock) {
-        // the row owning e: the last x with off[x] <= e (its capacity is > 0)
         long long lo = 0, hi = n;
         while (hi - lo > 1) {
             const long long mid = (lo + hi) >> 1;
-            if ((long long)off[mid] <= e)
+            if ((long long)L.off[mid] <= e)
                 lo = mid;
             else
                 hi = mid;
         }
-        const int x = (int)lo;
-        const int j = (int)(e - (long long)off[x]);
-        if (j >= deg[x]) continue;  // removed tail
-        const int y = col[e];
-        const int cx = lab[x];
-        if (lab[y] == cx) continue;  // own community
-        // first position in a's row (length da) holding an id >= key
-        auto lower = [&](int a, int da, int key) {
-            const int32_t *row = col + off[a];
-            int l = 0, h = da;
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if (row[mid] < key)
-                    l = mid + 1;
-                else
-                    h = mid;
-            }
-            return l;
-        };
-        const int dx = deg[x];
-        int kx = j;
-        if (y >= cstart[cx + 1]) kx -= lower(x, dx, cstart[cx + 1]) - lower(x, dx, cstart[cx]);
-        PairLink pl;
-        pl.e = (long long)off[y] + lower(y, deg[y], x);
-        pl.oo = (int)oo[y];
-        pl.on = (int)(oo[y + 1] - oo[y]);
-        plink[goff[x] + kx] = pl;
+        link_entry(L, (int)lo, (int)(e - (long long)L.off[lo]));
     }
+}
+
+// The rows of a list (after removals): one wavefront per row.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const int32_t *rows,
+                                                       const unsigned long long *count) {
+    const long long nr = (long long)*count;
+    const int lane = threadIdx.x & 63;
+    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nr;
+         i += ((long long)gridDim.x * kBlock) >> 6) {
+        const int x = rows[i];
+        for (int j = lane; j < L.deg[x]; j += 64) link_entry(L, x, j);
+    }
+}
+
+template <typename OffT>
+static LinkArgs<OffT> link_args(rs_graph *g) {
+    DeviceGraph &D = g->d;
+    LinkArgs<OffT> L;
+    L.off = (const OffT *)D.off;
+    L.deg = D.deg;
+    L.col = D.col;
+    L.lab = D.lab;
+    L.cstart = D.cstart;
+    L.goff = D.goff;
+    L.oo = D.oo;
+    L.plink = D.plink;
+    return L;
 }
 
 template <typename OffT>
@@ -1372,8 +1425,8 @@ static rs_status links_t(rs_graph *g) {
     DeviceGraph &D = g->d;
     if (D.nnz == 0) return RS_OK;
     const long long grid = std::min<long long>((D.nnz + kBlock - 1) / kBlock, 65536);
-    hipLaunchKernelGGL(k_links<OffT>, dim3((int)grid), dim3(kBlock), 0, g->stream, (const OffT *)D.off, D.deg,
-                       D.col, D.lab, D.cstart, D.goff, D.oo, (long long)D.n, (long long)D.nnz, D.plink);
+    hipLaunchKernelGGL(k_links<OffT>, dim3((int)grid), dim3(kBlock), 0, g->stream, link_args<OffT>(g),
+                       (long long)D.n, (long long)D.nnz);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "link-slot launch");
 }
@@ -1385,9 +1438,23 @@ __global__ void k_zero_u64(unsigned long long *p, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
 }
 
+// After an incremental pass: when w_max changed, every R is recomputed from
+// its raw sum (the same expression as the pass, so the bits equal a full
+// pass's).  Raw sums are 0 for vertices without foreign neighbours.
+__global__ __launch_bounds__(kBlock) void k_rescale(const unsigned long long *wmax_old, const DevCounters *ctr,
+                                                    const VCard *card, const double *raw, double *R, long long n) {
+    const unsigned long long wb = ctr->wmax_bits;
+    if (wb == *wmax_old) return;
+    const double wmax = bitsd(wb);
+    for (long long u = (long long)blockIdx.x * kBlock + threadIdx.x; u < n; u += (long long)gridDim.x * kBlock) {
+        const VMeta m = card[u].m;
+        R[u] = m.deg - (m.q - m.p) > 0 ? score_value(raw[u], m.deg, wmax) : 0.0;
+    }
+}
+
 // ------------------------------------------------------------ pass launcher
 template <typename OffT>
-static rs_status score_pass_t(rs_graph *g) {
+static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     DeviceGraph &D = g->d;
     hipEvent_t ev;
     RowArgs<OffT> A;
@@ -1405,15 +1472,18 @@ static rs_status score_pass_t(rs_graph *g) {
     A.card = D.card;
     A.goff = D.goff;
     A.prec = D.prec;
+    A.blist = inc ? inc->rows : nullptr;
     A.wown = D.wown;
     A.R = D.R;
+    A.raw = D.raw;
     A.tI = D.tI;
     A.tII = D.tII;
     A.part = D.part_rows;
     A.wmax_part = D.wmax_part;
-    if (g->grid_rows > 0) {
+    const int grid_rows = inc ? inc->n_rows : g->grid_rows;
+    if (grid_rows > 0) {
         timing_begin(g, K_ROWS, &ev);
-        hipLaunchKernelGGL(k_rows<OffT>, dim3(g->grid_rows), dim3(kBlock), 0, g->stream, A);
+        hipLaunchKernelGGL(k_rows<OffT>, dim3(grid_rows), dim3(kBlock), 0, g->stream, A);
         timing_end(g, K_ROWS, ev);
     }
     timing_begin(g, K_WMAX, &ev);
@@ -1441,36 +1511,47 @@ static rs_status score_pass_t(rs_graph *g) {
     S.prec = D.prec;
     S.plink = D.plink;
     S.R = D.R;
+    S.raw = D.raw;
     S.tI = D.tI;
     S.tII = D.tII;
     S.ctr = D.ctr;
     S.part = D.part_score;
     const int n_big = g->n_schunks - g->n_schunks_lds;
     const int grid_main = g->grid_score - n_big;
-    if (n_big > 0) {
+    const int run_big = inc ? inc->n_big : n_big, run_main = inc ? inc->n_main : grid_main;
+    if (run_big > 0) {
+        S.blist = inc ? inc->big : nullptr;
         timing_begin(g, K_SCORE_HUB, &ev);
-        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(n_big), dim3(kBlock), 0, g->stream, S, grid_main);
+        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(run_big), dim3(kBlock), 0, g->stream, S, grid_main);
         timing_end(g, K_SCORE_HUB, ev);
     }
-    if (grid_main > 0) {
+    if (run_main > 0) {
+        S.blist = inc ? inc->main : nullptr;
         timing_begin(g, K_SCORE, &ev);
-        hipLaunchKernelGGL(k_score<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
+        hipLaunchKernelGGL(k_score<OffT>, dim3(run_main), dim3(kBlock), 0, g->stream, S);
         timing_end(g, K_SCORE, ev);
     }
     if (g->n_shubs > 0) {
         timing_begin(g, K_HUB_SUM, &ev);
         hipLaunchKernelGGL(k_hub_sum, dim3((g->n_shubs + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
-                           g->stream, D.shubs, D.shub_first, D.hub_part, g->n_shubs, D.card, D.ctr, D.R, D.tI,
-                           D.tII);
+                           g->stream, D.shubs, D.shub_first, D.hub_part, g->n_shubs, D.card, D.ctr, D.R, D.raw,
+                           D.tI, D.tII);
         timing_end(g, K_HUB_SUM, ev);
     }
+    if (inc && D.n > 0)  // w_max moved: every score is rescaled from its raw sum
+        hipLaunchKernelGGL(k_rescale, dim3(grid_for(D.n, kBlock, 4096)), dim3(kBlock), 0, g->stream, inc->wmax_old,
+                           D.ctr, D.card, D.raw, D.R, (long long)D.n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "score pass launch");
     return RS_OK;
 }
 
 rs_status launch_score_pass(rs_graph *g) {
-    return g->d.off64 ? score_pass_t<long long>(g) : score_pass_t<int32_t>(g);
+    return g->d.off64 ? score_pass_t<long long>(g, nullptr) : score_pass_t<int32_t>(g, nullptr);
+}
+
+rs_status launch_score_lists(rs_graph *g, const PassLists &inc) {
+    return g->d.off64 ? score_pass_t<long long>(g, &inc) : score_pass_t<int32_t>(g, &inc);
 }
 
 rs_status launch_reduce_counts(rs_graph *g) {
@@ -2124,12 +2205,6 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
     if (tid == 0) *flag = 1u;
 }
 
-static inline int grid_for(long long items, int per_block, int cap) {
-    long long g = (items + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (int)g;
-}
 
 static rs_status final_order(rs_graph *g, long long keff) {
     DeviceGraph &D = g->d;
@@ -2273,11 +2348,13 @@ __device__ __forceinline__ long long find_entry(const OffT *off, const int32_t *
     return -1;
 }
 
-// The out-lists that a removal must update.
+// The out-lists that a removal must update, and the marks of the vertices
+// whose rows change (bit kRowChanged).
 struct OutLists {
     const int32_t *lab;
     const int64_t *oo;
     int32_t *outl;
+    unsigned int *vmark;
 };
 
 // Tombstone y in out(x), if there; returns whether it was found.
@@ -2302,6 +2379,8 @@ __device__ __forceinline__ int delete_edge(const OffT *off, const int32_t *deg, 
     if (atomicCAS(&col[e], y, ~y) != y) return 0;
     const long long f = find_entry(off, deg, col, y, x);
     if (f >= 0) col[f] = ~x;
+    atomicOr(&O.vmark[x], kRowChanged);
+    atomicOr(&O.vmark[y], kRowChanged);
     if (O.lab[x] != O.lab[y] && !out_drop(O, x, y)) out_drop(O, y, x);
     return 1;
 }
@@ -2345,12 +2424,13 @@ __global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *
     }
 }
 
-// Squeeze the marked entries out of every row (order kept), updating deg;
-// the freed tail of the row's capacity is set to -1, which the row tiles
-// read as "no entry".
+// Squeeze the removed entries out of every changed row (order kept),
+// updating deg; the freed tail of the row's capacity is set to -1, which the
+// row tiles read as "no entry".
 template <typename OffT>
-__global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, long long n) {
+__global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, const unsigned int *vmark, long long n) {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+        if (!(vmark[v] & kRowChanged)) continue;
         const long long rb = (long long)off[v];
         const int d = deg[v];
         int w = 0;
@@ -2368,6 +2448,7 @@ static OutLists out_lists(rs_graph *g) {
     O.lab = g->d.lab;
     O.oo = g->d.oo;
     O.outl = g->d.outl;
+    O.vmark = g->d.vmark;
     return O;
 }
 
@@ -2404,12 +2485,179 @@ rs_status launch_compact_rows(rs_graph *g) {
     const int grid = grid_for(g->d.n, 256, 8192);
     if (g->d.off64)
         hipLaunchKernelGGL(k_compact<long long>, dim3(grid), dim3(256), 0, g->stream, (const long long *)g->d.off,
-                           g->d.deg, g->d.col, (long long)g->d.n);
+                           g->d.deg, g->d.col, g->d.vmark, (long long)g->d.n);
     else
         hipLaunchKernelGGL(k_compact<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, (long long)g->d.n);
+                           g->d.deg, g->d.col, g->d.vmark, (long long)g->d.n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "compact launch");
+}
+
+// ------------------------------------------------------------ incremental re-score
+// After a removal batch only some results change.  With E the vertices whose
+// rows changed (endpoints of removed edges), a vertex u needs a new score iff
+//   u is in E, or u has a foreign neighbour in E (u's pair facts, type-I
+//   weights or out-lists involve it), or u is in the community of some v in
+//   E and adjacent to a foreign neighbour w of v (u's pair (u, w) sums a_v);
+// rows need recomputing only for E; the links of every row in or next to E.
+// The affected row tiles, score tiles and hub chunks are rerun whole, with
+// the block indices of the full launch, so every result and every partial is
+// what a full pass would give.
+
+// Append the vertices whose mark has one of `bits` to list (any order).
+__global__ __launch_bounds__(kBlock) void k_list_marked(const unsigned int *vmark, unsigned int bits, long long n,
+                                                        int32_t *list, unsigned long long *count) {
+    const int lane = threadIdx.x & 63;
+    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
+        const long long v = base + threadIdx.x;
+        const bool in = v < n && (vmark[v] & bits) != 0u;
+        const unsigned long long m = __ballot(in);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned long long pos = 0;
+        if (lane == leader) pos = atomicAdd(count, (unsigned long long)__popcll(m));
+        pos = __shfl(pos, leader);
+        if (in) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)v;
+    }
+}
+
+// A changed vertex x: x and its foreign neighbours are affected; every
+// neighbour's links change.  One wavefront per listed vertex.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_mark_nbrs(const OffT *off, const int32_t *deg, const int32_t *col,
+                                                      const int32_t *lab, unsigned int *vmark, const int32_t *list,
+                                                      const unsigned long long *count) {
+    const long long nl = (long long)*count;
+    const int lane = threadIdx.x & 63;
+    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nl;
+         i += ((long long)gridDim.x * kBlock) >> 6) {
+        const int x = list[i];
+        if (lane == 0) atomicOr(&vmark[x], kAffected);
+        const long long rb = (long long)off[x];
+        const int cx = lab[x];
+        for (int j = lane; j < deg[x]; j += 64) {
+            const int y = col[rb + j];
+            atomicOr(&vmark[y], lab[y] != cx ? (kNearChanged | kAffected) : kNearChanged);
+        }
+    }
+}
+
+// A changed vertex v and each foreign neighbour w: the members of C(v) in w's
+// row (an id range, found by binary search) are affected.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_mark_runs(const OffT *off, const int32_t *deg, const int32_t *col,
+                                                      const int32_t *lab, const int32_t *cstart, unsigned int *vmark,
+                                                      const int32_t *list, const unsigned long long *count) {
+    const long long nl = (long long)*count;
+    const int lane = threadIdx.x & 63;
+    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nl;
+         i += ((long long)gridDim.x * kBlock) >> 6) {
+        const int v = list[i];
+        const int c = lab[v];
+        const int id0 = cstart[c], id1 = cstart[c + 1];
+        const long long rb = (long long)off[v];
+        for (int j = lane; j < deg[v]; j += 64) {
+            const int w = col[rb + j];
+            if (lab[w] == c) continue;
+            const int32_t *row = col + off[w];
+            const int dw = deg[w];
+            int a = 0, b = dw;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (row[mid] < id0)
+                    a = mid + 1;
+                else
+                    b = mid;
+            }
+            for (int t = a; t < dw && row[t] < id1; ++t) atomicOr(&vmark[row[t]], kAffected);
+        }
+    }
+}
+
+// Marks -> units: a changed row flags its row block; an affected vertex its
+// score tile block or all chunks of its score hub.  Counts the affected
+// vertices, clears the marks and keeps w_max before the pass.
+__global__ __launch_bounds__(kBlock) void k_units(unsigned int *vmark, const int32_t *vrowb, const int32_t *vscore,
+                                                  long long n, uint8_t *rflag, uint8_t *sflag, uint8_t *hflag,
+                                                  unsigned long long *ictr, const DevCounters *ctr) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ictr[kIcWmaxOld] = ctr->wmax_bits;
+    unsigned long long aff = 0;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
+        const unsigned int m = vmark[v];
+        if (!m) continue;
+        vmark[v] = 0u;
+        if (m & kRowChanged) rflag[vrowb[v]] = 1;
+        if (m & kAffected) {
+            ++aff;
+            const int sc = vscore[v];
+            if (sc >= 0)
+                sflag[sc] = 1;
+            else
+                hflag[-1 - sc] = 1;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) aff += __shfl_xor(aff, o);
+    if ((threadIdx.x & 63) == 0 && aff) atomicAdd(&ictr[kIcAffected], aff);
+}
+
+// Flags -> block lists of the full launches (row blocks; main score blocks,
+// LDS-hub chunks included; big-hub chunks); the flags are cleared.
+__global__ __launch_bounds__(kBlock) void k_unit_lists(uint8_t *rflag, int n_rows, uint8_t *sflag, int n_main,
+                                                       uint8_t *hflag, int n_hubs, const int32_t *hub_first,
+                                                       int n_chunks_lds, int32_t *rlist, int32_t *slist,
+                                                       int32_t *hlist, unsigned long long *ictr) {
+    const int top = max(n_rows, max(n_main, n_hubs));
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < top; i += gridDim.x * kBlock) {
+        if (i < n_rows && rflag[i]) {
+            rflag[i] = 0;
+            rlist[atomicAdd(&ictr[kIcRows], 1ull)] = i;
+        }
+        if (i < n_main && sflag[i]) {
+            sflag[i] = 0;
+            slist[atomicAdd(&ictr[kIcMain], 1ull)] = i;
+        }
+        if (i < n_hubs && hflag[i]) {
+            hflag[i] = 0;
+            for (int c = hub_first[i]; c < hub_first[i + 1]; ++c) {
+                if (c < n_chunks_lds)
+                    slist[atomicAdd(&ictr[kIcMain], 1ull)] = c;
+                else
+                    hlist[atomicAdd(&ictr[kIcBig], 1ull)] = c - n_chunks_lds;
+            }
+        }
+    }
+}
+
+template <typename OffT>
+static rs_status incremental_marks_t(rs_graph *g) {
+    DeviceGraph &D = g->d;
+    if (D.n == 0) return RS_OK;
+    const OffT *off = (const OffT *)D.off;
+    const int gn = grid_for(D.n, kBlock, 4096);
+    hipLaunchKernelGGL(k_list_marked, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, kRowChanged, (long long)D.n,
+                       D.elist, &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_mark_nbrs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.vmark,
+                       D.elist, &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_mark_runs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.cstart,
+                       D.vmark, D.elist, &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_list_marked, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, kRowChanged | kNearChanged,
+                       (long long)D.n, D.llist, &D.ictr[kIcLinkRows]);
+    hipLaunchKernelGGL(k_links_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.llist,
+                       &D.ictr[kIcLinkRows]);
+    hipLaunchKernelGGL(k_units, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb, D.vscore, (long long)D.n,
+                       D.rflag, D.sflag, D.hflag, D.ictr, D.ctr);
+    const int n_big = g->n_schunks - g->n_schunks_lds;
+    const int n_main = g->grid_score - n_big;
+    const int top = std::max(g->grid_rows, std::max(n_main, g->n_shubs));
+    hipLaunchKernelGGL(k_unit_lists, dim3(grid_for(top, kBlock, 4096)), dim3(kBlock), 0, g->stream, D.rflag,
+                       g->grid_rows, D.sflag, n_main, D.hflag, g->n_shubs, D.shub_first, g->n_schunks_lds, D.rlist,
+                       D.slist, D.hlist, D.ictr);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "incremental marks launch");
+}
+
+rs_status launch_incremental_marks(rs_graph *g) {
+    return g->d.off64 ? incremental_marks_t<long long>(g) : incremental_marks_t<int32_t>(g);
 }
 
 // ============================================================ readers

@@ -178,6 +178,7 @@ struct HostGraph {
     std::vector<RowTile> rtiles;
     std::vector<int64_t> oo, goff;
     std::vector<int32_t> outl, cstart;
+    std::vector<int32_t> vrowb, vscore;  // the row block and score unit of each vertex
     std::vector<int32_t> rhubs, shubs, sfirst;
     int n_chunks_lds = 0;
 };
@@ -320,6 +321,24 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
             H.sfirst.push_back((int32_t)H.schunk.size());
             if (fgn[H.shubs[h]] <= kHubList) H.n_chunks_lds = (int)H.schunk.size();
         }
+        // the block of the full launch that handles each vertex: hubs take
+        // the first blocks, tile t of XCD x = t / per runs at block
+        // hubs + 8 (t % per) + ((x - hubs) mod 8) (the inverse of the
+        // kernels' block-to-tile map)
+        auto tile_block = [](int64_t t, int64_t n_tiles, int64_t hubs) {
+            const int64_t per = (n_tiles + 7) / 8, x = t / per, q = t % per;
+            return (int32_t)(hubs + 8 * q + (((x - hubs) % 8 + 8) % 8));
+        };
+        H.vrowb.assign(n, 0);
+        for (size_t h = 0; h < H.rhubs.size(); ++h) H.vrowb[H.rhubs[h]] = (int32_t)h;
+        for (size_t t = 0; t < H.rtv.size(); ++t)
+            for (int v = H.rtv[t].x; v < H.rtv[t].y; ++v)
+                H.vrowb[v] = tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size());
+        H.vscore.assign(n, 0);
+        for (size_t h = 0; h < H.shubs.size(); ++h) H.vscore[H.shubs[h]] = -1 - (int32_t)h;
+        for (size_t t = 0; t < H.stiles.size(); ++t)
+            for (int v = H.stiles[t].x; v < H.stiles[t].y; ++v)
+                H.vscore[v] = tile_block((int64_t)t, (int64_t)H.stiles.size(), (int64_t)H.n_chunks_lds);
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -368,6 +387,19 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.plink, sizeof(PairLink) * std::max<size_t>((size_t)H.goff[n], 1)},
         {(void **)&D.cstart, 4 * H.cstart.size()},
         {(void **)&D.wpart, 8 * (size_t)kWorkBlocks},
+        {(void **)&D.raw, 8 * N},
+        {(void **)&D.vmark, 4 * N},
+        {(void **)&D.vrowb, 4 * N},
+        {(void **)&D.vscore, 4 * N},
+        {(void **)&D.rflag, (size_t)std::max(g->grid_rows, 1)},
+        {(void **)&D.sflag, (size_t)std::max(g->grid_score, 1)},
+        {(void **)&D.hflag, nsh},
+        {(void **)&D.elist, 4 * N},
+        {(void **)&D.llist, 4 * N},
+        {(void **)&D.rlist, 4 * (size_t)std::max(g->grid_rows, 1)},
+        {(void **)&D.slist, 4 * (size_t)std::max(g->grid_score, 1)},
+        {(void **)&D.hlist, 4 * nch},
+        {(void **)&D.ictr, 8 * (size_t)kIcCount},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
@@ -421,6 +453,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     put(D.oo, H.oo.data(), 8 * H.oo.size());
     put(D.goff, H.goff.data(), 8 * H.goff.size());
     put(D.cstart, H.cstart.data(), 4 * H.cstart.size());
+    put(D.vrowb, H.vrowb.data(), 4 * H.vrowb.size());
+    put(D.vscore, H.vscore.data(), 4 * H.vscore.size());
     std::vector<VCard> cards;
     try {
         cards.resize(n);
@@ -439,6 +473,10 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     put(D.outl, H.outl.data(), 4 * H.outl.size());
     put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.vmark, 0, 4 * N, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.rflag, 0, (size_t)std::max(g->grid_rows, 1), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.sflag, 0, (size_t)std::max(g->grid_score, 1), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.hflag, 0, nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist_c, 0, 4 * 256, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
@@ -647,12 +685,31 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     if (e == hipSuccess && m) e = hipMemcpyAsync(d_buf + m, ed.data(), 4 * m, hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess && nv) e = hipMemcpyAsync(d_buf + 2 * m, vs.data(), 4 * nv, hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long), g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->d.ictr, 0, 8 * (size_t)kIcCount, g->stream);
     rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "removal upload");
+    // remove (marking the rows that change), compact those rows, then find
+    // what must be recomputed and rerun only that
     if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
     if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
     if (st == RS_OK) st = launch_compact_rows(g);
-    if (st == RS_OK) st = launch_links(g);
-    if (st == RS_OK) st = launch_score_pass(g);
+    if (st == RS_OK) st = launch_incremental_marks(g);
+    unsigned long long ic[kIcCount] = {};
+    if (st == RS_OK) {
+        e = hipMemcpyAsync(ic, g->d.ictr, sizeof(ic), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "incremental counts");
+    }
+    if (st == RS_OK) {
+        PassLists L;
+        L.rows = g->d.rlist;
+        L.n_rows = (int)ic[kIcRows];
+        L.main = g->d.slist;
+        L.n_main = (int)ic[kIcMain];
+        L.big = g->d.hlist;
+        L.n_big = (int)ic[kIcBig];
+        L.wmax_old = &g->d.ictr[kIcWmaxOld];
+        st = launch_score_lists(g, L);
+    }
     unsigned long long cnt[4] = {0, 0, 0, 0};
     if (st == RS_OK) {
         e = hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, g->stream);
@@ -667,7 +724,7 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
         res->edges_removed = (int64_t)(cnt[0] + cnt[2]);
         res->edges_ignored = m - (int64_t)cnt[0];
         res->vertices_removed = (int64_t)cnt[3];
-        res->affected = n;
+        res->affected = (int64_t)ic[kIcAffected];
     }
     return RS_OK;
 }

@@ -334,6 +334,72 @@ def test_removals_on_triangle_rich_hubs(rs):
     topk_matches(ids1, exp_ids, ora["R"], 50, alive=alive)
 
 
+def _apply_and_check_full(rs, h):
+    """After rs_apply_removals: a full pass gives the same bits and counts."""
+    R1 = rs.rs_read_scores(h)
+    c1 = rs.rs_read_vertex_counts(h)
+    k1 = rs.rs_read_counts(h)
+    rs.rs_score(h)
+    assert rs.rs_read_scores(h).tobytes() == R1.tobytes()
+    c2 = rs.rs_read_vertex_counts(h)
+    for key in ("border", "ell", "dprime", "tI", "tII"):
+        assert np.array_equal(c1[key], c2[key]), key
+    k2 = rs.rs_read_counts(h)
+    for key in ("n_border", "m_inter", "sum_ell", "sum_tI", "sum_tII", "omega_max"):
+        assert k1[key] == k2[key], key
+    return R1, c1, k1
+
+
+def test_incremental_removals(rs):
+    """rs_apply_removals re-scores only the vertices that depend on the
+    removed edges, and the result equals a full pass bit for bit: one edge,
+    a batch that moves w_max (rescaling every score), then several batches
+    in a row, each against the oracle on the mutated graph."""
+    g = lfr(20000, 14.0, 400, 0.25, seed=33, cmin=10, cmax=500)
+    rng = np.random.default_rng(7)
+    h = rs.rs_load_graph(g.off, g.col, g.labels)
+    try:
+        rs.rs_score(h)
+        w0 = rs.rs_read_counts(h)["omega_max"]
+        gu, gv = g.edges()
+        keep = np.ones(gu.size, bool)
+        dead = np.zeros(g.n, bool)
+        # one cross-community edge
+        cross = np.flatnonzero(g.labels[gu] != g.labels[gv])
+        i0 = int(cross[0])
+        res = rs.rs_apply_removals(h, edges=[[gu[i0], gv[i0]]])
+        assert res["edges_removed"] == 1 and 0 < res["affected"] < g.n // 10, res
+        keep[i0] = False
+        _apply_and_check_full(rs, h)
+        # the vertices holding the largest weights lose their edges: w_max moves
+        ora = oracle.score(g, rows=True)
+        ho = ora["hist_off"]
+        seg = np.zeros(g.n)
+        nz = np.flatnonzero(ho[1:] > ho[:-1])
+        seg[nz] = np.maximum.reduceat(ora["hist_w"], ho[:-1][nz])
+        vmax = np.where(ora["border"] > 0, np.maximum(ora["w_own"], seg), 0.0)
+        top = np.argsort(-vmax, kind="stable")[:20]
+        res = rs.rs_apply_removals(h, vertices=top)
+        dead[top] = True
+        keep &= ~dead[gu] & ~dead[gv]
+        _, _, k = _apply_and_check_full(rs, h)
+        assert k["omega_max"] != w0
+        # three more batches
+        for b in range(3):
+            live = np.flatnonzero(keep)
+            pick = rng.choice(live, 150, replace=False)
+            rs.rs_apply_removals(h, edges=np.stack([gu[pick], gv[pick]], 1))
+            keep[pick] = False
+            R1, c1, _ = _apply_and_check_full(rs, h)
+            g2 = from_edges(g.n, np.stack([gu[keep], gv[keep]], 1), g.labels)
+            o2 = oracle.score(g2)
+            rel_close(R1, o2["R"], 1e-6)
+            assert np.array_equal(c1["tI"], o2["tI"]) and np.array_equal(c1["tII"], o2["tII"])
+            _say(f"[parity] incremental batch {b}: ok")
+    finally:
+        h.free()
+
+
 def test_error_paths_on_device(rs):
     g = cfg_sbm_small(2)
     h = rs.rs_load_graph(g.off, g.col, g.labels)
