@@ -163,6 +163,39 @@ def cpu_baseline_sampled(g, k_top, cores, s1=20_000, s2=60_000):
                        f"({t_full:.1f}s) plus top-{k_top}")}
 
 
+def rescore_latency(rs, h, g, n_req, seed=11):
+    """Re-score latency on the resident graph: a stream of removal requests,
+    each either 1-1,000 random existing edges or 1-50 vertices drawn from the
+    current top-1,000 (half each), applied with rs_apply_removals (validation,
+    upload, incremental re-score) and followed by a top-100 query; the wall
+    time of both is one request's latency.  Runs after the timed steps (it
+    mutates the graph)."""
+    rng = np.random.default_rng(seed)
+    u, v = g.edges()
+    alive = np.ones(u.size, bool)
+    lat, aff = [], []
+    for _ in range(n_req):
+        if rng.random() < 0.5:
+            live = np.flatnonzero(alive)
+            k = min(int(rng.integers(1, 1001)), live.size)
+            pick = rng.choice(live, k, replace=False)
+            alive[pick] = False
+            kw = {"edges": np.stack([u[pick], v[pick]], 1)}
+        else:
+            ids, _ = rs.rs_topk(h, 1000)
+            k = min(int(rng.integers(1, 51)), ids.size)
+            kw = {"vertices": rng.choice(ids, k, replace=False)}
+        t0 = time.perf_counter()
+        res = rs.rs_apply_removals(h, **kw)
+        rs.rs_topk(h, 100)
+        lat.append(time.perf_counter() - t0)
+        aff.append(res["affected"])
+    return {"p50": 1000 * float(np.percentile(lat, 50)), "p99": 1000 * float(np.percentile(lat, 99)),
+            "mean": 1000 * float(np.mean(lat)), "requests": n_req, "mean_affected": float(np.mean(aff)),
+            "request": "half: 1-1,000 random existing edges; half: 1-50 vertices of the current top-1,000; "
+                       "then a top-100 query"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +204,8 @@ def main():
     ap.add_argument("--workload", default="lfr_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--rescore-requests", type=int, default=None,
+                    help="removal requests timed after the steps (0: skip; default 200, 20 above 1e8 entries)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build scores one resident graph per device and "
@@ -264,6 +299,10 @@ def main():
                  "alg_GBs": kb["pass"] / (gpu_ms * 1e-3) / 1e9 if gpu_ms else None},
         "counts": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in counts.items()},
     }
+    n_req = args.rescore_requests if args.rescore_requests is not None else (200 if g.nnz < 100_000_000 else 20)
+    if n_req > 0:
+        log(f"timing {n_req} removal + incremental re-score requests")
+        out["rescore_latency_ms"] = rescore_latency(rs, h, g, n_req)
     rs.rs_free_graph(h)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

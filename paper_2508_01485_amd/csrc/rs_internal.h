@@ -263,6 +263,14 @@ struct rs_graph {
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;
     int64_t hpin_cap = 0;
+    // removal batches: device staging kept between calls (grown on demand),
+    // pinned host staging of the batch and of the counts read back
+    int32_t *rem_buf = nullptr;
+    int64_t rem_cap = 0;
+    int32_t *rem_host = nullptr;
+    int64_t rem_host_cap = 0;
+    unsigned long long *rem_cnt = nullptr;       // device [4]: edges removed, -, edges of removed vertices, vertices
+    unsigned long long *rem_cnt_host = nullptr;  // pinned [4 + kIcCount]
 };
 
 namespace rs {
@@ -297,7 +305,6 @@ rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *
                               unsigned long long *d_removed);
 rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv,
                                  unsigned long long *d_removed_edges);
-rs_status launch_compact_rows(rs_graph *g);
 rs_status launch_links(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);

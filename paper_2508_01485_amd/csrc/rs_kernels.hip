@@ -1392,7 +1392,9 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs<OffT> L, long long n,
     }
 }
 
-// The rows of a list (after removals): one wavefront per row.
+// After removals, for every changed (compacted) row y: the links of y's own
+// foreign entries, and, in each foreign neighbour x's link to y, the index
+// of the entry (y, x), which moved with y's row.  One wavefront per row.
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const int32_t *rows,
                                                        const unsigned long long *count) {
@@ -1400,8 +1402,32 @@ __global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const i
     const int lane = threadIdx.x & 63;
     for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nr;
          i += ((long long)gridDim.x * kBlock) >> 6) {
-        const int x = rows[i];
-        for (int j = lane; j < L.deg[x]; j += 64) link_entry(L, x, j);
+        const int y = rows[i];
+        const long long rb = (long long)L.off[y];
+        const int cy = L.lab[y];
+        for (int j = lane; j < L.deg[y]; j += 64) {
+            link_entry(L, y, j);
+            const int x = L.col[rb + j];
+            const int cx = L.lab[x];
+            if (cx == cy) continue;
+            // y's index among x's foreign entries
+            const int32_t *row = L.col + L.off[x];
+            const int dx = L.deg[x];
+            auto lower = [&](int key) {
+                int l = 0, h = dx;
+                while (l < h) {
+                    const int mid = (l + h) >> 1;
+                    if (row[mid] < key)
+                        l = mid + 1;
+                    else
+                        h = mid;
+                }
+                return l;
+            };
+            int kx = lower(y);
+            if (y >= L.cstart[cx + 1]) kx -= lower(L.cstart[cx + 1]) - lower(L.cstart[cx]);
+            L.plink[L.goff[x] + kx].e = rb + j;
+        }
     }
 }
 
@@ -2424,25 +2450,6 @@ __global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *
     }
 }
 
-// Squeeze the removed entries out of every changed row (order kept),
-// updating deg; the freed tail of the row's capacity is set to -1, which the
-// row tiles read as "no entry".
-template <typename OffT>
-__global__ void k_compact(const OffT *off, int32_t *deg, int32_t *col, const unsigned int *vmark, long long n) {
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
-        if (!(vmark[v] & kRowChanged)) continue;
-        const long long rb = (long long)off[v];
-        const int d = deg[v];
-        int w = 0;
-        for (int j = 0; j < d; ++j) {
-            const int x = col[rb + j];
-            if (x >= 0) col[rb + (w++)] = x;
-        }
-        for (int j = w; j < d; ++j) col[rb + j] = -1;
-        deg[v] = w;
-    }
-}
-
 static OutLists out_lists(rs_graph *g) {
     OutLists O;
     O.lab = g->d.lab;
@@ -2481,17 +2488,6 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
     return e == hipSuccess ? RS_OK : hip_fail(e, "remove vertices launch");
 }
 
-rs_status launch_compact_rows(rs_graph *g) {
-    const int grid = grid_for(g->d.n, 256, 8192);
-    if (g->d.off64)
-        hipLaunchKernelGGL(k_compact<long long>, dim3(grid), dim3(256), 0, g->stream, (const long long *)g->d.off,
-                           g->d.deg, g->d.col, g->d.vmark, (long long)g->d.n);
-    else
-        hipLaunchKernelGGL(k_compact<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, g->d.vmark, (long long)g->d.n);
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? RS_OK : hip_fail(e, "compact launch");
-}
 
 // ------------------------------------------------------------ incremental re-score
 // After a removal batch only some results change.  With E the vertices whose
@@ -2499,30 +2495,65 @@ rs_status launch_compact_rows(rs_graph *g) {
 //   u is in E, or u has a foreign neighbour in E (u's pair facts, type-I
 //   weights or out-lists involve it), or u is in the community of some v in
 //   E and adjacent to a foreign neighbour w of v (u's pair (u, w) sums a_v);
-// rows need recomputing only for E; the links of every row in or next to E.
+// rows need recomputing only for E, and links only for E's entries and the
+// neighbours' links back to E.
 // The affected row tiles, score tiles and hub chunks are rerun whole, with
 // the block indices of the full launch, so every result and every partial is
 // what a full pass would give.
 
-// Append the vertices whose mark has one of `bits` to list (any order).
+// Append the vertices whose mark has one of `bits` to list (any order; one
+// atomic per workgroup and step).
 __global__ __launch_bounds__(kBlock) void k_list_marked(const unsigned int *vmark, unsigned int bits, long long n,
                                                         int32_t *list, unsigned long long *count) {
-    const int lane = threadIdx.x & 63;
+    __shared__ unsigned int s_cnt[kBlock / 64];
+    __shared__ unsigned long long s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
         const long long v = base + threadIdx.x;
         const bool in = v < n && (vmark[v] & bits) != 0u;
         const unsigned long long m = __ballot(in);
-        if (!m) continue;
-        const int leader = __ffsll((long long)m) - 1;
-        unsigned long long pos = 0;
-        if (lane == leader) pos = atomicAdd(count, (unsigned long long)__popcll(m));
-        pos = __shfl(pos, leader);
-        if (in) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)v;
+        if (lane == 0) s_cnt[wave] = (unsigned int)__popcll(m);
+        __syncthreads();
+        unsigned int before = 0, total = 0;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            if (i < wave) before += s_cnt[i];
+            total += s_cnt[i];
+        }
+        if (threadIdx.x == 0 && total) s_base = atomicAdd(count, (unsigned long long)total);
+        __syncthreads();
+        if (in) list[s_base + before + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)v;
+        __syncthreads();
     }
 }
 
-// A changed vertex x: x and its foreign neighbours are affected; every
-// neighbour's links change.  One wavefront per listed vertex.
+// Compact the listed changed rows (removed entries are complemented, < 0):
+// one wavefront per row, 64 entries at a time (ballot and prefix); the freed
+// tail of the capacity is set to -1.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_t *deg, int32_t *col,
+                                                         const int32_t *list, const unsigned long long *count) {
+    const long long nl = (long long)*count;
+    const int lane = threadIdx.x & 63;
+    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nl;
+         i += ((long long)gridDim.x * kBlock) >> 6) {
+        const int v = list[i];
+        const long long rb = (long long)off[v];
+        const int d = deg[v];
+        int w = 0;
+        for (int j0 = 0; j0 < d; j0 += 64) {
+            const int j = j0 + lane;
+            const int x = j < d ? col[rb + j] : -1;
+            const unsigned long long m = __ballot(x >= 0);
+            if (x >= 0) col[rb + w + __popcll(m & ((1ull << lane) - 1ull))] = x;
+            w += __popcll(m);
+        }
+        for (int j = w + lane; j < d; j += 64) col[rb + j] = -1;
+        if (lane == 0) deg[v] = w;
+    }
+}
+
+// A changed vertex x: x and its foreign neighbours are affected (the
+// neighbours are also marked kNearChanged).  One wavefront per listed vertex.
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_mark_nbrs(const OffT *off, const int32_t *deg, const int32_t *col,
                                                       const int32_t *lab, unsigned int *vmark, const int32_t *list,
@@ -2596,8 +2627,15 @@ __global__ __launch_bounds__(kBlock) void k_units(unsigned int *vmark, const int
                 hflag[-1 - sc] = 1;
         }
     }
+    __shared__ unsigned long long s_aff[kBlock / 64];
     for (int o = 32; o > 0; o >>= 1) aff += __shfl_xor(aff, o);
-    if ((threadIdx.x & 63) == 0 && aff) atomicAdd(&ictr[kIcAffected], aff);
+    if ((threadIdx.x & 63) == 0) s_aff[threadIdx.x >> 6] = aff;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / 64; ++i) t += s_aff[i];
+        if (t) atomicAdd(&ictr[kIcAffected], t);
+    }
 }
 
 // Flags -> block lists of the full launches (row blocks; main score blocks,
@@ -2633,18 +2671,19 @@ static rs_status incremental_marks_t(rs_graph *g) {
     DeviceGraph &D = g->d;
     if (D.n == 0) return RS_OK;
     const OffT *off = (const OffT *)D.off;
-    const int gn = grid_for(D.n, kBlock, 4096);
+    const int gn = grid_for(D.n, kBlock, 1024);
     hipLaunchKernelGGL(k_list_marked, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, kRowChanged, (long long)D.n,
                        D.elist, &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_compact_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.elist,
+                       &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_mark_nbrs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.vmark,
                        D.elist, &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_mark_runs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.cstart,
                        D.vmark, D.elist, &D.ictr[kIcChanged]);
-    hipLaunchKernelGGL(k_list_marked, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, kRowChanged | kNearChanged,
-                       (long long)D.n, D.llist, &D.ictr[kIcLinkRows]);
-    hipLaunchKernelGGL(k_links_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.llist,
-                       &D.ictr[kIcLinkRows]);
-    hipLaunchKernelGGL(k_units, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb, D.vscore, (long long)D.n,
+    hipLaunchKernelGGL(k_links_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.elist,
+                       &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_units, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb,
+                       D.vscore, (long long)D.n,
                        D.rflag, D.sflag, D.hflag, D.ictr, D.ctr);
     const int n_big = g->n_schunks - g->n_schunks_lds;
     const int n_main = g->grid_score - n_big;

@@ -77,6 +77,12 @@ static void release(rs_graph *g) {
     if (g->hpin) (void)hipHostFree(g->hpin);
     g->hpin = nullptr;
     g->hpin_cap = 0;
+    if (g->rem_buf) (void)hipFree(g->rem_buf);
+    if (g->rem_host) (void)hipHostFree(g->rem_host);
+    if (g->rem_cnt_host) (void)hipHostFree(g->rem_cnt_host);
+    g->rem_buf = g->rem_host = nullptr;
+    g->rem_cnt_host = nullptr;
+    g->rem_cap = g->rem_host_cap = 0;
     for (hipEvent_t e : g->timing.pool) (void)hipEventDestroy(e);
     for (auto &pe : g->timing.pending) {
         (void)hipEventDestroy(pe.second.first);
@@ -400,6 +406,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
         {(void **)&D.slist, 4 * (size_t)std::max(g->grid_score, 1)},
         {(void **)&D.hlist, 4 * nch},
         {(void **)&D.ictr, 8 * (size_t)kIcCount},
+        {(void **)&g->rem_cnt, 8 * 4},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
@@ -427,6 +434,13 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     for (auto &r : reqs) {
         hipError_t e = dev_alloc(g, r.p, r.bytes);
         if (e != hipSuccess) return hip_fail(e, "device allocation");
+    }
+    {
+        const hipError_t eh = hipHostMalloc((void **)&g->rem_cnt_host, 8 * (4 + (size_t)kIcCount), hipHostMallocDefault);
+        if (eh != hipSuccess) {
+            g->rem_cnt_host = nullptr;
+            return hip_fail(eh, "pinned counters");
+        }
     }
     std::vector<int32_t> off32, deg(n);
     for (int64_t v = 0; v < n; ++v) deg[v] = (int32_t)(H.off[v + 1] - H.off[v]);
@@ -673,29 +687,40 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     std::sort(vs.begin(), vs.end());
     vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
     const int64_t m = b->n_edges, nv = (int64_t)vs.size();
-    int32_t *d_buf = nullptr;
-    unsigned long long *d_cnt = nullptr;
-    hipError_t e = hipMalloc((void **)&d_buf, 4 * (size_t)std::max<int64_t>(2 * m + nv, 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&d_cnt, 4 * sizeof(unsigned long long));
-    if (e != hipSuccess) {
-        if (d_buf) (void)hipFree(d_buf);
-        return hip_fail(e, "removal staging");
+    const int64_t need = std::max<int64_t>(2 * m + nv, 1);
+    // staging kept between calls: grown (never shrunk) before anything is mutated
+    if (need > g->rem_cap || need > g->rem_host_cap) {
+        const int64_t cap = std::max<int64_t>(2 * need, 4096);
+        int32_t *nb = nullptr, *nh = nullptr;
+        hipError_t ea = hipMalloc((void **)&nb, 4 * (size_t)cap);
+        if (ea == hipSuccess) ea = hipHostMalloc((void **)&nh, 4 * (size_t)cap, hipHostMallocDefault);
+        if (ea != hipSuccess) {
+            if (nb) (void)hipFree(nb);
+            return hip_fail(ea, "removal staging");
+        }
+        if (g->rem_buf) (void)hipFree(g->rem_buf);
+        if (g->rem_host) (void)hipHostFree(g->rem_host);
+        g->rem_buf = nb;
+        g->rem_host = nh;
+        g->rem_cap = g->rem_host_cap = cap;
     }
-    if (m) e = hipMemcpyAsync(d_buf, es.data(), 4 * m, hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess && m) e = hipMemcpyAsync(d_buf + m, ed.data(), 4 * m, hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess && nv) e = hipMemcpyAsync(d_buf + 2 * m, vs.data(), 4 * nv, hipMemcpyHostToDevice, g->stream);
+    std::copy(es.begin(), es.end(), g->rem_host);
+    std::copy(ed.begin(), ed.end(), g->rem_host + m);
+    std::copy(vs.begin(), vs.end(), g->rem_host + 2 * m);
+    int32_t *d_buf = g->rem_buf;
+    unsigned long long *d_cnt = g->rem_cnt;
+    hipError_t e = hipMemcpyAsync(d_buf, g->rem_host, 4 * (size_t)(2 * m + nv), hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->d.ictr, 0, 8 * (size_t)kIcCount, g->stream);
     rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "removal upload");
-    // remove (marking the rows that change), compact those rows, then find
+    // remove (marking the rows that change), then compact those rows, find
     // what must be recomputed and rerun only that
     if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
     if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
-    if (st == RS_OK) st = launch_compact_rows(g);
     if (st == RS_OK) st = launch_incremental_marks(g);
-    unsigned long long ic[kIcCount] = {};
+    unsigned long long *ic = g->rem_cnt_host + 4;
     if (st == RS_OK) {
-        e = hipMemcpyAsync(ic, g->d.ictr, sizeof(ic), hipMemcpyDeviceToHost, g->stream);
+        e = hipMemcpyAsync(ic, g->d.ictr, 8 * (size_t)kIcCount, hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = hip_fail(e, "incremental counts");
     }
@@ -710,14 +735,12 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
         L.wmax_old = &g->d.ictr[kIcWmaxOld];
         st = launch_score_lists(g, L);
     }
-    unsigned long long cnt[4] = {0, 0, 0, 0};
+    unsigned long long *cnt = g->rem_cnt_host;
     if (st == RS_OK) {
-        e = hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, g->stream);
+        e = hipMemcpyAsync(cnt, d_cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = hip_fail(e, "removal result");
     }
-    (void)hipFree(d_buf);
-    (void)hipFree(d_cnt);
     if (st != RS_OK) return st;
     g->n_alive -= (int64_t)cnt[3];
     if (res) {
