@@ -236,6 +236,18 @@ struct DeviceGraph {
     unsigned long long *scratch_u = nullptr;  // [8] small counters
 };
 
+// A fixed launch sequence captured once into a HIP graph and replayed: the
+// score pass, or the common path of top-k for one k.  With timing on, the
+// timing events are captured too; their times are read after a replay has
+// completed (unread until then).
+struct Replay {
+    hipGraphExec_t exec = nullptr;
+    long long key = -1;
+    bool timed = false;
+    bool unread = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+};
+
 struct Timing {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -259,6 +271,8 @@ struct rs_graph {
     std::vector<int32_t> h_new2old, h_old2new, h_comm2orig;
     rs::DeviceGraph d;
     rs::Timing timing;
+    rs::Replay pass_rep, topk_rep;
+    bool graphs_off = false;  // eager launches only (RS_GRAPHS=0, or a capture failed)
     std::vector<void *> allocations;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;
@@ -300,6 +314,9 @@ struct PassLists {
 };
 rs_status launch_score_lists(rs_graph *g, const PassLists &inc);
 rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);
+// Read the timing events of completed replays into the timing totals.
+void drain_replays(rs_graph *g);
+void release_replays(rs_graph *g);
 rs_status launch_reduce_counts(rs_graph *g);
 rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t m,
                               unsigned long long *d_removed);

@@ -1478,6 +1478,84 @@ __global__ __launch_bounds__(kBlock) void k_rescale(const unsigned long long *wm
     }
 }
 
+// ------------------------------------------------------------ graph replay
+static void drain_one(rs_graph *g, Replay &R) {
+    if (!R.unread) return;
+    if (!R.events.empty()) (void)hipEventSynchronize(R.events.back().second.second);
+    for (auto &pe : R.events) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
+            g->timing.ms[pe.first] += t;
+            g->timing.launches[pe.first] += 1;
+        }
+    }
+    R.unread = false;
+}
+
+void drain_replays(rs_graph *g) {
+    drain_one(g, g->pass_rep);
+    drain_one(g, g->topk_rep);
+}
+
+static void drop_replay(rs_graph *g, Replay &R) {
+    drain_one(g, R);
+    if (R.exec) (void)hipGraphExecDestroy(R.exec);
+    R.exec = nullptr;
+    R.key = -1;
+    for (auto &pe : R.events) {
+        g->timing.pool.push_back(pe.second.first);
+        g->timing.pool.push_back(pe.second.second);
+    }
+    R.events.clear();
+}
+
+void release_replays(rs_graph *g) {
+    drop_replay(g, g->pass_rep);
+    drop_replay(g, g->topk_rep);
+}
+
+// Enqueue a fixed launch sequence on the graph's stream through a replayed
+// HIP graph (captured on first use, and again when the key changes), or
+// eagerly when graphs are off, when per-kernel timing is on (its events are
+// recorded around eager launches), when the stream is the null stream, or
+// when the caller is capturing the stream itself.
+template <class F>
+static rs_status replay(rs_graph *g, Replay &R, long long key, F enqueue) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (g->graphs_off || g->timing.on || !g->stream || hipStreamIsCapturing(g->stream, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return enqueue();
+    if (!R.exec || R.key != key) {
+        drop_replay(g, R);
+        const size_t p0 = g->timing.pending.size();
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed);
+        rs_status st = RS_OK;
+        if (e == hipSuccess) {
+            st = enqueue();
+            e = hipStreamEndCapture(g->stream, &graph);
+        }
+        if (e == hipSuccess && st == RS_OK) e = hipGraphInstantiate(&R.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        // the events captured in the sequence now belong to the replay
+        R.events.assign(g->timing.pending.begin() + (long)p0, g->timing.pending.end());
+        g->timing.pending.resize(p0);
+        if (e != hipSuccess || st != RS_OK) {
+            (void)hipGetLastError();
+            drop_replay(g, R);
+            g->graphs_off = true;  // this stream cannot be captured: stay eager
+            return enqueue();
+        }
+        R.key = key;
+        R.timed = g->timing.on;
+    }
+    drain_one(g, R);  // a previous replay's times, before its events are recorded again
+    const hipError_t e = hipGraphLaunch(R.exec, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    R.unread = R.timed;
+    return RS_OK;
+}
+
 // ------------------------------------------------------------ pass launcher
 template <typename OffT>
 static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
@@ -1573,7 +1651,9 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
 }
 
 rs_status launch_score_pass(rs_graph *g) {
-    return g->d.off64 ? score_pass_t<long long>(g, nullptr) : score_pass_t<int32_t>(g, nullptr);
+    return replay(g, g->pass_rep, 0, [g]() {
+        return g->d.off64 ? score_pass_t<long long>(g, nullptr) : score_pass_t<int32_t>(g, nullptr);
+    });
 }
 
 rs_status launch_score_lists(rs_graph *g, const PassLists &inc) {
@@ -2253,11 +2333,11 @@ static hipError_t copy_out(rs_graph *g, long long keff, int32_t *ids, double *sc
     return e;
 }
 
-rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count) {
+// The common path of top-k: histogram, threshold, collect, and one
+// workgroup that ranks the candidates into a compact device block
+// [flag | ids | scores], copied once into pinned host memory.
+static rs_status topk_common(rs_graph *g, long long keff) {
     DeviceGraph &D = g->d;
-    const long long keff = k < g->n_alive ? k : g->n_alive;
-    *count = keff;
-    if (keff <= 0) return RS_OK;
     hipEvent_t ev;
     long long chunk = (D.n + 63) / 64;  // about 64 blocks, each < 2^16 keys
     if (chunk < 16384) chunk = 16384;
@@ -2276,9 +2356,25 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     hipLaunchKernelGGL(k_topk_collect, dim3((int)((D.n + cchunk - 1) / cchunk)), dim3(kCollThreads), 0, g->stream,
                        D.R, D.new2old, D.alive, D.n, cchunk, D.tstate, D.tfinal, D.ttie, D.thist);
     timing_end(g, K_TOPK_COLLECT, ev);
-    // common path: one workgroup ranks the candidates into a compact device
-    // block [flag | ids | scores], copied once into pinned host memory
+    const size_t sc_off = 16 + ((4 * (size_t)keff + 7) & ~(size_t)7);
+    char *dblk = D.tblk;
+    timing_begin(g, K_TOPK_RANK, &ev);
+    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, g->stream, D.tstate, D.tfinal, D.ttie, keff, D.R,
+                       D.new2old, (int32_t *)(dblk + 16), (double *)(dblk + sc_off), (unsigned int *)dblk);
+    timing_end(g, K_TOPK_RANK, ev);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(g->hpin, dblk, sc_off + 8 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
+    return e == hipSuccess ? RS_OK : hip_fail(e, "top-k");
+}
+
+rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count) {
+    DeviceGraph &D = g->d;
+    const long long keff = k < g->n_alive ? k : g->n_alive;
+    *count = keff;
+    if (keff <= 0) return RS_OK;
+    hipEvent_t ev;
     if (g->hpin_cap < keff) {
+        drop_replay(g, g->topk_rep);  // it copies into the buffer being replaced
         if (g->hpin) (void)hipHostFree(g->hpin);
         g->hpin = nullptr;
         g->hpin_cap = 0;
@@ -2290,15 +2386,11 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
         g->hpin_cap = keff;
     }
     const size_t sc_off = 16 + ((4 * (size_t)keff + 7) & ~(size_t)7);
-    char *dblk = D.tblk;
-    timing_begin(g, K_TOPK_RANK, &ev);
-    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, g->stream, D.tstate, D.tfinal, D.ttie, keff, D.R,
-                       D.new2old, (int32_t *)(dblk + 16), (double *)(dblk + sc_off), (unsigned int *)dblk);
-    timing_end(g, K_TOPK_RANK, ev);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(g->hpin, dblk, sc_off + 8 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    rs_status cst = replay(g, g->topk_rep, keff, [g, keff]() { return topk_common(g, keff); });
+    if (cst != RS_OK) return cst;
+    hipError_t e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "top-k");
+    drain_replays(g);
     if (*(const unsigned int *)g->hpin) {
         memcpy(ids, (const char *)g->hpin + 16, 4 * (size_t)keff);
         memcpy(scores, (const char *)g->hpin + sc_off, 8 * (size_t)keff);

@@ -72,6 +72,8 @@ static hipError_t dev_alloc(rs_graph *g, void **p, size_t bytes) {
 
 static void release(rs_graph *g) {
     if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    release_replays(g);
     for (void *p : g->allocations) (void)hipFree(p);
     g->allocations.clear();
     if (g->hpin) (void)hipHostFree(g->hpin);
@@ -617,6 +619,7 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     if (!g) return fail(RS_ERR_NOMEM, "handle allocation failed");
     g->stream = (hipStream_t)hip_stream;  // NULL: created after validation
     g->wide_offsets = (flags & RS_LOAD_WIDE_OFFSETS) != 0;
+    if (const char *gv = std::getenv("RS_GRAPHS")) g->graphs_off = gv[0] == '0';
     rs_status st = csr->offset_bytes == 8 ? load_t<int64_t>(csr, g) : load_t<int32_t>(csr, g);
     if (st != RS_OK) {
         std::string keep = g_err;
@@ -914,6 +917,7 @@ rs_status rs_read_timings(rs_graph *g, int32_t cap, double *ms, int64_t *launche
     if (!g) return fail(RS_ERR_ARG, "graph is NULL");
     hipError_t e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "timing sync");
+    drain_replays(g);
     for (auto &pe : g->timing.pending) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
