@@ -206,6 +206,53 @@ const char *rs_kernel_name(int32_t id);
 /* rs_free_graph: release all device memory of g (NULL is ignored). */
 void rs_free_graph(rs_graph *g);
 
+/*
+ * Served scoring: a request loop over several resident graphs (the removal
+ * model of Section V applied as a stream of requests).  The server keeps a
+ * host copy of each registered graph and loads it into device memory on its
+ * first request, within an HBM budget: when a graph does not fit, idle graphs
+ * are evicted least-recently-used first (an evicted graph is reloaded from
+ * its host copy with its removal history applied).  n_slots worker threads
+ * take requests in submission order; requests on one graph run one at a time
+ * in that order, requests on different graphs overlap on the device (each
+ * graph has its own stream).  A request applies a removal batch (incremental
+ * re-score, as rs_apply_removals) and returns the top-k; its result equals
+ * applying the graph's batches one by one to a lone rs_graph.
+ *
+ *   rs_server_create      n_slots >= 1 workers; hbm_budget bytes of device
+ *                         memory for resident graphs (<= 0: unlimited)
+ *   rs_server_add_graph   copies the CSR (host arrays only) and returns its
+ *                         id (0, 1, ...); nothing is loaded yet
+ *   rs_server_submit      copies the batch; returns a request id at once
+ *   rs_server_wait        blocks until the request is done; ids[k] and
+ *                         scores[k] receive its top-k (count of them), info
+ *                         its timings (ns since the server started) and the
+ *                         re-score's counts; the request is then forgotten
+ *   rs_server_stats       loads, evictions, requests done, device bytes
+ * Errors: RS_ERR_ARG, RS_ERR_RANGE (graph id or vertex id), RS_ERR_GRAPH,
+ * RS_ERR_NOMEM (a graph larger than the whole budget), RS_ERR_HIP; a failed
+ * request reports its status through rs_server_wait.
+ */
+typedef struct rs_server rs_server;
+typedef struct {
+    int64_t t_submit, t_start, t_done; /* ns since rs_server_create */
+    int64_t affected;                  /* vertices re-scored by the removal */
+    int64_t edges_removed;
+    int32_t loaded;                    /* 1 if the graph was (re)loaded for this request */
+    int32_t pad;
+} rs_request_info;
+typedef struct {
+    int64_t requests_done, loads, evictions, device_bytes, peak_device_bytes;
+} rs_server_stats_t;
+rs_status rs_server_create(int32_t n_slots, int64_t hbm_budget, rs_server **out);
+rs_status rs_server_add_graph(rs_server *s, const rs_csr *csr, int32_t *graph_id);
+rs_status rs_server_submit(rs_server *s, int32_t graph_id, const rs_removals *batch, int64_t k, int64_t *request_id);
+rs_status rs_server_wait(rs_server *s, int64_t request_id, int32_t *ids, double *scores, int64_t *count,
+                         rs_request_info *info);
+rs_status rs_server_stats(rs_server *s, rs_server_stats_t *st);
+void rs_server_free(rs_server *s);
+
+
 const char *rs_status_string(rs_status s);
 
 /* Detail of the last error on the calling thread ("" if none). */

@@ -63,10 +63,23 @@ class rs_counts(ctypes.Structure):
                 ("sum_tII", ctypes.c_int64), ("sum_work_I", ctypes.c_int64), ("omega_max", ctypes.c_double)]
 
 
+class rs_request_info(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_int64), ("t_start", ctypes.c_int64), ("t_done", ctypes.c_int64),
+                ("affected", ctypes.c_int64), ("edges_removed", ctypes.c_int64), ("loaded", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class rs_server_stats_t(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("loads", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64)]
+
+
 EXPORTS = [
     "rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores", "rs_read_counts",
     "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime", "rs_set_timing", "rs_read_timings",
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
+    "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
+    "rs_server_free",
 ]
 
 
@@ -94,9 +107,17 @@ def _load_lib(path=LIB_PATH):
     lib.rs_status_string.restype = ctypes.c_char_p
     lib.rs_last_error.argtypes = []
     lib.rs_last_error.restype = ctypes.c_char_p
+    lib.rs_server_create.argtypes = [I32, I64, ctypes.POINTER(P)]
+    lib.rs_server_add_graph.argtypes = [P, ctypes.POINTER(rs_csr), ctypes.POINTER(I32)]
+    lib.rs_server_submit.argtypes = [P, I32, ctypes.POINTER(rs_removals), I64, ctypes.POINTER(I64)]
+    lib.rs_server_wait.argtypes = [P, I64, P, P, ctypes.POINTER(I64), ctypes.POINTER(rs_request_info)]
+    lib.rs_server_stats.argtypes = [P, ctypes.POINTER(rs_server_stats_t)]
+    lib.rs_server_free.argtypes = [P]
+    lib.rs_server_free.restype = None
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
-                 "rs_set_timing", "rs_read_timings"):
+                 "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
+                 "rs_server_submit", "rs_server_wait", "rs_server_stats"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -275,3 +296,87 @@ def rs_status_string(s: int) -> str:
 
 def rs_last_error() -> str:
     return _lib.rs_last_error().decode()
+
+
+class RSServer:
+    """The served form (wraps ``rs_server*``): register graphs, submit removal
+    requests (each followed by a top-k), wait for their results."""
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.rs_server_create(int(slots), int(hbm_budget), ctypes.byref(h)), "rs_server_create")
+        self.handle = h
+        self.k = {}
+
+    def add_graph(self, row_offsets, col, labels) -> int:
+        off = np.ascontiguousarray(row_offsets, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        csr = rs_csr(off.size - 1, col.size, 8, 0, off.ctypes.data, col.ctypes.data, lab.ctypes.data)
+        gid = ctypes.c_int32()
+        _check(_lib.rs_server_add_graph(self.handle, ctypes.byref(csr), ctypes.byref(gid)), "rs_server_add_graph")
+        return gid.value
+
+    def submit(self, graph_id: int, k: int, edges=None, vertices=None) -> int:
+        e = np.zeros((0, 2), np.int32) if edges is None else np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        v = np.zeros(0, np.int32) if vertices is None else np.ascontiguousarray(vertices, dtype=np.int32).ravel()
+        src = np.ascontiguousarray(e[:, 0])
+        dst = np.ascontiguousarray(e[:, 1])
+        b = rs_removals(e.shape[0], src.ctypes.data if e.shape[0] else None,
+                        dst.ctypes.data if e.shape[0] else None, v.size, v.ctypes.data if v.size else None)
+        rid = ctypes.c_int64()
+        _check(_lib.rs_server_submit(self.handle, int(graph_id), ctypes.byref(b), int(k), ctypes.byref(rid)),
+               "rs_server_submit")
+        self.k[rid.value] = int(k)
+        return rid.value
+
+    def wait(self, request_id: int):
+        """(ids, scores, info dict) of a finished request."""
+        k = max(self.k.pop(request_id, 0), 1)
+        ids = np.zeros(k, np.int32)
+        sc = np.zeros(k, np.float64)
+        cnt = ctypes.c_int64()
+        info = rs_request_info()
+        _check(_lib.rs_server_wait(self.handle, int(request_id), ids.ctypes.data, sc.ctypes.data, ctypes.byref(cnt),
+                                   ctypes.byref(info)), "rs_server_wait")
+        return ids[: cnt.value], sc[: cnt.value], {f: getattr(info, f) for f, _ in rs_request_info._fields_}
+
+    def stats(self) -> dict:
+        st = rs_server_stats_t()
+        _check(_lib.rs_server_stats(self.handle, ctypes.byref(st)), "rs_server_stats")
+        return {f: getattr(st, f) for f, _ in rs_server_stats_t._fields_}
+
+    def free(self):
+        if self.handle:
+            _lib.rs_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rs_server_create(slots: int = 4, hbm_budget: int = 0) -> RSServer:
+    return RSServer(slots, hbm_budget)
+
+
+def rs_server_add_graph(s: RSServer, row_offsets, col, labels) -> int:
+    return s.add_graph(row_offsets, col, labels)
+
+
+def rs_server_submit(s: RSServer, graph_id: int, k: int, edges=None, vertices=None) -> int:
+    return s.submit(graph_id, k, edges=edges, vertices=vertices)
+
+
+def rs_server_wait(s: RSServer, request_id: int):
+    return s.wait(request_id)
+
+
+def rs_server_stats(s: RSServer) -> dict:
+    return s.stats()
+
+
+def rs_server_free(s: RSServer):
+    s.free()

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librs.so")
-SOURCES = ["rs_runtime.hip", "rs_kernels.hip"]
+SOURCES = ["rs_runtime.hip", "rs_kernels.hip", "rs_serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

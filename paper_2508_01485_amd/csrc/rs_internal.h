@@ -265,6 +265,7 @@ struct rs_graph {
     bool scored = false;
     bool wide_offsets = false;  // 64-bit device edge offsets even for nnz <= INT32_MAX
     int64_t n_alive = 0;
+    int64_t dev_bytes = 0;  // device memory held by the graph
     int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0, n_schunks = 0;
     int n_schunks_lds = 0;               // chunks of hubs whose foreign list fits in LDS (listed first)
     int grid_rows = 0, grid_score = 0;   // hubs first, then the tiles in XCD-major order

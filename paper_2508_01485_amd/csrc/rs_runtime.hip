@@ -66,7 +66,10 @@ static hipError_t dev_alloc(rs_graph *g, void **p, size_t bytes) {
         if (std::atoll(f) == idx) return hipErrorOutOfMemory;
     }
     hipError_t e = hipMalloc(p, bytes ? bytes : 16);
-    if (e == hipSuccess) g->allocations.push_back(*p);
+    if (e == hipSuccess) {
+        g->allocations.push_back(*p);
+        g->dev_bytes += (int64_t)(bytes ? bytes : 16);
+    }
     return e;
 }
 

@@ -1,0 +1,100 @@
+"""The served form: requests on several resident graphs, run concurrently by
+the server's workers (and, under a small HBM budget, with evictions and
+reloads), give exactly the results of applying each graph's batches one by
+one to a lone handle."""
+import sys
+
+import numpy as np
+import pytest
+
+from rsgen import lfr
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[served]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _graphs():
+    return [lfr(n, 12.0, 200, 0.25, seed=60 + i, cmin=10, cmax=300) for i, n in enumerate((3000, 5000, 4000, 6000))]
+
+
+def _requests(graphs, count, seed):
+    """(graph index, edges or None, vertices or None) in submission order."""
+    rng = np.random.default_rng(seed)
+    alive = [np.ones(g.edges()[0].size, bool) for g in graphs]
+    out = []
+    for _ in range(count):
+        gi = int(rng.integers(len(graphs)))
+        g = graphs[gi]
+        u, v = g.edges()
+        if rng.random() < 0.6:
+            live = np.flatnonzero(alive[gi])
+            pick = rng.choice(live, min(int(rng.integers(1, 80)), live.size), replace=False)
+            alive[gi][pick] = False
+            out.append((gi, np.stack([u[pick], v[pick]], 1), None))
+        else:
+            out.append((gi, None, rng.choice(g.n, int(rng.integers(1, 6)), replace=False)))
+    return out
+
+
+def _alone(rs, graphs, reqs, k):
+    """Each graph's batches applied in order to a lone handle."""
+    handles = []
+    for g in graphs:
+        h = rs.rs_load_graph(g.off, g.col, g.labels)
+        rs.rs_score(h)
+        handles.append(h)
+    res = []
+    for gi, e, v in reqs:
+        rs.rs_apply_removals(handles[gi], edges=e, vertices=v)
+        res.append(rs.rs_topk(handles[gi], k))
+    for h in handles:
+        h.free()
+    return res
+
+
+def _served(rs, graphs, reqs, k, slots, budget):
+    srv = rs.RSServer(slots=slots, hbm_budget=budget)
+    try:
+        gids = [srv.add_graph(g.off, g.col, g.labels) for g in graphs]
+        rids = [srv.submit(gids[gi], k, edges=e, vertices=v) for gi, e, v in reqs]
+        out = [srv.wait(r) for r in rids]
+        return out, srv.stats()
+    finally:
+        srv.free()
+
+
+def _compare(alone, served):
+    for i, ((ia, sa), (ib, sb, info)) in enumerate(zip(alone, served)):
+        assert np.array_equal(ia, ib), i
+        assert sa.tobytes() == sb.tobytes(), i
+        assert info["t_submit"] <= info["t_start"] <= info["t_done"]
+
+
+def test_served_requests_equal_alone():
+    import paper_2508_01485_amd as rs
+    graphs = _graphs()
+    reqs = _requests(graphs, 40, 1)
+    alone = _alone(rs, graphs, reqs, 50)
+    served, st = _served(rs, graphs, reqs, 50, slots=3, budget=0)
+    _compare(alone, served)
+    assert st["requests_done"] == 40 and st["loads"] == len(graphs) and st["evictions"] == 0, st
+    _say("mix of 40 requests on 4 graphs, 3 slots: identical to alone", st)
+
+
+def test_served_under_budget_evicts_and_reloads():
+    """A budget of about two graphs: graphs are evicted and reloaded with
+    their removal history, and every result is still the lone one."""
+    import paper_2508_01485_amd as rs
+    graphs = _graphs()
+    reqs = _requests(graphs, 40, 2)
+    alone = _alone(rs, graphs, reqs, 30)
+    big = max(48 * g.nnz + 360 * g.n + (8 << 20) for g in graphs)
+    served, st = _served(rs, graphs, reqs, 30, slots=2, budget=2 * big)
+    _compare(alone, served)
+    assert st["evictions"] > 0 and st["loads"] > len(graphs), st
+    assert st["peak_device_bytes"] <= 2 * big, st
+    _say("budget of two graphs: identical to alone", st)
