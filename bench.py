@@ -31,6 +31,8 @@ WORKLOADS = {
     "lfr_1m": ("LFR-style n=1,000,000, degree exponent 2.5 mean 20 max 5,000, community sizes "
                "exponent 1.5 on [50, 20,000], mixing 0.1, seed 0", 1000),
     "lfr_20m": ("LFR-style n=20,000,000, mean degree 30, max 100,000, mixing 0.15, seed 0", 10000),
+    "served": ("resident LFR-style graphs (seeds 5000+g), n log-uniform on [1e5, nmax], mean degree 20, "
+               "max 5,000, mixing 0.1; Poisson removal requests, each followed by a top-100 query", 100),
 }
 
 
@@ -196,6 +198,112 @@ def rescore_latency(rs, h, g, n_req, seed=11):
                        "then a top-100 query"}
 
 
+def bench_served(args):
+    """The served form: several graphs behind rs_server, an HBM budget of half
+    their footprint, removal requests (half 1-1,000 random existing edges,
+    half 1-50 vertices of the graph's latest top-100), each followed by a
+    top-100 query.  Capacity = requests/s with all requests queued at once;
+    then Poisson arrivals at 0.5, 0.8 and 1.0 times that rate, latency =
+    completion - arrival (and service = completion - start) per request."""
+    import threading
+
+    import paper_2508_01485_amd as rs
+    from rsgen import cached, lfr
+    rng = np.random.default_rng(5000)
+    ns = np.exp(rng.uniform(np.log(1e5), np.log(args.served_nmax), args.served_graphs)).astype(np.int64)
+    graphs = []
+    t0 = time.perf_counter()
+    for gi, n in enumerate(ns):
+        graphs.append(cached(f"served_{gi}_n{n}", lambda n=n, gi=gi: lfr(int(n), 20.0, 5000, 0.1, 5000 + gi)))
+        log(f"graph {gi}: n={graphs[-1].n} m={graphs[-1].m}")
+    log(f"generated {len(graphs)} graphs in {time.perf_counter() - t0:.1f}s")
+    est = sum(48 * g.nnz + 360 * g.n + (8 << 20) for g in graphs)
+    srv = rs.RSServer(slots=args.served_slots, hbm_budget=est // 2)
+    gids = [srv.add_graph(g.off, g.col, g.labels) for g in graphs]
+    edges = [g.edges() for g in graphs]
+    alive = [np.ones(e[0].size, bool) for e in edges]
+    tops = [None] * len(graphs)
+    lock = threading.Lock()
+
+    def make_request():
+        gi = int(rng.integers(len(graphs)))
+        u, v = edges[gi]
+        with lock:
+            top = tops[gi]
+        if rng.random() < 0.5 or top is None or top.size == 0:
+            live = np.flatnonzero(alive[gi])
+            pick = rng.choice(live, min(int(rng.integers(1, 1001)), live.size), replace=False)
+            alive[gi][pick] = False
+            return gi, {"edges": np.stack([u[pick], v[pick]], 1)}
+        return gi, {"vertices": rng.choice(top, min(int(rng.integers(1, 51)), top.size), replace=False)}
+
+    def run(n_req, rate):
+        """Submit n_req requests (all at once if rate is None, else Poisson),
+        waiting for them in a second thread; returns per-request info."""
+        rids = []
+        done = []
+        cv = threading.Condition()
+
+        def waiter():
+            i = 0
+            while True:
+                with cv:
+                    while i >= len(rids) and len(rids) < n_req:
+                        cv.wait()
+                    if i >= len(rids):
+                        return
+                    rid, gi = rids[i]
+                i += 1
+                ids, sc, info = srv.wait(rid)
+                with lock:
+                    tops[gi] = ids
+                done.append(info)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t_begin = time.perf_counter()
+        for _ in range(n_req):
+            if rate:
+                time.sleep(float(rng.exponential(1.0 / rate)))
+            gi, kw = make_request()
+            rid = srv.submit(gids[gi], 100, **kw)
+            with cv:
+                rids.append((rid, gi))
+                cv.notify()
+        th.join()
+        wall = time.perf_counter() - t_begin
+        lat = np.array([(d["t_done"] - d["t_submit"]) / 1e6 for d in done])
+        svc = np.array([(d["t_done"] - d["t_start"]) / 1e6 for d in done])
+        return {"requests": n_req, "wall_s": wall, "requests_per_s": n_req / wall,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                "service_ms": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99))},
+                "mean_affected": float(np.mean([d["affected"] for d in done])),
+                "reloads": int(sum(d["loaded"] for d in done))}
+
+    log("warm-up (loads)")
+    run(2 * len(graphs), None)
+    log("capacity: all requests queued at once")
+    cap = run(args.served_requests, None)
+    mu = cap["requests_per_s"]
+    rates = {}
+    for f in (0.5, 0.8, 1.0):
+        log(f"Poisson arrivals at {f} x capacity ({f * mu:.0f}/s)")
+        rates[str(f)] = run(args.served_requests, f * mu)
+    st = srv.stats()
+    srv.free()
+    m_total = sum(g.m for g in graphs)
+    out = {
+        "metric": METRIC, "value": mu, "unit": "requests/s", "n_gpus": 1, "steps": args.served_requests,
+        "warmup": 2 * len(graphs), "ms_per_step": 1000.0 / mu, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served: {len(graphs)} {WORKLOADS['served'][0]}".replace("nmax", f"{args.served_nmax:.0e}"),
+                   "graphs": len(graphs), "n_total": int(sum(g.n for g in graphs)), "m_total": int(m_total),
+                   "slots": args.served_slots, "hbm_budget_bytes": int(est // 2), "top_k": 100},
+        "capacity": cap, "poisson": rates, "server": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +312,10 @@ def main():
     ap.add_argument("--workload", default="lfr_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--served-graphs", type=int, default=16)
+    ap.add_argument("--served-nmax", type=float, default=1e6)
+    ap.add_argument("--served-slots", type=int, default=4)
+    ap.add_argument("--served-requests", type=int, default=300)
     ap.add_argument("--rescore-requests", type=int, default=None,
                     help="removal requests timed after the steps (0: skip; default 200, 20 above 1e8 entries)")
     args = ap.parse_args()
@@ -213,6 +325,10 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+
+    if args.workload == "served":
+        bench_served(args)
         return
 
     import torch

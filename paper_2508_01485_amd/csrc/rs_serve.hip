@@ -310,9 +310,12 @@ rs_status rs_server_wait(rs_server *s, int64_t request_id, int32_t *ids, double 
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return rs::fail(RS_ERR_ARG, "unknown request id");
-    s->cv_done.wait(lk, [&] { return it->second.done; });
-    Request r = std::move(it->second);
-    s->reqs.erase(it);
+    // submissions may rehash the map while this thread waits: keep a pointer
+    // to the element (stable), not the iterator (invalidated by a rehash)
+    Request *rq = &it->second;
+    s->cv_done.wait(lk, [&] { return rq->done; });
+    Request r = std::move(*rq);
+    s->reqs.erase(request_id);
     lk.unlock();
     if (r.status != RS_OK) return rs::fail(r.status, r.error);
     if (count) *count = r.count;

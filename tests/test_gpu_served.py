@@ -98,3 +98,42 @@ def test_served_under_budget_evicts_and_reloads():
     assert st["evictions"] > 0 and st["loads"] > len(graphs), st
     assert st["peak_device_bytes"] <= 2 * big, st
     _say("budget of two graphs: identical to alone", st)
+
+
+def test_served_submit_while_waiting():
+    """Requests submitted from one thread while another waits for earlier
+    ones (the request table grows during the waits); results equal alone."""
+    import threading
+
+    import paper_2508_01485_amd as rs
+    graphs = _graphs()
+    reqs = _requests(graphs, 120, 3)
+    alone = _alone(rs, graphs, reqs, 20)
+    srv = rs.RSServer(slots=3, hbm_budget=0)
+    try:
+        gids = [srv.add_graph(g.off, g.col, g.labels) for g in graphs]
+        rids, out = [], []
+        cv = threading.Condition()
+
+        def waiter():
+            i = 0
+            while i < len(reqs):
+                with cv:
+                    while i >= len(rids):
+                        cv.wait()
+                    rid = rids[i]
+                out.append(srv.wait(rid))
+                i += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        for gi, e, v in reqs:
+            rid = srv.submit(gids[gi], 20, edges=e, vertices=v)
+            with cv:
+                rids.append(rid)
+                cv.notify()
+        th.join()
+    finally:
+        srv.free()
+    _compare(alone, out)
+    _say("120 requests submitted while waiting: identical to alone")
