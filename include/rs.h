@@ -203,6 +203,27 @@ rs_status rs_set_timing(rs_graph *g, int32_t on);
 rs_status rs_read_timings(rs_graph *g, int32_t cap, double *ms, int64_t *launches, int32_t *n_kernels);
 const char *rs_kernel_name(int32_t id);
 
+/*
+ * Batched scoring: many independent graphs scored together.  The batch is
+ * one CSR over the disjoint union of the graphs: graph i owns the vertex
+ * range [vertex_offsets[i], vertex_offsets[i+1]) (n_graphs + 1 offsets, from
+ * 0 to csr->n; host arrays only), its edges stay inside that range (global
+ * ids), and its labels are its own (graphs may reuse label values: no
+ * community spans two graphs).  rs_score scores the whole batch in one pass
+ * with each graph's own w_max (Algorithm 1, Step 2, per graph), so every
+ * score equals that of the graph loaded alone, bit for bit.
+ *   rs_load_batch   as rs_load_graph; RS_ERR_GRAPH also for an edge that
+ *                   joins two graphs
+ *   rs_topk_batch   the top-k of every graph (1 <= k <= 32): ids[i*k + j]
+ *                   and scores[i*k + j] for graph i, ids relative to the
+ *                   graph's first vertex, in the order of rs_topk; counts[i]
+ *                   = min(k, live vertices of graph i).  Waits for the stream.
+ * rs_apply_removals refuses a batch (RS_ERR_STATE).
+ */
+rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const rs_csr *csr, void *hip_stream,
+                        uint32_t flags, rs_graph **out);
+rs_status rs_topk_batch(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *counts);
+
 /* rs_free_graph: release all device memory of g (NULL is ignored). */
 void rs_free_graph(rs_graph *g);
 

@@ -79,7 +79,7 @@ EXPORTS = [
     "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime", "rs_set_timing", "rs_read_timings",
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
     "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
-    "rs_server_free",
+    "rs_server_free", "rs_load_batch", "rs_topk_batch",
 ]
 
 
@@ -114,10 +114,12 @@ def _load_lib(path=LIB_PATH):
     lib.rs_server_stats.argtypes = [P, ctypes.POINTER(rs_server_stats_t)]
     lib.rs_server_free.argtypes = [P]
     lib.rs_server_free.restype = None
+    lib.rs_load_batch.argtypes = [I32, P, ctypes.POINTER(rs_csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.rs_topk_batch.argtypes = [P, I64, P, P, P]
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
                  "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
-                 "rs_server_submit", "rs_server_wait", "rs_server_stats"):
+                 "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -380,3 +382,32 @@ def rs_server_stats(s: RSServer) -> dict:
 
 def rs_server_free(s: RSServer):
     s.free()
+
+
+def rs_load_batch(vertex_offsets, row_offsets, col, labels, stream=None, flags: int = 0) -> RSGraph:
+    """Load a batch: the disjoint union of graphs (graph i = vertices
+    [vertex_offsets[i], vertex_offsets[i+1]), global ids, per-graph labels)."""
+    vo = np.ascontiguousarray(vertex_offsets, dtype=np.int64)
+    off = np.ascontiguousarray(row_offsets, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    csr = rs_csr(off.size - 1, col.size, 8, 0, off.ctypes.data, col.ctypes.data, lab.ctypes.data)
+    s = stream
+    if s is not None and hasattr(s, "cuda_stream"):
+        s = s.cuda_stream
+    h = ctypes.c_void_p()
+    _check(_lib.rs_load_batch(vo.size - 1, vo.ctypes.data, ctypes.byref(csr), s, flags, ctypes.byref(h)),
+           "rs_load_batch")
+    g = RSGraph(h, off.size - 1, col.size)
+    g.n_graphs = vo.size - 1
+    return g
+
+
+def rs_topk_batch(g: RSGraph, k: int):
+    """(ids [G, k] relative to each graph, scores [G, k], counts [G])."""
+    G = g.n_graphs
+    ids = np.zeros((G, k), np.int32)
+    sc = np.zeros((G, k), np.float64)
+    cnt = np.zeros(G, np.int64)
+    _check(_lib.rs_topk_batch(g.handle, int(k), ids.ctypes.data, sc.ctypes.data, cnt.ctypes.data), "rs_topk_batch")
+    return ids, sc, cnt

@@ -60,6 +60,7 @@ constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise com
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
+constexpr int kBatchK = 32;          // largest k of the per-graph top-k of a batch
 
 // Vertex marks of an incremental re-score (after removals).
 constexpr unsigned int kRowChanged = 1u;   // the row lost entries
@@ -213,6 +214,14 @@ struct DeviceGraph {
     int32_t *elist = nullptr, *llist = nullptr;                   // [n] changed rows, rows whose links move
     int32_t *rlist = nullptr, *slist = nullptr, *hlist = nullptr; // block lists
     unsigned long long *ictr = nullptr;     // [kIcCount]
+    // batched graphs (a disjoint union of n_graphs graphs, each a contiguous id range)
+    int64_t *vstart = nullptr;              // [n_graphs + 1] first vertex of each graph
+    int32_t *vgraph = nullptr;              // [n] graph of each vertex
+    unsigned long long *vmaxw = nullptr;    // [n] largest weight of each vertex (bits)
+    unsigned long long *gwmax = nullptr;    // [n_graphs] w_max of each graph (bits)
+    int32_t *bids = nullptr;                // [n_graphs * kBatchK] per-graph top-k
+    double *bscores = nullptr;
+    int64_t *bcounts = nullptr;             // [n_graphs]
     int32_t *outl = nullptr;    // [m'] out-lists: foreign neighbours of higher rank, ascending (removed: ~id)
     int32_t *reckey = nullptr;  // [nnz] interaction-matrix record keys
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
@@ -274,6 +283,8 @@ struct rs_graph {
     rs::Timing timing;
     rs::Replay pass_rep, topk_rep;
     bool graphs_off = false;  // eager launches only (RS_GRAPHS=0, or a capture failed)
+    int32_t n_graphs = 0;     // > 0: a batch of graphs loaded as one disjoint union
+    std::vector<int64_t> h_vstart;
     std::vector<void *> allocations;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;
@@ -325,6 +336,7 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
                                  unsigned long long *d_removed_edges);
 rs_status launch_links(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
+rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);
 

@@ -112,6 +112,7 @@ struct RowArgs {
     long long *tI, *tII;
     RowPart *part;
     unsigned long long *wmax_part;  // [grid] w_max bits of each block (dense copy for k_wmax)
+    unsigned long long *vmaxw;      // batched graphs: [n] bits of each vertex's largest weight, else null
 };
 
 struct RowResult {
@@ -240,6 +241,7 @@ struct RowTileShared {
     int runlab[kRowTile];                // label of each run (-1: removed tail)
     double vX[kRowTileV];
     int vd[kRowTileV], vell[kRowTileV], vlab[kRowTileV];
+    unsigned long long vmw[kRowTileV];   // batched graphs: each vertex's largest weight (bits)
     unsigned short vrf[kRowTileV], vo[kRowTileV];
 };
 
@@ -363,6 +365,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         res.q = below + fown;
         res.wown = fown > 0 ? weight_present_t(S.tab, d, X, ell, fown) : weight_absent_t(S.tab, d, X, ell);
         res.lmax = res.wown;
+        if (A.vmaxw) S.vmw[i] = dbits(res.wown);
         int4 k4;  // the first record keys: the labels of the first valid runs
         k4.x = ell > 0 ? S.runlab[rf] : INT_MAX;
         k4.y = ell > 1 ? S.runlab[rf + 1] : INT_MAX;
@@ -386,6 +389,11 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         rd.w = w;
         A.recdat[idx] = rd;
         acc.wmax = fmax(acc.wmax, w);
+        if (A.vmaxw) atomicMax(&S.vmw[i], dbits(w));  // weights are >= 0: bits order like values
+    }
+    if (A.vmaxw) {
+        __syncthreads();
+        for (int i = tid; i < nv; i += kBlock) A.vmaxw[v0 + i] = S.vmw[i];
     }
     // pair facts at the foreign entries: entry (w, u) gets the record of
     // C(u) in w's row (contiguous writes along the runs)
@@ -608,6 +616,7 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
         k4.z = ell > 2 ? A.reckey[rb + 2] : INT_MAX;
         k4.w = ell > 3 ? A.reckey[rb + 3] : INT_MAX;
         finish_row(A, v, d, r, k4, (long long)rb, A.goff[v], cv, acc);
+        if (A.vmaxw) A.vmaxw[v] = dbits(r.lmax);
     }
 }
 
@@ -706,6 +715,26 @@ __global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, 
     }
 }
 
+// Batched graphs: each graph's w_max from its vertices' largest weights (one
+// workgroup per graph; the vertices of a graph are a contiguous id range).
+__global__ __launch_bounds__(kBlock) void k_wmax_graphs(const unsigned long long *vmaxw, const int64_t *vstart,
+                                                        int n_graphs, unsigned long long *gwmax) {
+    __shared__ unsigned long long s[kBlock / 64];
+    for (int gi = blockIdx.x; gi < n_graphs; gi += gridDim.x) {
+        unsigned long long m = 0;
+        for (long long v = vstart[gi] + threadIdx.x; v < vstart[gi + 1]; v += kBlock) m = max(m, vmaxw[v]);
+        for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
+        if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int i = 0; i < kBlock / 64; ++i) t = max(t, s[i]);
+            gwmax[gi] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // All row totals of the last pass (for the counter readers).
 __global__ __launch_bounds__(kBlock) void k_reduce_rows(const RowPart *part, int np, DevCounters *c) {
     reduce_row_parts(part, np, c);
@@ -730,6 +759,8 @@ struct ScoreArgs {
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
     const int *blist;       // incremental pass: the blocks to run (else every block)
+    const unsigned long long *gwmax;  // batched graphs: w_max bits of each graph, else null
+    const int32_t *vgraph;            // batched graphs: graph of each vertex
     double *R, *raw;
     long long *tI, *tII;
     const DevCounters *ctr;
@@ -932,7 +963,7 @@ __device__ __forceinline__ double score_value(double acc, int d, double wmax) {
 template <typename OffT>
 __device__ __forceinline__ void score_store(const ScoreArgs<OffT> &A, int u, int d, double acc, long long cI,
                                             long long cII, double wmax, ScoreAcc &sa) {
-    A.R[u] = score_value(acc, d, wmax);
+    A.R[u] = score_value(acc, d, A.gwmax ? bitsd(A.gwmax[A.vgraph[u]]) : wmax);
     A.raw[u] = acc;
     A.tI[u] = cI;
     A.tII[u] = cII;
@@ -1226,7 +1257,8 @@ __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int par
 // whose foreign list became empty keeps the zeros the row pass wrote.
 __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const int32_t *hub_first,
                                                     const HubPart *hub_part, int n_hubs, const VCard *card,
-                                                    const DevCounters *ctr, double *R, double *raw,
+                                                    const DevCounters *ctr, const unsigned long long *gwmax,
+                                                    const int32_t *vgraph, double *R, double *raw,
                                                     long long *tI, long long *tII) {
     const int hub = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1250,7 +1282,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const i
         const int u = hubs[hub];
         const VMeta m = card[u].m;
         if (m.deg - (m.q - m.p) > 0) {
-            R[u] = score_value(acc, m.deg, bitsd(ctr->wmax_bits));
+            R[u] = score_value(acc, m.deg, bitsd(gwmax ? gwmax[vgraph[u]] : ctr->wmax_bits));
             raw[u] = acc;
             tI[u] = c1;
             tII[u] = c2;
@@ -1580,6 +1612,7 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     A.wown = D.wown;
     A.R = D.R;
     A.raw = D.raw;
+    A.vmaxw = g->n_graphs > 0 ? D.vmaxw : nullptr;
     A.tI = D.tI;
     A.tII = D.tII;
     A.part = D.part_rows;
@@ -1592,6 +1625,9 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     }
     timing_begin(g, K_WMAX, &ev);
     hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.wmax_part, g->grid_rows, D.ctr);
+    if (g->n_graphs > 0)
+        hipLaunchKernelGGL(k_wmax_graphs, dim3(grid_for(g->n_graphs, 1, 4096)), dim3(kBlock), 0, g->stream, D.vmaxw,
+                           D.vstart, g->n_graphs, D.gwmax);
     timing_end(g, K_WMAX, ev);
 
     ScoreArgs<OffT> S;
@@ -1616,6 +1652,8 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     S.plink = D.plink;
     S.R = D.R;
     S.raw = D.raw;
+    S.gwmax = g->n_graphs > 0 ? D.gwmax : nullptr;
+    S.vgraph = D.vgraph;
     S.tI = D.tI;
     S.tII = D.tII;
     S.ctr = D.ctr;
@@ -1638,8 +1676,8 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     if (g->n_shubs > 0) {
         timing_begin(g, K_HUB_SUM, &ev);
         hipLaunchKernelGGL(k_hub_sum, dim3((g->n_shubs + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
-                           g->stream, D.shubs, D.shub_first, D.hub_part, g->n_shubs, D.card, D.ctr, D.R, D.raw,
-                           D.tI, D.tII);
+                           g->stream, D.shubs, D.shub_first, D.hub_part, g->n_shubs, D.card, D.ctr, D.gwmax,
+                           D.vgraph, D.R, D.raw, D.tI, D.tII);
         timing_end(g, K_HUB_SUM, ev);
     }
     if (inc && D.n > 0)  // w_max moved: every score is rescaled from its raw sum
@@ -2445,6 +2483,98 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     return e == hipSuccess ? RS_OK : hip_fail(e, "top-k copy");
 }
 
+// ------------------------------------------------------------ batched top-k
+// Top-k of every graph of a batch (one workgroup per graph, k <= kBatchK):
+// each thread keeps the k best keys of its strided share of the graph's
+// vertices, sorted, in LDS (column-major, so threads hit distinct banks); the
+// union of these lists holds the graph's top-k, which k rounds of a
+// block-wide maximum over the list heads take out in order.  Keys are
+// (score bits, 0xffffffff - the caller's id within its graph).
+__global__ __launch_bounds__(kBlock) void k_topk_graphs(const double *R, const int32_t *new2old, const uint8_t *alive,
+                                                        const int64_t *vstart, int n_graphs, int k, int32_t *ids,
+                                                        double *scores, int64_t *counts) {
+    __shared__ unsigned long long lhi[kBatchK][kBlock];
+    __shared__ unsigned int llo[kBatchK][kBlock];
+    __shared__ unsigned long long whi[kBlock / 64];
+    __shared__ unsigned int wlo[kBlock / 64];
+    __shared__ int wt[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int gi = blockIdx.x; gi < n_graphs; gi += gridDim.x) {
+        const long long v0 = vstart[gi], v1 = vstart[gi + 1];
+        int cnt = 0;
+        for (long long v = v0 + tid; v < v1; v += kBlock) {
+            if (!alive[v]) continue;
+            const unsigned long long hi = score_bits(R[v]);
+            const unsigned int lo = 0xffffffffu - (unsigned int)(new2old[v] - (int)v0);
+            // insert into this thread's descending list of at most k keys
+            if (cnt == k && !(hi > lhi[k - 1][tid] || (hi == lhi[k - 1][tid] && lo > llo[k - 1][tid]))) continue;
+            int p = cnt < k ? cnt++ : k - 1;
+            while (p > 0 && (hi > lhi[p - 1][tid] || (hi == lhi[p - 1][tid] && lo > llo[p - 1][tid]))) {
+                lhi[p][tid] = lhi[p - 1][tid];
+                llo[p][tid] = llo[p - 1][tid];
+                --p;
+            }
+            lhi[p][tid] = hi;
+            llo[p][tid] = lo;
+        }
+        int ptr = 0;
+        int taken = 0;
+        for (int r = 0; r < k; ++r) {
+            // this thread's head, then the block maximum (ties cannot occur:
+            // ids are distinct within a graph)
+            bool has = ptr < cnt;
+            unsigned long long hh = has ? lhi[ptr][tid] : 0ull;
+            unsigned int hl = has ? llo[ptr][tid] : 0u;
+            int ht = has ? tid : -1;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long oh = (unsigned long long)__shfl_xor((long long)hh, o);
+                const unsigned int ol = (unsigned int)__shfl_xor((int)hl, o);
+                const int ot = __shfl_xor(ht, o);
+                if (ot >= 0 && (ht < 0 || oh > hh || (oh == hh && ol > hl))) {
+                    hh = oh;
+                    hl = ol;
+                    ht = ot;
+                }
+            }
+            if (lane == 0) {
+                whi[wave] = hh;
+                wlo[wave] = hl;
+                wt[wave] = ht;
+            }
+            __syncthreads();
+            unsigned long long bh = 0;
+            unsigned int bl = 0;
+            int bt = -1;
+            for (int w = 0; w < kBlock / 64; ++w)
+                if (wt[w] >= 0 && (bt < 0 || whi[w] > bh || (whi[w] == bh && wlo[w] > bl))) {
+                    bh = whi[w];
+                    bl = wlo[w];
+                    bt = wt[w];
+                }
+            __syncthreads();
+            if (bt < 0) break;  // fewer live vertices than k
+            if (tid == bt) ++ptr;
+            if (tid == 0) {
+                ids[(long long)gi * k + r] = (int32_t)(0xffffffffu - bl);
+                scores[(long long)gi * k + r] = __longlong_as_double((long long)bh);
+            }
+            ++taken;
+        }
+        if (tid == 0) counts[gi] = taken;
+        __syncthreads();
+    }
+}
+
+rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts) {
+    DeviceGraph &D = g->d;
+    if (g->n_graphs <= 0) return RS_OK;
+    hipLaunchKernelGGL(k_topk_graphs, dim3(grid_for(g->n_graphs, 1, 8192)), dim3(kBlock), 0, g->stream, D.R,
+                       D.new2old, D.alive, D.vstart, g->n_graphs, (int)k, d_ids, d_scores, d_counts);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "batched top-k launch");
+}
+
 // ============================================================ removals
 // A removed CSR entry is marked by complementing it (~x < 0), which keeps
 // every row ordered on the decoded value until the compaction below.
@@ -2792,17 +2922,18 @@ rs_status launch_incremental_marks(rs_graph *g) {
 }
 
 // ============================================================ readers
-__global__ void k_gather_scores(const double *R, const int32_t *new2old, const DevCounters *ctr, long long n, int raw,
+__global__ void k_gather_scores(const double *R, const int32_t *new2old, const DevCounters *ctr,
+                                const unsigned long long *gwmax, const int32_t *vgraph, long long n, int raw,
                                 double *out) {
     const double wmax = bitsd(ctr->wmax_bits);
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x)
-        out[new2old[v]] = raw ? R[v] * wmax : R[v];
+        out[new2old[v]] = raw ? R[v] * (gwmax ? bitsd(gwmax[vgraph[v]]) : wmax) : R[v];
 }
 
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw) {
     const int grid = grid_for(g->d.n, 256, 8192);
     hipLaunchKernelGGL(k_gather_scores, dim3(grid), dim3(256), 0, g->stream, g->d.R, g->d.new2old, g->d.ctr,
-                       (long long)g->d.n, raw, d_out);
+                       g->n_graphs > 0 ? g->d.gwmax : nullptr, g->d.vgraph, (long long)g->d.n, raw, d_out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "gather launch");
 }

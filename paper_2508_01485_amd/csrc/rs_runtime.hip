@@ -635,6 +635,110 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     return RS_OK;
 }
 
+rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const rs_csr *csr, void *hip_stream,
+                        uint32_t flags, rs_graph **out) {
+    clear_error();
+    if (!out) return fail(RS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_graphs < 1 || !vertex_offsets || !csr) return fail(RS_ERR_ARG, "n_graphs < 1, or a NULL array");
+    if (csr->on_device) return fail(RS_ERR_ARG, "a batch is loaded from host arrays");
+    if (csr->n < 0 || csr->nnz < 0) return fail(RS_ERR_ARG, "negative n or nnz");
+    if (csr->offset_bytes != 4 && csr->offset_bytes != 8) return fail(RS_ERR_ARG, "offset_bytes must be 4 or 8");
+    if (!csr->row_offsets || (csr->n > 0 && !csr->labels) || (csr->nnz > 0 && !csr->col))
+        return fail(RS_ERR_ARG, "null CSR array");
+    const int64_t n = csr->n;
+    if (vertex_offsets[0] != 0 || vertex_offsets[n_graphs] != n) return fail(RS_ERR_ARG, "vertex_offsets must run 0..n");
+    for (int32_t gi = 0; gi < n_graphs; ++gi)
+        if (vertex_offsets[gi + 1] < vertex_offsets[gi]) return fail(RS_ERR_ARG, "vertex_offsets decrease");
+    auto rowoff = [&](int64_t v) {
+        return csr->offset_bytes == 8 ? ((const int64_t *)csr->row_offsets)[v]
+                                      : (int64_t)((const int32_t *)csr->row_offsets)[v];
+    };
+    // every edge stays inside its graph; labels are ranked per graph and
+    // offset so that no community spans two graphs (the ranks keep each
+    // graph's label order, hence its internal numbering)
+    std::vector<int32_t> lab2;
+    try {
+        lab2.resize(n);
+        int64_t base = 0;
+        for (int32_t gi = 0; gi < n_graphs; ++gi) {
+            const int64_t a = vertex_offsets[gi], b = vertex_offsets[gi + 1];
+            for (int64_t v = a; v < b; ++v)
+                for (int64_t e = rowoff(v); e < rowoff(v + 1); ++e)
+                    if (csr->col[e] < a || csr->col[e] >= b) return fail(RS_ERR_GRAPH, "an edge joins two graphs of the batch");
+            std::vector<int32_t> u(csr->labels + a, csr->labels + b);
+            std::sort(u.begin(), u.end());
+            u.erase(std::unique(u.begin(), u.end()), u.end());
+            for (int64_t v = a; v < b; ++v) {
+                if (csr->labels[v] < 0) return fail(RS_ERR_GRAPH, "negative label");
+                lab2[v] = (int32_t)(base + (std::lower_bound(u.begin(), u.end(), csr->labels[v]) - u.begin()));
+            }
+            base += (int64_t)u.size();
+            if (base > (int64_t)INT32_MAX) return fail(RS_ERR_RANGE, "too many communities in the batch");
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host staging of the batch failed");
+    }
+    rs_csr c = *csr;
+    c.labels = lab2.data();
+    rs_graph *g = nullptr;
+    rs_status st = rs_load_graph(&c, hip_stream, flags, &g);
+    if (st != RS_OK) return st;
+    DeviceGraph &D = g->d;
+    g->n_graphs = n_graphs;
+    g->h_vstart.assign(vertex_offsets, vertex_offsets + n_graphs + 1);
+    std::vector<int32_t> vg(n);
+    for (int32_t gi = 0; gi < n_graphs; ++gi)
+        for (int64_t v = vertex_offsets[gi]; v < vertex_offsets[gi + 1]; ++v) vg[v] = gi;
+    const size_t N = (size_t)std::max<int64_t>(n, 1), G = (size_t)n_graphs;
+    struct Req {
+        void **p;
+        size_t bytes;
+    } reqs[] = {
+        {(void **)&D.vstart, 8 * (G + 1)},
+        {(void **)&D.vgraph, 4 * N},
+        {(void **)&D.vmaxw, 8 * N},
+        {(void **)&D.gwmax, 8 * G},
+        {(void **)&D.bids, 4 * G * kBatchK},
+        {(void **)&D.bscores, 8 * G * kBatchK},
+        {(void **)&D.bcounts, 8 * G},
+    };
+    hipError_t e = hipSuccess;
+    for (auto &r : reqs) {
+        e = dev_alloc(g, r.p, r.bytes);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(D.vstart, vertex_offsets, 8 * (G + 1), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(D.vgraph, vg.data(), 4 * n, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && n) e = hipMemsetAsync(D.vmaxw, 0, 8 * n, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "batch upload");
+        std::string keep = g_err;
+        rs_free_graph(g);
+        g_err = keep;
+        return st;
+    }
+    *out = g;
+    return RS_OK;
+}
+
+rs_status rs_topk_batch(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *counts) {
+    clear_error();
+    if (!g || !ids || !scores || !counts) return fail(RS_ERR_ARG, "graph or an output is NULL");
+    if (g->n_graphs <= 0) return fail(RS_ERR_STATE, "not a batch");
+    if (k < 1 || k > kBatchK) return fail(RS_ERR_ARG, "k must be 1.." + std::to_string(kBatchK));
+    if (!g->scored) return fail(RS_ERR_STATE, "rs_topk_batch before rs_score");
+    rs_status st = launch_topk_graphs(g, k, g->d.bids, g->d.bscores, g->d.bcounts);
+    if (st != RS_OK) return st;
+    const size_t G = (size_t)g->n_graphs;
+    hipError_t e = hipMemcpyAsync(ids, g->d.bids, 4 * G * (size_t)k, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(scores, g->d.bscores, 8 * G * (size_t)k, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, g->d.bcounts, 8 * G, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? RS_OK : hip_fail(e, "batched top-k copy");
+}
+
 void rs_free_graph(rs_graph *g) {
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
@@ -667,6 +771,7 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     clear_error();
     if (!g || !b) return fail(RS_ERR_ARG, "graph or batch is NULL");
     if (!g->scored) return fail(RS_ERR_STATE, "rs_apply_removals before rs_score");
+    if (g->n_graphs > 0) return fail(RS_ERR_STATE, "removals are not applied to a batch of graphs");
     if (b->n_edges < 0 || b->n_vertices < 0) return fail(RS_ERR_ARG, "negative batch size");
     if (b->n_edges > 0 && (!b->src || !b->dst)) return fail(RS_ERR_ARG, "edge arrays are NULL");
     if (b->n_vertices > 0 && !b->vertices) return fail(RS_ERR_ARG, "vertex array is NULL");
