@@ -4,8 +4,13 @@ One step = one full scoring pass (rs_score: border detection, interaction
 matrix, weights, w_max, type-II aggregate, Eq. RSI scores) plus rs_topk(K) on a
 graph already resident in HBM.  Prints ONE JSON line (rank 0, N=1).
 
-  python bench.py [--steps K] [--warmup W] [--workload lfr_1m|sbm_2k|lfr_20m]
+  python bench.py [--steps K] [--warmup W] [--workload lfr_1m|sbm_2k|lfr_20m|batch|served]
                   [--no-cpu-baseline] [--copy-calibration]
+
+--workload batch scores many small graphs as one batch (one pass over their
+disjoint union, per-graph w_max and top-k) and times the same graphs scored
+one by one as separate resident graphs beside it; --workload served drives the
+request server.
 
 --copy-calibration runs only a plain device copy of known size, for scaling the
 FETCH_SIZE / WRITE_SIZE counters of rocprofv3 runs.
@@ -31,6 +36,9 @@ WORKLOADS = {
     "lfr_1m": ("LFR-style n=1,000,000, degree exponent 2.5 mean 20 max 5,000, community sizes "
                "exponent 1.5 on [50, 20,000], mixing 0.1, seed 0", 1000),
     "lfr_20m": ("LFR-style n=20,000,000, mean degree 30, max 100,000, mixing 0.15, seed 0", 10000),
+    "batch": ("graphs g = 0..G-1 (seed 1000+g): n log-uniform on [200, 50,000], mean degree U[8, 40], "
+              "U{5..500} communities (at most n/10), mixing U[0.05, 0.3], SBM or LFR-style (max degree "
+              "min(1,000, n/4)) with probability 1/2; scored as one batch, per-graph w_max and top-20", 20),
     "served": ("resident LFR-style graphs (seeds 5000+g), n log-uniform on [1e5, nmax], mean degree 20, "
                "max 5,000, mixing 0.1; Poisson removal requests, each followed by a top-100 query", 100),
 }
@@ -304,6 +312,108 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch(args):
+    """The batched form: G graphs packed into one disjoint union and scored by
+    one pass (rs_score + rs_topk_batch(20)); beside it the same graphs loaded
+    as G separate resident graphs, each scored by rs_score + rs_topk(20) in
+    turn.  Every per-graph top-20 of the batch is compared with the separate
+    graph's, bit for bit."""
+    import torch
+
+    import paper_2508_01485_amd as rs
+    from rsgen import cfg_batch, pack_batch
+    K = WORKLOADS["batch"][1]
+    t0 = time.perf_counter()
+    graphs = cfg_batch(args.batch_graphs, workers=min(16, os.cpu_count() or 1))
+    vo, off, col, lab = pack_batch(graphs)
+    n_tot, m_tot = int(vo[-1]), int(off[-1]) // 2
+    log(f"generated {len(graphs)} graphs (n={n_tot}, m={m_tot}) in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    h = rs.rs_load_batch(vo, off, col, lab, stream=stream)
+    load_s = time.perf_counter() - t0
+    del off, col
+    log(f"batch loaded in {load_s:.2f}s")
+    for _ in range(args.warmup):
+        rs.rs_score(h)
+        rs.rs_topk_batch(h, K)
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        rs.rs_score(h)
+        bids, bsc, bcnt = rs.rs_topk_batch(h, K)  # waits for the stream
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t_start) / args.steps
+    rs.rs_set_timing(h, True)
+    rs.rs_read_timings(h)
+    for _ in range(args.steps):
+        rs.rs_score(h)
+        rs.rs_topk_batch(h, K)
+    torch.cuda.synchronize()
+    timings = rs.rs_read_timings(h)
+    counts = rs.rs_read_counts(h)
+    rs.rs_free_graph(h)
+    log("kernel ms/launch:", {k: round(v[0] / v[1], 4) for k, v in timings.items() if v[1]})
+
+    log("loading the graphs one by one")
+    t0 = time.perf_counter()
+    hs = [rs.rs_load_graph(g.off, g.col, g.labels, stream=stream) for g in graphs]
+    log(f"{len(hs)} graphs loaded in {time.perf_counter() - t0:.1f}s")
+    for x in hs:  # warm-up sweep
+        rs.rs_score(x)
+        rs.rs_topk(x, K)
+    seq = []
+    same = True
+    for rep_i in range(args.batch_sweeps):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        tops = []
+        for x in hs:
+            rs.rs_score(x)
+            tops.append(rs.rs_topk(x, K))
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - s0)
+        if rep_i == 0:
+            for i, (ids, sc) in enumerate(tops):
+                c = int(bcnt[i])
+                same &= c == ids.size and np.array_equal(bids[i, :c], ids) and bsc[i, :c].tobytes() == sc.tobytes()
+    for x in hs:
+        x.free()
+    t_seq = float(np.median(seq))
+
+    s_off = 8
+    kb = kernel_bytes(counts, n_tot, 2 * m_tot, s_off, K * len(graphs))
+    def avg(name):
+        ms, nl = timings.get(name, (0.0, 0))
+        return 1000.0 * ms / nl if nl else 0.0
+    avg_us = {"k_rows": avg("k_rows"), "k_score": avg("k_score") + avg("k_score_hub") + avg("k_hub_sum")}
+    dom = max(avg_us, key=avg_us.get)
+    achieved = kb[dom] / (avg_us[dom] * 1e-6) / 1e9
+    deg = [g.nnz / max(g.n, 1) for g in graphs]
+    out = {
+        "metric": METRIC, "value": m_tot / t_batch, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * t_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch: {len(graphs)} {WORKLOADS['batch'][0]}", "graphs": len(graphs),
+                   "n_total": n_tot, "m_total": m_tot, "n_max": int(max(g.n for g in graphs)),
+                   "mean_degree_range": [round(min(deg), 2), round(max(deg), 2)],
+                   "sbm_graphs": int(sum(g.meta["kind"] == "sbm" for g in graphs)), "top_k": K},
+        "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)), "p90": 1000 * float(np.percentile(lat, 90))},
+        "load_s": load_s,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": kb[dom],
+                     "avg_us": avg_us[dom]},
+        "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]},
+        "one_by_one": {"ms_per_sweep": 1000.0 * t_seq, "edges_per_s": m_tot / t_seq,
+                       "batch_speedup": t_seq / t_batch, "top20_identical": bool(same)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +422,8 @@ def main():
     ap.add_argument("--workload", default="lfr_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-sweeps", type=int, default=3)
     ap.add_argument("--served-graphs", type=int, default=16)
     ap.add_argument("--served-nmax", type=float, default=1e6)
     ap.add_argument("--served-slots", type=int, default=4)
@@ -329,6 +441,9 @@ def main():
 
     if args.workload == "served":
         bench_served(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
 
     import torch

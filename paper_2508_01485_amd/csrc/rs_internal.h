@@ -84,6 +84,8 @@ enum KernelId {
     K_TOPK_TIE,
     K_TOPK_RANK,
     K_HUB_SUM,
+    K_TOPK_GRAPHS,
+    K_WMAX_GRAPHS,
     K_COUNT
 };
 
@@ -217,8 +219,9 @@ struct DeviceGraph {
     // batched graphs (a disjoint union of n_graphs graphs, each a contiguous id range)
     int64_t *vstart = nullptr;              // [n_graphs + 1] first vertex of each graph
     int32_t *vgraph = nullptr;              // [n] graph of each vertex
-    unsigned long long *vmaxw = nullptr;    // [n] largest weight of each vertex (bits)
     unsigned long long *gwmax = nullptr;    // [n_graphs] w_max of each graph (bits)
+    int32_t *gblk_off = nullptr, *gblk = nullptr;  // the row blocks of each graph
+    int32_t *gorder = nullptr;              // graphs by decreasing vertex count (top-k order of work)
     int32_t *bids = nullptr;                // [n_graphs * kBatchK] per-graph top-k
     double *bscores = nullptr;
     int64_t *bcounts = nullptr;             // [n_graphs]
@@ -285,6 +288,7 @@ struct rs_graph {
     bool graphs_off = false;  // eager launches only (RS_GRAPHS=0, or a capture failed)
     int32_t n_graphs = 0;     // > 0: a batch of graphs loaded as one disjoint union
     std::vector<int64_t> h_vstart;
+    std::vector<int32_t> h_gblk_off, h_gblk;
     std::vector<void *> allocations;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;

@@ -112,7 +112,6 @@ struct RowArgs {
     long long *tI, *tII;
     RowPart *part;
     unsigned long long *wmax_part;  // [grid] w_max bits of each block (dense copy for k_wmax)
-    unsigned long long *vmaxw;      // batched graphs: [n] bits of each vertex's largest weight, else null
 };
 
 struct RowResult {
@@ -241,7 +240,6 @@ struct RowTileShared {
     int runlab[kRowTile];                // label of each run (-1: removed tail)
     double vX[kRowTileV];
     int vd[kRowTileV], vell[kRowTileV], vlab[kRowTileV];
-    unsigned long long vmw[kRowTileV];   // batched graphs: each vertex's largest weight (bits)
     unsigned short vrf[kRowTileV], vo[kRowTileV];
 };
 
@@ -365,7 +363,6 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         res.q = below + fown;
         res.wown = fown > 0 ? weight_present_t(S.tab, d, X, ell, fown) : weight_absent_t(S.tab, d, X, ell);
         res.lmax = res.wown;
-        if (A.vmaxw) S.vmw[i] = dbits(res.wown);
         int4 k4;  // the first record keys: the labels of the first valid runs
         k4.x = ell > 0 ? S.runlab[rf] : INT_MAX;
         k4.y = ell > 1 ? S.runlab[rf + 1] : INT_MAX;
@@ -389,11 +386,6 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         rd.w = w;
         A.recdat[idx] = rd;
         acc.wmax = fmax(acc.wmax, w);
-        if (A.vmaxw) atomicMax(&S.vmw[i], dbits(w));  // weights are >= 0: bits order like values
-    }
-    if (A.vmaxw) {
-        __syncthreads();
-        for (int i = tid; i < nv; i += kBlock) A.vmaxw[v0 + i] = S.vmw[i];
     }
     // pair facts at the foreign entries: entry (w, u) gets the record of
     // C(u) in w's row (contiguous writes along the runs)
@@ -616,7 +608,6 @@ __device__ void hub_row(const RowArgs<OffT> &A, RowTileShared &S, int v, RowAcc 
         k4.z = ell > 2 ? A.reckey[rb + 2] : INT_MAX;
         k4.w = ell > 3 ? A.reckey[rb + 3] : INT_MAX;
         finish_row(A, v, d, r, k4, (long long)rb, A.goff[v], cv, acc);
-        if (A.vmaxw) A.vmaxw[v] = dbits(r.lmax);
     }
 }
 
@@ -715,24 +706,20 @@ __global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, 
     }
 }
 
-// Batched graphs: each graph's w_max from its vertices' largest weights (one
-// workgroup per graph; the vertices of a graph are a contiguous id range).
-__global__ __launch_bounds__(kBlock) void k_wmax_graphs(const unsigned long long *vmaxw, const int64_t *vstart,
-                                                        int n_graphs, unsigned long long *gwmax) {
-    __shared__ unsigned long long s[kBlock / 64];
-    for (int gi = blockIdx.x; gi < n_graphs; gi += gridDim.x) {
-        unsigned long long m = 0;
-        for (long long v = vstart[gi] + threadIdx.x; v < vstart[gi + 1]; v += kBlock) m = max(m, vmaxw[v]);
-        for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
-        if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long t = 0;
-            for (int i = 0; i < kBlock / 64; ++i) t = max(t, s[i]);
-            gwmax[gi] = t;
-        }
-        __syncthreads();
-    }
+// Batched graphs: each graph's w_max, the maximum of the w_max of its row
+// blocks (row tiles never span two graphs), one wavefront per graph.  The
+// block values are fp64 bits maximised as integers, as for the whole-graph
+// w_max, so a graph's w_max has the bits it has when the graph is alone.
+__global__ __launch_bounds__(kBlock) void k_wmax_graphs(const unsigned long long *wpart, const int32_t *gblk_off,
+                                                        const int32_t *gblk, int n_graphs,
+                                                        unsigned long long *gwmax) {
+    const int gi = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gi >= n_graphs) return;  // whole wavefronts leave; no barrier follows
+    unsigned long long m = 0;
+    for (int i = gblk_off[gi] + lane; i < gblk_off[gi + 1]; i += 64) m = max(m, wpart[gblk[i]]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
+    if (lane == 0) gwmax[gi] = m;
 }
 
 // All row totals of the last pass (for the counter readers).
@@ -1612,7 +1599,6 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     A.wown = D.wown;
     A.R = D.R;
     A.raw = D.raw;
-    A.vmaxw = g->n_graphs > 0 ? D.vmaxw : nullptr;
     A.tI = D.tI;
     A.tII = D.tII;
     A.part = D.part_rows;
@@ -1625,10 +1611,13 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     }
     timing_begin(g, K_WMAX, &ev);
     hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.wmax_part, g->grid_rows, D.ctr);
-    if (g->n_graphs > 0)
-        hipLaunchKernelGGL(k_wmax_graphs, dim3(grid_for(g->n_graphs, 1, 4096)), dim3(kBlock), 0, g->stream, D.vmaxw,
-                           D.vstart, g->n_graphs, D.gwmax);
     timing_end(g, K_WMAX, ev);
+    if (g->n_graphs > 0) {
+        timing_begin(g, K_WMAX_GRAPHS, &ev);
+        hipLaunchKernelGGL(k_wmax_graphs, dim3((g->n_graphs + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                           g->stream, D.wmax_part, D.gblk_off, D.gblk, g->n_graphs, D.gwmax);
+        timing_end(g, K_WMAX_GRAPHS, ev);
+    }
 
     ScoreArgs<OffT> S;
     S.off = (const OffT *)D.off;
@@ -2484,93 +2473,166 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
 }
 
 // ------------------------------------------------------------ batched top-k
-// Top-k of every graph of a batch (one workgroup per graph, k <= kBatchK):
-// each thread keeps the k best keys of its strided share of the graph's
-// vertices, sorted, in LDS (column-major, so threads hit distinct banks); the
-// union of these lists holds the graph's top-k, which k rounds of a
-// block-wide maximum over the list heads take out in order.  Keys are
-// (score bits, 0xffffffff - the caller's id within its graph).
-__global__ __launch_bounds__(kBlock) void k_topk_graphs(const double *R, const int32_t *new2old, const uint8_t *alive,
-                                                        const int64_t *vstart, int n_graphs, int k, int32_t *ids,
-                                                        double *scores, int64_t *counts) {
-    __shared__ unsigned long long lhi[kBatchK][kBlock];
-    __shared__ unsigned int llo[kBatchK][kBlock];
-    __shared__ unsigned long long whi[kBlock / 64];
-    __shared__ unsigned int wlo[kBlock / 64];
-    __shared__ int wt[kBlock / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int gi = blockIdx.x; gi < n_graphs; gi += gridDim.x) {
-        const long long v0 = vstart[gi], v1 = vstart[gi + 1];
-        int cnt = 0;
-        for (long long v = v0 + tid; v < v1; v += kBlock) {
-            if (!alive[v]) continue;
-            const unsigned long long hi = score_bits(R[v]);
-            const unsigned int lo = 0xffffffffu - (unsigned int)(new2old[v] - (int)v0);
-            // insert into this thread's descending list of at most k keys
-            if (cnt == k && !(hi > lhi[k - 1][tid] || (hi == lhi[k - 1][tid] && lo > llo[k - 1][tid]))) continue;
-            int p = cnt < k ? cnt++ : k - 1;
-            while (p > 0 && (hi > lhi[p - 1][tid] || (hi == lhi[p - 1][tid] && lo > llo[p - 1][tid]))) {
-                lhi[p][tid] = lhi[p - 1][tid];
-                llo[p][tid] = llo[p - 1][tid];
-                --p;
-            }
-            lhi[p][tid] = hi;
-            llo[p][tid] = lo;
-        }
-        int ptr = 0;
-        int taken = 0;
-        for (int r = 0; r < k; ++r) {
-            // this thread's head, then the block maximum (ties cannot occur:
-            // ids are distinct within a graph)
-            bool has = ptr < cnt;
-            unsigned long long hh = has ? lhi[ptr][tid] : 0ull;
-            unsigned int hl = has ? llo[ptr][tid] : 0u;
-            int ht = has ? tid : -1;
+// Top-k of every graph of a batch (k <= kBatchK), one wavefront per graph,
+// the largest graphs first: each lane keeps the k best keys of its strided
+// share of the graph's vertices, sorted, in its own LDS column (k * 64 keys
+// per wavefront: lanes hit distinct banks and no barrier is needed).  Keys
+// below a lower bound of the graph's k-th key are dropped with a register
+// compare: first the k-th largest of the lanes' maximum keys (a first pass
+// over the scores; k lanes hold a key at least that large), then, as lists
+// fill, the largest k-th key over the lanes whose lists are full (that lane
+// alone holds k keys at least as large).  The union of the lane
+// lists holds the graph's top-k, which k rounds of a wavefront maximum over
+// the list heads take out in order.  Scores are loaded kTopkGU per lane at a
+// time so their latencies overlap.  Keys are (score bits, 0xffffffff - the
+// caller's id within its graph); ids are distinct, so no two keys tie.
+constexpr int kTopkGU = 16;
+
+__device__ __forceinline__ bool key_gt(unsigned long long ah, unsigned int al, unsigned long long bh, unsigned int bl) {
+    return ah > bh || (ah == bh && al > bl);
+}
+
+// Wavefront maximum of (flag, hi, lo) keys; lanes without a key pass flag 0.
+__device__ __forceinline__ void wave_max_key(bool &f, unsigned long long &h, unsigned int &l, int &who) {
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const unsigned long long oh = (unsigned long long)__shfl_xor((long long)hh, o);
-                const unsigned int ol = (unsigned int)__shfl_xor((int)hl, o);
-                const int ot = __shfl_xor(ht, o);
-                if (ot >= 0 && (ht < 0 || oh > hh || (oh == hh && ol > hl))) {
-                    hh = oh;
-                    hl = ol;
-                    ht = ot;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long oh = (unsigned long long)__shfl_xor((long long)h, o);
+        const unsigned int ol = (unsigned int)__shfl_xor((int)l, o);
+        const int ow = __shfl_xor(who, o);
+        const bool of = __shfl_xor((int)f, o) != 0;
+        if (of && (!f || key_gt(oh, ol, h, l))) {
+            h = oh;
+            l = ol;
+            who = ow;
+            f = true;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_topk_graphs(const double *R, const int32_t *new2old, const uint8_t *alive,
+                                                    const int64_t *vstart, const int32_t *gorder, int n_graphs, int k,
+                                                    int32_t *ids, double *scores, int64_t *counts) {
+    extern __shared__ unsigned long long topk_lds[];  // [k][64] score bits, then [k][64] low keys
+    unsigned long long *lhi = topk_lds;
+    unsigned int *llo = (unsigned int *)(topk_lds + 64 * k);
+    const int lane = threadIdx.x;
+    for (int oi = blockIdx.x; oi < n_graphs; oi += gridDim.x) {
+        const int gi = gorder[oi];
+        const long long v0 = vstart[gi], v1 = vstart[gi + 1];
+        // first pass: each lane's largest key, then the k-th largest of those
+        bool mf = false;
+        unsigned long long mh = 0;
+        unsigned int ml = 0;
+        for (long long base = v0; base < v1; base += 64 * kTopkGU) {
+#pragma unroll
+            for (int j = 0; j < kTopkGU; ++j) {
+                const long long v = base + 64 * j + lane;
+                if (v < v1 && alive[v]) {
+                    const unsigned long long h = score_bits(R[v]);
+                    const unsigned int l = 0xffffffffu - (unsigned int)(new2old[v] - (int)v0);
+                    if (!mf || key_gt(h, l, mh, ml)) {
+                        mh = h;
+                        ml = l;
+                        mf = true;
+                    }
                 }
             }
+        }
+        int rank = 0, nfull = 0;
+        for (int m = 0; m < 64; ++m) {
+            const unsigned long long oh = (unsigned long long)__shfl((long long)mh, m);
+            const unsigned int ol = (unsigned int)__shfl((int)ml, m);
+            const bool of = __shfl((int)mf, m) != 0;
+            nfull += of;
+            rank += of && key_gt(oh, ol, mh, ml);
+        }
+        const unsigned long long at_k = __ballot(mf && rank == k - 1);
+        const bool have_lb = nfull >= k && at_k != 0ull;  // (uniform)
+        unsigned long long lbh = 0;
+        unsigned int lbl = 0;
+        if (have_lb) {
+            const int src = __ffsll((long long)at_k) - 1;
+            lbh = (unsigned long long)__shfl((long long)mh, src);
+            lbl = (unsigned int)__shfl((int)ml, src);
+        }
+        int cnt = 0;
+        unsigned long long th = 0, tl_h = 0;  // wavefront bound; this lane's k-th key
+        unsigned int tl = 0, tl_l = 0;
+        bool have_th = false;
+        for (long long base = v0; base < v1; base += 64 * kTopkGU) {
+            unsigned long long hi[kTopkGU];
+            unsigned int lo[kTopkGU];
+            bool ok[kTopkGU];
+#pragma unroll
+            for (int j = 0; j < kTopkGU; ++j) {
+                const long long v = base + 64 * j + lane;
+                ok[j] = v < v1;
+                hi[j] = 0;
+                lo[j] = 0;
+                if (ok[j]) {
+                    ok[j] = alive[v] != 0;
+                    hi[j] = score_bits(R[v]);
+                    lo[j] = 0xffffffffu - (unsigned int)(new2old[v] - (int)v0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kTopkGU; ++j) {
+                if (!ok[j]) continue;
+                if (have_lb && key_gt(lbh, lbl, hi[j], lo[j])) continue;
+                if (have_th && !key_gt(hi[j], lo[j], th, tl)) continue;
+                if (cnt == k && !key_gt(hi[j], lo[j], tl_h, tl_l)) continue;
+                int p = cnt < k ? cnt++ : k - 1;
+                while (p > 0 && key_gt(hi[j], lo[j], lhi[64 * (p - 1) + lane], llo[64 * (p - 1) + lane])) {
+                    lhi[64 * p + lane] = lhi[64 * (p - 1) + lane];
+                    llo[64 * p + lane] = llo[64 * (p - 1) + lane];
+                    --p;
+                }
+                lhi[64 * p + lane] = hi[j];
+                llo[64 * p + lane] = lo[j];
+                if (cnt == k) {
+                    tl_h = lhi[64 * (k - 1) + lane];
+                    tl_l = llo[64 * (k - 1) + lane];
+                }
+            }
+            bool f = cnt == k;
+            unsigned long long h = f ? tl_h : 0ull;
+            unsigned int l = f ? tl_l : 0u;
+            int who = lane;
+            wave_max_key(f, h, l, who);
+            if (f) {
+                have_th = true;
+                th = h;
+                tl = l;
+            }
+        }
+        int ptr = 0, taken = 0;
+        for (int r = 0; r < k; ++r) {
+            bool f = ptr < cnt;
+            unsigned long long hh = f ? lhi[64 * ptr + lane] : 0ull;
+            unsigned int hl = f ? llo[64 * ptr + lane] : 0u;
+            int who = lane;
+            wave_max_key(f, hh, hl, who);
+            if (!f) break;  // fewer live vertices than k (uniform across the wavefront)
+            if (lane == who) ++ptr;
             if (lane == 0) {
-                whi[wave] = hh;
-                wlo[wave] = hl;
-                wt[wave] = ht;
-            }
-            __syncthreads();
-            unsigned long long bh = 0;
-            unsigned int bl = 0;
-            int bt = -1;
-            for (int w = 0; w < kBlock / 64; ++w)
-                if (wt[w] >= 0 && (bt < 0 || whi[w] > bh || (whi[w] == bh && wlo[w] > bl))) {
-                    bh = whi[w];
-                    bl = wlo[w];
-                    bt = wt[w];
-                }
-            __syncthreads();
-            if (bt < 0) break;  // fewer live vertices than k
-            if (tid == bt) ++ptr;
-            if (tid == 0) {
-                ids[(long long)gi * k + r] = (int32_t)(0xffffffffu - bl);
-                scores[(long long)gi * k + r] = __longlong_as_double((long long)bh);
+                ids[(long long)gi * k + r] = (int32_t)(0xffffffffu - hl);
+                scores[(long long)gi * k + r] = __longlong_as_double((long long)hh);
             }
             ++taken;
         }
-        if (tid == 0) counts[gi] = taken;
-        __syncthreads();
+        if (lane == 0) counts[gi] = taken;
     }
 }
 
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts) {
     DeviceGraph &D = g->d;
     if (g->n_graphs <= 0) return RS_OK;
-    hipLaunchKernelGGL(k_topk_graphs, dim3(grid_for(g->n_graphs, 1, 8192)), dim3(kBlock), 0, g->stream, D.R,
-                       D.new2old, D.alive, D.vstart, g->n_graphs, (int)k, d_ids, d_scores, d_counts);
+    hipEvent_t ev = nullptr;
+    timing_begin(g, K_TOPK_GRAPHS, &ev);
+    hipLaunchKernelGGL(k_topk_graphs, dim3(grid_for(g->n_graphs, 1, 1 << 20)), dim3(64), (size_t)(12 * 64 * k),
+                       g->stream, D.R, D.new2old, D.alive, D.vstart, D.gorder, g->n_graphs, (int)k, d_ids, d_scores,
+                       d_counts);
+    timing_end(g, K_TOPK_GRAPHS, ev);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "batched top-k launch");
 }

@@ -191,16 +191,26 @@ struct HostGraph {
     std::vector<int32_t> outl, cstart;
     std::vector<int32_t> vrowb, vscore;  // the row block and score unit of each vertex
     std::vector<int32_t> rhubs, shubs, sfirst;
+    std::vector<int32_t> gblk_off, gblk;  // batches: the row blocks of each graph
     int n_chunks_lds = 0;
 };
 
 // Greedy cut of the vertex sequence into tiles of consecutive vertices: a
 // tile closes when the next vertex would push its weight past wcap or its
-// vertex count past vcap.  A vertex heavier than wcap is a hub.
+// vertex count past vcap, and at every vertex listed in cuts (ascending).  A
+// vertex heavier than wcap is a hub.
 static void cut_tiles(int64_t n, const std::vector<int64_t> &weight, int64_t wcap, int64_t vcap,
-                      std::vector<int2> &tiles, std::vector<int32_t> &hubs) {
+                      std::vector<int2> &tiles, std::vector<int32_t> &hubs,
+                      const std::vector<int64_t> &cuts = std::vector<int64_t>()) {
     int64_t lo = 0, w = 0;
+    size_t ci = 0;
     for (int64_t v = 0; v < n; ++v) {
+        if (ci < cuts.size() && cuts[ci] <= v) {
+            while (ci < cuts.size() && cuts[ci] <= v) ++ci;
+            if (v > lo) tiles.push_back(make_int2((int)lo, (int)v));
+            lo = v;
+            w = 0;
+        }
         const int64_t x = weight[v];
         if (x > wcap) {
             if (v > lo) tiles.push_back(make_int2((int)lo, (int)v));
@@ -219,9 +229,12 @@ static void cut_tiles(int64_t n, const std::vector<int64_t> &weight, int64_t wca
     if (n > lo) tiles.push_back(make_int2((int)lo, (int)n));
 }
 
+// vstart: for a batch, the first vertex of each graph and n (a graph's
+// vertices keep one contiguous id range through the renumbering, since its
+// labels are ranked above those of the graphs before it); empty otherwise.
 template <class OffIn>
 static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const int32_t *col, const int32_t *lab,
-                                HostGraph &H) {
+                                const std::vector<int64_t> &vstart, HostGraph &H) {
     try {
         // communities: ascending caller label -> internal id 0..k-1
         H.comm2orig.assign(lab, lab + n);
@@ -310,7 +323,7 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
         if (H.oo[n] > (int64_t)INT32_MAX) return fail(RS_ERR_RANGE, "out-lists exceed 32-bit offsets");
         H.cstart.resize(k + 1);
         for (int64_t c = 0; c <= k; ++c) H.cstart[c] = (int32_t)start[c];
-        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs);
+        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs, vstart);
         H.rtiles.resize(H.rtv.size());
         for (size_t t = 0; t < H.rtv.size(); ++t) {
             RowTile &rt = H.rtiles[t];
@@ -350,6 +363,27 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
         for (size_t t = 0; t < H.stiles.size(); ++t)
             for (int v = H.stiles[t].x; v < H.stiles[t].y; ++v)
                 H.vscore[v] = tile_block((int64_t)t, (int64_t)H.stiles.size(), (int64_t)H.n_chunks_lds);
+        if (!vstart.empty()) {
+            // each row block lies in one graph (tiles are cut at the graph
+            // starts): list the blocks of every graph, for its w_max
+            const int64_t G = (int64_t)vstart.size() - 1;
+            auto graph_of = [&](int64_t v) {
+                return (int64_t)(std::upper_bound(vstart.begin(), vstart.end(), v) - vstart.begin()) - 1;
+            };
+            std::vector<std::pair<int32_t, int32_t>> bg;  // (graph, block)
+            for (size_t h = 0; h < H.rhubs.size(); ++h) bg.emplace_back((int32_t)graph_of(H.rhubs[h]), (int32_t)h);
+            for (size_t t = 0; t < H.rtv.size(); ++t)
+                bg.emplace_back((int32_t)graph_of(H.rtv[t].x),
+                                tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size()));
+            std::sort(bg.begin(), bg.end());
+            H.gblk_off.assign(G + 1, 0);
+            H.gblk.resize(bg.size());
+            for (size_t i = 0; i < bg.size(); ++i) {
+                ++H.gblk_off[bg[i].first + 1];
+                H.gblk[i] = bg[i].second;
+            }
+            for (int64_t gi = 0; gi < G; ++gi) H.gblk_off[gi + 1] += H.gblk_off[gi];
+        }
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -540,8 +574,10 @@ static rs_status load_t(const rs_csr *csr, rs_graph *g) {
     rs_status st = validate_graph<OffIn>(n, nnz, off, col, lab);
     if (st != RS_OK) return st;
     HostGraph H;
-    st = build_internal<OffIn>(n, nnz, off, col, lab, H);
+    st = build_internal<OffIn>(n, nnz, off, col, lab, g->h_vstart, H);
     if (st != RS_OK) return st;
+    g->h_gblk_off.swap(H.gblk_off);
+    g->h_gblk.swap(H.gblk);
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (!g->stream) {
@@ -603,8 +639,9 @@ const char *rs_status_string(rs_status s) {
 
 const char *rs_last_error(void) { return g_err.c_str(); }
 
-rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_graph **out) {
-    clear_error();
+// A batch passes its graph starts (n_graphs + 1 entries), else vstart is NULL.
+static rs_status load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, const int64_t *vstart,
+                            int32_t n_graphs, rs_graph **out) {
     if (!out) return fail(RS_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!csr) return fail(RS_ERR_ARG, "csr is NULL");
@@ -623,6 +660,10 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     g->stream = (hipStream_t)hip_stream;  // NULL: created after validation
     g->wide_offsets = (flags & RS_LOAD_WIDE_OFFSETS) != 0;
     if (const char *gv = std::getenv("RS_GRAPHS")) g->graphs_off = gv[0] == '0';
+    if (vstart) {
+        g->n_graphs = n_graphs;
+        g->h_vstart.assign(vstart, vstart + n_graphs + 1);
+    }
     rs_status st = csr->offset_bytes == 8 ? load_t<int64_t>(csr, g) : load_t<int32_t>(csr, g);
     if (st != RS_OK) {
         std::string keep = g_err;
@@ -633,6 +674,11 @@ rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_
     }
     *out = g;
     return RS_OK;
+}
+
+rs_status rs_load_graph(const rs_csr *csr, void *hip_stream, uint32_t flags, rs_graph **out) {
+    clear_error();
+    return load_graph(csr, hip_stream, flags, nullptr, 0, out);
 }
 
 rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const rs_csr *csr, void *hip_stream,
@@ -682,11 +728,9 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
     rs_csr c = *csr;
     c.labels = lab2.data();
     rs_graph *g = nullptr;
-    rs_status st = rs_load_graph(&c, hip_stream, flags, &g);
+    rs_status st = load_graph(&c, hip_stream, flags, vertex_offsets, n_graphs, &g);
     if (st != RS_OK) return st;
     DeviceGraph &D = g->d;
-    g->n_graphs = n_graphs;
-    g->h_vstart.assign(vertex_offsets, vertex_offsets + n_graphs + 1);
     std::vector<int32_t> vg(n);
     for (int32_t gi = 0; gi < n_graphs; ++gi)
         for (int64_t v = vertex_offsets[gi]; v < vertex_offsets[gi + 1]; ++v) vg[v] = gi;
@@ -697,8 +741,10 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
     } reqs[] = {
         {(void **)&D.vstart, 8 * (G + 1)},
         {(void **)&D.vgraph, 4 * N},
-        {(void **)&D.vmaxw, 8 * N},
         {(void **)&D.gwmax, 8 * G},
+        {(void **)&D.gblk_off, 4 * (G + 1)},
+        {(void **)&D.gorder, 4 * G},
+        {(void **)&D.gblk, 4 * std::max<size_t>(g->h_gblk.size(), 1)},
         {(void **)&D.bids, 4 * G * kBatchK},
         {(void **)&D.bscores, 8 * G * kBatchK},
         {(void **)&D.bcounts, 8 * G},
@@ -710,7 +756,16 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
     }
     if (e == hipSuccess) e = hipMemcpyAsync(D.vstart, vertex_offsets, 8 * (G + 1), hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess && n) e = hipMemcpyAsync(D.vgraph, vg.data(), 4 * n, hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess && n) e = hipMemsetAsync(D.vmaxw, 0, 8 * n, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(D.gblk_off, g->h_gblk_off.data(), 4 * (G + 1), hipMemcpyHostToDevice, g->stream);
+    std::vector<int32_t> order(G);
+    for (size_t i = 0; i < G; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return vertex_offsets[a + 1] - vertex_offsets[a] > vertex_offsets[b + 1] - vertex_offsets[b];
+    });
+    if (e == hipSuccess) e = hipMemcpyAsync(D.gorder, order.data(), 4 * G, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && !g->h_gblk.empty())
+        e = hipMemcpyAsync(D.gblk, g->h_gblk.data(), 4 * g->h_gblk.size(), hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) {
         st = hip_fail(e, "batch upload");
@@ -1009,7 +1064,7 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
 
 static const char *kKernelNames[K_COUNT] = {
     "k_rows", "k_wmax", "k_score_hub", "k_score", "k_topk_hist", "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order",
-    "k_hub_sum"};
+    "k_hub_sum", "k_topk_graphs", "k_wmax_graphs"};
 
 const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
 

@@ -15,6 +15,9 @@ from .graphs import (  # noqa: F401
     cfg_sbm_small,
     cfg_lfr_1m,
     cfg_lfr_20m,
+    cfg_batch_graph,
+    cfg_batch,
+    pack_batch,
     graph_stats,
     cached,
 )

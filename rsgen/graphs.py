@@ -493,3 +493,61 @@ def cfg_lfr_1m(seed: int = 0, log=None) -> Graph:
 def cfg_lfr_20m(seed: int = 0, log=None) -> Graph:
     """LFR-style: n=2e7, mean degree 30, max 100,000, mixing 0.15 (same size law)."""
     return lfr(20_000_000, 30.0, 100_000, 0.15, seed, log=log)
+
+
+def cfg_batch_graph(index: int, seed_base: int = 1000) -> Graph:
+    """One graph of the batched workload (seed seed_base + index): n
+    log-uniform on [200, 50,000], mean degree U[8, 40], U{5..500} communities
+    (at most n/10), mixing U[0.05, 0.3]; with probability 1/2 an SBM with
+    equal blocks, else LFR-style with max degree min(1,000, n/4) and community
+    sizes on [m/4, 4m] around m = n / communities (the s^-1.5 law's mean on
+    [a, b] is sqrt(ab) = m)."""
+    seed = seed_base + index
+    rng = np.random.default_rng(seed)
+    n = int(round(np.exp(rng.uniform(np.log(200), np.log(50_000)))))
+    mean_deg = float(rng.uniform(8.0, 40.0))
+    k = int(min(rng.integers(5, 501), max(n // 10, 1)))
+    mu = float(rng.uniform(0.05, 0.3))
+    if rng.random() < 0.5:
+        sizes = np.full(k, n // k, np.int64)
+        sizes[: n % k] += 1
+        s = n / k
+        p_in = min(1.0, (1.0 - mu) * mean_deg / max(s - 1.0, 1.0))
+        p_out = min(1.0, mu * mean_deg / max(n - s, 1.0))
+        g = sbm(sizes, p_in, p_out, seed)
+    else:
+        m = n / k
+        g = lfr(n, mean_deg, min(1000, n // 4), mu, seed, cmin=max(2, int(m / 4)), cmax=max(3, int(4 * m)))
+    g.meta.update({"batch_index": index, "mean_deg_target": mean_deg, "communities_target": k, "mu_target": mu})
+    return g
+
+
+def _batch_one(args):
+    return cfg_batch_graph(*args)
+
+
+def cfg_batch(n_graphs: int = 4096, seed_base: int = 1000, workers: int = 1) -> list:
+    """The batched workload's graphs 0..n_graphs-1 (in index order)."""
+    jobs = [(i, seed_base) for i in range(n_graphs)]
+    if workers <= 1:
+        return [_batch_one(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_batch_one, jobs, chunksize=8)
+
+
+def pack_batch(graphs):
+    """Disjoint union of graphs: (vertex_offsets [G+1] int64, row_offsets
+    int64, col int32 with global ids, labels int32 as given per graph)."""
+    vo = np.zeros(len(graphs) + 1, np.int64)
+    vo[1:] = np.cumsum([g.n for g in graphs])
+    eo = np.zeros(len(graphs) + 1, np.int64)
+    eo[1:] = np.cumsum([g.nnz for g in graphs])
+    off = np.zeros(int(vo[-1]) + 1, np.int64)
+    col = np.empty(int(eo[-1]), np.int32)
+    lab = np.empty(int(vo[-1]), np.int32)
+    for i, g in enumerate(graphs):
+        off[vo[i] + 1: vo[i + 1] + 1] = g.off[1:] + eo[i]
+        col[eo[i]: eo[i + 1]] = g.col + np.int32(vo[i])
+        lab[vo[i]: vo[i + 1]] = g.labels
+    return vo, off, col, lab

@@ -90,6 +90,32 @@ def test_batch_equals_alone(k):
     _say(f"k={k}: every graph's bits equal its lone load")
 
 
+def test_batch_of_many_tiny_graphs():
+    """Hundreds of graphs of 0-60 vertices (many per row tile), k above most
+    graph sizes: counts = live vertices, lists equal the lone loads."""
+    import paper_2508_01485_amd as rs
+    rng = np.random.default_rng(81)
+    gs = [random_small(int(rng.integers(0, 61)), float(rng.uniform(0.05, 0.5)), int(rng.integers(1, 7)), seed=900 + i)
+          for i in range(300)]
+    vo, off, col, lab = _union(gs)
+    h = rs.rs_load_batch(vo, off, col, lab)
+    try:
+        rs.rs_score(h)
+        ids, sc, cnt = rs.rs_topk_batch(h, 32)
+        R = rs.rs_read_scores(h)
+    finally:
+        h.free()
+    for i, g in enumerate(gs):
+        assert cnt[i] == min(32, g.n), i
+        if g.n == 0:
+            continue
+        ref = _alone(rs, g, 32)
+        assert R[vo[i]:vo[i + 1]].tobytes() == ref["R"].tobytes(), i
+        assert np.array_equal(ids[i, :cnt[i]], ref["ids"]), i
+        assert sc[i, :cnt[i]].tobytes() == ref["scores"].tobytes(), i
+    _say("300 tiny graphs: identical to their lone loads")
+
+
 def test_batch_rescore_is_stable():
     """A second score pass on a batch gives the same bits (replayed graphs)."""
     import paper_2508_01485_amd as rs
