@@ -3,7 +3,7 @@
 // graph's own stream).
 //
 // A request applies one removal batch to one graph (the removal model of
-// Section V), re-scores incrementally and reads the top-k.  Worker threads
+// Section VII-B), re-scores incrementally and reads the top-k.  Worker threads
 // take requests in submission order, skipping requests whose graph is busy,
 // so the requests of one graph run one at a time in order while those of
 // different graphs overlap on the device.  Graphs are loaded on demand within
