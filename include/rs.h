@@ -134,10 +134,27 @@ typedef struct {
  * endpoints, their neighbours in other communities, and the members of an
  * endpoint's community adjacent to those neighbours); if w_max moves, every
  * score is rescaled.  This follows the removal model of the experiments
- * (Section V).  Waits for the stream.  RS_ERR_STATE before the first
+ * (Section VII-B).  Waits for the stream.  RS_ERR_STATE before the first
  * rs_score.
  */
 rs_status rs_apply_removals(rs_graph *g, const rs_removals *batch, rs_removal_result *res);
+
+/*
+ * Target-community mode (Section VI-A: spanners are searched in large,
+ * user-given communities and the interaction matrix has one column per
+ * considered community, with T summed over those; Section VII-C: the k
+ * largest communities by member count).  Keeps the k_c communities with the
+ * most members at load (ties: the smaller caller label first) and removes
+ * every vertex of the others as rs_apply_removals does, so the counts, T,
+ * weights, w_max and triads involve the target communities only: the result
+ * is the pass over the subgraph the targets induce (degrees included).
+ * Vertices outside the targets score 0 and are excluded from rs_topk.  The
+ * handle stays restricted; a later call keeps the intersection.  Runs the
+ * first rs_score if none ran yet; res as for rs_apply_removals (all zero when
+ * k_c covers every community).  Errors: RS_ERR_ARG for k_c < 1, RS_ERR_STATE
+ * on a batch.  Waits for the stream.
+ */
+rs_status rs_restrict_to_targets(rs_graph *g, int32_t k_c, rs_removal_result *res);
 
 /*
  * rs_read_scores: out[n] host array, indexed by caller vertex id.
@@ -229,7 +246,7 @@ void rs_free_graph(rs_graph *g);
 
 /*
  * Served scoring: a request loop over several resident graphs (the removal
- * model of Section V applied as a stream of requests).  The server keeps a
+ * model of Section VII-B applied as a stream of requests).  The server keeps a
  * host copy of each registered graph and loads it into device memory on its
  * first request, within an HBM budget: when a graph does not fit, idle graphs
  * are evicted least-recently-used first (an evicted graph is reloaded from

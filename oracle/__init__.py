@@ -169,3 +169,34 @@ def triads(g, u: int, lib=None):
     kind = np.zeros(max(k, 1), np.int32)
     lib.rso_triads(g.n, _ptr(off), _ptr(col), _ptr(lab), u, k, _ptr(w), _ptr(v), _ptr(kind))
     return [(int(w[i]), int(v[i]), int(kind[i])) for i in range(k)]
+
+
+class _Graph:
+    """Plain container (n, off, col, labels) for graphs built here."""
+
+    def __init__(self, n, off, col, labels):
+        self.n, self.off, self.col, self.labels = int(n), off, col, labels
+
+
+def target_communities(labels, k_c: int):
+    """Target-community mode (Section VI-A, the considered communities;
+    Section VII-C, the k largest by member count): the labels of the k_c
+    communities with the most members, ties broken by the smaller label."""
+    labs, counts = np.unique(np.asarray(labels), return_counts=True)
+    order = np.lexsort((labs, -counts))
+    return labs[order[:k_c]]
+
+
+def restrict_to_targets(g, k_c: int):
+    """(graph, keep): the subgraph induced by the target communities' members
+    (every edge with an endpoint outside them dropped, those vertices left
+    isolated with their labels) and the mask of the kept vertices.  Counts,
+    T = sum of f over the considered communities, degrees and triads of the
+    scoring pass then involve the targets only."""
+    keep = np.isin(g.labels, target_communities(g.labels, k_c))
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.off))
+    dst = np.asarray(g.col, dtype=np.int64)
+    ok = keep[src] & keep[dst]
+    off = np.zeros(g.n + 1, np.int64)
+    np.cumsum(np.bincount(src[ok], minlength=g.n), out=off[1:])
+    return _Graph(g.n, off, dst[ok].astype(np.int32), np.asarray(g.labels, dtype=np.int32)), keep

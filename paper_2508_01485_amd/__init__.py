@@ -79,7 +79,7 @@ EXPORTS = [
     "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime", "rs_set_timing", "rs_read_timings",
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
     "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
-    "rs_server_free", "rs_load_batch", "rs_topk_batch",
+    "rs_server_free", "rs_load_batch", "rs_topk_batch", "rs_restrict_to_targets",
 ]
 
 
@@ -116,10 +116,12 @@ def _load_lib(path=LIB_PATH):
     lib.rs_server_free.restype = None
     lib.rs_load_batch.argtypes = [I32, P, ctypes.POINTER(rs_csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
     lib.rs_topk_batch.argtypes = [P, I64, P, P, P]
+    lib.rs_restrict_to_targets.argtypes = [P, I32, ctypes.POINTER(rs_removal_result)]
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
                  "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
-                 "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch"):
+                 "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch",
+                 "rs_restrict_to_targets"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -225,6 +227,13 @@ def rs_apply_removals(g: RSGraph, edges=None, vertices=None) -> dict:
                     dst.ctypes.data if e.shape[0] else None, v.size, v.ctypes.data if v.size else None)
     r = rs_removal_result()
     _check(_lib.rs_apply_removals(g.handle, ctypes.byref(b), ctypes.byref(r)), "rs_apply_removals")
+    return {k: getattr(r, k) for k, _ in rs_removal_result._fields_}
+
+
+def rs_restrict_to_targets(g: RSGraph, k_c: int) -> dict:
+    """Target-community mode: keep the k_c largest communities (removal result)."""
+    r = rs_removal_result()
+    _check(_lib.rs_restrict_to_targets(g.handle, int(k_c), ctypes.byref(r)), "rs_restrict_to_targets")
     return {k: getattr(r, k) for k, _ in rs_removal_result._fields_}
 
 

@@ -1870,11 +1870,53 @@ __global__ __launch_bounds__(kBlock) void k_topk_find0(unsigned int *hist, unsig
 }
 
 // Histogram of digit j over a key list (refinement of a large tie class).
+// The refine levels are launched back to back with no host round trip: a
+// level whose predecessor already took its threshold bin whole (done, at an
+// earlier digit) does nothing.
+__device__ __forceinline__ bool refine_finished(const TopkState *st, int level) {
+    return st->done != 0u && (int)st->digit < level;
+}
+
 __global__ __launch_bounds__(kBlock) void k_list_hist(const TopkKey *list, const unsigned long long *count, int j,
-                                                      unsigned int *hist) {
+                                                      const TopkState *st, unsigned int *hist) {
+    __shared__ unsigned int s_d, s_c;  // the workgroup's aggregated digit and its count
+    if (refine_finished(st, j)) return;
     const long long n = (long long)*count;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-        atomicAdd(&hist[key_digit(list[i], j)], 1u);
+    if (threadIdx.x == 0) {
+        s_d = 0xffffffffu;
+        s_c = 0u;
+    }
+    __syncthreads();
+    // keys of one wavefront that share a digit (common: a class of equal
+    // scores shares every score digit, and ids share their high digits) are
+    // added at once, into the workgroup's counter when the digit is the
+    // workgroup's, so a class of equal keys costs one global atomic per
+    // workgroup
+    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
+        const long long i = base + threadIdx.x;
+        const bool act = i < n;
+        const unsigned int d = act ? key_digit(list[i], j) : 0u;
+        const int lane = threadIdx.x & 63;
+        unsigned long long pend = __ballot(act);
+        // up to four digits shared by several lanes are added by one lane
+        // each; the lanes left over add their own
+        for (int r = 0; r < 4 && pend; ++r) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const unsigned int dl = (unsigned int)__shfl((int)d, leader);
+            const unsigned long long mm = __ballot(act && d == dl);
+            if (lane == leader) {
+                const unsigned int prev = atomicCAS(&s_d, 0xffffffffu, dl);
+                if (prev == 0xffffffffu || prev == dl)
+                    atomicAdd(&s_c, (unsigned int)__popcll(mm));
+                else
+                    atomicAdd(&hist[dl], (unsigned int)__popcll(mm));
+            }
+            pend &= ~mm;
+        }
+        if ((pend >> lane) & 1ull) atomicAdd(&hist[d], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_c) atomicAdd(&hist[s_d], s_c);
 }
 
 // One block of 1024 threads: find the threshold digit of the current level,
@@ -1882,6 +1924,7 @@ __global__ __launch_bounds__(kBlock) void k_list_hist(const TopkKey *list, const
 __global__ __launch_bounds__(1024) void k_topk_find(unsigned int *hist, TopkState *st, int level) {
     __shared__ long long s_scan[1024];
     __shared__ long long s_total;
+    if (refine_finished(st, level)) return;  // (uniform; the histogram is still clear)
     const int t = threadIdx.x;
     const long long need = st->take;
     // thread t owns bins [base, base + 63]; bins descend with t
@@ -2020,10 +2063,11 @@ __global__ __launch_bounds__(kCollThreads) void k_topk_collect(const double *R, 
 }
 
 __global__ __launch_bounds__(kBlock) void k_list_collect(const TopkKey *list, const unsigned long long *count,
-                                                         TopkState *st, TopkKey *fin, TopkKey *tie,
+                                                         int level, TopkState *st, TopkKey *fin, TopkKey *tie,
                                                          unsigned long long *tie_count) {
     __shared__ unsigned int s_cnt[kBlock / 64];
     __shared__ unsigned long long s_base;
+    if (refine_finished(st, level)) return;
     const long long n = (long long)*count;
     const int j = (int)st->digit;
     const unsigned int th = st->thresh;
@@ -2437,30 +2481,25 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     if (st.overflow) {
         // A tie class larger than the pairwise ranker: refine it digit by
         // digit.  The final list already holds the keys above the tie class.
+        // All levels are enqueued at once; the lists only shrink, so the
+        // tie count bounds every level's grid, and the levels after the one
+        // that finishes return at once.
         unsigned long long *cnt = D.scratch_u;  // [0] current list size, [1] next list size
         TopkKey *cur = D.ttie, *nxt = D.ttie2;
+        const int grid_l = grid_for((long long)st.n_tie, 16 * kBlock, 4096);
         e = hipMemcpyAsync(cnt, &D.tstate->n_tie, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
         for (int j = 1; j <= 5 && e == hipSuccess; ++j) {
-            unsigned long long cur_n = 0;
-            e = hipMemcpyAsync(&cur_n, cnt, sizeof(cur_n), hipMemcpyDeviceToHost, g->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-            if (e != hipSuccess) break;
-            const int grid_l = grid_for((long long)cur_n, kBlock, 4096);
-            hipLaunchKernelGGL(k_list_hist, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, j, D.thist);
             timing_begin(g, K_TOPK_FIND, &ev);
+            hipLaunchKernelGGL(k_list_hist, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, j, D.tstate, D.thist);
             hipLaunchKernelGGL(k_topk_find, dim3(1), dim3(1024), 0, g->stream, D.thist, D.tstate, j);
             timing_end(g, K_TOPK_FIND, ev);
             hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, cnt + 1, 1);
-            hipLaunchKernelGGL(k_list_collect, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, D.tstate,
+            hipLaunchKernelGGL(k_list_collect, dim3(grid_l), dim3(kBlock), 0, g->stream, cur, cnt, j, D.tstate,
                                D.tfinal, nxt, cnt + 1);
             e = hipMemcpyAsync(cnt, cnt + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, g->stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(&st, D.tstate, sizeof(st), hipMemcpyDeviceToHost, g->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-            if (e != hipSuccess) break;
             TopkKey *tmp = cur;
             cur = nxt;
             nxt = tmp;
-            if (st.done) break;
         }
         if (e == hipSuccess) e = hipMemsetAsync(&D.tstate->overflow, 0, sizeof(unsigned int), g->stream);
         if (e != hipSuccess) return hip_fail(e, "top-k refine");

@@ -918,6 +918,40 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     return RS_OK;
 }
 
+rs_status rs_restrict_to_targets(rs_graph *g, int32_t k_c, rs_removal_result *res) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    if (k_c < 1) return fail(RS_ERR_ARG, "k_c < 1");
+    if (g->n_graphs > 0) return fail(RS_ERR_STATE, "target mode is not applied to a batch of graphs");
+    // internal communities are numbered in ascending caller label, so a
+    // stable sort by decreasing size breaks ties by the smaller label
+    const int64_t k = g->d.k;
+    std::vector<int32_t> cs, order, drop;
+    hipError_t e = d2h(cs, g->d.cstart, k + 1);
+    if (e != hipSuccess) return hip_fail(e, "community ranges");
+    try {
+        order.resize(k);
+        for (int64_t c = 0; c < k; ++c) order[c] = (int32_t)c;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return cs[a + 1] - cs[a] > cs[b + 1] - cs[b]; });
+        for (int64_t i = k_c; i < k; ++i)
+            for (int32_t v = cs[order[i]]; v < cs[order[i] + 1]; ++v) drop.push_back(g->h_new2old[v]);
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host staging allocation failed");
+    }
+    if (!g->scored) {
+        rs_status st = launch_score_pass(g);
+        if (st != RS_OK) return st;
+        g->scored = true;
+    }
+    if (drop.empty()) {
+        if (res) *res = rs_removal_result{0, 0, 0, 0};
+        return RS_OK;
+    }
+    rs_removals b{0, nullptr, nullptr, (int64_t)drop.size(), drop.data()};
+    return rs_apply_removals(g, &b, res);
+}
+
 rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw) {
     clear_error();
     if (!g || (!out && n > 0)) return fail(RS_ERR_ARG, "graph or out is NULL");

@@ -15,11 +15,16 @@ W_REL = 1e-9     # weights: closed form of Eq. H_optimal vs the direct entropy s
 TIE_REL = 1e-9
 
 
-def gpu_run(g, k, stream=None, flags=0):
+def gpu_run(g, k, stream=None, flags=0, targets=None):
+    """Load, score (or, with targets = k_c, restrict to the k_c largest
+    communities) and read every output."""
     import paper_2508_01485_amd as rs
     h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream, flags=flags)
     try:
-        rs.rs_score(h)
+        if targets is None:
+            rs.rs_score(h)
+        else:
+            rs.rs_restrict_to_targets(h, targets)
         ids, sc = rs.rs_topk(h, k)
         out = {"ids": ids, "scores": sc, "R": rs.rs_read_scores(h), "raw": rs.rs_read_scores(h, raw=True),
                "counts": rs.rs_read_counts(h)}
@@ -72,8 +77,9 @@ def topk_matches(gpu_ids, ora_ids, ora_R_all, k, alive=None):
     return exempt
 
 
-def compare(g, gpu, ora, k):
-    """Full comparison; returns a dict of diagnostics."""
+def compare(g, gpu, ora, k, alive=None):
+    """Full comparison; returns a dict of diagnostics.  alive: the live
+    vertices when some were removed (the oracle's top-k skips the others)."""
     n = g.n
     for key in ("ell", "dprime", "tI", "tII"):
         assert np.array_equal(np.asarray(gpu[key], np.int64), np.asarray(ora[key], np.int64)), key
@@ -103,7 +109,7 @@ def compare(g, gpu, ora, k):
     assert np.array_equal(goff, exp_off) and np.array_equal(gcol, g.col[keep])
     rr = rel_close(gpu["R"], ora["R"], REL)
     rel_close(gpu["raw"], ora["raw"], REL)
-    ora_ids, ora_sc = oracle.topk(ora["R"], k)
-    ex = topk_matches(gpu["ids"], ora_ids, ora["R"], k)
+    ora_ids, ora_sc = oracle.topk(ora["R"], k, alive=alive)
+    ex = topk_matches(gpu["ids"], ora_ids, ora["R"], k, alive=alive)
     rel_close(gpu["scores"], gpu["R"][gpu["ids"]], 0.0)
     return {"w_rel": wr, "w_own_rel": wo, "R_rel": rr, "tie_exempt": ex}
