@@ -39,6 +39,8 @@ WORKLOADS = {
     "batch": ("graphs g = 0..G-1 (seed 1000+g): n log-uniform on [200, 50,000], mean degree U[8, 40], "
               "U{5..500} communities (at most n/10), mixing U[0.05, 0.3], SBM or LFR-style (max degree "
               "min(1,000, n/4)) with probability 1/2; scored as one batch, per-graph w_max and top-20", 20),
+    "robustness": ("LFR-style n=100,000, mean degree 20, max 1,000, community sizes on [50, 5,000], mixing 0.1, "
+                   "seed 0; 5% of the edges (or vertices) removed per step up to 75%", 25),
     "served": ("resident LFR-style graphs (seeds 5000+g), n log-uniform on [1e5, nmax], mean degree 20, "
                "max 5,000, mixing 0.1; Poisson removal requests, each followed by a top-100 query", 100),
 }
@@ -419,6 +421,75 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_robustness(args):
+    """The robustness workload (absolute AWCC, Section VII-B): the top-25 RS
+    vertices of the intact graph against 25 random border vertices; 5% of
+    the original edges (or vertices) removed per step, up to 75%; after each
+    step the absolute AWCC of both sets, mean over v of |zeta(v)| / d0(v)
+    with d0 the intact degree, for two readings of zeta(v): the communities
+    reachable by paths in the disrupted graph (rs_reachable_communities) and
+    those of v's remaining neighbours (the row length ell).  Each step's
+    removal (with the incremental re-score) and reach query are timed."""
+    import torch
+
+    import paper_2508_01485_amd as rs
+    from rsgen import lfr
+    n = args.robust_n
+    g = lfr(n, 20.0, 1000, 0.1, 0, cmin=50, cmax=5000)
+    log(f"graph n={g.n} m={g.m}")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    u, v = g.edges()
+    d0 = np.diff(g.off).astype(np.float64)
+    curves, t_rem, t_reach = {}, [], []
+    for mode in ("edges", "vertices"):
+        rng = np.random.default_rng(11 if mode == "edges" else 12)
+        h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream)
+        rs.rs_score(h)
+        s_rs, _ = rs.rs_topk(h, 25)
+        border = np.flatnonzero(rs.rs_read_vertex_counts(h)["border"])
+        s_rand = rng.choice(border, 25, replace=False)
+        src = np.concatenate([s_rs, s_rand]).astype(np.int32)
+        order = rng.permutation(u.size if mode == "edges" else g.n)
+        per = (u.size if mode == "edges" else g.n) // 20
+        cur = {"removed_pct": [], "rs_paths": [], "random_paths": [], "rs_neighbours": [], "random_neighbours": []}
+        for step in range(16):
+            if step:
+                pick = order[(step - 1) * per: step * per]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "edges":
+                    rs.rs_apply_removals(h, edges=np.stack([u[pick], v[pick]], 1))
+                else:
+                    rs.rs_apply_removals(h, vertices=pick)
+                t_rem.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            reach = rs.rs_reachable_communities(h, src)
+            t_reach.append(time.perf_counter() - t0)
+            ell = rs.rs_read_vertex_counts(h)["ell"][src]
+            a_reach = reach / d0[src]
+            a_hop = ell / d0[src]
+            cur["removed_pct"].append(5 * step)
+            cur["rs_paths"].append(round(float(a_reach[:25].mean()), 5))
+            cur["random_paths"].append(round(float(a_reach[25:].mean()), 5))
+            cur["rs_neighbours"].append(round(float(a_hop[:25].mean()), 5))
+            cur["random_neighbours"].append(round(float(a_hop[25:].mean()), 5))
+        h.free()
+        curves[mode] = cur
+        log(mode, cur)
+    ms_step = 1000.0 * (float(np.mean(t_rem)) + float(np.mean(t_reach)))
+    out = {
+        "metric": METRIC, "value": 1000.0 / ms_step, "unit": "disruption steps/s", "n_gpus": 1,
+        "steps": len(t_rem), "warmup": 0, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"robustness: {WORKLOADS['robustness'][0]}", "n": g.n, "m": g.m, "sets": 25},
+        "removal_ms": {"p50": 1000 * float(np.percentile(t_rem, 50)), "p99": 1000 * float(np.percentile(t_rem, 99))},
+        "reach_ms": {"p50": 1000 * float(np.percentile(t_reach, 50)), "p99": 1000 * float(np.percentile(t_reach, 99))},
+        "absolute_awcc": curves,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +500,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--targets", type=int, default=0,
                     help="target-community mode: score only the K largest communities (0: all)")
+    ap.add_argument("--robust-n", type=int, default=100_000)
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-sweeps", type=int, default=3)
     ap.add_argument("--served-graphs", type=int, default=16)
@@ -451,6 +523,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "robustness":
+        bench_robustness(args)
         return
 
     import torch

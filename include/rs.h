@@ -157,6 +157,20 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *batch, rs_removal_re
 rs_status rs_restrict_to_targets(rs_graph *g, int32_t k_c, rs_removal_result *res);
 
 /*
+ * Reachable communities, for the absolute AWCC of the robustness experiments
+ * (Section VII-B: the average of |zeta(v)| / d(v) over a vertex set, where
+ * after a disruption only |zeta(v)| is recomputed, over the paths the
+ * disrupted graph still has).  For each of the n_sources source vertices
+ * (caller ids, at most 1,024), counts[i] = the number of distinct communities
+ * among the vertices other than the source in the source's connected
+ * component of the current graph (after every removal applied so far); a
+ * removed or isolated source gets 0.  Host arrays; waits for the stream.
+ * Errors: RS_ERR_ARG (NULL arrays, n_sources outside 0..1024), RS_ERR_RANGE
+ * (a source id >= n).  Valid on a batch too (components never span graphs).
+ */
+rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t *sources, int64_t *counts);
+
+/*
  * rs_read_scores: out[n] host array, indexed by caller vertex id.
  *   raw = 0: R(u) of Algorithm 1 (every triad term divided by w_max);
  *   raw = 1: the sum of Eq. RSI without the w_max division (= R * w_max).

@@ -200,3 +200,34 @@ def restrict_to_targets(g, k_c: int):
     off = np.zeros(g.n + 1, np.int64)
     np.cumsum(np.bincount(src[ok], minlength=g.n), out=off[1:])
     return _Graph(g.n, off, dst[ok].astype(np.int32), np.asarray(g.labels, dtype=np.int32)), keep
+
+
+def reachable_communities(g, sources, alive=None):
+    """|zeta(v)| after a disruption, for the absolute AWCC of the robustness
+    experiments (Section VII-B): for each source, a breadth-first search over
+    the current graph, and the number of distinct communities among the
+    vertices it reaches other than the source itself.  A removed source
+    (alive False) reaches nothing."""
+    from collections import deque
+    off = np.asarray(g.off, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    lab = np.asarray(g.labels)
+    out = np.zeros(len(sources), np.int64)
+    for i, s in enumerate(sources):
+        s = int(s)
+        if alive is not None and not alive[s]:
+            continue
+        seen = {s}
+        queue = deque([s])
+        comms = set()
+        while queue:
+            x = queue.popleft()
+            for e in range(off[x], off[x + 1]):
+                y = int(col[e])
+                if y not in seen:
+                    seen.add(y)
+                    comms.add(int(lab[y]))
+                    queue.append(y)
+        # the source's own community counts when another member is reached
+        out[i] = len(comms)
+    return out

@@ -80,6 +80,7 @@ EXPORTS = [
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
     "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
     "rs_server_free", "rs_load_batch", "rs_topk_batch", "rs_restrict_to_targets",
+    "rs_reachable_communities",
 ]
 
 
@@ -117,11 +118,12 @@ def _load_lib(path=LIB_PATH):
     lib.rs_load_batch.argtypes = [I32, P, ctypes.POINTER(rs_csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
     lib.rs_topk_batch.argtypes = [P, I64, P, P, P]
     lib.rs_restrict_to_targets.argtypes = [P, I32, ctypes.POINTER(rs_removal_result)]
+    lib.rs_reachable_communities.argtypes = [P, I64, P, P]
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
                  "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
                  "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch",
-                 "rs_restrict_to_targets"):
+                 "rs_restrict_to_targets", "rs_reachable_communities"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -235,6 +237,15 @@ def rs_restrict_to_targets(g: RSGraph, k_c: int) -> dict:
     r = rs_removal_result()
     _check(_lib.rs_restrict_to_targets(g.handle, int(k_c), ctypes.byref(r)), "rs_restrict_to_targets")
     return {k: getattr(r, k) for k, _ in rs_removal_result._fields_}
+
+
+def rs_reachable_communities(g: RSGraph, sources) -> np.ndarray:
+    """Distinct communities among the other members of each source's component."""
+    src = np.ascontiguousarray(sources, dtype=np.int32).ravel()
+    out = np.zeros(max(src.size, 1), np.int64)
+    _check(_lib.rs_reachable_communities(g.handle, src.size, src.ctypes.data if src.size else None,
+                                         out.ctypes.data), "rs_reachable_communities")
+    return out[: src.size]
 
 
 def rs_read_scores(g: RSGraph, raw: bool = False):

@@ -60,6 +60,7 @@ constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise com
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
+constexpr int kMaxReachSources = 1024;  // sources per rs_reachable_communities call
 constexpr int kBatchK = 32;          // largest k of the per-graph top-k of a batch
 
 // Vertex marks of an incremental re-score (after removals).
@@ -342,6 +343,8 @@ rs_status launch_links(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);
+rs_status launch_reach(rs_graph *g, const int32_t *d_src, int ns, int32_t *comp, unsigned int *bits, int words,
+                       unsigned int *d_changed, unsigned int *h_changed);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);
 
 }  // namespace rs

@@ -3045,4 +3045,101 @@ rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count) {
     return e == hipSuccess ? RS_OK : hip_fail(e, "zero launch");
 }
 
+// ============================================================ reachable communities
+// For the absolute AWCC of the robustness experiments (Section VII-B): the
+// connected components of the current graph by hooking and pointer jumping
+// (labels only decrease along parent links, so no cycle can form), then, for
+// each source, the communities of the other members of its component.
+__global__ __launch_bounds__(kBlock) void k_cc_init(int32_t *comp, long long n) {
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock)
+        comp[v] = (int32_t)v;
+}
+
+// Hook the root of the larger label under the smaller one across every live
+// edge; comp[] holds roots here (the jump kernel ran before).
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_cc_hook(const OffT *off, const int32_t *deg, const int32_t *col,
+                                                    int32_t *comp, long long n, unsigned int *changed) {
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
+        const long long rb = (long long)off[v];
+        const int d = deg[v];
+        bool hooked = false;
+        for (int j = 0; j < d; ++j) {
+            const int32_t x = col[rb + j];
+            if (x < 0) continue;  // (rows are compacted after removals; defensive)
+            const int32_t cu = comp[x], cv = comp[v];
+            if (cu < cv) {
+                atomicMin(&comp[cv], cu);
+                hooked = true;
+            }
+        }
+        if (hooked) *changed = 1u;
+    }
+}
+
+// Point every vertex at its root.
+__global__ __launch_bounds__(kBlock) void k_cc_jump(int32_t *comp, long long n) {
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
+        int32_t c = comp[v];
+        while (comp[c] != c) c = comp[c];
+        comp[v] = c;
+    }
+}
+
+// bits[i][c] = 1 when some vertex other than source i lies in source i's
+// component and belongs to community c.
+__global__ __launch_bounds__(kBlock) void k_reach_bits(const int32_t *comp, const int32_t *lab, long long n,
+                                                       const int32_t *src, int ns, int words, unsigned int *bits) {
+    __shared__ int32_t s_c[kMaxReachSources], s_v[kMaxReachSources];
+    for (int i = threadIdx.x; i < ns; i += kBlock) {
+        s_v[i] = src[i];
+        s_c[i] = comp[src[i]];
+    }
+    __syncthreads();
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
+        const int32_t c = comp[v];
+        const int32_t l = lab[v];
+        for (int i = 0; i < ns; ++i)
+            if (s_c[i] == c && s_v[i] != (int32_t)v) atomicOr(&bits[(long long)i * words + (l >> 5)], 1u << (l & 31));
+    }
+}
+
+__global__ void k_zero_u32(unsigned int *p, long long count) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <typename OffT>
+static rs_status components_t(rs_graph *g, int32_t *comp, unsigned int *d_changed, unsigned int *h_changed) {
+    DeviceGraph &D = g->d;
+    const int grid = grid_for(D.n, kBlock, 8192);
+    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(kBlock), 0, g->stream, comp, (long long)D.n);
+    for (int it = 0; it < 512; ++it) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, d_changed, 1ll);
+        hipLaunchKernelGGL(k_cc_hook<OffT>, dim3(grid), dim3(kBlock), 0, g->stream, (const OffT *)D.off, D.deg, D.col,
+                           comp, (long long)D.n, d_changed);
+        hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(kBlock), 0, g->stream, comp, (long long)D.n);
+        hipError_t e = hipMemcpyAsync(h_changed, d_changed, sizeof(unsigned int), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) return hip_fail(e, "components");
+        if (*h_changed == 0u) return RS_OK;
+    }
+    return fail(RS_ERR_STATE, "components did not converge");
+}
+
+rs_status launch_reach(rs_graph *g, const int32_t *d_src, int ns, int32_t *comp, unsigned int *bits, int words,
+                       unsigned int *d_changed, unsigned int *h_changed) {
+    DeviceGraph &D = g->d;
+    rs_status st = D.off64 ? components_t<long long>(g, comp, d_changed, h_changed)
+                           : components_t<int32_t>(g, comp, d_changed, h_changed);
+    if (st != RS_OK) return st;
+    const int grid = grid_for(D.n, kBlock, 8192);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((long long)ns * words, kBlock, 1024)), dim3(kBlock), 0, g->stream,
+                       bits, (long long)ns * words);
+    hipLaunchKernelGGL(k_reach_bits, dim3(grid), dim3(kBlock), 0, g->stream, comp, D.lab, (long long)D.n, d_src, ns,
+                       words, bits);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "reach launch");
+}
+
 }  // namespace rs

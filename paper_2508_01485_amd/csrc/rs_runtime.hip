@@ -952,6 +952,54 @@ rs_status rs_restrict_to_targets(rs_graph *g, int32_t k_c, rs_removal_result *re
     return rs_apply_removals(g, &b, res);
 }
 
+rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t *sources, int64_t *counts) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    if (n_sources < 0 || n_sources > kMaxReachSources)
+        return fail(RS_ERR_ARG, "n_sources must be 0.." + std::to_string(kMaxReachSources));
+    if (n_sources > 0 && (!sources || !counts)) return fail(RS_ERR_ARG, "sources or counts is NULL");
+    const int64_t n = g->d.n;
+    std::vector<int32_t> src((size_t)n_sources);
+    for (int64_t i = 0; i < n_sources; ++i) {
+        if (sources[i] < 0 || sources[i] >= n) return fail(RS_ERR_RANGE, "source id out of range");
+        src[i] = g->h_old2new[sources[i]];
+    }
+    if (n_sources == 0) return RS_OK;
+    const int words = std::max(1, (int)((g->d.k + 31) / 32));
+    const size_t nb = 4 * (size_t)n_sources * words;
+    int32_t *d_src = nullptr, *comp = nullptr;
+    unsigned int *bits = nullptr, *d_flag = nullptr, *h_flag = nullptr;
+    hipError_t e = hipMalloc((void **)&comp, 4 * (size_t)std::max<int64_t>(n, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_src, 4 * (size_t)n_sources);
+    if (e == hipSuccess) e = hipMalloc((void **)&bits, nb);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_flag, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h_flag, sizeof(unsigned int), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_src, src.data(), 4 * (size_t)n_sources, hipMemcpyHostToDevice, g->stream);
+    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "reach buffers");
+    if (st == RS_OK) st = launch_reach(g, d_src, (int)n_sources, comp, bits, words, d_flag, h_flag);
+    std::vector<unsigned int> hb;
+    if (st == RS_OK) {
+        hb.resize(nb / 4);
+        e = hipMemcpyAsync(hb.data(), bits, nb, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "reach copy");
+    }
+    if (st == RS_OK)
+        for (int64_t i = 0; i < n_sources; ++i) {
+            int64_t c = 0;
+            for (int w = 0; w < words; ++w) c += __builtin_popcount(hb[(size_t)i * words + w]);
+            counts[i] = c;
+        }
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (comp) (void)hipFree(comp);
+    if (d_src) (void)hipFree(d_src);
+    if (bits) (void)hipFree(bits);
+    if (d_flag) (void)hipFree(d_flag);
+    if (h_flag) (void)hipHostFree(h_flag);
+    return st;
+}
+
 rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw) {
     clear_error();
     if (!g || (!out && n > 0)) return fail(RS_ERR_ARG, "graph or out is NULL");
