@@ -61,7 +61,9 @@ constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
 constexpr int kMaxReachSources = 1024;  // sources per rs_reachable_communities call
-constexpr int kBatchK = 32;          // largest k of the per-graph top-k of a batch
+constexpr int kBatchK = 32;
+constexpr int kSegVerts = 1024;   // vertices per batched top-k segment (64 lanes x 16 keys)
+constexpr int kSegMax = 64;       // segments per graph merged by one wavefront          // largest k of the per-graph top-k of a batch
 
 // Vertex marks of an incremental re-score (after removals).
 constexpr unsigned int kRowChanged = 1u;   // the row lost entries
@@ -223,6 +225,10 @@ struct DeviceGraph {
     unsigned long long *gwmax = nullptr;    // [n_graphs] w_max of each graph (bits)
     int32_t *gblk_off = nullptr, *gblk = nullptr;  // the row blocks of each graph
     int32_t *gorder = nullptr;              // graphs by decreasing vertex count (top-k order of work)
+    int32_t *seg_g = nullptr, *sfirst = nullptr;  // top-k segments: graph of each, first of each graph
+    unsigned long long *c_hi = nullptr;     // [segments * kBatchK] segment top-k keys (score bits)
+    unsigned int *c_lo = nullptr;           // [segments * kBatchK] segment top-k keys (low words)
+    int32_t *c_cnt = nullptr;               // [segments] keys per segment list
     int32_t *bids = nullptr;                // [n_graphs * kBatchK] per-graph top-k
     double *bscores = nullptr;
     int64_t *bcounts = nullptr;             // [n_graphs]
@@ -290,6 +296,7 @@ struct rs_graph {
     int32_t n_graphs = 0;     // > 0: a batch of graphs loaded as one disjoint union
     std::vector<int64_t> h_vstart;
     std::vector<int32_t> h_gblk_off, h_gblk;
+    int32_t n_segs = 0;       // batched top-k segments (0: the one-wavefront-per-graph form)
     std::vector<void *> allocations;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;

@@ -2663,14 +2663,119 @@ __global__ __launch_bounds__(64) void k_topk_graphs(const double *R, const int32
     }
 }
 
+// Segmented form, for batches whose graphs have at most 64 segments of
+// kSegKeys = 64 * kTopkGU vertices: one wavefront per segment holds its keys
+// in registers (kTopkGU per lane) and takes out the segment's top-k by k
+// rounds of a wavefront maximum over the lanes' best remaining keys; then one
+// wavefront per graph merges the graph's segment lists (one per lane, staged
+// in its LDS column) by k rounds over the list heads.  The latency of a
+// graph is then that of one segment plus one merge, whatever its size.
+constexpr int kSegKeys = 64 * kTopkGU;
+static_assert(kSegKeys == kSegVerts, "a segment is one key per lane and register slot");
+
+__global__ __launch_bounds__(kBlock) void k_topk_seg(const double *R, const int32_t *new2old, const uint8_t *alive,
+                                                     const int64_t *vstart, const int32_t *seg_g,
+                                                     const int32_t *sfirst, int n_segs, int k,
+                                                     unsigned long long *c_hi, unsigned int *c_lo, int32_t *c_cnt) {
+    const int seg = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (seg >= n_segs) return;  // whole wavefronts leave; no barrier follows
+    const int gi = seg_g[seg];
+    const long long gv0 = vstart[gi];
+    const long long s0 = gv0 + (long long)(seg - sfirst[gi]) * kSegKeys;
+    const long long s1 = min(s0 + (long long)kSegKeys, (long long)vstart[gi + 1]);
+    unsigned long long hi[kTopkGU];
+    unsigned int lo[kTopkGU];
+    unsigned int valid = 0u;
+#pragma unroll
+    for (int j = 0; j < kTopkGU; ++j) {
+        const long long v = s0 + 64 * j + lane;
+        hi[j] = 0ull;
+        lo[j] = 0u;
+        if (v < s1 && alive[v]) {
+            hi[j] = score_bits(R[v]);
+            lo[j] = 0xffffffffu - (unsigned int)(new2old[v] - (int)gv0);
+            valid |= 1u << j;
+        }
+    }
+    int r = 0;
+#pragma unroll 1
+    for (; r < k; ++r) {
+        bool f = false;
+        unsigned long long bh = 0ull;
+        unsigned int bl = 0u;
+        int bj = 0;
+#pragma unroll
+        for (int j = 0; j < kTopkGU; ++j) {
+            const bool ok = ((valid >> j) & 1u) != 0u;
+            const bool better = ok && (!f || key_gt(hi[j], lo[j], bh, bl));
+            bh = better ? hi[j] : bh;
+            bl = better ? lo[j] : bl;
+            bj = better ? j : bj;
+            f = f || ok;
+        }
+        int who = lane;
+        wave_max_key(f, bh, bl, who);
+        if (!f) break;  // the segment has fewer live vertices than k (uniform)
+        if (lane == who) valid &= ~(1u << bj);
+        if (lane == 0) {
+            c_hi[(long long)seg * k + r] = bh;
+            c_lo[(long long)seg * k + r] = bl;
+        }
+    }
+    if (lane == 0) c_cnt[seg] = r;
+}
+
+__global__ __launch_bounds__(64) void k_topk_merge(const unsigned long long *c_hi, const unsigned int *c_lo,
+                                                   const int32_t *c_cnt, const int32_t *sfirst, int n_graphs, int k,
+                                                   int32_t *ids, double *scores, int64_t *counts) {
+    extern __shared__ unsigned long long topk_lds[];  // [k][64] score bits, then [k][64] low keys
+    unsigned long long *lhi = topk_lds;
+    unsigned int *llo = (unsigned int *)(topk_lds + 64 * k);
+    const int lane = threadIdx.x;
+    for (int gi = blockIdx.x; gi < n_graphs; gi += gridDim.x) {
+        const int sa = sfirst[gi], ns = sfirst[gi + 1] - sa;  // ns <= 64
+        const int cnt = lane < ns ? c_cnt[sa + lane] : 0;
+        for (int r = 0; r < cnt; ++r) {
+            lhi[64 * r + lane] = c_hi[(long long)(sa + lane) * k + r];
+            llo[64 * r + lane] = c_lo[(long long)(sa + lane) * k + r];
+        }
+        int ptr = 0, taken = 0;
+        for (int r = 0; r < k; ++r) {
+            bool f = ptr < cnt;
+            unsigned long long hh = f ? lhi[64 * ptr + lane] : 0ull;
+            unsigned int hl = f ? llo[64 * ptr + lane] : 0u;
+            int who = lane;
+            wave_max_key(f, hh, hl, who);
+            if (!f) break;
+            if (lane == who) ++ptr;
+            if (lane == 0) {
+                ids[(long long)gi * k + r] = (int32_t)(0xffffffffu - hl);
+                scores[(long long)gi * k + r] = __longlong_as_double((long long)hh);
+            }
+            ++taken;
+        }
+        if (lane == 0) counts[gi] = taken;
+    }
+}
+
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts) {
     DeviceGraph &D = g->d;
     if (g->n_graphs <= 0) return RS_OK;
     hipEvent_t ev = nullptr;
     timing_begin(g, K_TOPK_GRAPHS, &ev);
-    hipLaunchKernelGGL(k_topk_graphs, dim3(grid_for(g->n_graphs, 1, 1 << 20)), dim3(64), (size_t)(12 * 64 * k),
-                       g->stream, D.R, D.new2old, D.alive, D.vstart, D.gorder, g->n_graphs, (int)k, d_ids, d_scores,
-                       d_counts);
+    if (g->n_segs > 0) {
+        hipLaunchKernelGGL(k_topk_seg, dim3((g->n_segs + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                           g->stream, D.R, D.new2old, D.alive, D.vstart, D.seg_g, D.sfirst, g->n_segs, (int)k,
+                           D.c_hi, D.c_lo, D.c_cnt);
+        hipLaunchKernelGGL(k_topk_merge, dim3(grid_for(g->n_graphs, 1, 1 << 20)), dim3(64), (size_t)(12 * 64 * k),
+                           g->stream, D.c_hi, D.c_lo, D.c_cnt, D.sfirst, g->n_graphs, (int)k, d_ids, d_scores,
+                           d_counts);
+    } else {
+        hipLaunchKernelGGL(k_topk_graphs, dim3(grid_for(g->n_graphs, 1, 1 << 20)), dim3(64), (size_t)(12 * 64 * k),
+                           g->stream, D.R, D.new2old, D.alive, D.vstart, D.gorder, g->n_graphs, (int)k, d_ids,
+                           d_scores, d_counts);
+    }
     timing_end(g, K_TOPK_GRAPHS, ev);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "batched top-k launch");

@@ -758,6 +758,37 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
     if (e == hipSuccess && n) e = hipMemcpyAsync(D.vgraph, vg.data(), 4 * n, hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(D.gblk_off, g->h_gblk_off.data(), 4 * (G + 1), hipMemcpyHostToDevice, g->stream);
+    // top-k segments, when every graph has at most kSegMax of them
+    int64_t nmax = 0;
+    for (size_t i = 0; i < G; ++i) nmax = std::max<int64_t>(nmax, vertex_offsets[i + 1] - vertex_offsets[i]);
+    std::vector<int32_t> seg_g, sfirst(G + 1, 0);
+    if (nmax <= (int64_t)kSegVerts * kSegMax) {
+        for (size_t i = 0; i < G; ++i) {
+            const int64_t ns = (vertex_offsets[i + 1] - vertex_offsets[i] + kSegVerts - 1) / kSegVerts;
+            for (int64_t j = 0; j < ns; ++j) seg_g.push_back((int32_t)i);
+            sfirst[i + 1] = (int32_t)seg_g.size();
+        }
+    }
+    const size_t S = seg_g.size();
+    if (e == hipSuccess && S > 0) {
+        struct Req2 {
+            void **p;
+            size_t bytes;
+        } more[] = {
+            {(void **)&D.seg_g, 4 * S},
+            {(void **)&D.sfirst, 4 * (G + 1)},
+            {(void **)&D.c_hi, 8 * S * kBatchK},
+            {(void **)&D.c_lo, 4 * S * kBatchK},
+            {(void **)&D.c_cnt, 4 * S},
+        };
+        for (auto &r : more) {
+            e = dev_alloc(g, r.p, r.bytes);
+            if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(D.seg_g, seg_g.data(), 4 * S, hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(D.sfirst, sfirst.data(), 4 * (G + 1), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess) g->n_segs = (int32_t)S;
+    }
     std::vector<int32_t> order(G);
     for (size_t i = 0; i < G; ++i) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {

@@ -116,6 +116,31 @@ def test_batch_of_many_tiny_graphs():
     _say("300 tiny graphs: identical to their lone loads")
 
 
+def test_batch_with_a_graph_above_the_segment_limit():
+    """A graph of more than 64 top-k segments (65,536 vertices) sends the
+    batch to the one-wavefront-per-graph top-k; results still equal the lone
+    loads.  Segment-boundary sizes (1,024, 2,048 and 1,025 vertices) ride along."""
+    import paper_2508_01485_amd as rs
+    gs = [lfr(70000, 8.0, 150, 0.3, seed=82, cmin=20, cmax=2000),
+          random_small(1024, 0.01, 5, 83), random_small(2048, 0.005, 7, 84), random_small(1025, 0.01, 3, 85)]
+    for big in (True, False):
+        sel = gs if big else gs[1:]
+        vo, off, col, lab = _union(sel)
+        h = rs.rs_load_batch(vo, off, col, lab)
+        try:
+            rs.rs_score(h)
+            ids, sc, cnt = rs.rs_topk_batch(h, 25)
+        finally:
+            h.free()
+        for i, g in enumerate(sel):
+            ref = _alone(rs, g, 25)
+            c = int(cnt[i])
+            assert c == ref["ids"].size, (big, i)
+            assert np.array_equal(ids[i, :c], ref["ids"]), (big, i)
+            assert sc[i, :c].tobytes() == ref["scores"].tobytes(), (big, i)
+    _say("batches with and without a graph above the segment limit: identical to lone loads")
+
+
 def test_batch_rescore_is_stable():
     """A second score pass on a batch gives the same bits (replayed graphs)."""
     import paper_2508_01485_amd as rs
