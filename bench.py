@@ -366,6 +366,14 @@ def bench_batch(args):
     rs.rs_free_graph(h)
     log("kernel ms/launch:", {k: round(v[0] / v[1], 4) for k, v in timings.items() if v[1]})
 
+    if args.batch_sweeps <= 0:  # the batch alone (e.g. under a profiler)
+        print(json.dumps({"metric": METRIC, "value": m_tot / t_batch, "unit": "edges/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * t_batch,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": f"batch: {len(graphs)} graphs"},
+                          "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]}}),
+              flush=True)
+        return
     log("loading the graphs one by one")
     t0 = time.perf_counter()
     hs = [rs.rs_load_graph(g.off, g.col, g.labels, stream=stream) for g in graphs]

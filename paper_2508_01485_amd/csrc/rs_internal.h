@@ -297,6 +297,8 @@ struct rs_graph {
     std::vector<int64_t> h_vstart;
     std::vector<int32_t> h_gblk_off, h_gblk;
     int32_t n_segs = 0;       // batched top-k segments (0: the one-wavefront-per-graph form)
+    int32_t *reach_comp = nullptr, *reach_src = nullptr;  // reachable-community buffers (first use)
+    unsigned int *reach_bits = nullptr, *reach_flag = nullptr, *reach_hflag = nullptr;
     std::vector<void *> allocations;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;

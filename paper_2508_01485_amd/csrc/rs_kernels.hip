@@ -3204,8 +3204,13 @@ __global__ __launch_bounds__(kBlock) void k_reach_bits(const int32_t *comp, cons
     for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
         const int32_t c = comp[v];
         const int32_t l = lab[v];
+        const unsigned int bit = 1u << (l & 31);
         for (int i = 0; i < ns; ++i)
-            if (s_c[i] == c && s_v[i] != (int32_t)v) atomicOr(&bits[(long long)i * words + (l >> 5)], 1u << (l & 31));
+            if (s_c[i] == c && s_v[i] != (int32_t)v) {
+                unsigned int *w = &bits[(long long)i * words + (l >> 5)];
+                if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+                    atomicOr(w, bit);  // most members find their community's bit already set
+            }
     }
 }
 
@@ -3219,11 +3224,16 @@ static rs_status components_t(rs_graph *g, int32_t *comp, unsigned int *d_change
     DeviceGraph &D = g->d;
     const int grid = grid_for(D.n, kBlock, 8192);
     hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(kBlock), 0, g->stream, comp, (long long)D.n);
-    for (int it = 0; it < 512; ++it) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, d_changed, 1ll);
-        hipLaunchKernelGGL(k_cc_hook<OffT>, dim3(grid), dim3(kBlock), 0, g->stream, (const OffT *)D.off, D.deg, D.col,
-                           comp, (long long)D.n, d_changed);
-        hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(kBlock), 0, g->stream, comp, (long long)D.n);
+    // rounds go in groups of four between host checks; the flag tells
+    // whether the group's last round hooked anything (rounds after
+    // convergence change nothing)
+    for (int it = 0; it < 512; it += 4) {
+        for (int q = 0; q < 4; ++q) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, d_changed, 1ll);
+            hipLaunchKernelGGL(k_cc_hook<OffT>, dim3(grid), dim3(kBlock), 0, g->stream, (const OffT *)D.off, D.deg,
+                               D.col, comp, (long long)D.n, d_changed);
+            hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(kBlock), 0, g->stream, comp, (long long)D.n);
+        }
         hipError_t e = hipMemcpyAsync(h_changed, d_changed, sizeof(unsigned int), hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) return hip_fail(e, "components");

@@ -85,6 +85,10 @@ static void release(rs_graph *g) {
     if (g->rem_buf) (void)hipFree(g->rem_buf);
     if (g->rem_host) (void)hipHostFree(g->rem_host);
     if (g->rem_cnt_host) (void)hipHostFree(g->rem_cnt_host);
+    if (g->reach_hflag) (void)hipHostFree(g->reach_hflag);
+    g->reach_hflag = nullptr;
+    g->reach_comp = g->reach_src = nullptr;
+    g->reach_bits = g->reach_flag = nullptr;
     g->rem_buf = g->rem_host = nullptr;
     g->rem_cnt_host = nullptr;
     g->rem_cap = g->rem_host_cap = 0;
@@ -998,21 +1002,30 @@ rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t
     if (n_sources == 0) return RS_OK;
     const int words = std::max(1, (int)((g->d.k + 31) / 32));
     const size_t nb = 4 * (size_t)n_sources * words;
-    int32_t *d_src = nullptr, *comp = nullptr;
-    unsigned int *bits = nullptr, *d_flag = nullptr, *h_flag = nullptr;
-    hipError_t e = hipMalloc((void **)&comp, 4 * (size_t)std::max<int64_t>(n, 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&d_src, 4 * (size_t)n_sources);
-    if (e == hipSuccess) e = hipMalloc((void **)&bits, nb);
-    if (e == hipSuccess) e = hipMalloc((void **)&d_flag, sizeof(unsigned int));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&h_flag, sizeof(unsigned int), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_src, src.data(), 4 * (size_t)n_sources, hipMemcpyHostToDevice, g->stream);
-    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "reach buffers");
-    if (st == RS_OK) st = launch_reach(g, d_src, (int)n_sources, comp, bits, words, d_flag, h_flag);
+    // buffers kept by the handle from the first call (sized for the largest
+    // source count, 1,024)
+    hipError_t e = hipSuccess;
+    if (!g->reach_comp) {
+        const size_t cap_bits = 4 * (size_t)kMaxReachSources * words;
+        e = dev_alloc(g, (void **)&g->reach_comp, 4 * (size_t)std::max<int64_t>(n, 1));
+        if (e == hipSuccess) e = dev_alloc(g, (void **)&g->reach_src, 4 * (size_t)kMaxReachSources);
+        if (e == hipSuccess) e = dev_alloc(g, (void **)&g->reach_bits, cap_bits);
+        if (e == hipSuccess) e = dev_alloc(g, (void **)&g->reach_flag, sizeof(unsigned int));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&g->reach_hflag, sizeof(unsigned int), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g->reach_comp = nullptr;  // (device buffers stay tracked and are freed with the handle)
+            return hip_fail(e, "reach buffers");
+        }
+    }
+    e = hipMemcpyAsync(g->reach_src, src.data(), 4 * (size_t)n_sources, hipMemcpyHostToDevice, g->stream);
+    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "reach upload");
+    if (st == RS_OK)
+        st = launch_reach(g, g->reach_src, (int)n_sources, g->reach_comp, g->reach_bits, words, g->reach_flag,
+                          g->reach_hflag);
     std::vector<unsigned int> hb;
     if (st == RS_OK) {
         hb.resize(nb / 4);
-        e = hipMemcpyAsync(hb.data(), bits, nb, hipMemcpyDeviceToHost, g->stream);
+        e = hipMemcpyAsync(hb.data(), g->reach_bits, nb, hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = hip_fail(e, "reach copy");
     }
@@ -1022,12 +1035,6 @@ rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t
             for (int w = 0; w < words; ++w) c += __builtin_popcount(hb[(size_t)i * words + w]);
             counts[i] = c;
         }
-    if (g->stream) (void)hipStreamSynchronize(g->stream);
-    if (comp) (void)hipFree(comp);
-    if (d_src) (void)hipFree(d_src);
-    if (bits) (void)hipFree(bits);
-    if (d_flag) (void)hipFree(d_flag);
-    if (h_flag) (void)hipHostFree(h_flag);
     return st;
 }
 
