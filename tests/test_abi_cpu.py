@@ -92,3 +92,36 @@ def test_null_arguments():
     assert lib.rs_topk(None, 5, None, None, ctypes.byref(cnt)) == 1
     assert lib.rs_apply_removals(None, None, None) == 1
     lib.rs_free_graph(None)  # ignored
+
+
+def test_null_arguments_of_the_later_entry_points():
+    import paper_2508_01485_amd as rs
+    lib = rs.lib()
+    res = rs.rs_removal_result()
+    assert lib.rs_restrict_to_targets(None, 3, ctypes.byref(res)) == 1
+    cnt = np.zeros(1, np.int64)
+    assert lib.rs_reachable_communities(None, 1, None, cnt.ctypes.data) == 1
+    assert lib.rs_topk_batch(None, 4, None, None, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.rs_load_batch(0, None, None, None, 0, ctypes.byref(h)) == 1
+
+
+def test_batch_validation_before_device_work():
+    """Graph ranges that do not run 0..n, and an edge between two graphs of
+    the batch, are refused before anything touches a device."""
+    import paper_2508_01485_amd as rs
+    g = _good()
+    two_off = np.concatenate([g.off, g.off[1:] + g.off[-1]]).astype(np.int64)
+    two_col = np.concatenate([g.col, g.col + 5]).astype(np.int32)
+    two_lab = np.concatenate([g.labels, g.labels]).astype(np.int32)
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_load_batch([0, 5, 9], two_off, two_col, two_lab)
+    assert ei.value.status == 1 and "0..n" in ei.value.detail
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_load_batch([0, 6, 10], two_off, two_col, two_lab)  # vertex 5 starts graph 2 but 0-4 link to it
+    assert ei.value.status in (1, 2)
+    bad = two_col.copy()
+    bad[0] = 7  # vertex 0 of graph 0 -> vertex 7 of graph 1
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_load_batch([0, 5, 10], two_off, bad, two_lab)
+    assert ei.value.status == 2 and "joins two graphs" in ei.value.detail
