@@ -126,13 +126,47 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}))
 
 
-def cpu_baseline(g, k_top, budget_s=12.0, targets=None):
-    import oracle
+def cpu_model():
     try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = min(cores, 16)
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measured_copy_gbs(nbytes=1 << 30, reps=10):
+    """Achievable device bandwidth: a plain device-to-device copy of nbytes
+    (read + write counted), best of reps, timed with HIP events."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
+def cpu_baseline(g, k_top, budget_s=12.0, targets=None, cores=None):
+    import oracle
+    if cores is None:
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count() or 1
+        cores = min(cores, 16)
     if g.nnz > 100_000_000:
         return cpu_baseline_sampled(g, k_top, cores)
     alive, what = None, "full workload graph"
@@ -151,7 +185,8 @@ def cpu_baseline(g, k_top, budget_s=12.0, targets=None):
             break
     t = float(np.median(times))
     return {"value": m / t, "unit": "edges/s", "cores": cores, "kind": "oracle",
-            "sample": f"{what}, {len(times)} repeats of score + top-{k_top}, median {t:.3f} s"}
+            "sample": f"{what}, {len(times)} repeats of score + top-{k_top}, median {t:.3f} s "
+                      f"({cores} threads of {cpu_model()})"}
 
 
 def cpu_baseline_sampled(g, k_top, cores, s1=20_000, s2=60_000):
@@ -639,6 +674,9 @@ def main():
         c["target_communities"] = args.targets
         c["m_scored"] = int(m_scored)
         c["mu_realized"] = round(counts["m_inter"] / max(m_scored, 1), 4)
+    copy_gbs = measured_copy_gbs()
+    out["roofline"]["copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     n_req = args.rescore_requests if args.rescore_requests is not None else (200 if g.nnz < 100_000_000 else 20)
     if n_req > 0:
         log(f"timing {n_req} removal + incremental re-score requests")
@@ -647,6 +685,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, k_top, targets=args.targets)
+        if g.nnz <= 100_000_000:
+            log("timing the CPU oracle on one core")
+            out["cpu_baseline_1core"] = cpu_baseline(g, k_top, budget_s=8.0, targets=args.targets, cores=1)
     print(json.dumps(out), flush=True)
 
 
