@@ -264,7 +264,8 @@ void rs_free_graph(rs_graph *g);
  * host copy of each registered graph and loads it into device memory on its
  * first request, within an HBM budget: when a graph does not fit, idle graphs
  * are evicted least-recently-used first (an evicted graph is reloaded from
- * its host copy with its removal history applied).  n_slots worker threads
+ * the validated, renumbered host form its first load built, with its removal
+ * history applied).  n_slots worker threads
  * take requests in submission order; requests on one graph run one at a time
  * in that order, requests on different graphs overlap on the device (each
  * graph has its own stream).  A request applies a removal batch (incremental

@@ -352,6 +352,11 @@ rs_status launch_links(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);
+// Host-built graphs kept for reloads (the request server).
+struct Prebuilt;
+rs_status prebuild_graph(const rs_csr *csr, Prebuilt **out);
+rs_status load_prebuilt(Prebuilt *P, void *hip_stream, rs_graph **out);
+void free_prebuilt(Prebuilt *P);
 rs_status launch_reach(rs_graph *g, const int32_t *d_src, int ns, int32_t *comp, unsigned int *bits, int words,
                        unsigned int *d_changed, unsigned int *h_changed);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);

@@ -394,7 +394,8 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
     return RS_OK;
 }
 
-static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
+// keep: H stays intact for later uploads (its host maps are copied, not moved)
+static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool keep = false) {
     DeviceGraph &D = g->d;
     D.n = n;
     D.nnz = nnz;
@@ -545,9 +546,19 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz) {
     if (rst != RS_OK) return rst;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "pair-slot map");
-    g->h_new2old.swap(H.new2old);
-    g->h_old2new.swap(H.old2new);
-    g->h_comm2orig.swap(H.comm2orig);
+    if (keep) {
+        try {
+            g->h_new2old = H.new2old;
+            g->h_old2new = H.old2new;
+            g->h_comm2orig = H.comm2orig;
+        } catch (const std::bad_alloc &) {
+            return fail(RS_ERR_NOMEM, "host maps");
+        }
+    } else {
+        g->h_new2old.swap(H.new2old);
+        g->h_old2new.swap(H.old2new);
+        g->h_comm2orig.swap(H.comm2orig);
+    }
     g->n_alive = n;
     return RS_OK;
 }
@@ -591,6 +602,67 @@ static rs_status load_t(const rs_csr *csr, rs_graph *g) {
     }
     return upload(g, H, n, nnz);
 }
+
+// A validated, renumbered and tiled host form of a graph, kept by the
+// request server so that a graph evicted from device memory is reloaded by
+// an upload alone.
+struct Prebuilt {
+    HostGraph H;
+    int64_t n = 0, nnz = 0;
+};
+
+rs_status prebuild_graph(const rs_csr *csr, Prebuilt **out) {
+    if (!out || !csr) return fail(RS_ERR_ARG, "csr or out is NULL");
+    *out = nullptr;
+    if (csr->on_device || csr->offset_bytes != 8) return fail(RS_ERR_ARG, "prebuilt graphs take host int64 offsets");
+    if (csr->n < 0 || csr->nnz < 0 || csr->n > (int64_t)INT32_MAX - 1) return fail(RS_ERR_RANGE, "n or nnz out of range");
+    if (!csr->row_offsets || (csr->n > 0 && !csr->labels) || (csr->nnz > 0 && !csr->col))
+        return fail(RS_ERR_ARG, "null CSR array");
+    const int64_t *off = (const int64_t *)csr->row_offsets;
+    rs_status st = validate_graph<int64_t>(csr->n, csr->nnz, off, csr->col, csr->labels);
+    if (st != RS_OK) return st;
+    Prebuilt *P = new (std::nothrow) Prebuilt();
+    if (!P) return fail(RS_ERR_NOMEM, "prebuilt graph");
+    st = build_internal<int64_t>(csr->n, csr->nnz, off, csr->col, csr->labels, std::vector<int64_t>(), P->H);
+    if (st != RS_OK) {
+        delete P;
+        return st;
+    }
+    P->n = csr->n;
+    P->nnz = csr->nnz;
+    *out = P;
+    return RS_OK;
+}
+
+rs_status load_prebuilt(Prebuilt *P, void *hip_stream, rs_graph **out) {
+    if (!P || !out) return fail(RS_ERR_ARG, "prebuilt graph or out is NULL");
+    *out = nullptr;
+    rs_graph *g = new (std::nothrow) rs_graph();
+    if (!g) return fail(RS_ERR_NOMEM, "handle allocation failed");
+    g->stream = (hipStream_t)hip_stream;
+    if (const char *gv = std::getenv("RS_GRAPHS")) g->graphs_off = gv[0] == '0';
+    hipError_t e = hipGetDevice(&g->device);
+    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "hipGetDevice");
+    if (st == RS_OK && !g->stream) {
+        e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            g->own_stream = true;
+        else
+            st = hip_fail(e, "hipStreamCreate");
+    }
+    if (st == RS_OK) st = upload(g, P->H, P->n, P->nnz, true);
+    if (st != RS_OK) {
+        std::string keep = g_err;
+        release(g);
+        delete g;
+        g_err = keep;
+        return st;
+    }
+    *out = g;
+    return RS_OK;
+}
+
+void free_prebuilt(Prebuilt *P) { delete P; }
 
 template <class T>
 static hipError_t d2h(std::vector<T> &dst, const void *src, int64_t count);

@@ -8,8 +8,9 @@
 // so the requests of one graph run one at a time in order while those of
 // different graphs overlap on the device.  Graphs are loaded on demand within
 // an HBM budget; an idle graph may be evicted (least recently used first) and
-// is later reloaded from its host copy with its whole removal history applied
-// as one batch, which gives the same graph and the same bits (the result of a
+// is later reloaded from its validated, renumbered host form (built on its
+// first load) with its whole removal history applied as one batch, which
+// gives the same graph and the same bits (the result of a
 // removal is the graph minus the union of removed edges and vertices, and a
 // re-score equals a full pass on it).
 #include <algorithm>
@@ -34,6 +35,7 @@ struct ServedGraph {
     // removal history (caller ids): edges as (src, dst) pairs, vertices
     std::vector<int32_t> hist_src, hist_dst, hist_vert;
     rs_graph *h = nullptr;
+    rs::Prebuilt *pre = nullptr;  // validated, renumbered host form (built on the first load)
     int64_t bytes = 0;     // device bytes while resident
     int64_t estimate = 0;  // device bytes expected before the first load
     bool busy = false;
@@ -169,19 +171,29 @@ struct rs_server {
     }
 
     // Load a graph and bring it to its current state: a full pass, then its
-    // removal history as one batch.
+    // removal history as one batch.  The first load validates and renumbers
+    // the host copy once and keeps that form (the copy itself is dropped);
+    // a reload after an eviction only uploads it.
     rs_status load(ServedGraph &sg, Request &r) {
         (void)r;
-        rs_csr c;
-        c.n = sg.n;
-        c.nnz = sg.nnz;
-        c.offset_bytes = 8;
-        c.on_device = 0;
-        c.row_offsets = sg.off.data();
-        c.col = sg.col.data();
-        c.labels = sg.lab.data();
+        rs_status st = RS_OK;
+        if (!sg.pre) {
+            rs_csr c;
+            c.n = sg.n;
+            c.nnz = sg.nnz;
+            c.offset_bytes = 8;
+            c.on_device = 0;
+            c.row_offsets = sg.off.data();
+            c.col = sg.col.data();
+            c.labels = sg.lab.data();
+            st = rs::prebuild_graph(&c, &sg.pre);
+            if (st != RS_OK) return st;
+            std::vector<int64_t>().swap(sg.off);
+            std::vector<int32_t>().swap(sg.col);
+            std::vector<int32_t>().swap(sg.lab);
+        }
         rs_graph *h = nullptr;
-        rs_status st = rs_load_graph(&c, nullptr, 0, &h);
+        st = rs::load_prebuilt(sg.pre, nullptr, &h);
         if (st == RS_OK) st = rs_score(h);
         if (st == RS_OK && (!sg.hist_src.empty() || !sg.hist_vert.empty())) {
             rs_removals b;
@@ -348,8 +360,10 @@ void rs_server_free(rs_server *s) {
     s->cv_work.notify_all();
     for (auto &t : s->workers)
         if (t.joinable()) t.join();
-    for (auto &sg : s->graphs)
+    for (auto &sg : s->graphs) {
         if (sg.h) rs_free_graph(sg.h);
+        rs::free_prebuilt(sg.pre);
+    }
     delete s;
 }
 
