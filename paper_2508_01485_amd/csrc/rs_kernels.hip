@@ -1363,6 +1363,8 @@ struct LinkArgs {
     const int32_t *deg, *col, *lab, *cstart;
     const int64_t *goff, *oo;
     PairLink *plink;
+    const unsigned int *vmark;  // after removals: kRowChanged marks the rows that changed
+    const VCard *card;          // the last pass's own-run bounds [p, q) of the unchanged rows
 };
 
 // The link of x's row entry j (if it is a current foreign entry).
@@ -1419,33 +1421,53 @@ __global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const i
                                                        const unsigned long long *count) {
     const long long nr = (long long)*count;
     const int lane = threadIdx.x & 63;
+    // first position in a row holding an id >= key
+    auto lower = [&](const int32_t *row, int d, int key) {
+        int l = 0, h = d;
+        while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (row[mid] < key)
+                l = mid + 1;
+            else
+                h = mid;
+        }
+        return l;
+    };
     for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nr;
          i += ((long long)gridDim.x * kBlock) >> 6) {
         const int y = rows[i];
         const long long rb = (long long)L.off[y];
         const int cy = L.lab[y];
-        for (int j = lane; j < L.deg[y]; j += 64) {
-            link_entry(L, y, j);
+        const int dy = L.deg[y];
+        // y's own run [py, qy) in its compacted row (the same for all its entries)
+        const int py = lower(L.col + rb, dy, L.cstart[cy]);
+        const int qy = lower(L.col + rb, dy, L.cstart[cy + 1]);
+        for (int j = lane; j < dy; j += 64) {
             const int x = L.col[rb + j];
             const int cx = L.lab[x];
             if (cx == cy) continue;
-            // y's index among x's foreign entries
-            const int32_t *row = L.col + L.off[x];
+            // the entry (x, y): its position in x's row, found once for both links
+            const long long xb = (long long)L.off[x];
             const int dx = L.deg[x];
-            auto lower = [&](int key) {
-                int l = 0, h = dx;
-                while (l < h) {
-                    const int mid = (l + h) >> 1;
-                    if (row[mid] < key)
-                        l = mid + 1;
-                    else
-                        h = mid;
-                }
-                return l;
-            };
-            int kx = lower(y);
-            if (y >= L.cstart[cx + 1]) kx -= lower(L.cstart[cx + 1]) - lower(L.cstart[cx]);
-            L.plink[L.goff[x] + kx].e = rb + j;
+            const int ex = lower(L.col + xb, dx, y);
+            // y's link for its entry j: the reverse entry and x's out-list
+            PairLink pl;
+            pl.e = xb + ex;
+            pl.oo = (int)L.oo[x];
+            pl.on = (int)(L.oo[x + 1] - L.oo[x]);
+            L.plink[L.goff[y] + (j < py ? j : j - (qy - py))] = pl;
+            // x's link for its entry ex points back at (y, x), which moved with
+            // y's row; x's own run is its card's when x's row did not change
+            int px, qx;
+            if (L.vmark[x] & kRowChanged) {
+                px = lower(L.col + xb, dx, L.cstart[cx]);
+                qx = lower(L.col + xb, dx, L.cstart[cx + 1]);
+            } else {
+                const VMeta m = L.card[x].m;
+                px = m.p;
+                qx = m.q;
+            }
+            L.plink[L.goff[x] + (ex < px ? ex : ex - (qx - px))].e = rb + j;
         }
     }
 }
@@ -1461,6 +1483,8 @@ static LinkArgs<OffT> link_args(rs_graph *g) {
     L.cstart = D.cstart;
     L.goff = D.goff;
     L.oo = D.oo;
+    L.vmark = D.vmark;
+    L.card = D.card;
     L.plink = D.plink;
     return L;
 }
