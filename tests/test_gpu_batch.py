@@ -161,6 +161,29 @@ def test_batch_rescore_is_stable():
         assert x.tobytes() == y.tobytes()
 
 
+def test_reachable_communities_on_a_batch():
+    """Components never span graphs, so each source's count on the batch
+    equals the oracle's search inside its own graph."""
+    import oracle
+    import paper_2508_01485_amd as rs
+    gs = [random_small(60, 0.03, 5, 91), sbm([40, 30, 30], 0.05, 0.01, seed=92), random_small(1, 0.0, 1, 93),
+          lfr(2000, 5.0, 60, 0.3, seed=94, cmin=10, cmax=200)]
+    vo, off, col, lab = _union(gs)
+    rng = np.random.default_rng(95)
+    src = rng.choice(int(vo[-1]), 40, replace=False)
+    h = rs.rs_load_batch(vo, off, col, lab)
+    try:
+        got = rs.rs_reachable_communities(h, src)
+        with pytest.raises(rs.RSError, match="not applied to a batch"):
+            rs.rs_restrict_to_targets(h, 2)
+    finally:
+        h.free()
+    for s_, c in zip(src, got):
+        gi = int(np.searchsorted(vo, s_, side="right") - 1)
+        exp = oracle.reachable_communities(gs[gi], [int(s_ - vo[gi])])[0]
+        assert c == exp, (s_, gi, c, exp)
+
+
 def test_batch_errors():
     import paper_2508_01485_amd as rs
     gs = _graphs()[:3]
