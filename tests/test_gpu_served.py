@@ -137,3 +137,30 @@ def test_served_submit_while_waiting():
         srv.free()
     _compare(alone, out)
     _say("120 requests submitted while waiting: identical to alone")
+
+
+def test_served_request_on_an_invalid_graph_fails_cleanly():
+    """A graph is validated on its first load: a request on an asymmetric
+    graph fails with RS_ERR_GRAPH through wait, and a valid graph served
+    beside it is unaffected."""
+    import paper_2508_01485_amd as rs
+    good = _graphs()[0]
+    bad_col = good.col.copy()
+    bad_col[0] = bad_col[0] + 1 if bad_col[0] + 1 < good.n else bad_col[0] - 1  # breaks symmetry (or sorting)
+    srv = rs.RSServer(slots=2, hbm_budget=0)
+    try:
+        gb = srv.add_graph(good.off, bad_col, good.labels)
+        gg = srv.add_graph(good.off, good.col, good.labels)
+        rb = srv.submit(gb, 10, vertices=[0])
+        rg = srv.submit(gg, 10, vertices=[0])
+        with pytest.raises(rs.RSError) as ei:
+            srv.wait(rb)
+        assert ei.value.status == 2, ei.value
+        ids, sc, info = srv.wait(rg)
+        assert ids.size == 10
+        with pytest.raises(rs.RSError):  # and again on a later request
+            srv.wait(srv.submit(gb, 5))
+    finally:
+        srv.free()
+    ref = _alone(rs, [good], [(0, None, np.array([0]))], 10)[0]
+    assert np.array_equal(ids, ref[0]) and sc.tobytes() == ref[1].tobytes()
