@@ -4,7 +4,7 @@ One step = one full scoring pass (rs_score: border detection, interaction
 matrix, weights, w_max, type-II aggregate, Eq. RSI scores) plus rs_topk(K) on a
 graph already resident in HBM.  Prints ONE JSON line (rank 0, N=1).
 
-  python bench.py [--steps K] [--warmup W] [--workload lfr_1m|sbm_2k|lfr_20m|batch|served]
+  python bench.py [--steps K] [--warmup W] [--workload lfr_20m|lfr_1m|sbm_2k|batch|served|robustness]
                   [--no-cpu-baseline] [--copy-calibration]
 
 --workload batch scores many small graphs as one batch (one pass over their
@@ -220,12 +220,15 @@ def rescore_latency(rs, h, g, n_req, seed=11):
     each either 1-1,000 random existing edges or 1-50 vertices drawn from the
     current top-1,000 (half each), applied with rs_apply_removals (validation,
     upload, incremental re-score) and followed by a top-100 query; the wall
-    time of both is one request's latency.  Runs after the timed steps (it
-    mutates the graph)."""
+    time of both is one request's latency.  Beside it, the plain baseline: a
+    full recompute (rs_score + rs_topk(100)) of the same mutated graph right
+    after each request, whose top-100 must be bit-identical to the
+    incremental one.  Runs after the timed steps (it mutates the graph)."""
     rng = np.random.default_rng(seed)
     u, v = g.edges()
     alive = np.ones(u.size, bool)
-    lat, aff = [], []
+    lat, full, aff = [], [], []
+    same = True
     for _ in range(n_req):
         if rng.random() < 0.5:
             live = np.flatnonzero(alive)
@@ -239,13 +242,22 @@ def rescore_latency(rs, h, g, n_req, seed=11):
             kw = {"vertices": rng.choice(ids, k, replace=False)}
         t0 = time.perf_counter()
         res = rs.rs_apply_removals(h, **kw)
-        rs.rs_topk(h, 100)
+        i1, s1 = rs.rs_topk(h, 100)
         lat.append(time.perf_counter() - t0)
         aff.append(res["affected"])
-    return {"p50": 1000 * float(np.percentile(lat, 50)), "p99": 1000 * float(np.percentile(lat, 99)),
-            "mean": 1000 * float(np.mean(lat)), "requests": n_req, "mean_affected": float(np.mean(aff)),
+        t0 = time.perf_counter()
+        rs.rs_score(h)
+        i2, s2 = rs.rs_topk(h, 100)
+        full.append(time.perf_counter() - t0)
+        same &= np.array_equal(i1, i2) and s1.tobytes() == s2.tobytes()
+    pct = lambda x, q: 1000 * float(np.percentile(x, q))  # noqa: E731
+    return {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": 1000 * float(np.mean(lat)), "requests": n_req,
+            "mean_affected": float(np.mean(aff)),
+            "full_recompute_ms": {"p50": pct(full, 50), "p99": pct(full, 99)},
+            "speedup_p50": float(np.percentile(full, 50) / np.percentile(lat, 50)),
+            "top100_identical": bool(same),
             "request": "half: 1-1,000 random existing edges; half: 1-50 vertices of the current top-1,000; "
-                       "then a top-100 query"}
+                       "then a top-100 query; baseline: rs_score + rs_topk(100) of the same mutated graph"}
 
 
 def bench_served(args):
@@ -538,7 +550,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lfr_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lfr_20m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--targets", type=int, default=0,

@@ -740,6 +740,7 @@ struct ScoreArgs {
     int n_chunks, n_chunks_lds;
     HubPart *hub_part;
     const int32_t *outl;
+    const int64_t *oo;      // out-list offsets
     const int32_t *reckey;
     const RecDat *recdat;
     const VCard *card;
@@ -790,78 +791,53 @@ __device__ __forceinline__ int lds_lower(const int *a, int lo, int hi, int x) {
     }
     return lo;
 }
-// The scored vertex u as seen by its pairs (u, w): its foreign list N'(u),
-// ascending.  Tile form: u's entries [pb, pe) of the unit's LDS list.
-struct TileU {
-    const int *w;
-    int pb, pe;
-    __device__ __forceinline__ int nf() const { return pe - pb; }
-    __device__ __forceinline__ int list_at(int j) const { return w[pb + j]; }
-    __device__ __forceinline__ bool in_list(int x) const {
-        const int i = lds_lower(w, pb, pe, x);
-        return i < pe && w[i] == x;
+__device__ __forceinline__ bool lds_has(const int *a, int lo, int hi, int x) {
+    const int i = lds_lower(a, lo, hi, x);
+    return i < hi && a[i] == x;
+}
+
+// Out-lists keep removed entries complemented (~id) in place, so a list is
+// ascending in the decoded id.
+__device__ __forceinline__ int out_id(int x) { return x < 0 ? ~x : x; }
+
+// Whether the n out-list entries a[0..n) in LDS hold the live id x.
+__device__ __forceinline__ bool lds_has_out(const int *a, int n, int x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (out_id(a[mid]) < x)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-};
+    return lo < n && a[lo] == x;
+}
 
-// Hub form: u's foreign list in HBM (the row minus [p, p + h)).  Every
-// stride-th entry is staged in LDS (samp, ns entries), so a membership probe
-// is a binary search in LDS followed by a 16-ary search of one stride-long
-// block in HBM.
-constexpr int kHubSamp = 2048;  // LDS samples of a big hub's foreign list
-struct HubU {
-    const int32_t *row;
-    int p, h, n_f;
-    const int *samp;
-    int ns, stride;
-    __device__ __forceinline__ int nf() const { return n_f; }
-    __device__ __forceinline__ int list_at(int j) const { return row[j < p ? j : j + h]; }
-    __device__ __forceinline__ bool in_list(int x) const {
-        // last sample <= x
-        int lo = 0, hi = ns;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (samp[mid] <= x)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        if (lo == 0) return false;  // below the first entry
-        int b = (lo - 1) * stride, e = min(n_f, b + stride);
-        while (e - b > 16) {
-            const int st = (e - b + 15) >> 4;
-            int cnt = 0;
+// Whether the out-list entries outl[o0, o1) in HBM hold the live id t: a
+// 16-ary search on the decoded ids (each step 15 independent loads); a list
+// of up to 16 entries is one step.
+__device__ __forceinline__ bool out_has(const int32_t *outl, long long o0, long long o1, int t) {
+    long long lo = o0, hi = o1;
+    while (hi - lo > 16) {
+        const long long st = (hi - lo + 15) >> 4;
+        int cnt = 0;
 #pragma unroll
-            for (int j = 1; j < 16; ++j) {
-                const int y = b + j * st;
-                cnt += (y < e && list_at(y) <= x) ? 1 : 0;
-            }
-            b += cnt * st;
-            e = min(e, b + st);
+        for (int j = 1; j < 16; ++j) {
+            const long long x = lo + j * st;
+            cnt += (x < hi && out_id(outl[x]) <= t) ? 1 : 0;
         }
-        bool f = false;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int y = b + j;
-            if (y < e && list_at(y) == x) f = true;
-        }
-        return f;
+        lo += cnt * st;
+        hi = min(hi, lo + st);
     }
-};
+    bool f = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const long long x = lo + j;
+        if (x < hi && outl[x] == t) f = true;
+    }
+    return f;
+}
 
-struct PairRes {
-    double val;
-    int t2, t1;
-};
-
-
-// The terms of Eq. RSI that pass through the foreign neighbour w of u
-// (Lemmas 1-2, unnormalised weights):
-//   type-II: w_w(C(u))^(2/3) * sum of a_v over the other neighbours v of w in
-//            C(u) (a_v = cbrt(w_v(C(v)))), count f_w(C(u)) - 1;
-//   type-I : the triangles {u, w, y} of G' with y in out(w) -- each triangle
-//            at u is found by exactly one of its two pairs -- each adding
-//            both ordered triads (w, y) and (y, w):
-//              cbrt(w_y(C(u)) w_w(C(y)) w_w(C(u))) + cbrt(w_w(C(u)) w_y(C(w)) w_y(C(u))).
 // Slot of community c among a vertex's record keys: the card's first four
 // keys, else a 16-ary search of the key array (-1 if absent).
 __device__ __forceinline__ int card_find(const VCard &c, const int32_t *reckey, int x) {
@@ -875,67 +851,28 @@ __device__ __forceinline__ int card_find(const VCard &c, const int32_t *reckey, 
     return kfind(reckey + c.off, c.m.ell, x);
 }
 
-// The terms of one pair (u, w), w a foreign neighbour of u, from the pair's
-// facts (w_w(C(u)) = W and the run of C(u) in w's row, at w's entry for u)
-// and its link (that entry, w's out-list):
-//   type II (Lemma 2): W^(2/3) times the sum of a_v over the other members of
-//     that run (v in C(u), v adjacent to w; counted whether or not v ~ u);
-//   type I: every v in w's out-list that is also a foreign neighbour of u
-//     closes the G' triangle {u, w, v}; its two ordered triads (w, v) and
-//     (v, w) add cbrt(w_v(C(u)) w_w(C(v)) W) + cbrt(W w_v(C(w)) w_v(C(u))).
-template <class UV, typename OffT>
-__device__ PairRes score_pair(const ScoreArgs<OffT> &A, const UV &U, int u, int cu, int w, const PairRec &pr,
-                              const PairLink &pl) {
-    PairRes out = {0.0, 0, 0};
-    const double W = pr.w;
-    out.t2 = pr.f - 1;
-    // the out-list's first entries load together with the run below
-    const int o0 = pl.oo, o1 = pl.oo + pl.on;
-    int y[4];
+// The type-II terms of the pair (u, w), w a foreign neighbour of u (Lemma 2,
+// unnormalised weights), from the pair's facts at w's entry for u (W =
+// w_w(C(u)) and the run of C(u) in w's row): W^(2/3) times the sum of a_v
+// over the other members v of that run (v in C(u), v adjacent to w; counted
+// whether or not v ~ u), and the count f_w(C(u)) - 1.
+template <typename OffT>
+__device__ __forceinline__ double type2_pair(const ScoreArgs<OffT> &A, int u, const PairRec &pr, long long e) {
+    if (pr.f <= 1) return 0.0;
+    double S = 0.0;
+    const int32_t *run = A.col + (e - pr.back);
+    for (int i = 0; i < pr.f; i += 8) {
+        int x[8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) y[t] = o0 + t < o1 ? A.outl[o0 + t] : -1;
-    if (pr.f > 1) {
-        double S = 0.0;
-        const int32_t *run = A.col + (pl.e - pr.back);
-        for (int i = 0; i < pr.f; i += 8) {
-            int x[8];
+        for (int t = 0; t < 8; ++t) x[t] = i + t < pr.f ? run[i + t] : u;
+        double av[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) x[t] = i + t < pr.f ? run[i + t] : u;
-            double av[8];
+        for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.card[x[t]].a : 0.0;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.card[x[t]].a : 0.0;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) S += av[t];
-        }
-        const double c1 = cbrt(W);
-        out.val = c1 * c1 * S;
+        for (int t = 0; t < 8; ++t) S += av[t];
     }
-    for (int j0 = o0; j0 < o1; j0 += 4) {
-        if (j0 > o0) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) y[t] = j0 + t < o1 ? A.outl[j0 + t] : -1;
-        }
-        unsigned int hm = 0u;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            if (y[t] >= 0 && U.in_list(y[t])) hm |= 1u << t;
-        while (hm) {
-            const int t = __builtin_ctz(hm);
-            hm &= hm - 1u;
-            const int v = A.outl[j0 + t];
-            const VCard cv = A.card[v];
-            const VCard cw = A.card[w];
-            const int s1 = card_find(cv, A.reckey, cu);
-            const int s2 = card_find(cv, A.reckey, cw.lab);
-            const int s3 = card_find(cw, A.reckey, cv.lab);
-            const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
-            const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
-            const double w_wv = s3 >= 0 ? A.recdat[cw.off + s3].w : 0.0;
-            out.val += cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
-            out.t1 += 2;
-        }
-    }
-    return out;
+    const double c1 = cbrt(pr.w);
+    return c1 * c1 * S;
 }
 
 struct ScoreAcc {
@@ -1003,6 +940,128 @@ __device__ void hub_chunk_store(const ScoreArgs<OffT> &A, const double *red, con
     sa.tII += hp.tII;
 }
 
+// Per-pair facts of a unit's type-I scan, and the hits found so far.
+constexpr int kHitCap = 768;  // hits held before their terms are evaluated (>= 2 rounds)
+struct TypeIShared {
+    int ibeg[kBlock];      // first work item of each pair (exclusive prefix of the out-list lengths)
+    int ioo[kBlock];       // out-list start of each pair's w
+    int pv[kBlock];        // u of each pair
+    int pcu[kBlock];       // C(u)
+    int pw[kBlock];        // w
+    double pW[kBlock];     // w_w(C(u))
+    int wc[kBlock / 64];
+};
+struct HitBuf {
+    int hitp[kHitCap];     // pair of each hit (ascending)
+    int hity[kHitCap];     // third vertex of each hit
+    double hitv[kHitCap];  // the hit's two ordered triads
+};
+
+// The terms of the nb held hits, then each pair's own lane adds its hits
+// (a contiguous range of the list) in list order.
+template <typename OffT>
+__device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const TypeIShared &T, HitBuf &H, int nb,
+                                            bool mine, double &val, int &t1) {
+    const int tid = threadIdx.x;
+    for (int h = tid; h < nb; h += kBlock) {
+        const int q = H.hitp[h], v = H.hity[h];
+        const int w = T.pw[q], cu = T.pcu[q];
+        const double W = T.pW[q];
+        const VCard cv = A.card[v];
+        const VCard cw = A.card[w];
+        const int s1 = card_find(cv, A.reckey, cu);
+        const int s2 = card_find(cv, A.reckey, cw.lab);
+        const int s3 = card_find(cw, A.reckey, cv.lab);
+        const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
+        const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
+        const double w_wv = s3 >= 0 ? A.recdat[cw.off + s3].w : 0.0;
+        H.hitv[h] = cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
+    }
+    __syncthreads();
+    if (mine) {
+        int a = 0, b = nb;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (H.hitp[mid] < tid)
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        for (int h = a; h < nb && H.hitp[h] == tid; ++h) {
+            val += H.hitv[h];
+            t1 += 2;
+        }
+    }
+    __syncthreads();
+}
+
+// Type-I triads of a unit's pairs (Eq. RSI with v adjacent to u and C(v) !=
+// C(u): the triangles of G').  The pair (u, w) finds the triangles {u, w, v}
+// with v in out(w) (each triangle at u is found by exactly one of its two
+// pairs).  Every position of every pair's out-list is one work item; the
+// unit's items are taken kBlock at a time, so consecutive lanes read
+// consecutive entries of one list and no lane scans a long list alone.  A
+// live entry v with edge(p, v) closes a triangle.  Hits are appended in item
+// order, so each pair's hits stay contiguous and in out-list order; when the
+// list is nearly full (and at the end) every held hit's two ordered triads
+// (w, v) and (v, w),
+//   cbrt(w_v(C(u)) w_w(C(v)) W) + cbrt(W w_v(C(w)) w_v(C(u))),  W = w_w(C(u)),
+// are evaluated, one lane per hit, and the pair's own lane adds them to its
+// sum in list order (so the sum's order is fixed).  Every thread of the block
+// takes part; `items` is the lane's out-list length (0 without a pair), and
+// T.ioo, T.pv, T.pcu, T.pw, T.pW hold the lane's pair.  H may overlay LDS
+// that the caller is done with (the scan's first barrier comes before H is
+// written).
+template <class Edge, typename OffT>
+__device__ void typeI_scan(const ScoreArgs<OffT> &A, TypeIShared &T, HitBuf &H, int items, const Edge &edge,
+                           double &val, int &t1) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int total = 0;
+    const int first = block_excl_scan(items, T.wc, total);
+    T.ibeg[tid] = first;
+    __syncthreads();
+    int nb = 0;  // held hits (the same in every thread)
+    for (int base = 0; base < total; base += kBlock) {
+        const int i = base + tid;
+        bool hit = false;
+        int p = 0, y = -1;
+        if (i < total) {
+            int lo = 0, hi = kBlock;  // the last pair whose first item is <= i
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (T.ibeg[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            p = lo;
+            y = A.outl[T.ioo[p] + (i - T.ibeg[p])];
+            hit = y >= 0 && y != T.pv[p] && edge(p, y);
+        }
+        const unsigned long long m = __ballot(hit);
+        if (lane == 0) T.wc[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, nh = 0;
+#pragma unroll
+        for (int x = 0; x < kBlock / 64; ++x) {
+            const int c = T.wc[x];
+            if (x < wave) before += c;
+            nh += c;
+        }
+        if (hit) {
+            const int s = nb + before + __popcll(m & ((1ull << lane) - 1ull));
+            H.hitp[s] = p;
+            H.hity[s] = y;
+        }
+        nb += nh;
+        __syncthreads();
+        if (nb > kHitCap - kBlock || (base + kBlock >= total && nb > 0)) {
+            typeI_flush(A, T, H, nb, items > 0, val, t1);
+            nb = 0;
+        }
+    }
+}
+
 // ------------------------------------------------------------ score units
 // A score unit is either a tile -- <= kScoreTileV consecutive vertices with
 // at most kScoreTileP foreign entries -- or one chunk of kScoreTileP pairs of
@@ -1017,14 +1076,22 @@ static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: 
 struct ScoreUnitShared {
     int w[kHubList];                 // foreign neighbours
     int pb[kScoreTileV + 1];         // tile: first pair of each vertex
-    long long ou[kScoreTileV], go[kScoreTileV];  // tile: row start and first pair slot of each vertex
-    int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV];
     unsigned short pu[kScoreTileP];  // tile: vertex of each pair
-    double val[kBlock];              // the lane's pair terms
-    int t2[kBlock], t1[kBlock];
     int ws[kBlock / 64];
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
+    TypeIShared ti;
+    union {  // three phases that never overlap
+        struct {  // prologue: the tile's vertices
+            long long ou[kScoreTileV], go[kScoreTileV];  // row start and first pair slot
+            int cu[kScoreTileV], p[kScoreTileV], h[kScoreTileV];
+        } v;
+        HitBuf hits;  // type-I scan
+        struct {      // epilogue: the lanes' pair terms
+            double val[kBlock];
+            int t2[kBlock], t1[kBlock];
+        } e;
+    } u;
 };
 
 // A hub chunk's partial: block tree sum of the lanes' terms (thread 0 gets it).
@@ -1044,6 +1111,21 @@ __device__ __forceinline__ void chunk_tree(double x, long long y1, long long y2,
     }
     __syncthreads();
 }
+
+// Edge tests of a unit's type-I scan: u's foreign list is in LDS (a tile
+// vertex's slice, or a hub's whole list).
+struct TileEdge {
+    const ScoreUnitShared *S;
+    __device__ __forceinline__ bool operator()(int p, int y) const {
+        const int i = S->pu[p];
+        return lds_has(S->w, S->pb[i], S->pb[i + 1], y);
+    }
+};
+struct HubListEdge {
+    const int *w;
+    int n;
+    __device__ __forceinline__ bool operator()(int, int y) const { return lds_has(w, 0, n, y); }
+};
 
 template <typename OffT>
 __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hub_unit, int idx, double wmax,
@@ -1078,11 +1160,11 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             const VMeta m = cv.m;
             deg = m.deg;
             dp = m.deg - (m.q - m.p);
-            S.ou[tid] = cv.off;
-            S.go[tid] = cv.goff;
-            S.cu[tid] = cv.lab;
-            S.p[tid] = m.p;
-            S.h[tid] = m.q - m.p;
+            S.u.v.ou[tid] = cv.off;
+            S.u.v.go[tid] = cv.goff;
+            S.u.v.cu[tid] = cv.lab;
+            S.u.v.p[tid] = m.p;
+            S.u.v.h[tid] = m.q - m.p;
         }
         pb = block_excl_scan(dp, S.ws, total);
         if (tid < nv) {
@@ -1094,66 +1176,97 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         if (tid < total) {
             const int i = S.pu[tid];
             const int j = tid - S.pb[i];
-            S.w[tid] = A.col[S.ou[i] + (j < S.p[i] ? j : j + S.h[i])];
+            S.w[tid] = A.col[S.u.v.ou[i] + (j < S.u.v.p[i] ? j : j + S.u.v.h[i])];
         }
         __syncthreads();
     }
-    // ---- the lane's pair
+    // ---- the lane's pair: type II
     const bool has = tid < total;
-    PairRes r = {0.0, 0, 0};
+    double val = 0.0;
+    int t2 = 0, t1 = 0, items = 0;
     if (has) {
-        TileU U;
-        U.w = S.w;
-        int k, u, cu;
+        int u, cu, w;
         long long slot;
         if (hub_unit) {
-            k = chunk * kBlock + tid;
-            U.pb = 0;
-            U.pe = hdp;
+            const int k = chunk * kBlock + tid;
             u = hu;
             cu = hcu;
+            w = S.w[k];
             slot = hgo + k;
         } else {
-            k = tid;
             const int i = S.pu[tid];
-            U.pb = S.pb[i];
-            U.pe = S.pb[i + 1];
             u = v0 + i;
-            cu = S.cu[i];
-            slot = S.go[i] + (tid - U.pb);
+            cu = S.u.v.cu[i];
+            w = S.w[tid];
+            slot = S.u.v.go[i] + (tid - S.pb[i]);
         }
-        const int w = S.w[k];
         const PairLink pl = A.plink[slot];
         const PairRec pr = A.prec[pl.e];
-        r = score_pair(A, U, u, cu, w, pr, pl);
+        val = type2_pair(A, u, pr, pl.e);
+        t2 = pr.f - 1;
+        items = pl.on;
+        S.ti.ioo[tid] = pl.oo;
+        S.ti.pv[tid] = u;
+        S.ti.pcu[tid] = cu;
+        S.ti.pw[tid] = w;
+        S.ti.pW[tid] = pr.w;
+    }
+    // ---- type I
+    if (hub_unit) {
+        HubListEdge E;
+        E.w = S.w;
+        E.n = hdp;
+        typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
+    } else {
+        TileEdge E;
+        E.S = &S;
+        typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
     }
     // ---- epilogue: sums in a fixed order
     if (!hub_unit) {
-        S.val[tid] = r.val;
-        S.t2[tid] = r.t2;
-        S.t1[tid] = r.t1;
+        S.u.e.val[tid] = val;
+        S.u.e.t2[tid] = t2;
+        S.u.e.t1[tid] = t1;
         __syncthreads();
         if (tid < nv && dp > 0) {
             double acc = 0.0;
             long long c1 = 0, c2 = 0;
             for (int q = pb; q < pb + dp; ++q) {
-                acc += S.val[q];
-                c2 += S.t2[q];
-                c1 += S.t1[q];
+                acc += S.u.e.val[q];
+                c2 += S.u.e.t2[q];
+                c1 += S.u.e.t1[q];
             }
             score_store(A, v0 + tid, deg, acc, c1, c2, wmax, sa);
         }
         return;
     }
-    chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
+    chunk_tree(val, t1, t2, S.red, S.ired);
     if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
 
-// A hub whose foreign list exceeds kHubList: u's list is read from HBM.
+// A hub whose foreign list exceeds kHubList: u's list stays in HBM.  The
+// type-I edge test of (u, y) uses the out-lists instead: the edge is in
+// exactly one of out(u) (staged in LDS when it fits) and out(y).
+constexpr int kHubOutStage = 1024;
 struct ScoreHubBigShared {
     double red[kBlock / 64];
     long long ired[2][kBlock / 64];
-    int samp[kHubSamp];
+    int outu[kHubOutStage];
+    TypeIShared ti;
+    HitBuf hits;
+};
+
+struct HubOutEdge {
+    const int *stage;      // out(u) in LDS (n_stage entries), or null
+    int n_stage;
+    const int32_t *outl;
+    const int64_t *oo;
+    long long uo0, uo1;    // out(u) in HBM
+    int u;
+    __device__ __forceinline__ bool operator()(int, int y) const {
+        if (stage ? lds_has_out(stage, n_stage, y) : out_has(outl, uo0, uo1, y)) return true;
+        return out_has(outl, oo[y], oo[y + 1], u);
+    }
 };
 
 template <typename OffT>
@@ -1167,25 +1280,37 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     const int h = m.q - m.p;
     const int dp = m.deg - h;
     const int cu = cu_.lab;
-    HubU U;
-    U.row = A.col + ou;
-    U.p = m.p;
-    U.h = h;
-    U.n_f = dp;
-    U.stride = max(64, (dp + kHubSamp - 1) / kHubSamp);
-    U.ns = (dp + U.stride - 1) / U.stride;
-    U.samp = S.samp;
-    for (int j = tid; j < U.ns; j += kBlock) S.samp[j] = U.list_at(j * U.stride);
-    __syncthreads();
+    const long long uo0 = A.oo[u], uo1 = A.oo[u + 1];
+    const int n_out = (int)(uo1 - uo0);
+    const bool staged = n_out <= kHubOutStage;
+    if (staged)
+        for (int j = tid; j < n_out; j += kBlock) S.outu[j] = A.outl[uo0 + j];
     const int k = chunk * kScoreTileP + tid;
-    PairRes r = {0.0, 0, 0};
+    double val = 0.0;
+    int t2 = 0, t1 = 0, items = 0;
     if (k < dp) {
-        const int w = U.list_at(k);
+        const int w = A.col[ou + (k < m.p ? k : k + h)];
         const PairLink pl = A.plink[cu_.goff + k];
         const PairRec pr = A.prec[pl.e];
-        r = score_pair(A, U, u, cu, w, pr, pl);
+        val = type2_pair(A, u, pr, pl.e);
+        t2 = pr.f - 1;
+        items = pl.on;
+        S.ti.ioo[tid] = pl.oo;
+        S.ti.pv[tid] = u;
+        S.ti.pcu[tid] = cu;
+        S.ti.pw[tid] = w;
+        S.ti.pW[tid] = pr.w;
     }
-    chunk_tree(r.val, r.t1, r.t2, S.red, S.ired);
+    HubOutEdge E;
+    E.stage = staged ? S.outu : nullptr;
+    E.n_stage = n_out;
+    E.outl = A.outl;
+    E.oo = A.oo;
+    E.uo0 = uo0;
+    E.uo1 = uo1;
+    E.u = u;
+    typeI_scan(A, S.ti, S.hits, items, E, val, t1);  // its first barrier also covers the staging
+    chunk_tree(val, t1, t2, S.red, S.ired);
     if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
 
@@ -1658,6 +1783,7 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     S.n_chunks_lds = g->n_schunks_lds;
     S.hub_part = D.hub_part;
     S.outl = D.outl;
+    S.oo = D.oo;
     S.reckey = D.reckey;
     S.recdat = D.recdat;
     S.card = D.card;

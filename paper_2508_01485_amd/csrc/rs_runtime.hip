@@ -776,6 +776,11 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
         return csr->offset_bytes == 8 ? ((const int64_t *)csr->row_offsets)[v]
                                       : (int64_t)((const int32_t *)csr->row_offsets)[v];
     };
+    // the row offsets first: the scan below walks every row
+    if (rowoff(0) != 0) return fail(RS_ERR_GRAPH, "row_offsets[0] != 0");
+    for (int64_t v = 0; v < n; ++v)
+        if (rowoff(v + 1) < rowoff(v)) return fail(RS_ERR_GRAPH, "row_offsets decrease at vertex " + std::to_string(v));
+    if (rowoff(n) != csr->nnz) return fail(RS_ERR_GRAPH, "row_offsets[n] != nnz");
     // every edge stays inside its graph; labels are ranked per graph and
     // offset so that no community spans two graphs (the ranks keep each
     // graph's label order, hence its internal numbering)
@@ -973,6 +978,7 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
         }
         if (g->rem_buf) (void)hipFree(g->rem_buf);
         if (g->rem_host) (void)hipHostFree(g->rem_host);
+        g->dev_bytes += 4 * (cap - g->rem_cap);  // the device staging counts toward the graph's footprint
         g->rem_buf = nb;
         g->rem_host = nh;
         g->rem_cap = g->rem_host_cap = cap;

@@ -36,8 +36,9 @@ struct ServedGraph {
     std::vector<int32_t> hist_src, hist_dst, hist_vert;
     rs_graph *h = nullptr;
     rs::Prebuilt *pre = nullptr;  // validated, renumbered host form (built on the first load)
-    int64_t bytes = 0;     // device bytes while resident
+    int64_t bytes = 0;     // device bytes counted in the budget while resident
     int64_t estimate = 0;  // device bytes expected before the first load
+    int64_t known = 0;     // device bytes measured at the last residency (0: never loaded)
     bool busy = false;
     int64_t last_use = 0;
 };
@@ -103,7 +104,7 @@ struct rs_server {
             int32_t victim = -1;
             for (int32_t i = 0; i < (int32_t)graphs.size(); ++i) {
                 const ServedGraph &sg = graphs[i];
-                if (i != keep && sg.h && !sg.busy && (victim < 0 || sg.last_use < graphs[victim].last_use))
+                if (i != keep && !sg.busy && sg.h && (victim < 0 || sg.last_use < graphs[victim].last_use))
                     victim = i;
             }
             if (victim < 0) return false;
@@ -111,6 +112,7 @@ struct rs_server {
             rs_free_graph(sg.h);
             sg.h = nullptr;
             used -= sg.bytes;
+            sg.known = sg.bytes;
             sg.bytes = 0;
             ++evictions;
         }
@@ -130,7 +132,7 @@ struct rs_server {
             // residency: reserve the graph's bytes, evicting idle graphs
             bool fresh = false;
             if (!sg.h) {
-                const int64_t need = sg.bytes > 0 ? sg.bytes : sg.estimate;
+                const int64_t need = sg.known > 0 ? sg.known : sg.estimate;
                 if (budget > 0 && need > budget) {
                     r.status = RS_ERR_NOMEM;
                     r.error = "graph larger than the whole HBM budget";
@@ -141,22 +143,46 @@ struct rs_server {
                     fresh = true;
                 }
             }
+            // sg is busy from here on: no other worker frees or replaces
+            // its handle, and the handle is only published under mu
+            rs_graph *h = sg.h;
             lk.unlock();
             rs_status st = r.status;
-            if (st == RS_OK && fresh) st = load(sg, r);
-            if (st == RS_OK) st = serve(sg, r);
+            if (st == RS_OK && fresh) {
+                st = load(sg, &h);
+                if (st == RS_OK) {
+                    lk.lock();
+                    sg.h = h;
+                    // the reservation becomes the measured size; idle graphs
+                    // make way if the estimate was short, else the request fails
+                    used += h->dev_bytes - sg.bytes;
+                    sg.bytes = h->dev_bytes;
+                    sg.known = sg.bytes;
+                    if (!make_room(0, r.gid)) {
+                        rs_free_graph(h);
+                        sg.h = h = nullptr;
+                        used -= sg.bytes;
+                        sg.bytes = 0;
+                        st = RS_ERR_NOMEM;
+                        r.error = "the graph's device footprint exceeds the HBM budget left by busy graphs";
+                    }
+                    lk.unlock();
+                }
+            }
+            if (st == RS_OK) st = serve(sg, h, r);
             if (st != RS_OK && r.error.empty()) r.error = rs_last_error();
             lk.lock();
             if (fresh) {
-                if (sg.h) {  // the reservation becomes the actual size
-                    used += sg.h->dev_bytes - sg.bytes;
-                    sg.bytes = sg.h->dev_bytes;
-                } else {
+                if (!sg.h) {  // the load failed: give the reservation back
                     used -= sg.bytes;
                     sg.bytes = 0;
                 }
                 r.info.loaded = sg.h ? 1 : 0;
                 if (sg.h) ++loads;
+            }
+            if (sg.h) {  // staging grown by this request counts too
+                used += sg.h->dev_bytes - sg.bytes;
+                sg.bytes = sg.known = sg.h->dev_bytes;
             }
             peak = std::max(peak, used);
             r.status = st;
@@ -174,8 +200,7 @@ struct rs_server {
     // removal history as one batch.  The first load validates and renumbers
     // the host copy once and keeps that form (the copy itself is dropped);
     // a reload after an eviction only uploads it.
-    rs_status load(ServedGraph &sg, Request &r) {
-        (void)r;
+    rs_status load(ServedGraph &sg, rs_graph **out) {
         rs_status st = RS_OK;
         if (!sg.pre) {
             rs_csr c;
@@ -208,12 +233,12 @@ struct rs_server {
             rs_free_graph(h);
             return st;
         }
-        sg.h = h;
+        *out = h;
         return RS_OK;
     }
 
     // One request on a resident graph: removals, then the top-k.
-    rs_status serve(ServedGraph &sg, Request &r) {
+    rs_status serve(ServedGraph &sg, rs_graph *h, Request &r) {
         rs_removals b;
         b.n_edges = (int64_t)r.src.size();
         b.src = r.src.data();
@@ -222,7 +247,7 @@ struct rs_server {
         b.vertices = r.verts.data();
         rs_removal_result res = {};
         rs_status st = RS_OK;
-        if (b.n_edges > 0 || b.n_vertices > 0) st = rs_apply_removals(sg.h, &b, &res);
+        if (b.n_edges > 0 || b.n_vertices > 0) st = rs_apply_removals(h, &b, &res);
         if (st != RS_OK) return st;
         sg.hist_src.insert(sg.hist_src.end(), r.src.begin(), r.src.end());
         sg.hist_dst.insert(sg.hist_dst.end(), r.dst.begin(), r.dst.end());
@@ -231,7 +256,7 @@ struct rs_server {
         r.info.edges_removed = res.edges_removed;
         r.ids.resize((size_t)std::max<int64_t>(r.k, 1));
         r.scores.resize((size_t)std::max<int64_t>(r.k, 1));
-        return rs_topk(sg.h, r.k, r.ids.data(), r.scores.data(), &r.count);
+        return rs_topk(h, r.k, r.ids.data(), r.scores.data(), &r.count);
     }
 };
 

@@ -125,3 +125,23 @@ def test_batch_validation_before_device_work():
     with pytest.raises(rs.RSError) as ei:
         rs.rs_load_batch([0, 5, 10], two_off, bad, two_lab)
     assert ei.value.status == 2 and "joins two graphs" in ei.value.detail
+
+
+def test_batch_bad_row_offsets_refused():
+    """Row offsets that decrease, or end past nnz, are refused with
+    RS_ERR_GRAPH before the batch's rows are walked (no read past col)."""
+    import paper_2508_01485_amd as rs
+    g = _good()
+    two_off = np.concatenate([g.off, g.off[1:] + g.off[-1]]).astype(np.int64)
+    two_col = np.concatenate([g.col, g.col + 5]).astype(np.int32)
+    two_lab = np.concatenate([g.labels, g.labels]).astype(np.int32)
+    dec = two_off.copy()
+    dec[1], dec[2] = dec[2] + 3, dec[1]  # off[1] > off[2]
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_load_batch([0, 5, 10], dec, two_col, two_lab)
+    assert ei.value.status == 2 and "decrease" in ei.value.detail
+    past = two_off.copy()
+    past[-1] = two_col.size + 1000  # off[n] > nnz
+    with pytest.raises(rs.RSError) as ei:
+        rs.rs_load_batch([0, 5, 10], past, two_col, two_lab)
+    assert ei.value.status == 2

@@ -1,44 +1,84 @@
-"""Parity at the LFR-style n=2e7 (~290M edges) size, in the launch form the
-benchmark times: every per-vertex integer (border, ell, d') and the own
-weight for all 2e7 vertices against the oracle's rows; R, tI and tII on
-sampled vertices (random ones, the highest-degree ones and the returned
-top ids) against the oracle's per-vertex scores; the top-k list checked by
-properties that hold at any size.
+"""Parity at the LFR-style n = 2e7 size (~287M edges, int64 row offsets at the
+boundary), in the launch form the benchmark times, against reference values
+the oracle wrote for this graph with a full pass over every vertex
+(``tests/golden/make_lfr20m_golden.py``):
 
-Generating the graph takes several minutes of host time, so the test runs
-only when RS_FULL_SCALE=1 is set (with RS_GRAPH_CACHE set, a graph stored by
-an earlier run, e.g. of the benchmark, is reused).
+* the regenerated graph is the one the oracle scored (sizes and SHA-256 of
+  the CSR and the labels);
+* every per-vertex integer of all 2e7 vertices -- border, ell, d', tI, tII --
+  and the zero pattern of R, bit for bit (SHA-256 of the arrays);
+* the totals: border count, inter-community edges, sums of tI and tII, and
+  w_max (within 1e-12 relative);
+* R on 100,000 random vertices and on the 1,000 vertices of highest degree,
+  within 1e-6 relative;
+* the top-10,000 against the oracle's, position by position outside the
+  oracle's near-tie classes (Algorithm 1 Step 4).
+
+R of the other vertices is covered by the zero pattern and, through the
+ranking, by the top-10,000; no other score is compared one by one.
+
+Generating the graph takes about two minutes of host time (with
+RS_GRAPH_CACHE set, a graph stored by an earlier run is reused).  Progress
+goes to stderr so a long generation is visibly alive.
 """
+import hashlib
+import json
 import os
 import sys
 
 import numpy as np
 import pytest
 
-import oracle
 from rsgen import cached, cfg_lfr_20m
-from tests.parity import rel_close
+from tests.golden.make_lfr20m_golden import OUT_JSON, OUT_NPZ, sample_ids
+from tests.parity import TIE_REL, rel_close
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow,
-              pytest.mark.skipif(os.environ.get("RS_FULL_SCALE") != "1",
-                                 reason="full-scale case (minutes of graph generation): set RS_FULL_SCALE=1")]
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 K = 10_000
 
 
 def _say(*a):
-    print("[full-scale]", *a, flush=True)
-    sys.stdout.flush()
+    sys.__stderr__.write("[full-scale] " + " ".join(str(x) for x in a) + "\n")
+    sys.__stderr__.flush()
 
 
-def test_lfr_20m_sampled_parity():
-    import paper_2508_01485_amd as rs
+def _sha(a, dtype):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+
+def _classes(scores):
+    """Near-tie class index of each position of a descending score list."""
+    cls = np.zeros(scores.size, np.int64)
+    for i in range(1, scores.size):
+        a, b = scores[i - 1], scores[i]
+        same = a == b or (max(abs(a), abs(b)) > 0 and abs(a - b) <= TIE_REL * max(abs(a), abs(b)))
+        cls[i] = cls[i - 1] + (0 if same else 1)
+    return cls
+
+
+@pytest.mark.skipif(not (os.path.exists(OUT_JSON) and os.path.exists(OUT_NPZ)),
+                    reason="the oracle's reference values for this graph have not been written yet "
+                           "(tests/golden/make_lfr20m_golden.py)")
+def test_lfr_20m_oracle_parity():
     import torch
 
+    import paper_2508_01485_amd as rs
+
+    with open(OUT_JSON) as f:
+        gold = json.load(f)
+    top = np.load(OUT_NPZ, allow_pickle=False)
     g = cached("lfr_20m_seed0", lambda: cfg_lfr_20m(0, log=_say), log=_say)
     _say(f"graph n={g.n} m={g.m} nnz={g.nnz}")
+    fp = gold["graph"]
+    assert (g.n, g.m, g.nnz) == (fp["n"], fp["m"], fp["nnz"]), "not the graph the oracle scored"
+    assert _sha(g.off, np.int64) == fp["off_sha256"]
+    assert _sha(g.col, np.int32) == fp["col_sha256"]
+    assert _sha(g.labels, np.int32) == fp["labels_sha256"]
+
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    _say("loading on cuda:0")
     h = rs.rs_load_graph(g.off, g.col, g.labels, stream=stream)
     try:
         rs.rs_score(h)
@@ -50,33 +90,39 @@ def test_lfr_20m_sampled_parity():
         h.free()
     _say("GPU pass done")
 
-    # top-k by properties: sorted (R desc, id asc), scores are R, nothing left out
-    assert ids.size == min(K, g.n)
-    assert np.array_equal(sc, R[ids])
-    order = np.lexsort((ids, -sc))
-    assert np.array_equal(order, np.arange(ids.size))
-    rest = np.ones(g.n, bool)
-    rest[ids] = False
-    last_s, last_id = sc[-1], ids[-1]
-    assert not np.any(R[rest] > last_s)
-    assert not np.any((R[rest] == last_s) & (np.flatnonzero(rest) < last_id))
+    # every per-vertex integer and the zero pattern, all vertices
+    hs = gold["sha256"]
+    assert _sha(vc["border"].astype(np.uint8), np.uint8) == hs["border"]
+    assert _sha(vc["ell"], np.int32) == hs["ell"]
+    assert _sha(vc["dprime"], np.int32) == hs["dprime"]
+    assert _sha(vc["tI"], np.int64) == hs["tI"]
+    assert _sha(vc["tII"], np.int64) == hs["tII"]
+    assert _sha(R == 0, np.uint8) == hs["R_zero"]
+    assert cnt["n_border"] == gold["n_border"]
+    assert cnt["m_inter"] == gold["m_inter"]
+    assert cnt["sum_tI"] == gold["sum_tI"] and cnt["sum_tII"] == gold["sum_tII"]
+    om = float.fromhex(gold["omega_max_hex"])
+    assert abs(cnt["omega_max"] - om) <= 1e-12 * om
 
-    # oracle: every row (so all per-vertex integers and weights), scores on a sample
-    rng = np.random.default_rng(2024)
-    deg = np.diff(g.off)
-    sample = np.unique(np.concatenate([rng.choice(g.n, 4000, replace=False),
-                                       np.argsort(-deg, kind="stable")[:200], ids[:300]]))
-    _say(f"oracle on {sample.size} sampled vertices")
-    ora = oracle.score(g, subset=sample, nthreads=16)
-    _say("oracle done")
-    assert np.array_equal(vc["border"].astype(np.uint8), ora["border"])
-    assert np.array_equal(vc["ell"], ora["ell"])
-    assert np.array_equal(vc["dprime"], ora["dprime"])
-    rel_close(vc["w_own"], ora["w_own"], 1e-9)
-    assert cnt["n_border"] == ora["n_border"]
-    assert cnt["m_inter"] == ora["m_inter"]
-    assert abs(cnt["omega_max"] - ora["omega_max"]) <= 1e-12 * ora["omega_max"]
-    assert np.array_equal(vc["tI"][sample], ora["tI"][sample])
-    assert np.array_equal(vc["tII"][sample], ora["tII"][sample])
-    rel_close(R[sample], ora["R"][sample], 1e-6)
-    _say(f"ok: {sample.size} sampled scores, all {g.n} rows")
+    # scores on the sample and the hubs
+    samp = sample_ids(g)
+    worst = rel_close(R[samp], top["sample_R"], 1e-6)
+    _say(f"R on {samp.size} sampled vertices: max relative error {worst:.2e}")
+
+    # top-K: scores are R, and the order is the oracle's outside near-tie classes
+    assert ids.size == K
+    assert np.array_equal(sc, R[ids])
+    o_ids, o_sc = top["ids"], top["scores"]
+    cls = _classes(o_sc)
+    # the class at the K-th position must end inside the stored list
+    assert cls[K - 1] != cls[-1], "a near-tie class reaches past the stored oracle list"
+    cls_of = dict(zip(o_ids.tolist(), cls.tolist()))
+    exempt = 0
+    for pos, (gi, oi) in enumerate(zip(ids.tolist(), o_ids[:K].tolist())):
+        if gi == oi:
+            continue
+        assert gi in cls_of and cls_of[gi] == cls[pos], f"position {pos}: gpu {gi} vs oracle {oi} not near-tied"
+        exempt += 1
+    same = ids == o_ids[:K]
+    rel_close(sc[same], o_sc[:K][same], 1e-6)
+    _say(f"top-{K} equal to the oracle's ({exempt} positions inside near-tie classes)")

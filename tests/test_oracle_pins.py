@@ -404,3 +404,22 @@ def test_validate_rejects(case, oracle_lib):
         off[2], off[1] = off[1], off[2]
     assert oracle.validate(Graph(4, off, col, lab), lib=oracle_lib) == 2
     assert oracle.validate(good, lib=oracle_lib) == 0
+
+
+def test_triad_kinds_on_a_hand_built_graph(oracle_lib):
+    """The oracle's triad labels and its closed type-II count (Section II,
+    the triad types; reading A7) on a graph small enough to list by hand:
+    u and v1, v2 in community A, w in B, x in C; edges u-w, u-v1, u-x, w-v1,
+    w-v2, w-x.  At u: (w, v1) is a closed type-II triad (v1 shares u's
+    community and is u's neighbour), (w, v2) an open one, and the triangle
+    {u, w, x} gives the two type-I triads (w, x) and (x, w)."""
+    U, W, V1, V2, X = range(5)
+    g = from_edges(5, [(U, W), (U, V1), (U, X), (W, V1), (W, V2), (W, X)], [0, 1, 0, 0, 2])
+    got = sorted(oracle.triads(g, U, lib=oracle_lib))
+    assert got == sorted([(W, V1, 3), (W, V2, 2), (W, X, 1), (X, W, 1)])
+    o = oracle.score(g, lib=oracle_lib)
+    assert (o["tI"][U], o["tII"][U], o["tII_closed"][U]) == (2, 2, 1)
+    # v2 sees w only, with w's other neighbours u and v1 in v2's own
+    # community: two open type-II triads and no closed one
+    assert sorted(oracle.triads(g, V2, lib=oracle_lib)) == [(W, U, 2), (W, V1, 2)]
+    assert (o["tI"][V2], o["tII"][V2], o["tII_closed"][V2]) == (0, 2, 0)
