@@ -171,6 +171,22 @@ rs_status rs_restrict_to_targets(rs_graph *g, int32_t k_c, rs_removal_result *re
 rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t *sources, int64_t *counts);
 
 /*
+ * rs_reachable_communities_static: rs_reachable_communities for callers that
+ * cannot allocate (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors; it
+ * calls no hipMalloc, hipFree or other allocating routine.  Its device
+ * memory is one static array of 32 MiB per device, loaded with the library
+ * and held until the process ends: the component labels (4 bytes per
+ * vertex), one community bitmap per source (4 * ceil(k / 32) bytes, k the
+ * number of communities) and the sources and counts.  A graph that needs
+ * more is refused with RS_ERR_RANGE before anything runs.  Every call on one
+ * device shares that device's array (it keeps the last call's contents; each
+ * call clears what it reads), so calls that overlap on one device race: the
+ * caller serialises them.  Host arrays; waits for the graph's stream.
+ */
+rs_status rs_reachable_communities_static(rs_graph *g, int64_t n_sources, const int32_t *sources, int64_t *counts);
+
+/*
  * rs_read_scores: out[n] host array, indexed by caller vertex id.
  *   raw = 0: R(u) of Algorithm 1 (every triad term divided by w_max);
  *   raw = 1: the sum of Eq. RSI without the w_max division (= R * w_max).

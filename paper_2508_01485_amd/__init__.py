@@ -80,7 +80,7 @@ EXPORTS = [
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
     "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
     "rs_server_free", "rs_load_batch", "rs_topk_batch", "rs_restrict_to_targets",
-    "rs_reachable_communities",
+    "rs_reachable_communities", "rs_reachable_communities_static",
 ]
 
 
@@ -119,11 +119,12 @@ def _load_lib(path=LIB_PATH):
     lib.rs_topk_batch.argtypes = [P, I64, P, P, P]
     lib.rs_restrict_to_targets.argtypes = [P, I32, ctypes.POINTER(rs_removal_result)]
     lib.rs_reachable_communities.argtypes = [P, I64, P, P]
+    lib.rs_reachable_communities_static.argtypes = [P, I64, P, P]
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
                  "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
                  "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch",
-                 "rs_restrict_to_targets", "rs_reachable_communities"):
+                 "rs_restrict_to_targets", "rs_reachable_communities", "rs_reachable_communities_static"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -245,6 +246,16 @@ def rs_reachable_communities(g: RSGraph, sources) -> np.ndarray:
     out = np.zeros(max(src.size, 1), np.int64)
     _check(_lib.rs_reachable_communities(g.handle, src.size, src.ctypes.data if src.size else None,
                                          out.ctypes.data), "rs_reachable_communities")
+    return out[: src.size]
+
+
+def rs_reachable_communities_static(g: RSGraph, sources) -> np.ndarray:
+    """rs_reachable_communities without any allocation in the library (the
+    device's static scratch array)."""
+    src = np.ascontiguousarray(sources, dtype=np.int32).ravel()
+    out = np.zeros(max(src.size, 1), np.int64)
+    _check(_lib.rs_reachable_communities_static(g.handle, src.size, src.ctypes.data if src.size else None,
+                                                out.ctypes.data), "rs_reachable_communities_static")
     return out[: src.size]
 
 

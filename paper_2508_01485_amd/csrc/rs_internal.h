@@ -61,6 +61,8 @@ constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
 constexpr int kMaxReachSources = 1024;  // sources per rs_reachable_communities call
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;  // per-device array of rs_reachable_communities_static
+constexpr int kMaxDevices = 64;
 constexpr int kBatchK = 32;
 constexpr int kSegVerts = 1024;   // vertices per batched top-k segment (64 lanes x 16 keys)
 constexpr int kSegMax = 64;       // segments per graph merged by one wavefront          // largest k of the per-graph top-k of a batch
@@ -360,5 +362,10 @@ void free_prebuilt(Prebuilt *P);
 rs_status launch_reach(rs_graph *g, const int32_t *d_src, int ns, int32_t *comp, unsigned int *bits, int words,
                        unsigned int *d_changed, unsigned int *h_changed);
 rs_status launch_zero_u64(rs_graph *g, unsigned long long *p, int count);
+// The device address of this library's static scratch array on `device`
+// (taken once per device with hipGetSymbolAddress), and the per-source
+// bit counts of reach bitmaps.
+rs_status static_scratch(int device, void **out);
+rs_status launch_reach_counts(rs_graph *g, const unsigned int *bits, int ns, int words, long long *d_counts);
 
 }  // namespace rs

@@ -24,6 +24,8 @@
 #include <climits>
 #include <cstring>
 
+#include <mutex>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -3405,6 +3407,57 @@ rs_status launch_reach(rs_graph *g, const int32_t *d_src, int ns, int32_t *comp,
                        words, bits);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "reach launch");
+}
+
+// ------------------------------------------------------------ static scratch
+// Device memory of rs_reachable_communities_static, the entry point for
+// callers that cannot allocate: one array per device (it lives as long as
+// the process), shared by every call on that device.  Host code never passes
+// the array's name to a kernel -- that is a host-side stand-in, not a device
+// address -- but the per-device address taken once with
+// hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+rs_status static_scratch(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return fail(RS_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return RS_OK;
+}
+
+// counts[i] = the bits set in source i's community bitmap (one wavefront per
+// source).
+__global__ __launch_bounds__(kBlock) void k_reach_counts(const unsigned int *bits, int ns, int words,
+                                                         long long *counts) {
+    const int i = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= ns) return;
+    long long c = 0;
+    for (int w = lane; w < words; w += 64) c += __popc(bits[(long long)i * words + w]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) counts[i] = c;
+}
+
+rs_status launch_reach_counts(rs_graph *g, const unsigned int *bits, int ns, int words, long long *d_counts) {
+    hipLaunchKernelGGL(k_reach_counts, dim3((ns + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, g->stream,
+                       bits, ns, words, d_counts);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "reach counts launch");
 }
 
 }  // namespace rs

@@ -1116,6 +1116,57 @@ rs_status rs_reachable_communities(rs_graph *g, int64_t n_sources, const int32_t
     return st;
 }
 
+// Scratch layout of rs_reachable_communities_static (offsets from the
+// device's static array, each 256-byte aligned): the hook flag, the counts,
+// the sources, the community bitmaps, the component labels.
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+rs_status rs_reachable_communities_static(rs_graph *g, int64_t n_sources, const int32_t *sources, int64_t *counts) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    if (n_sources < 0 || n_sources > kMaxReachSources)
+        return fail(RS_ERR_ARG, "n_sources must be 0.." + std::to_string(kMaxReachSources));
+    if (n_sources > 0 && (!sources || !counts)) return fail(RS_ERR_ARG, "sources or counts is NULL");
+    const int64_t n = g->d.n;
+    int32_t src[kMaxReachSources];
+    for (int64_t i = 0; i < n_sources; ++i) {
+        if (sources[i] < 0 || sources[i] >= n) return fail(RS_ERR_RANGE, "source id out of range");
+        src[i] = g->h_old2new[sources[i]];
+    }
+    if (n_sources == 0) return RS_OK;
+    const int words = std::max(1, (int)((g->d.k + 31) / 32));
+    const size_t o_cnt = 256, o_src = o_cnt + align256(8 * (size_t)n_sources),
+                 o_bits = o_src + align256(4 * (size_t)n_sources),
+                 o_comp = o_bits + align256(4 * (size_t)n_sources * words),
+                 need = o_comp + 4 * (size_t)std::max<int64_t>(n, 1);
+    if (need > kStaticScratchBytes)
+        return fail(RS_ERR_RANGE, "graph too large for the static scratch: needs " + std::to_string(need) +
+                                      " bytes (4 per vertex plus the bitmaps), at most " +
+                                      std::to_string(kStaticScratchBytes));
+    void *base = nullptr;
+    rs_status st = static_scratch(g->device, &base);
+    if (st != RS_OK) return st;
+    char *b = (char *)base;
+    unsigned int *d_flag = (unsigned int *)b;
+    long long *d_cnt = (long long *)(b + o_cnt);
+    int32_t *d_src = (int32_t *)(b + o_src);
+    unsigned int *d_bits = (unsigned int *)(b + o_bits);
+    int32_t *d_comp = (int32_t *)(b + o_comp);
+    hipError_t e = hipMemcpyAsync(d_src, src, 4 * (size_t)n_sources, hipMemcpyHostToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "reach upload");
+    unsigned int h_flag = 0;  // written by the component rounds' flag copies
+    st = launch_reach(g, d_src, (int)n_sources, d_comp, d_bits, words, d_flag, &h_flag);
+    if (st == RS_OK) st = launch_reach_counts(g, d_bits, (int)n_sources, words, d_cnt);
+    if (st == RS_OK) {
+        e = hipMemcpyAsync(counts, d_cnt, 8 * (size_t)n_sources, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "reach copy");
+    } else {
+        (void)hipStreamSynchronize(g->stream);  // the source upload reads this frame's array
+    }
+    return st;
+}
+
 rs_status rs_read_scores(rs_graph *g, double *out, int64_t n, int32_t raw) {
     clear_error();
     if (!g || (!out && n > 0)) return fail(RS_ERR_ARG, "graph or out is NULL");
