@@ -56,7 +56,7 @@ constexpr int kHubKeys = 1024;       // score hubs with at most this many record
 constexpr int kHubList = 1024;       // score hubs with at most this many foreign entries stage them in LDS
 constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
-constexpr int kTieCap = 16384;       // largest tie class ranked by pairwise compare
+constexpr int kTieCap = 16384;       // largest tie class ranked through sorted chunks
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
 constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
@@ -67,6 +67,9 @@ constexpr int kBatchK = 32;
 constexpr int kSegVerts = 1024;   // vertices per batched top-k segment (64 lanes x 16 keys)
 constexpr int kSegMax = 64;       // segments per graph merged by one wavefront          // largest k of the per-graph top-k of a batch
 
+// An incremental re-score whose units exceed this many tenths of the full
+// pass's workgroups runs the full pass instead.
+constexpr int kFullPassTenths = 6;
 // Vertex marks of an incremental re-score (after removals).
 constexpr unsigned int kRowChanged = 1u;   // the row lost entries
 constexpr unsigned int kAffected = 2u;     // the score must be recomputed

@@ -943,30 +943,39 @@ __device__ void hub_chunk_store(const ScoreArgs<OffT> &A, const double *red, con
 }
 
 // Per-pair facts of a unit's type-I scan, and the hits found so far.
-constexpr int kHitCap = 768;  // hits held before their terms are evaluated (>= 2 rounds)
+constexpr int kScanR = 2;                  // work items per lane per round
+constexpr int kWaveHitCap = 192;           // hits a wavefront holds before evaluating them
+constexpr int kHitCap = kWaveHitCap * (kBlock / 64);
+static_assert(kWaveHitCap >= 64 * kScanR, "a round's hits always fit after a flush");
 struct TypeIShared {
-    int ibeg[kBlock];      // first work item of each pair (exclusive prefix of the out-list lengths)
+    int ibeg[kBlock];      // first work item of each pair within its wavefront's list
     int ioo[kBlock];       // out-list start of each pair's w
     int pv[kBlock];        // u of each pair
     int pcu[kBlock];       // C(u)
     int pw[kBlock];        // w
     double pW[kBlock];     // w_w(C(u))
-    int wc[kBlock / 64];
 };
 struct HitBuf {
-    int hitp[kHitCap];     // pair of each hit (ascending)
+    int hitp[kHitCap];     // pair of each hit (per wavefront: ascending)
     int hity[kHitCap];     // third vertex of each hit
     double hitv[kHitCap];  // the hit's two ordered triads
 };
 
-// The terms of the nb held hits, then each pair's own lane adds its hits
-// (a contiguous range of the list) in list order.
+// Lanes of one wavefront exchange data through LDS: the writes must be
+// complete and visible before other lanes read them.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The terms of a wavefront's nb held hits (from slot h0), then each pair's
+// own lane adds its hits (a contiguous range of the list) in list order.
 template <typename OffT>
-__device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const TypeIShared &T, HitBuf &H, int nb,
-                                            bool mine, double &val, int &t1) {
-    const int tid = threadIdx.x;
-    for (int h = tid; h < nb; h += kBlock) {
-        const int q = H.hitp[h], v = H.hity[h];
+__device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const TypeIShared &T, HitBuf &H, int h0, int nb,
+                                            int lane, int me, bool mine, double &val, int &t1) {
+    for (int h = lane; h < nb; h += 64) {
+        const int q = H.hitp[h0 + h], v = H.hity[h0 + h];
         const int w = T.pw[q], cu = T.pcu[q];
         const double W = T.pW[q];
         const VCard cv = A.card[v];
@@ -977,88 +986,93 @@ __device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const Type
         const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
         const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
         const double w_wv = s3 >= 0 ? A.recdat[cw.off + s3].w : 0.0;
-        H.hitv[h] = cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
+        H.hitv[h0 + h] = cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
     }
-    __syncthreads();
+    wave_sync();
     if (mine) {
         int a = 0, b = nb;
         while (a < b) {
             const int mid = (a + b) >> 1;
-            if (H.hitp[mid] < tid)
+            if (H.hitp[h0 + mid] < me)
                 a = mid + 1;
             else
                 b = mid;
         }
-        for (int h = a; h < nb && H.hitp[h] == tid; ++h) {
-            val += H.hitv[h];
+        for (int h = a; h < nb && H.hitp[h0 + h] == me; ++h) {
+            val += H.hitv[h0 + h];
             t1 += 2;
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Type-I triads of a unit's pairs (Eq. RSI with v adjacent to u and C(v) !=
 // C(u): the triangles of G').  The pair (u, w) finds the triangles {u, w, v}
 // with v in out(w) (each triangle at u is found by exactly one of its two
-// pairs).  Every position of every pair's out-list is one work item; the
-// unit's items are taken kBlock at a time, so consecutive lanes read
-// consecutive entries of one list and no lane scans a long list alone.  A
-// live entry v with edge(p, v) closes a triangle.  Hits are appended in item
-// order, so each pair's hits stay contiguous and in out-list order; when the
+// pairs).  Every position of every pair's out-list is one work item.  Each
+// wavefront works through the items of its own 64 pairs, kScanR items per
+// lane per round with their loads in flight together (consecutive lanes read
+// consecutive entries of one list, and no lane scans a long list alone); the
+// wavefronts of the block do not wait for each other.  A live entry v with
+// edge(p, v) closes a triangle.  Hits are appended in item order, so each
+// pair's hits stay contiguous and in out-list order; when the wavefront's
 // list is nearly full (and at the end) every held hit's two ordered triads
 // (w, v) and (v, w),
 //   cbrt(w_v(C(u)) w_w(C(v)) W) + cbrt(W w_v(C(w)) w_v(C(u))),  W = w_w(C(u)),
 // are evaluated, one lane per hit, and the pair's own lane adds them to its
-// sum in list order (so the sum's order is fixed).  Every thread of the block
-// takes part; `items` is the lane's out-list length (0 without a pair), and
-// T.ioo, T.pv, T.pcu, T.pw, T.pW hold the lane's pair.  H may overlay LDS
-// that the caller is done with (the scan's first barrier comes before H is
-// written).
+// sum in list order (so the sum's order is fixed).  `items` is the lane's
+// out-list length (0 without a pair), and T.ioo, T.pv, T.pcu, T.pw, T.pW hold
+// the lane's pair; they must be visible block-wide (a barrier) before the call.
 template <class Edge, typename OffT>
 __device__ void typeI_scan(const ScoreArgs<OffT> &A, TypeIShared &T, HitBuf &H, int items, const Edge &edge,
                            double &val, int &t1) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int total = 0;
-    const int first = block_excl_scan(items, T.wc, total);
-    T.ibeg[tid] = first;
-    __syncthreads();
-    int nb = 0;  // held hits (the same in every thread)
-    for (int base = 0; base < total; base += kBlock) {
-        const int i = base + tid;
-        bool hit = false;
-        int p = 0, y = -1;
-        if (i < total) {
-            int lo = 0, hi = kBlock;  // the last pair whose first item is <= i
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (T.ibeg[mid] <= i)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            p = lo;
-            y = A.outl[T.ioo[p] + (i - T.ibeg[p])];
-            hit = y >= 0 && y != T.pv[p] && edge(p, y);
-        }
-        const unsigned long long m = __ballot(hit);
-        if (lane == 0) T.wc[wave] = __popcll(m);
-        __syncthreads();
-        int before = 0, nh = 0;
+    const int w0 = wave * 64;          // the wavefront's first pair
+    const int h0 = wave * kWaveHitCap;  // and its hit slots
+    int incl = items;
 #pragma unroll
-        for (int x = 0; x < kBlock / 64; ++x) {
-            const int c = T.wc[x];
-            if (x < wave) before += c;
-            nh += c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 63);
+    T.ibeg[tid] = incl - items;
+    wave_sync();
+    int nb = 0;  // held hits of this wavefront
+    for (int base = 0; base < total; base += 64 * kScanR) {
+        int y[kScanR], p[kScanR];
+#pragma unroll
+        for (int r = 0; r < kScanR; ++r) {
+            const int i = base + r * 64 + lane;
+            p[r] = w0;
+            y[r] = -1;
+            if (i < total) {
+                int lo = 0, hi = 64;  // the last pair of the wavefront whose first item is <= i
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (T.ibeg[w0 + mid] <= i)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                p[r] = w0 + lo;
+                y[r] = A.outl[T.ioo[w0 + lo] + (i - T.ibeg[w0 + lo])];
+            }
         }
-        if (hit) {
-            const int s = nb + before + __popcll(m & ((1ull << lane) - 1ull));
-            H.hitp[s] = p;
-            H.hity[s] = y;
+#pragma unroll
+        for (int r = 0; r < kScanR; ++r) {
+            const bool hit = y[r] >= 0 && y[r] != T.pv[p[r]] && edge(p[r], y[r]);
+            const unsigned long long m = __ballot(hit);
+            if (hit) {
+                const int s = nb + __popcll(m & ((1ull << lane) - 1ull));
+                H.hitp[h0 + s] = p[r];
+                H.hity[h0 + s] = y[r];
+            }
+            nb += __popcll(m);
         }
-        nb += nh;
-        __syncthreads();
-        if (nb > kHitCap - kBlock || (base + kBlock >= total && nb > 0)) {
-            typeI_flush(A, T, H, nb, items > 0, val, t1);
+        if (nb > kWaveHitCap - 64 * kScanR || (base + 64 * kScanR >= total && nb > 0)) {
+            wave_sync();
+            typeI_flush(A, T, H, h0, nb, lane, tid, items > 0, val, t1);
             nb = 0;
         }
     }
@@ -1213,7 +1227,8 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         S.ti.pw[tid] = w;
         S.ti.pW[tid] = pr.w;
     }
-    // ---- type I
+    // ---- type I (the hit lists overlay the prologue's vertex facts)
+    __syncthreads();
     if (hub_unit) {
         HubListEdge E;
         E.w = S.w;
@@ -1224,7 +1239,8 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         E.S = &S;
         typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
     }
-    // ---- epilogue: sums in a fixed order
+    // ---- epilogue: sums in a fixed order (its terms overlay the hit lists)
+    __syncthreads();
     if (!hub_unit) {
         S.u.e.val[tid] = val;
         S.u.e.t2[tid] = t2;
@@ -1311,7 +1327,8 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     E.uo0 = uo0;
     E.uo1 = uo1;
     E.u = u;
-    typeI_scan(A, S.ti, S.hits, items, E, val, t1);  // its first barrier also covers the staging
+    __syncthreads();  // the staged out-list
+    typeI_scan(A, S.ti, S.hits, items, E, val, t1);
     chunk_tree(val, t1, t2, S.red, S.ired);
     if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
 }
@@ -2243,36 +2260,6 @@ __global__ __launch_bounds__(kBlock) void k_list_collect(const TopkKey *list, co
     }
 }
 
-// Rank the tie class pairwise; the key of rank r < take goes to the final
-// list at position above + r (the final list then holds `above` keys).
-__global__ __launch_bounds__(kBlock) void k_tie_rank(const TopkKey *list, TopkState *st, TopkKey *fin) {
-    __shared__ TopkKey tile[kBlock];
-    const long long n = (long long)st->n_tie;
-    if (st->done || n > kTieCap) {
-        if (!st->done && n > kTieCap && blockIdx.x == 0 && threadIdx.x == 0) st->overflow = 1u;
-        return;
-    }
-    const long long above = (long long)st->n_final;
-    const long long take = st->take;
-    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
-        const long long i = base + threadIdx.x;
-        TopkKey me;
-        me.hi = 0;
-        me.lo = 0;
-        me.v = -1;
-        if (i < n) me = list[i];
-        long long rank = 0;
-        for (long long t0 = 0; t0 < n; t0 += kBlock) {
-            __syncthreads();
-            if (t0 + threadIdx.x < n) tile[threadIdx.x] = list[t0 + threadIdx.x];
-            __syncthreads();
-            const int lim = (int)min((long long)kBlock, n - t0);
-            for (int jj = 0; jj < lim; ++jj) rank += key_gt(tile[jj], me) ? 1 : 0;
-        }
-        if (i < n && rank < take) fin[above + rank] = me;
-    }
-}
-
 // Final order of `count` keys (count <= kSortCap): bitonic sort, descending,
 // in LDS by one block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_final_sort(const TopkKey *fin, long long count, const TopkState *st,
@@ -2535,16 +2522,135 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
 }
 
 
+// ------------------------------------------------------------ rank by sorted chunks
+// Ranking of a key list of up to kMergeChunks * kChunkKeys keys without
+// pairwise comparison of every pair: each chunk of kChunkKeys keys is sorted
+// (descending, bitonic in LDS), then every key's rank is its index in its own
+// chunk plus, for every other chunk, the number of that chunk's keys above it
+// (a binary search of the chunk staged in LDS).  Keys are unique (the caller
+// id is part of the key), so the ranks are a permutation.
+constexpr int kChunkKeys = 2048;
+constexpr int kMergeChunks = 32;
+static_assert(kChunkKeys == 2 * 1024, "a chunk is two keys per thread of a 1024-thread block");
+
+// The list a rank pass works on, and whether it is needed: the tie class of
+// the threshold bin (mode 0, skipped when the bin was taken whole or is too
+// large), or the final list of keff keys (mode 1, skipped while the list is
+// incomplete).
+__device__ __forceinline__ long long rank_count(const TopkState *st, int mode, long long keff) {
+    if (mode == 0) {
+        const long long n = (long long)st->n_tie;
+        return (st->done || n > kTieCap) ? -1 : n;
+    }
+    const long long have = (long long)st->n_final + (st->done ? 0 : st->take);
+    return (st->overflow || have != keff) ? -1 : keff;
+}
+
+__global__ __launch_bounds__(1024) void k_chunk_sort(const TopkKey *in, TopkState *st, int mode, long long keff,
+                                                     TopkKey *out) {
+    __shared__ TopkKey s[kChunkKeys];
+    const long long n = rank_count(st, mode, keff);
+    // a tie class too large to rank here is refined digit by digit instead
+    if (mode == 0 && n < 0 && !st->done && blockIdx.x == 0 && threadIdx.x == 0) st->overflow = 1u;
+    const long long c0 = (long long)blockIdx.x * kChunkKeys;
+    if (n < 0 || c0 >= n) return;
+    const int cnt = (int)min((long long)kChunkKeys, n - c0);
+    for (int i = threadIdx.x; i < kChunkKeys; i += blockDim.x) {
+        if (i < cnt) {
+            s[i] = in[c0 + i];
+        } else {
+            s[i].hi = 0;
+            s[i].lo = 0;  // below every real key (a real key has lo >= 2^31)
+            s[i].v = -1;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= kChunkKeys; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < kChunkKeys; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool desc = (i & k) == 0;
+                    const TopkKey x = s[i], y = s[l];
+                    if (desc ? key_gt(y, x) : key_gt(x, y)) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) out[c0 + i] = s[i];
+}
+
+// Ranks from the sorted chunks (256 keys per block, all in one chunk).  Mode
+// 0: a tie key of rank r < take goes to the final list after the keys above
+// the bin; mode 1: the key of rank r is the r-th output.
+__global__ __launch_bounds__(kBlock) void k_merge_rank(const TopkKey *sorted, const TopkState *st, int mode,
+                                                       long long keff, TopkKey *fin, const double *R,
+                                                       const int32_t *new2old, int32_t *out_ids, double *out_sc) {
+    __shared__ unsigned long long s_hi[kChunkKeys];
+    __shared__ unsigned int s_lo[kChunkKeys];
+    static_assert(kChunkKeys % kBlock == 0, "a block's keys lie in one chunk");
+    const long long n = rank_count(st, mode, keff);
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (n < 0 || (long long)blockIdx.x * kBlock >= n) return;
+    const int mine = (int)(((long long)blockIdx.x * kBlock) / kChunkKeys);
+    const int nch = (int)((n + kChunkKeys - 1) / kChunkKeys);
+    TopkKey me;
+    me.hi = 0;
+    me.lo = 0;
+    me.v = -1;
+    if (i < n) me = sorted[i];
+    long long rank = i - (long long)mine * kChunkKeys;
+    for (int c = 0; c < nch; ++c) {
+        if (c == mine) continue;
+        const long long c0 = (long long)c * kChunkKeys;
+        const int cnt = (int)min((long long)kChunkKeys, n - c0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += kBlock) {
+            const TopkKey x = sorted[c0 + j];
+            s_hi[j] = x.hi;
+            s_lo[j] = x.lo;
+        }
+        __syncthreads();
+        int lo = 0, hi = cnt;  // keys of chunk c above me: a prefix of it
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const bool gt = s_hi[mid] > me.hi || (s_hi[mid] == me.hi && s_lo[mid] > me.lo);
+            if (gt)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        rank += lo;
+    }
+    if (i >= n) return;
+    if (mode == 0) {
+        if (rank < st->take) fin[(long long)st->n_final + rank] = me;
+    } else {
+        out_ids[rank] = new2old[me.v];
+        out_sc[rank] = R[me.v];
+    }
+}
+
 static rs_status final_order(rs_graph *g, long long keff) {
     DeviceGraph &D = g->d;
     hipEvent_t ev;
     timing_begin(g, K_TOPK_RANK, &ev);
-    if (keff <= kSortCap)
+    if (keff <= kSortCap) {
         hipLaunchKernelGGL(k_final_sort, dim3(1), dim3(1024), 0, g->stream, D.tfinal, keff, D.tstate, D.R,
                            D.new2old, D.tout_ids, D.tout_sc);
-    else
+    } else if (keff <= (long long)kMergeChunks * kChunkKeys) {
+        hipLaunchKernelGGL(k_chunk_sort, dim3((int)((keff + kChunkKeys - 1) / kChunkKeys)), dim3(1024), 0, g->stream,
+                           D.tfinal, D.tstate, 1, keff, D.ttie2);
+        hipLaunchKernelGGL(k_merge_rank, dim3((int)((keff + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream,
+                           D.ttie2, D.tstate, 1, keff, D.tfinal, D.R, D.new2old, D.tout_ids, D.tout_sc);
+    } else {
         hipLaunchKernelGGL(k_final_rank, dim3(grid_for(keff, kBlock, 4096)), dim3(kBlock), 0, g->stream, D.tfinal,
                            keff, D.tstate, D.R, D.new2old, D.tout_ids, D.tout_sc);
+    }
     timing_end(g, K_TOPK_RANK, ev);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "top-k order launch");
@@ -2621,9 +2727,13 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     }
     TopkState st;
 
-    // General path: rank the tie class pairwise, then order the final list.
+    // General path: rank the tie class (sorted chunks), then order the final list.
     timing_begin(g, K_TOPK_TIE, &ev);
-    hipLaunchKernelGGL(k_tie_rank, dim3(kTieCap / kBlock), dim3(kBlock), 0, g->stream, D.ttie, D.tstate, D.tfinal);
+    static_assert(kTieCap <= kMergeChunks * kChunkKeys, "a rankable tie class fits the merge");
+    hipLaunchKernelGGL(k_chunk_sort, dim3(kTieCap / kChunkKeys), dim3(1024), 0, g->stream, D.ttie, D.tstate, 0, 0ll,
+                       D.ttie2);
+    hipLaunchKernelGGL(k_merge_rank, dim3(kTieCap / kBlock), dim3(kBlock), 0, g->stream, D.ttie2, D.tstate, 0, 0ll,
+                       D.tfinal, D.R, D.new2old, D.tout_ids, D.tout_sc);
     timing_end(g, K_TOPK_TIE, ev);
     rs_status rs_st = final_order(g, keff);
     if (rs_st != RS_OK) return rs_st;

@@ -1004,15 +1004,23 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
         if (e != hipSuccess) st = hip_fail(e, "incremental counts");
     }
     if (st == RS_OK) {
-        PassLists L;
-        L.rows = g->d.rlist;
-        L.n_rows = (int)ic[kIcRows];
-        L.main = g->d.slist;
-        L.n_main = (int)ic[kIcMain];
-        L.big = g->d.hlist;
-        L.n_big = (int)ic[kIcBig];
-        L.wmax_old = &g->d.ictr[kIcWmaxOld];
-        st = launch_score_lists(g, L);
+        // Rerun the listed units, or, when they are a large share of the
+        // pass (a removed hub touches much of the graph), the whole pass:
+        // its bits are the same, and full launches run faster per unit.
+        const int64_t n_units = (int64_t)ic[kIcRows] + (int64_t)ic[kIcMain] + (int64_t)ic[kIcBig];
+        if (10 * n_units > kFullPassTenths * ((int64_t)g->grid_rows + (int64_t)g->grid_score)) {
+            st = launch_score_pass(g);
+        } else {
+            PassLists L;
+            L.rows = g->d.rlist;
+            L.n_rows = (int)ic[kIcRows];
+            L.main = g->d.slist;
+            L.n_main = (int)ic[kIcMain];
+            L.big = g->d.hlist;
+            L.n_big = (int)ic[kIcBig];
+            L.wmax_old = &g->d.ictr[kIcWmaxOld];
+            st = launch_score_lists(g, L);
+        }
     }
     unsigned long long *cnt = g->rem_cnt_host;
     if (st == RS_OK) {

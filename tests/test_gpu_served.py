@@ -1,7 +1,8 @@
 """The served form: requests on several resident graphs, run concurrently by
 the server's workers (and, under a small HBM budget, with evictions and
 reloads), give exactly the results of applying each graph's batches one by
-one to a lone handle."""
+one to a lone handle, and each request's top-k is the CPU oracle's on that
+graph's mutated state."""
 import sys
 
 import numpy as np
@@ -164,3 +165,54 @@ def test_served_request_on_an_invalid_graph_fails_cleanly():
         srv.free()
     ref = _alone(rs, [good], [(0, None, np.array([0]))], 10)[0]
     assert np.array_equal(ids, ref[0]) and sc.tobytes() == ref[1].tobytes()
+
+
+def _oracle_results(graphs, reqs, k):
+    """Each request's top-k from the oracle on the graph's state after that
+    request: the edges and vertices removed so far (a removed vertex loses
+    its edges and leaves the ranking)."""
+    import oracle
+    from rsgen import from_edges
+    state = []
+    for g in graphs:
+        u, v = g.edges()
+        state.append({"idx": {(int(a), int(b)): i for i, (a, b) in enumerate(zip(u, v))},
+                      "e": np.ones(u.size, bool), "v": np.ones(g.n, bool), "u": u, "w": v})
+    out = []
+    for gi, e, vs in reqs:
+        s, g = state[gi], graphs[gi]
+        if e is not None:
+            for a, b in np.asarray(e).tolist():
+                s["e"][s["idx"][(min(a, b), max(a, b))]] = False
+        if vs is not None:
+            s["v"][np.asarray(vs)] = False
+            s["e"] &= s["v"][s["u"]] & s["v"][s["w"]]
+        cur = from_edges(g.n, np.stack([s["u"][s["e"]], s["w"][s["e"]]], 1), g.labels)
+        o = oracle.score(cur)
+        ids, sc = oracle.topk(o["R"], k, alive=s["v"].astype(np.uint8))
+        out.append((ids, sc, o["R"], s["v"].copy()))
+    return out
+
+
+def _compare_oracle(ora, served, k):
+    from tests.parity import REL, rel_close, topk_matches
+    exempt = 0
+    for i, ((oi, osc, oR, alive), (ib, sb, _)) in enumerate(zip(ora, served)):
+        assert ib.size == oi.size, i
+        exempt += topk_matches(ib, oi, oR, k, alive=alive.astype(np.uint8))
+        rel_close(sb, oR[ib], REL)
+    return exempt
+
+
+def test_served_requests_match_oracle():
+    """Every request served in the mix (4 graphs, 3 slots, then a budget of
+    about two graphs with evictions and reloads) returns the top-k of the
+    oracle run on that graph's mutated state."""
+    import paper_2508_01485_amd as rs
+    graphs = _graphs()
+    for seed, slots, budget_graphs in ((4, 3, 0), (5, 2, 2)):
+        reqs = _requests(graphs, 30, seed)
+        big = max(48 * g.nnz + 360 * g.n + (8 << 20) for g in graphs)
+        served, st = _served(rs, graphs, reqs, 25, slots=slots, budget=budget_graphs * big)
+        ex = _compare_oracle(_oracle_results(graphs, reqs, 25), served, 25)
+        _say(f"{len(reqs)} served requests equal the oracle's top-25 ({ex} near-tie positions)", st)
