@@ -366,113 +366,159 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_arrays(n_graphs):
+    """The batched workload packed as one disjoint union (vertex offsets, row
+    offsets, columns, labels) and its statistics; cached in $RS_GRAPH_CACHE
+    when that is set, so a later run (e.g. under a profiler) starts no
+    generator workers."""
+    from rsgen import Graph, cached, cfg_batch, pack_batch
+
+    def make():
+        graphs = cfg_batch(n_graphs, workers=min(16, os.cpu_count() or 1))
+        vo, off, col, lab = pack_batch(graphs)
+        deg = [g.nnz / max(g.n, 1) for g in graphs]
+        meta = {"vertex_offsets": [int(x) for x in vo], "n_max": int(max(g.n for g in graphs)),
+                "mean_degree_range": [round(min(deg), 2), round(max(deg), 2)],
+                "sbm_graphs": int(sum(g.meta["kind"] == "sbm" for g in graphs))}
+        return Graph(int(vo[-1]), off, col, lab, meta=meta)
+
+    g = cached(f"batch_{n_graphs}", make, log=log)
+    return np.asarray(g.meta["vertex_offsets"], np.int64), g.off, g.col, g.labels, g.meta
+
+
+def graph_of_batch(vo, off, col, lab, i):
+    """Graph i of a packed batch, with ids relative to the graph."""
+    a, b = int(vo[i]), int(vo[i + 1])
+    e0, e1 = int(off[a]), int(off[b])
+    return off[a:b + 1] - e0, col[e0:e1] - np.int32(a), lab[a:b]
+
+
 def bench_batch(args):
     """The batched form: G graphs packed into one disjoint union and scored by
-    one pass (rs_score + rs_topk_batch(20)); beside it the same graphs loaded
-    as G separate resident graphs, each scored by rs_score + rs_topk(20) in
-    turn.  Every per-graph top-20 of the batch is compared with the separate
-    graph's, bit for bit."""
+    one pass (rs_score + rs_topk_batch(20)), first with the default schedule,
+    then with the cut-offs the autotuner picks for the batch's degree
+    signature (searched on a cache miss, then served from the cache); beside
+    it the same graphs loaded as G separate resident graphs, each scored by
+    rs_score + rs_topk(20) in turn.  Every per-graph top-20 is compared:
+    tuned against untuned, and batch against one by one."""
+    import tempfile
+
     import torch
 
     import paper_2508_01485_amd as rs
-    from rsgen import cfg_batch, pack_batch
+    from paper_2508_01485_amd import autotune
     K = WORKLOADS["batch"][1]
     t0 = time.perf_counter()
-    graphs = cfg_batch(args.batch_graphs, workers=min(16, os.cpu_count() or 1))
-    vo, off, col, lab = pack_batch(graphs)
+    vo, off, col, lab, meta = batch_arrays(args.batch_graphs)
+    G = vo.size - 1
     n_tot, m_tot = int(vo[-1]), int(off[-1]) // 2
-    log(f"generated {len(graphs)} graphs (n={n_tot}, m={m_tot}) in {time.perf_counter() - t0:.1f}s")
+    log(f"{G} graphs (n={n_tot}, m={m_tot}) ready in {time.perf_counter() - t0:.1f}s")
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     h = rs.rs_load_batch(vo, off, col, lab, stream=stream)
     load_s = time.perf_counter() - t0
-    del off, col
     log(f"batch loaded in {load_s:.2f}s")
-    for _ in range(args.warmup):
-        rs.rs_score(h)
-        rs.rs_topk_batch(h, K)
-    lat = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        rs.rs_score(h)
-        bids, bsc, bcnt = rs.rs_topk_batch(h, K)  # waits for the stream
-        lat.append(time.perf_counter() - s0)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t_start) / args.steps
-    rs.rs_set_timing(h, True)
-    rs.rs_read_timings(h)
-    for _ in range(args.steps):
-        rs.rs_score(h)
-        rs.rs_topk_batch(h, K)
-    torch.cuda.synchronize()
-    timings = rs.rs_read_timings(h)
+
+    def timed():
+        for _ in range(args.warmup):
+            rs.rs_score(h)
+            rs.rs_topk_batch(h, K)
+        lat = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            rs.rs_score(h)
+            top = rs.rs_topk_batch(h, K)  # waits for the stream
+            lat.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t_start) / args.steps
+        rs.rs_set_timing(h, True)
+        rs.rs_read_timings(h)
+        for _ in range(args.steps):
+            rs.rs_score(h)
+            rs.rs_topk_batch(h, K)
+        torch.cuda.synchronize()
+        tm = rs.rs_read_timings(h)
+        rs.rs_set_timing(h, False)
+        return t, lat, top, tm
+
+    t_untuned, _, top_u, _ = timed()
+    log(f"untuned {1000 * t_untuned:.2f} ms per step; tuning")
+    cache_path = args.tune_cache or os.path.join(tempfile.mkdtemp(), "tiling.json")
+    tune = autotune.tune(h, off, n_graphs=G, cache_path=cache_path)
+    log(f"tuned: {tune}")
+    t_batch, lat, (bids, bsc, bcnt), timings = timed()
+    tuned_same = bool(np.array_equal(bids, top_u[0]) and np.array_equal(bcnt, top_u[2]))
+    tuned_rel = float(np.max(np.abs(bsc - top_u[1]) / np.maximum(np.maximum(np.abs(bsc), np.abs(top_u[1])), 1e-300)))
+    again = autotune.tune(h, off, n_graphs=G, cache_path=cache_path)  # the same signature: from the cache
+    rs.rs_score(h)
     counts = rs.rs_read_counts(h)
     rs.rs_free_graph(h)
     log("kernel ms/launch:", {k: round(v[0] / v[1], 4) for k, v in timings.items() if v[1]})
 
-    if args.batch_sweeps <= 0:  # the batch alone (e.g. under a profiler)
-        print(json.dumps({"metric": METRIC, "value": m_tot / t_batch, "unit": "edges/s", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * t_batch,
-                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-                          "data": "synthetic", "config": {"workload": f"batch: {len(graphs)} graphs"},
-                          "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]}}),
-              flush=True)
-        return
-    log("loading the graphs one by one")
-    t0 = time.perf_counter()
-    hs = [rs.rs_load_graph(g.off, g.col, g.labels, stream=stream) for g in graphs]
-    log(f"{len(hs)} graphs loaded in {time.perf_counter() - t0:.1f}s")
-    for x in hs:  # warm-up sweep
-        rs.rs_score(x)
-        rs.rs_topk(x, K)
-    seq = []
-    same = True
-    for rep_i in range(args.batch_sweeps):
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        tops = []
-        for x in hs:
-            rs.rs_score(x)
-            tops.append(rs.rs_topk(x, K))
-        torch.cuda.synchronize()
-        seq.append(time.perf_counter() - s0)
-        if rep_i == 0:
-            for i, (ids, sc) in enumerate(tops):
-                c = int(bcnt[i])
-                same &= c == ids.size and np.array_equal(bids[i, :c], ids) and bsc[i, :c].tobytes() == sc.tobytes()
-    for x in hs:
-        x.free()
-    t_seq = float(np.median(seq))
-
-    s_off = 8
-    kb = kernel_bytes(counts, n_tot, 2 * m_tot, s_off, K * len(graphs))
     def avg(name):
         ms, nl = timings.get(name, (0.0, 0))
         return 1000.0 * ms / nl if nl else 0.0
+    kb = kernel_bytes(counts, n_tot, 2 * m_tot, 8, K * G)
     avg_us = {"k_rows": avg("k_rows"), "k_score": avg("k_score") + avg("k_score_hub") + avg("k_hub_sum")}
     dom = max(avg_us, key=avg_us.get)
     achieved = kb[dom] / (avg_us[dom] * 1e-6) / 1e9
-    deg = [g.nnz / max(g.n, 1) for g in graphs]
     out = {
         "metric": METRIC, "value": m_tot / t_batch, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * t_batch, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batch: {len(graphs)} {WORKLOADS['batch'][0]}", "graphs": len(graphs),
-                   "n_total": n_tot, "m_total": m_tot, "n_max": int(max(g.n for g in graphs)),
-                   "mean_degree_range": [round(min(deg), 2), round(max(deg), 2)],
-                   "sbm_graphs": int(sum(g.meta["kind"] == "sbm" for g in graphs)), "top_k": K},
+        "config": {"workload": f"batch: {G} {WORKLOADS['batch'][0]}", "graphs": G,
+                   "n_total": n_tot, "m_total": m_tot, "n_max": meta["n_max"],
+                   "mean_degree_range": meta["mean_degree_range"], "sbm_graphs": meta["sbm_graphs"], "top_k": K},
         "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)), "p90": 1000 * float(np.percentile(lat, 90))},
         "load_s": load_s,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": kb[dom],
                      "avg_us": avg_us[dom]},
         "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]},
-        "one_by_one": {"ms_per_sweep": 1000.0 * t_seq, "edges_per_s": m_tot / t_seq,
-                       "batch_speedup": t_seq / t_batch, "top20_identical": bool(same)},
+        "autotune": {"untuned_ms_per_step": 1000.0 * t_untuned, "tuned_ms_per_step": 1000.0 * t_batch,
+                     "speedup": t_untuned / t_batch, "tiling": tune["tiling"], "default": autotune.DEFAULT,
+                     "signature": tune["signature"], "search_s": round(tune["seconds"], 2),
+                     "candidates_timed": tune.get("candidates_timed"), "cache_hit_after": again["cached"],
+                     "cache_hit_s": round(again["seconds"], 3), "top20_ids_identical_to_untuned": tuned_same,
+                     "top20_max_rel_diff_to_untuned": tuned_rel},
     }
+    if args.batch_sweeps > 0:  # the same graphs one by one
+        log("loading the graphs one by one")
+        t0 = time.perf_counter()
+        hs = []
+        for i in range(G):
+            o, c, lb = graph_of_batch(vo, off, col, lab, i)
+            hs.append(rs.rs_load_graph(o, c, lb, stream=stream))
+        log(f"{len(hs)} graphs loaded in {time.perf_counter() - t0:.1f}s")
+        for x in hs:  # warm-up sweep
+            rs.rs_score(x)
+            rs.rs_topk(x, K)
+        seq = []
+        same, rel = True, 0.0
+        for rep_i in range(args.batch_sweeps):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            tops = []
+            for x in hs:
+                rs.rs_score(x)
+                tops.append(rs.rs_topk(x, K))
+            torch.cuda.synchronize()
+            seq.append(time.perf_counter() - s0)
+            if rep_i == 0:
+                for i, (ids, sc) in enumerate(tops):
+                    c = int(bcnt[i])
+                    same &= c == ids.size and np.array_equal(bids[i, :c], ids)
+                    if c and c == ids.size:
+                        rel = max(rel, float(np.max(np.abs(bsc[i, :c] - sc) / np.maximum(np.abs(sc), 1e-300))))
+        for x in hs:
+            x.free()
+        t_seq = float(np.median(seq))
+        out["one_by_one"] = {"ms_per_sweep": 1000.0 * t_seq, "edges_per_s": m_tot / t_seq,
+                             "batch_speedup": t_seq / t_batch, "batch_speedup_untuned": t_seq / t_untuned,
+                             "top20_ids_identical": bool(same), "top20_max_rel_diff": rel}
     print(json.dumps(out), flush=True)
 
 
@@ -558,6 +604,8 @@ def main():
     ap.add_argument("--robust-n", type=int, default=100_000)
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-sweeps", type=int, default=3)
+    ap.add_argument("--tune-cache", default="",
+                    help="autotuner cache file for the batch workload (default: a fresh temporary file)")
     ap.add_argument("--served-graphs", type=int, default=16)
     ap.add_argument("--served-nmax", type=float, default=1e6)
     ap.add_argument("--served-slots", type=int, default=4)

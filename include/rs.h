@@ -272,6 +272,41 @@ rs_status rs_load_batch(int32_t n_graphs, const int64_t *vertex_offsets, const r
 rs_status rs_topk_batch(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *counts);
 
 /* rs_free_graph: release all device memory of g (NULL is ignored). */
+/*
+ * The static schedule's cut-offs (the degree bins of the pass): a row tile
+ * covers consecutive vertices with at most row_entries row entries and
+ * row_vertices vertices, and a longer row is a hub row with a workgroup of
+ * its own; a score tile covers at most score_pairs foreign entries (pairs of
+ * G') and score_vertices vertices, and a vertex with more foreign entries is
+ * a score hub whose pairs are cut into chunks of 256 (one workgroup each),
+ * with its foreign list staged in LDS when it has at most hub_list entries.
+ * Every graph is loaded with the defaults (2048, 512, 256, 256, 1024), which
+ * are also the largest values (row_entries at least 64).  This is the load
+ * balance of the parallel algorithm's kernels (Section VI-B, grid-stride
+ * kernels over vertices and edges; Section VI-C, the cost of skewed degrees).
+ *
+ * rs_get_tiling reads a graph's cut-offs.  rs_set_tiling re-cuts its schedule
+ * (host work over n, and the schedule's device arrays are replaced); the
+ * graph must then be scored again (RS_ERR_STATE from the readers until
+ * rs_score).  Scores and counts do not depend on the cut-offs, except that
+ * vertices that change between tile and hub sum their terms in another
+ * order (the same values within rounding).  Errors: RS_ERR_ARG (a value out
+ * of range).
+ *
+ * rs_autotune: the project's autotuner.  It cuts the schedule for each of the
+ * n_cand candidates in turn, runs one untimed pass and then `reps` timed
+ * passes (HIP events on the graph's stream), writes each candidate's mean
+ * pass time in milliseconds to ms[i], and keeps the fastest (its index in
+ * *best).  A graph scored before the call is scored again with the chosen
+ * cut-offs.  Host arrays; waits for the stream.
+ */
+typedef struct {
+    int32_t row_entries, row_vertices, score_pairs, score_vertices, hub_list;
+} rs_tiling;
+rs_status rs_get_tiling(rs_graph *g, rs_tiling *t);
+rs_status rs_set_tiling(rs_graph *g, const rs_tiling *t);
+rs_status rs_autotune(rs_graph *g, int32_t n_cand, const rs_tiling *cand, int32_t reps, int32_t *best, double *ms);
+
 void rs_free_graph(rs_graph *g);
 
 /*

@@ -63,6 +63,14 @@ class rs_counts(ctypes.Structure):
                 ("sum_tII", ctypes.c_int64), ("sum_work_I", ctypes.c_int64), ("omega_max", ctypes.c_double)]
 
 
+class rs_tiling(ctypes.Structure):
+    _fields_ = [("row_entries", ctypes.c_int32), ("row_vertices", ctypes.c_int32), ("score_pairs", ctypes.c_int32),
+                ("score_vertices", ctypes.c_int32), ("hub_list", ctypes.c_int32)]
+
+
+TILING_FIELDS = ("row_entries", "row_vertices", "score_pairs", "score_vertices", "hub_list")
+
+
 class rs_request_info(ctypes.Structure):
     _fields_ = [("t_submit", ctypes.c_int64), ("t_start", ctypes.c_int64), ("t_done", ctypes.c_int64),
                 ("affected", ctypes.c_int64), ("edges_removed", ctypes.c_int64), ("loaded", ctypes.c_int32),
@@ -80,7 +88,7 @@ EXPORTS = [
     "rs_kernel_name", "rs_free_graph", "rs_status_string", "rs_last_error",
     "rs_server_create", "rs_server_add_graph", "rs_server_submit", "rs_server_wait", "rs_server_stats",
     "rs_server_free", "rs_load_batch", "rs_topk_batch", "rs_restrict_to_targets",
-    "rs_reachable_communities", "rs_reachable_communities_static",
+    "rs_reachable_communities", "rs_reachable_communities_static", "rs_get_tiling", "rs_set_tiling", "rs_autotune",
 ]
 
 
@@ -120,11 +128,15 @@ def _load_lib(path=LIB_PATH):
     lib.rs_restrict_to_targets.argtypes = [P, I32, ctypes.POINTER(rs_removal_result)]
     lib.rs_reachable_communities.argtypes = [P, I64, P, P]
     lib.rs_reachable_communities_static.argtypes = [P, I64, P, P]
+    lib.rs_get_tiling.argtypes = [P, ctypes.POINTER(rs_tiling)]
+    lib.rs_set_tiling.argtypes = [P, ctypes.POINTER(rs_tiling)]
+    lib.rs_autotune.argtypes = [P, I32, P, I32, ctypes.POINTER(I32), P]
     for name in ("rs_load_graph", "rs_score", "rs_topk", "rs_apply_removals", "rs_read_scores",
                  "rs_read_counts", "rs_read_vertex_counts", "rs_read_rows", "rs_read_gprime",
                  "rs_set_timing", "rs_read_timings", "rs_server_create", "rs_server_add_graph",
                  "rs_server_submit", "rs_server_wait", "rs_server_stats", "rs_load_batch", "rs_topk_batch",
-                 "rs_restrict_to_targets", "rs_reachable_communities", "rs_reachable_communities_static"):
+                 "rs_restrict_to_targets", "rs_reachable_communities", "rs_reachable_communities_static",
+                 "rs_get_tiling", "rs_set_tiling", "rs_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -257,6 +269,30 @@ def rs_reachable_communities_static(g: RSGraph, sources) -> np.ndarray:
     _check(_lib.rs_reachable_communities_static(g.handle, src.size, src.ctypes.data if src.size else None,
                                                 out.ctypes.data), "rs_reachable_communities_static")
     return out[: src.size]
+
+
+def rs_get_tiling(g: RSGraph) -> dict:
+    """The graph's schedule cut-offs (see rs.h)."""
+    t = rs_tiling()
+    _check(_lib.rs_get_tiling(g.handle, ctypes.byref(t)), "rs_get_tiling")
+    return {f: int(getattr(t, f)) for f in TILING_FIELDS}
+
+
+def rs_set_tiling(g: RSGraph, tiling: dict):
+    """Re-cut the graph's schedule; the graph must be scored again."""
+    t = rs_tiling(*[int(tiling[f]) for f in TILING_FIELDS])
+    _check(_lib.rs_set_tiling(g.handle, ctypes.byref(t)), "rs_set_tiling")
+
+
+def rs_autotune(g: RSGraph, candidates, reps: int = 3):
+    """(index of the fastest candidate, mean pass ms of each); the graph keeps
+    the fastest cut-offs."""
+    arr = (rs_tiling * len(candidates))(*[rs_tiling(*[int(c[f]) for f in TILING_FIELDS]) for c in candidates])
+    ms = np.zeros(max(len(candidates), 1), np.float64)
+    best = ctypes.c_int32(-1)
+    _check(_lib.rs_autotune(g.handle, len(candidates), ctypes.cast(arr, ctypes.c_void_p), int(reps),
+                            ctypes.byref(best), ms.ctypes.data), "rs_autotune")
+    return int(best.value), ms[: len(candidates)]
 
 
 def rs_read_scores(g: RSGraph, raw: bool = False):

@@ -70,12 +70,23 @@ constexpr int kSegMax = 64;       // segments per graph merged by one wavefront 
 // An incremental re-score whose units exceed this many tenths of the full
 // pass's workgroups runs the full pass instead.
 constexpr int kFullPassTenths = 6;
+// Tile and bin cut-offs of a graph's static schedule: chosen at load (the
+// defaults) or by the autotuner.  Each is at most the compile-time size the
+// kernels' LDS is laid out for.
+struct Tiling {
+    int row_entries = kRowTile;        // row capacity one row tile covers; a longer row is a hub row
+    int row_vertices = kRowTileV;      // vertices of one row tile
+    int score_pairs = kScoreTileP;     // foreign entries of one score tile; more make a score hub
+    int score_vertices = kScoreTileV;  // vertices of one score tile
+    int hub_list = kHubList;           // score hubs with at most this many foreign entries stage them in LDS
+};
+
 // Vertex marks of an incremental re-score (after removals).
 constexpr unsigned int kRowChanged = 1u;   // the row lost entries
 constexpr unsigned int kAffected = 2u;     // the score must be recomputed
 constexpr unsigned int kNearChanged = 4u;  // a neighbour's row changed: links move
 // Counters of an incremental re-score (ictr[]).
-enum IncCounter { kIcChanged = 0, kIcLinkRows, kIcRows, kIcMain, kIcBig, kIcAffected, kIcWmaxOld, kIcCount };
+enum IncCounter { kIcChanged = 0, kIcLinkRows, kIcRows, kIcMain, kIcBig, kIcAffected, kIcWmaxOld, kIcChunks, kIcCount };
 
 // Grid of a tiled launch: one workgroup per hub, then the tiles rounded up to
 // a multiple of the 8 XCDs.
@@ -222,6 +233,7 @@ struct DeviceGraph {
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
     uint8_t *rflag = nullptr, *sflag = nullptr, *hflag = nullptr;  // unit flags
     int32_t *elist = nullptr, *llist = nullptr;                   // [n] changed rows, rows whose links move
+    int2 *echunk = nullptr;                 // [n + nnz / 64] chunks of 64 entries of the changed rows
     int32_t *rlist = nullptr, *slist = nullptr, *hlist = nullptr; // block lists
     unsigned long long *ictr = nullptr;     // [kIcCount]
     // batched graphs (a disjoint union of n_graphs graphs, each a contiguous id range)
@@ -304,7 +316,8 @@ struct rs_graph {
     int32_t n_segs = 0;       // batched top-k segments (0: the one-wavefront-per-graph form)
     int32_t *reach_comp = nullptr, *reach_src = nullptr;  // reachable-community buffers (first use)
     unsigned int *reach_bits = nullptr, *reach_flag = nullptr, *reach_hflag = nullptr;
-    std::vector<void *> allocations;
+    std::vector<std::pair<void *, size_t>> allocations;  // device buffers and their sizes
+    rs::Tiling tiling;
     // pinned host buffer of the common top-k path: [flag | ids | scores]
     void *hpin = nullptr;
     int64_t hpin_cap = 0;

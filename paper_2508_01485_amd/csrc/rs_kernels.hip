@@ -757,21 +757,34 @@ struct ScoreArgs {
     ScorePart *part;
 };
 
-// Index of c among the n ascending keys k[0..n), or -1.  Each step reads 15
-// evenly spaced keys (independent loads) and keeps the slice between the two
-// that bracket c, so n keys take ceil(log16 n) dependent steps.
+// Index of c among the n ascending keys k[0..n), or -1.  Interpolation
+// search: a vertex's record keys are community ids spread over [0, k), so
+// the position of c is predicted from the keys at the two ends of the range
+// and the 16 keys around it (one memory line) are read together; a miss
+// narrows the range to one side of them.  Each step is two dependent loads,
+// and a near-uniform spread of keys needs one step.
 __device__ __forceinline__ int kfind(const int32_t *k, int n, int c) {
     int lo = 0, hi = n;
     while (hi - lo > 16) {
-        const int st = (hi - lo + 15) >> 4;
-        int cnt = 0;
+        const int klo = k[lo], khi = k[hi - 1];
+        if (c < klo || c > khi) return -1;
+        const long long span = (long long)khi - klo;
+        const int guess = lo + (span > 0 ? (int)((long long)(c - klo) * (hi - 1 - lo) / span) : 0);
+        const int b = max(lo, min(guess - 7, hi - 16));
+        int x[16];
 #pragma unroll
-        for (int j = 1; j < 16; ++j) {
-            const int x = lo + j * st;
-            cnt += (x < hi && k[x] <= c) ? 1 : 0;
+        for (int j = 0; j < 16; ++j) x[j] = k[b + j];
+        if (c < x[0]) {
+            hi = b;
+        } else if (c > x[15]) {
+            lo = b + 16;
+        } else {
+            int f = -1;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (x[j] == c) f = b + j;
+            return f;
         }
-        lo += cnt * st;
-        hi = min(hi, lo + st);
     }
     int f = -1;
 #pragma unroll
@@ -1559,11 +1572,12 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs<OffT> L, long long n,
 
 // After removals, for every changed (compacted) row y: the links of y's own
 // foreign entries, and, in each foreign neighbour x's link to y, the index
-// of the entry (y, x), which moved with y's row.  One wavefront per row.
+// of the entry (y, x), which moved with y's row.  One wavefront per chunk of
+// 64 entries of a listed row (chunks: k_row_chunks).
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const int32_t *rows,
-                                                       const unsigned long long *count) {
-    const long long nr = (long long)*count;
+__global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const int32_t *rows, const int2 *chunks,
+                                                       const unsigned long long *n_chunks) {
+    const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
     // first position in a row holding an id >= key
     auto lower = [&](const int32_t *row, int d, int key) {
@@ -1577,42 +1591,43 @@ __global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const i
         }
         return l;
     };
-    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nr;
-         i += ((long long)gridDim.x * kBlock) >> 6) {
-        const int y = rows[i];
+    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
+         q += ((long long)gridDim.x * kBlock) >> 6) {
+        const int2 it = chunks[q];
+        const int y = rows[it.x];
         const long long rb = (long long)L.off[y];
         const int cy = L.lab[y];
         const int dy = L.deg[y];
+        const int j = it.y * 64 + lane;
+        if (j >= dy) continue;
         // y's own run [py, qy) in its compacted row (the same for all its entries)
         const int py = lower(L.col + rb, dy, L.cstart[cy]);
         const int qy = lower(L.col + rb, dy, L.cstart[cy + 1]);
-        for (int j = lane; j < dy; j += 64) {
-            const int x = L.col[rb + j];
-            const int cx = L.lab[x];
-            if (cx == cy) continue;
-            // the entry (x, y): its position in x's row, found once for both links
-            const long long xb = (long long)L.off[x];
-            const int dx = L.deg[x];
-            const int ex = lower(L.col + xb, dx, y);
-            // y's link for its entry j: the reverse entry and x's out-list
-            PairLink pl;
-            pl.e = xb + ex;
-            pl.oo = (int)L.oo[x];
-            pl.on = (int)(L.oo[x + 1] - L.oo[x]);
-            L.plink[L.goff[y] + (j < py ? j : j - (qy - py))] = pl;
-            // x's link for its entry ex points back at (y, x), which moved with
-            // y's row; x's own run is its card's when x's row did not change
-            int px, qx;
-            if (L.vmark[x] & kRowChanged) {
-                px = lower(L.col + xb, dx, L.cstart[cx]);
-                qx = lower(L.col + xb, dx, L.cstart[cx + 1]);
-            } else {
-                const VMeta m = L.card[x].m;
-                px = m.p;
-                qx = m.q;
-            }
-            L.plink[L.goff[x] + (ex < px ? ex : ex - (qx - px))].e = rb + j;
+        const int x = L.col[rb + j];
+        const int cx = L.lab[x];
+        if (cx == cy) continue;
+        // the entry (x, y): its position in x's row, found once for both links
+        const long long xb = (long long)L.off[x];
+        const int dx = L.deg[x];
+        const int ex = lower(L.col + xb, dx, y);
+        // y's link for its entry j: the reverse entry and x's out-list
+        PairLink pl;
+        pl.e = xb + ex;
+        pl.oo = (int)L.oo[x];
+        pl.on = (int)(L.oo[x + 1] - L.oo[x]);
+        L.plink[L.goff[y] + (j < py ? j : j - (qy - py))] = pl;
+        // x's link for its entry ex points back at (y, x), which moved with
+        // y's row; x's own run is its card's when x's row did not change
+        int px, qx;
+        if (L.vmark[x] & kRowChanged) {
+            px = lower(L.col + xb, dx, L.cstart[cx]);
+            qx = lower(L.col + xb, dx, L.cstart[cx + 1]);
+        } else {
+            const VMeta m = L.card[x].m;
+            px = m.p;
+            qx = m.q;
         }
+        L.plink[L.goff[x] + (ex < px ? ex : ex - (qx - px))].e = rb + j;
     }
 }
 
@@ -3242,56 +3257,83 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_
     }
 }
 
+// The listed (changed, compacted) rows cut into chunks of 64 entries, at
+// least one per row: (row's list index, chunk).  One slot per wavefront in
+// the chunk counter (a wavefront prefix orders its lanes' chunks).
+__global__ __launch_bounds__(kBlock) void k_row_chunks(const int32_t *deg, const int32_t *list,
+                                                       const unsigned long long *count, int2 *chunks,
+                                                       unsigned long long *n_chunks) {
+    const long long nl = (long long)*count;
+    const int lane = threadIdx.x & 63;
+    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~63); base < nl;
+         base += (long long)gridDim.x * kBlock) {
+        const long long i = base + lane;
+        const int nc = i < nl ? max(1, (deg[list[i]] + 63) >> 6) : 0;
+        int incl = nc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        unsigned long long first = 0;
+        if (lane == 63) first = atomicAdd(n_chunks, (unsigned long long)incl);
+        first = __shfl(first, 63);
+        for (int c = 0; c < nc; ++c) chunks[first + (incl - nc) + c] = make_int2((int)i, c);
+    }
+}
+
 // A changed vertex x: x and its foreign neighbours are affected (the
-// neighbours are also marked kNearChanged).  One wavefront per listed vertex.
+// neighbours are also marked kNearChanged).  One wavefront per row chunk.
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_mark_nbrs(const OffT *off, const int32_t *deg, const int32_t *col,
                                                       const int32_t *lab, unsigned int *vmark, const int32_t *list,
-                                                      const unsigned long long *count) {
-    const long long nl = (long long)*count;
+                                                      const int2 *chunks, const unsigned long long *n_chunks) {
+    const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
-    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nl;
-         i += ((long long)gridDim.x * kBlock) >> 6) {
-        const int x = list[i];
-        if (lane == 0) atomicOr(&vmark[x], kAffected);
-        const long long rb = (long long)off[x];
+    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
+         q += ((long long)gridDim.x * kBlock) >> 6) {
+        const int2 it = chunks[q];
+        const int x = list[it.x];
+        if (it.y == 0 && lane == 0) atomicOr(&vmark[x], kAffected);
+        const int j = it.y * 64 + lane;
+        if (j >= deg[x]) continue;
         const int cx = lab[x];
-        for (int j = lane; j < deg[x]; j += 64) {
-            const int y = col[rb + j];
-            atomicOr(&vmark[y], lab[y] != cx ? (kNearChanged | kAffected) : kNearChanged);
-        }
+        const int y = col[(long long)off[x] + j];
+        atomicOr(&vmark[y], lab[y] != cx ? (kNearChanged | kAffected) : kNearChanged);
     }
 }
 
 // A changed vertex v and each foreign neighbour w: the members of C(v) in w's
-// row (an id range, found by binary search) are affected.
+// row (an id range, found by binary search) are affected.  One wavefront per
+// row chunk of v.
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_mark_runs(const OffT *off, const int32_t *deg, const int32_t *col,
                                                       const int32_t *lab, const int32_t *cstart, unsigned int *vmark,
-                                                      const int32_t *list, const unsigned long long *count) {
-    const long long nl = (long long)*count;
+                                                      const int32_t *list, const int2 *chunks,
+                                                      const unsigned long long *n_chunks) {
+    const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
-    for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; i < nl;
-         i += ((long long)gridDim.x * kBlock) >> 6) {
-        const int v = list[i];
+    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
+         q += ((long long)gridDim.x * kBlock) >> 6) {
+        const int2 it = chunks[q];
+        const int v = list[it.x];
+        const int j = it.y * 64 + lane;
+        if (j >= deg[v]) continue;
         const int c = lab[v];
+        const int w = col[(long long)off[v] + j];
+        if (lab[w] == c) continue;
         const int id0 = cstart[c], id1 = cstart[c + 1];
-        const long long rb = (long long)off[v];
-        for (int j = lane; j < deg[v]; j += 64) {
-            const int w = col[rb + j];
-            if (lab[w] == c) continue;
-            const int32_t *row = col + off[w];
-            const int dw = deg[w];
-            int a = 0, b = dw;
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (row[mid] < id0)
-                    a = mid + 1;
-                else
-                    b = mid;
-            }
-            for (int t = a; t < dw && row[t] < id1; ++t) atomicOr(&vmark[row[t]], kAffected);
+        const int32_t *row = col + off[w];
+        const int dw = deg[w];
+        int a = 0, b = dw;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (row[mid] < id0)
+                a = mid + 1;
+            else
+                b = mid;
         }
+        for (int t = a; t < dw && row[t] < id1; ++t) atomicOr(&vmark[row[t]], kAffected);
     }
 }
 
@@ -3366,12 +3408,14 @@ static rs_status incremental_marks_t(rs_graph *g) {
                        D.elist, &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_compact_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.elist,
                        &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_row_chunks, dim3(gn), dim3(kBlock), 0, g->stream, D.deg, D.elist, &D.ictr[kIcChanged],
+                       D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_mark_nbrs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.vmark,
-                       D.elist, &D.ictr[kIcChanged]);
+                       D.elist, D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_mark_runs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.cstart,
-                       D.vmark, D.elist, &D.ictr[kIcChanged]);
+                       D.vmark, D.elist, D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_links_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.elist,
-                       &D.ictr[kIcChanged]);
+                       D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_units, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb,
                        D.vscore, (long long)D.n,
                        D.rflag, D.sflag, D.hflag, D.ictr, D.ctr);

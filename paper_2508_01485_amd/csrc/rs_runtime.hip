@@ -67,17 +67,30 @@ static hipError_t dev_alloc(rs_graph *g, void **p, size_t bytes) {
     }
     hipError_t e = hipMalloc(p, bytes ? bytes : 16);
     if (e == hipSuccess) {
-        g->allocations.push_back(*p);
+        g->allocations.push_back({*p, bytes ? bytes : 16});
         g->dev_bytes += (int64_t)(bytes ? bytes : 16);
     }
     return e;
+}
+
+// Free one buffer of the graph (the stream must be idle).
+static void dev_free(rs_graph *g, void **p) {
+    if (!*p) return;
+    for (size_t i = 0; i < g->allocations.size(); ++i)
+        if (g->allocations[i].first == *p) {
+            g->dev_bytes -= (int64_t)g->allocations[i].second;
+            g->allocations.erase(g->allocations.begin() + (long)i);
+            break;
+        }
+    (void)hipFree(*p);
+    *p = nullptr;
 }
 
 static void release(rs_graph *g) {
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     release_replays(g);
-    for (void *p : g->allocations) (void)hipFree(p);
+    for (auto &a : g->allocations) (void)hipFree(a.first);
     g->allocations.clear();
     if (g->hpin) (void)hipHostFree(g->hpin);
     g->hpin = nullptr;
@@ -184,19 +197,24 @@ static rs_status validate_graph(int64_t n, int64_t nnz, const OffIn *off, const 
 }
 
 // ------------------------------------------------------------ load
-struct HostGraph {
-    std::vector<int64_t> off;   // internal offsets
-    std::vector<int32_t> col;   // internal rows
-    std::vector<int32_t> lab;   // internal community per internal vertex
-    std::vector<int32_t> new2old, old2new, comm2orig;
+// The static schedule of a graph under one Tiling: row tiles and hub rows,
+// score tiles, score hubs and their chunks, and the blocks of each vertex.
+struct HostTiles {
     std::vector<int2> rtv, stiles, schunk;
     std::vector<RowTile> rtiles;
-    std::vector<int64_t> oo, goff;
-    std::vector<int32_t> outl, cstart;
     std::vector<int32_t> vrowb, vscore;  // the row block and score unit of each vertex
     std::vector<int32_t> rhubs, shubs, sfirst;
     std::vector<int32_t> gblk_off, gblk;  // batches: the row blocks of each graph
     int n_chunks_lds = 0;
+};
+
+struct HostGraph : HostTiles {
+    std::vector<int64_t> off;   // internal offsets
+    std::vector<int32_t> col;   // internal rows
+    std::vector<int32_t> lab;   // internal community per internal vertex
+    std::vector<int32_t> new2old, old2new, comm2orig;
+    std::vector<int64_t> oo, goff;
+    std::vector<int32_t> outl, cstart;
 };
 
 // Greedy cut of the vertex sequence into tiles of consecutive vertices: a
@@ -231,6 +249,76 @@ static void cut_tiles(int64_t n, const std::vector<int64_t> &weight, int64_t wca
         w += x;
     }
     if (n > lo) tiles.push_back(make_int2((int)lo, (int)n));
+}
+
+// Cut the static schedule for the tiling T from the internal row offsets,
+// each vertex's row capacity and load-time foreign degree (vstart: a batch's
+// graph starts; tiles never span two graphs).
+static void cut_all(int64_t n, const std::vector<int64_t> &off, const std::vector<int64_t> &cap,
+                    const std::vector<int64_t> &fgn, const std::vector<int64_t> &vstart, const Tiling &T,
+                    HostTiles &H) {
+    H = HostTiles();
+    cut_tiles(n, cap, T.row_entries, T.row_vertices, H.rtv, H.rhubs, vstart);
+    H.rtiles.resize(H.rtv.size());
+    for (size_t t = 0; t < H.rtv.size(); ++t) {
+        RowTile &rt = H.rtiles[t];
+        rt.v0 = H.rtv[t].x;
+        rt.v1 = H.rtv[t].y;
+        rt.e0 = off[rt.v0];
+        rt.te = (int)(off[rt.v1] - off[rt.v0]);
+        rt.pad = 0;
+    }
+    cut_tiles(n, fgn, T.score_pairs, T.score_vertices, H.stiles, H.shubs);
+    // a score hub's pairs are processed kScoreTileP at a time, one chunk per workgroup
+    // hubs whose foreign list fits in LDS are listed (and chunked) first
+    std::stable_partition(H.shubs.begin(), H.shubs.end(), [&](int32_t v) { return fgn[v] <= T.hub_list; });
+    H.sfirst.assign(1, 0);
+    H.n_chunks_lds = 0;
+    for (size_t h = 0; h < H.shubs.size(); ++h) {
+        const int64_t nch = (fgn[H.shubs[h]] + kScoreTileP - 1) / kScoreTileP;
+        for (int64_t c = 0; c < nch; ++c) H.schunk.push_back(make_int2((int)h, (int)c));
+        H.sfirst.push_back((int32_t)H.schunk.size());
+        if (fgn[H.shubs[h]] <= T.hub_list) H.n_chunks_lds = (int)H.schunk.size();
+    }
+    // the block of the full launch that handles each vertex: hubs take
+    // the first blocks, tile t of XCD x = t / per runs at block
+    // hubs + 8 (t % per) + ((x - hubs) mod 8) (the inverse of the
+    // kernels' block-to-tile map)
+    auto tile_block = [](int64_t t, int64_t n_tiles, int64_t hubs) {
+        const int64_t per = (n_tiles + 7) / 8, x = t / per, q = t % per;
+        return (int32_t)(hubs + 8 * q + (((x - hubs) % 8 + 8) % 8));
+    };
+    H.vrowb.assign(n, 0);
+    for (size_t h = 0; h < H.rhubs.size(); ++h) H.vrowb[H.rhubs[h]] = (int32_t)h;
+    for (size_t t = 0; t < H.rtv.size(); ++t)
+        for (int v = H.rtv[t].x; v < H.rtv[t].y; ++v)
+            H.vrowb[v] = tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size());
+    H.vscore.assign(n, 0);
+    for (size_t h = 0; h < H.shubs.size(); ++h) H.vscore[H.shubs[h]] = -1 - (int32_t)h;
+    for (size_t t = 0; t < H.stiles.size(); ++t)
+        for (int v = H.stiles[t].x; v < H.stiles[t].y; ++v)
+            H.vscore[v] = tile_block((int64_t)t, (int64_t)H.stiles.size(), (int64_t)H.n_chunks_lds);
+    if (!vstart.empty()) {
+        // each row block lies in one graph (tiles are cut at the graph
+        // starts): list the blocks of every graph, for its w_max
+        const int64_t G = (int64_t)vstart.size() - 1;
+        auto graph_of = [&](int64_t v) {
+            return (int64_t)(std::upper_bound(vstart.begin(), vstart.end(), v) - vstart.begin()) - 1;
+        };
+        std::vector<std::pair<int32_t, int32_t>> bg;  // (graph, block)
+        for (size_t h = 0; h < H.rhubs.size(); ++h) bg.emplace_back((int32_t)graph_of(H.rhubs[h]), (int32_t)h);
+        for (size_t t = 0; t < H.rtv.size(); ++t)
+            bg.emplace_back((int32_t)graph_of(H.rtv[t].x),
+                            tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size()));
+        std::sort(bg.begin(), bg.end());
+        H.gblk_off.assign(G + 1, 0);
+        H.gblk.resize(bg.size());
+        for (size_t i = 0; i < bg.size(); ++i) {
+            ++H.gblk_off[bg[i].first + 1];
+            H.gblk[i] = bg[i].second;
+        }
+        for (int64_t gi = 0; gi < G; ++gi) H.gblk_off[gi + 1] += H.gblk_off[gi];
+    }
 }
 
 // vstart: for a batch, the first vertex of each graph and n (a graph's
@@ -327,67 +415,7 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
         if (H.oo[n] > (int64_t)INT32_MAX) return fail(RS_ERR_RANGE, "out-lists exceed 32-bit offsets");
         H.cstart.resize(k + 1);
         for (int64_t c = 0; c <= k; ++c) H.cstart[c] = (int32_t)start[c];
-        cut_tiles(n, cap, kRowTile, kRowTileV, H.rtv, H.rhubs, vstart);
-        H.rtiles.resize(H.rtv.size());
-        for (size_t t = 0; t < H.rtv.size(); ++t) {
-            RowTile &rt = H.rtiles[t];
-            rt.v0 = H.rtv[t].x;
-            rt.v1 = H.rtv[t].y;
-            rt.e0 = H.off[rt.v0];
-            rt.te = (int)(H.off[rt.v1] - H.off[rt.v0]);
-            rt.pad = 0;
-        }
-        cut_tiles(n, fgn, kScoreTileP, kScoreTileV, H.stiles, H.shubs);
-        // a score hub's pairs are processed kScoreTileP at a time, one chunk per workgroup
-        // hubs whose foreign list fits in LDS are listed (and chunked) first
-        std::stable_partition(H.shubs.begin(), H.shubs.end(), [&](int32_t v) { return fgn[v] <= kHubList; });
-        H.sfirst.assign(1, 0);
-        H.n_chunks_lds = 0;
-        for (size_t h = 0; h < H.shubs.size(); ++h) {
-            const int64_t nch = (fgn[H.shubs[h]] + kScoreTileP - 1) / kScoreTileP;
-            for (int64_t c = 0; c < nch; ++c) H.schunk.push_back(make_int2((int)h, (int)c));
-            H.sfirst.push_back((int32_t)H.schunk.size());
-            if (fgn[H.shubs[h]] <= kHubList) H.n_chunks_lds = (int)H.schunk.size();
-        }
-        // the block of the full launch that handles each vertex: hubs take
-        // the first blocks, tile t of XCD x = t / per runs at block
-        // hubs + 8 (t % per) + ((x - hubs) mod 8) (the inverse of the
-        // kernels' block-to-tile map)
-        auto tile_block = [](int64_t t, int64_t n_tiles, int64_t hubs) {
-            const int64_t per = (n_tiles + 7) / 8, x = t / per, q = t % per;
-            return (int32_t)(hubs + 8 * q + (((x - hubs) % 8 + 8) % 8));
-        };
-        H.vrowb.assign(n, 0);
-        for (size_t h = 0; h < H.rhubs.size(); ++h) H.vrowb[H.rhubs[h]] = (int32_t)h;
-        for (size_t t = 0; t < H.rtv.size(); ++t)
-            for (int v = H.rtv[t].x; v < H.rtv[t].y; ++v)
-                H.vrowb[v] = tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size());
-        H.vscore.assign(n, 0);
-        for (size_t h = 0; h < H.shubs.size(); ++h) H.vscore[H.shubs[h]] = -1 - (int32_t)h;
-        for (size_t t = 0; t < H.stiles.size(); ++t)
-            for (int v = H.stiles[t].x; v < H.stiles[t].y; ++v)
-                H.vscore[v] = tile_block((int64_t)t, (int64_t)H.stiles.size(), (int64_t)H.n_chunks_lds);
-        if (!vstart.empty()) {
-            // each row block lies in one graph (tiles are cut at the graph
-            // starts): list the blocks of every graph, for its w_max
-            const int64_t G = (int64_t)vstart.size() - 1;
-            auto graph_of = [&](int64_t v) {
-                return (int64_t)(std::upper_bound(vstart.begin(), vstart.end(), v) - vstart.begin()) - 1;
-            };
-            std::vector<std::pair<int32_t, int32_t>> bg;  // (graph, block)
-            for (size_t h = 0; h < H.rhubs.size(); ++h) bg.emplace_back((int32_t)graph_of(H.rhubs[h]), (int32_t)h);
-            for (size_t t = 0; t < H.rtv.size(); ++t)
-                bg.emplace_back((int32_t)graph_of(H.rtv[t].x),
-                                tile_block((int64_t)t, (int64_t)H.rtv.size(), (int64_t)H.rhubs.size()));
-            std::sort(bg.begin(), bg.end());
-            H.gblk_off.assign(G + 1, 0);
-            H.gblk.resize(bg.size());
-            for (size_t i = 0; i < bg.size(); ++i) {
-                ++H.gblk_off[bg[i].first + 1];
-                H.gblk[i] = bg[i].second;
-            }
-            for (int64_t gi = 0; gi < G; ++gi) H.gblk_off[gi + 1] += H.gblk_off[gi];
-        }
+        cut_all(n, H.off, cap, fgn, vstart, Tiling(), H);
     } catch (const std::bad_alloc &) {
         return fail(RS_ERR_NOMEM, "host allocation failed while renumbering the graph");
     }
@@ -395,14 +423,19 @@ static rs_status build_internal(int64_t n, int64_t nnz, const OffIn *off, const 
 }
 
 // keep: H stays intact for later uploads (its host maps are copied, not moved)
-static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool keep = false) {
+// Allocate and fill the schedule's device arrays, freeing any earlier
+// ones: tiles and hubs, the per-block partials, the incremental re-score's
+// unit flags and lists, and each vertex's row block and score unit.  Leaves
+// the copies queued on the graph's stream.
+static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
     DeviceGraph &D = g->d;
-    D.n = n;
-    D.nnz = nnz;
-    D.k = (int32_t)H.comm2orig.size();
-    D.off64 = nnz > (int64_t)INT32_MAX || g->wide_offsets;
-    const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
-    const size_t offb = D.off64 ? 8 : 4;
+    void **tile_arrays[] = {(void **)&D.rtiles, (void **)&D.rhubs, (void **)&D.stiles, (void **)&D.shubs,
+                            (void **)&D.shub_first, (void **)&D.shub_chunk, (void **)&D.hub_part,
+                            (void **)&D.rflag, (void **)&D.sflag, (void **)&D.hflag, (void **)&D.rlist,
+                            (void **)&D.slist, (void **)&D.hlist, (void **)&D.part_rows, (void **)&D.wmax_part,
+                            (void **)&D.part_score, (void **)&D.vrowb, (void **)&D.vscore};
+    for (void **p : tile_arrays) dev_free(g, p);
+    const size_t N = (size_t)std::max<int64_t>(D.n, 1);
     g->n_rtiles = (int)H.rtiles.size();
     g->n_rhubs = (int)H.rhubs.size();
     g->n_stiles = (int)H.stiles.size();
@@ -414,6 +447,62 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     const size_t nch = std::max<size_t>(H.schunk.size(), 1);
     const size_t nrt = std::max<size_t>(H.rtiles.size(), 1), nrh = std::max<size_t>(H.rhubs.size(), 1);
     const size_t nst = std::max<size_t>(H.stiles.size(), 1), nsh = std::max<size_t>(H.shubs.size(), 1);
+    const size_t gr = (size_t)std::max(g->grid_rows, 1), gs = (size_t)std::max(g->grid_score, 1);
+    struct Req {
+        void **p;
+        size_t bytes;
+    } reqs[] = {
+        {(void **)&D.rtiles, sizeof(RowTile) * nrt},
+        {(void **)&D.rhubs, 4 * nrh},
+        {(void **)&D.stiles, sizeof(int2) * nst},
+        {(void **)&D.shubs, 4 * nsh},
+        {(void **)&D.shub_first, 4 * (nsh + 1)},
+        {(void **)&D.shub_chunk, sizeof(int2) * nch},
+        {(void **)&D.hub_part, sizeof(HubPart) * nch},
+        {(void **)&D.rflag, gr},
+        {(void **)&D.sflag, gs},
+        {(void **)&D.hflag, nsh},
+        {(void **)&D.rlist, 4 * gr},
+        {(void **)&D.slist, 4 * gs},
+        {(void **)&D.hlist, 4 * nch},
+        {(void **)&D.part_rows, sizeof(RowPart) * gr},
+        {(void **)&D.wmax_part, 8 * gr},
+        {(void **)&D.part_score, sizeof(ScorePart) * gs},
+        {(void **)&D.vrowb, 4 * N},
+        {(void **)&D.vscore, 4 * N},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = dev_alloc(g, r.p, r.bytes);
+        if (e != hipSuccess) return hip_fail(e, "device allocation");
+    }
+    hipStream_t s = g->stream;
+    hipError_t e = hipSuccess;
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    put(D.rtiles, H.rtiles.data(), sizeof(RowTile) * H.rtiles.size());
+    put(D.rhubs, H.rhubs.data(), 4 * H.rhubs.size());
+    put(D.stiles, H.stiles.data(), sizeof(int2) * H.stiles.size());
+    put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
+    put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
+    put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
+    put(D.vrowb, H.vrowb.data(), 4 * H.vrowb.size());
+    put(D.vscore, H.vscore.data(), 4 * H.vscore.size());
+    if (e == hipSuccess) e = hipMemsetAsync(D.rflag, 0, gr, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.sflag, 0, gs, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.hflag, 0, nsh, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * gs, s);
+    return e == hipSuccess ? RS_OK : hip_fail(e, "schedule upload");
+}
+
+static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool keep = false) {
+    DeviceGraph &D = g->d;
+    D.n = n;
+    D.nnz = nnz;
+    D.k = (int32_t)H.comm2orig.size();
+    D.off64 = nnz > (int64_t)INT32_MAX || g->wide_offsets;
+    const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
+    const size_t offb = D.off64 ? 8 : 4;
     struct Req {
         void **p;
         size_t bytes;
@@ -424,13 +513,6 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.lab, 4 * N},
         {(void **)&D.new2old, 4 * N},
         {(void **)&D.alive, N},
-        {(void **)&D.rtiles, sizeof(RowTile) * nrt},
-        {(void **)&D.rhubs, 4 * nrh},
-        {(void **)&D.stiles, sizeof(int2) * nst},
-        {(void **)&D.shubs, 4 * nsh},
-        {(void **)&D.shub_first, 4 * (nsh + 1)},
-        {(void **)&D.shub_chunk, sizeof(int2) * nch},
-        {(void **)&D.hub_part, sizeof(HubPart) * nch},
         {(void **)&D.oo, 8 * (N + 1)},
         {(void **)&D.goff, 8 * (N + 1)},
         {(void **)&D.prec, sizeof(PairRec) * Z},
@@ -439,16 +521,9 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.wpart, 8 * (size_t)kWorkBlocks},
         {(void **)&D.raw, 8 * N},
         {(void **)&D.vmark, 4 * N},
-        {(void **)&D.vrowb, 4 * N},
-        {(void **)&D.vscore, 4 * N},
-        {(void **)&D.rflag, (size_t)std::max(g->grid_rows, 1)},
-        {(void **)&D.sflag, (size_t)std::max(g->grid_score, 1)},
-        {(void **)&D.hflag, nsh},
         {(void **)&D.elist, 4 * N},
         {(void **)&D.llist, 4 * N},
-        {(void **)&D.rlist, 4 * (size_t)std::max(g->grid_rows, 1)},
-        {(void **)&D.slist, 4 * (size_t)std::max(g->grid_score, 1)},
-        {(void **)&D.hlist, 4 * nch},
+        {(void **)&D.echunk, sizeof(int2) * (N + Z / 64 + 1)},
         {(void **)&D.ictr, 8 * (size_t)kIcCount},
         {(void **)&g->rem_cnt, 8 * 4},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
@@ -459,9 +534,6 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.R, 8 * N},
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
-        {(void **)&D.part_rows, sizeof(RowPart) * std::max(g->grid_rows, 1)},
-        {(void **)&D.wmax_part, 8 * (size_t)std::max(g->grid_rows, 1)},
-        {(void **)&D.part_score, sizeof(ScorePart) * std::max(g->grid_score, 1)},
         {(void **)&D.ctr, sizeof(DevCounters)},
         {(void **)&D.thist, 4 * (size_t)kTopkBins},
         {(void **)&D.thist_c, 4 * 256},
@@ -503,16 +575,9 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     auto put = [&](void *dst, const void *src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     };
-    put(D.rtiles, H.rtiles.data(), sizeof(RowTile) * H.rtiles.size());
-    put(D.rhubs, H.rhubs.data(), 4 * H.rhubs.size());
-    put(D.stiles, H.stiles.data(), sizeof(int2) * H.stiles.size());
-    put(D.shubs, H.shubs.data(), 4 * H.shubs.size());
-    put(D.shub_first, H.sfirst.data(), 4 * H.sfirst.size());
     put(D.oo, H.oo.data(), 8 * H.oo.size());
     put(D.goff, H.goff.data(), 8 * H.goff.size());
     put(D.cstart, H.cstart.data(), 4 * H.cstart.size());
-    put(D.vrowb, H.vrowb.data(), 4 * H.vrowb.size());
-    put(D.vscore, H.vscore.data(), 4 * H.vscore.size());
     std::vector<VCard> cards;
     try {
         cards.resize(n);
@@ -529,18 +594,16 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     put(D.card, cards.data(), sizeof(VCard) * cards.size());
     if (e == hipSuccess && n) e = hipStreamSynchronize(s);  // the host cards must outlive the copy
     put(D.outl, H.outl.data(), 4 * H.outl.size());
-    put(D.shub_chunk, H.schunk.data(), sizeof(int2) * H.schunk.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.alive, 1, N, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.vmark, 0, 4 * N, s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.rflag, 0, (size_t)std::max(g->grid_rows, 1), s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.sflag, 0, (size_t)std::max(g->grid_score, 1), s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.hflag, 0, nsh, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist_c, 0, 4 * 256, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
     if (e == hipSuccess) e = hipMemsetAsync(D.tstate, 0, sizeof(TopkState), s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * std::max(g->grid_score, 1), s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "graph upload");
+    const rs_status tst = upload_tiles(g, H);
+    if (tst != RS_OK) return tst;
+    e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
     const rs_status rst = launch_links(g);  // each G' entry's reverse entry and out-list range
     if (rst != RS_OK) return rst;
@@ -698,6 +761,87 @@ static hipError_t read_offsets(rs_graph *g, std::vector<int64_t> &off) {
 using namespace rs;
 
 // ================================================================== C ABI
+// ------------------------------------------------------------ tiling
+static rs_status check_tiling(const rs_tiling *t) {
+    if (!t) return fail(RS_ERR_ARG, "tiling is NULL");
+    if (t->row_entries < 64 || t->row_entries > kRowTile || t->row_vertices < 1 || t->row_vertices > kRowTileV ||
+        t->score_pairs < 1 || t->score_pairs > kScoreTileP || t->score_vertices < 1 ||
+        t->score_vertices > kScoreTileV || t->hub_list < 1 || t->hub_list > kHubList)
+        return fail(RS_ERR_ARG, "tiling out of range: row_entries 64.." + std::to_string(kRowTile) +
+                                    ", row_vertices 1.." + std::to_string(kRowTileV) + ", score_pairs 1.." +
+                                    std::to_string(kScoreTileP) + ", score_vertices 1.." +
+                                    std::to_string(kScoreTileV) + ", hub_list 1.." + std::to_string(kHubList));
+    return RS_OK;
+}
+
+static Tiling to_tiling(const rs_tiling *t) {
+    Tiling T;
+    T.row_entries = t->row_entries;
+    T.row_vertices = t->row_vertices;
+    T.score_pairs = t->score_pairs;
+    T.score_vertices = t->score_vertices;
+    T.hub_list = t->hub_list;
+    return T;
+}
+
+// Re-cut the schedule of a resident graph for the tiling T.  The cut needs
+// each vertex's row capacity and load-time foreign degree, which the device
+// keeps as the capacity layout and the pair-slot offsets; the tiles are cut
+// on the host and the schedule's arrays replaced.  Captured replays are
+// dropped (their grids change), and the graph must be scored again.
+static rs_status retile(rs_graph *g, const Tiling &T) {
+    DeviceGraph &D = g->d;
+    const int64_t n = D.n;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "retile");
+    std::vector<int64_t> off, goff, cap, fgn;
+    HostTiles X;
+    try {
+        off.resize(n + 1);
+        goff.resize(n + 1);
+        cap.resize(n);
+        fgn.resize(n);
+        if (D.off64) {
+            e = hipMemcpy(off.data(), D.off, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost);
+        } else {
+            std::vector<int32_t> o32(n + 1);
+            e = hipMemcpy(o32.data(), D.off, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost);
+            for (int64_t v = 0; v <= n; ++v) off[v] = o32[v];
+        }
+        if (e == hipSuccess) e = hipMemcpy(goff.data(), D.goff, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "retile: reading the capacity layout");
+        for (int64_t v = 0; v < n; ++v) {
+            cap[v] = off[v + 1] - off[v];
+            fgn[v] = goff[v + 1] - goff[v];
+        }
+        cut_all(n, off, cap, fgn, g->h_vstart, T, X);
+    } catch (const std::bad_alloc &) {
+        return fail(RS_ERR_NOMEM, "host allocation failed while cutting tiles");
+    }
+    release_replays(g);
+    rs_status st = upload_tiles(g, X);
+    if (st == RS_OK && g->n_graphs > 0) {  // a batch's row blocks of each graph
+        dev_free(g, (void **)&D.gblk_off);
+        dev_free(g, (void **)&D.gblk);
+        e = dev_alloc(g, (void **)&D.gblk_off, 4 * X.gblk_off.size());
+        if (e == hipSuccess) e = dev_alloc(g, (void **)&D.gblk, 4 * std::max<size_t>(X.gblk.size(), 1));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(D.gblk_off, X.gblk_off.data(), 4 * X.gblk_off.size(), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess && !X.gblk.empty())
+            e = hipMemcpyAsync(D.gblk, X.gblk.data(), 4 * X.gblk.size(), hipMemcpyHostToDevice, g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "retile: batch row blocks");
+        g->h_gblk_off.swap(X.gblk_off);
+        g->h_gblk.swap(X.gblk);
+    }
+    if (st == RS_OK) {
+        e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = hip_fail(e, "retile");
+    }
+    g->tiling = T;
+    g->scored = false;
+    return st;
+}
+
 extern "C" {
 
 const char *rs_status_string(rs_status s) {
@@ -1171,6 +1315,65 @@ rs_status rs_reachable_communities_static(rs_graph *g, int64_t n_sources, const 
         if (e != hipSuccess) st = hip_fail(e, "reach copy");
     } else {
         (void)hipStreamSynchronize(g->stream);  // the source upload reads this frame's array
+    }
+    return st;
+}
+
+rs_status rs_get_tiling(rs_graph *g, rs_tiling *t) {
+    clear_error();
+    if (!g || !t) return fail(RS_ERR_ARG, "graph or tiling is NULL");
+    t->row_entries = g->tiling.row_entries;
+    t->row_vertices = g->tiling.row_vertices;
+    t->score_pairs = g->tiling.score_pairs;
+    t->score_vertices = g->tiling.score_vertices;
+    t->hub_list = g->tiling.hub_list;
+    return RS_OK;
+}
+
+rs_status rs_set_tiling(rs_graph *g, const rs_tiling *t) {
+    clear_error();
+    if (!g) return fail(RS_ERR_ARG, "graph is NULL");
+    rs_status st = check_tiling(t);
+    if (st != RS_OK) return st;
+    return retile(g, to_tiling(t));
+}
+
+rs_status rs_autotune(rs_graph *g, int32_t n_cand, const rs_tiling *cand, int32_t reps, int32_t *best, double *ms) {
+    clear_error();
+    if (!g || !cand || !best || !ms) return fail(RS_ERR_ARG, "graph, candidates, best or ms is NULL");
+    if (n_cand < 1 || reps < 1) return fail(RS_ERR_ARG, "n_cand and reps must be >= 1");
+    for (int32_t i = 0; i < n_cand; ++i) {
+        const rs_status st = check_tiling(&cand[i]);
+        if (st != RS_OK) return st;
+    }
+    const bool was_scored = g->scored;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    rs_status st = e == hipSuccess ? RS_OK : hip_fail(e, "autotune events");
+    int32_t b = -1;
+    for (int32_t i = 0; i < n_cand && st == RS_OK; ++i) {
+        st = retile(g, to_tiling(&cand[i]));
+        if (st == RS_OK) st = launch_score_pass(g);  // warm-up (and the replay's capture)
+        if (st != RS_OK) break;
+        e = hipEventRecord(e0, g->stream);
+        for (int32_t r = 0; r < reps && st == RS_OK && e == hipSuccess; ++r) st = launch_score_pass(g);
+        if (e == hipSuccess) e = hipEventRecord(e1, g->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess && st == RS_OK) st = hip_fail(e, "autotune timing");
+        ms[i] = (double)t / reps;
+        if (st == RS_OK && (b < 0 || ms[i] < ms[b])) b = i;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != RS_OK) return st;
+    *best = b;
+    st = retile(g, to_tiling(&cand[b]));
+    if (st == RS_OK && was_scored) {
+        st = launch_score_pass(g);
+        if (st == RS_OK) g->scored = true;
     }
     return st;
 }
