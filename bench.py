@@ -260,35 +260,46 @@ def rescore_latency(rs, h, g, n_req, seed=11):
                        "then a top-100 query; baseline: rs_score + rs_topk(100) of the same mutated graph"}
 
 
-def bench_served(args):
-    """The served form: several graphs behind rs_server, an HBM budget of half
-    their footprint, removal requests (half 1-1,000 random existing edges,
-    half 1-50 vertices of the graph's latest top-100), each followed by a
-    top-100 query.  Capacity = requests/s with all requests queued at once;
-    then Poisson arrivals at 0.5, 0.8 and 1.0 times that rate, latency =
-    completion - arrival (and service = completion - start) per request."""
-    import threading
-
-    import paper_2508_01485_amd as rs
+def _served_graph(args):
+    gi, n = args
     from rsgen import cached, lfr
+    return cached(f"served_{gi}_n{n}", lambda: lfr(int(n), 20.0, 5000, 0.1, 5000 + gi))
+
+
+def bench_served(args):
+    """The served form: several graphs behind rs_server, removal requests
+    (half 1-1,000 random existing edges, half 1-50 vertices of the graph's
+    latest top-100), each followed by a top-100 query.  Two phases, each on a
+    fresh server: every graph resident (budget above the whole footprint),
+    then an HBM budget of half the footprint (admission, eviction, reloads).
+    Per phase: capacity = requests/s with all requests queued at once; then
+    Poisson arrivals at 0.5, 0.8 and 1.0 times that rate, latency =
+    completion - arrival (and service = completion - start) per request,
+    also split into requests that reloaded an evicted graph and the rest.
+    Beside them, the plain baseline: the same graphs resident on their own
+    handles and each request of the resident phase's capacity mix answered
+    by a full pass (rs_score) plus rs_topk(100) of its graph, one request
+    after another; `value` is the resident phase's capacity."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+
     rng = np.random.default_rng(5000)
     ns = np.exp(rng.uniform(np.log(1e5), np.log(args.served_nmax), args.served_graphs)).astype(np.int64)
-    graphs = []
     t0 = time.perf_counter()
-    for gi, n in enumerate(ns):
-        graphs.append(cached(f"served_{gi}_n{n}", lambda n=n, gi=gi: lfr(int(n), 20.0, 5000, 0.1, 5000 + gi)))
-        log(f"graph {gi}: n={graphs[-1].n} m={graphs[-1].m}")
-    log(f"generated {len(graphs)} graphs in {time.perf_counter() - t0:.1f}s")
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        graphs = list(ex.map(_served_graph, list(enumerate(ns.tolist()))))
+    log(f"generated {len(graphs)} graphs (n={sum(g.n for g in graphs)}) in {time.perf_counter() - t0:.1f}s")
+    import paper_2508_01485_amd as rs  # after the generator pool: no forked process has loaded the HIP library
     est = sum(48 * g.nnz + 360 * g.n + (8 << 20) for g in graphs)
-    srv = rs.RSServer(slots=args.served_slots, hbm_budget=est // 2)
-    gids = [srv.add_graph(g.off, g.col, g.labels) for g in graphs]
     edges = [g.edges() for g in graphs]
     alive = [np.ones(e[0].size, bool) for e in edges]
     tops = [None] * len(graphs)
     lock = threading.Lock()
+    picked = []
 
     def make_request():
         gi = int(rng.integers(len(graphs)))
+        picked.append(gi)
         u, v = edges[gi]
         with lock:
             top = tops[gi]
@@ -299,7 +310,10 @@ def bench_served(args):
             return gi, {"edges": np.stack([u[pick], v[pick]], 1)}
         return gi, {"vertices": rng.choice(top, min(int(rng.integers(1, 51)), top.size), replace=False)}
 
-    def run(n_req, rate):
+    def pct(x):
+        return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))} if len(x) else None
+
+    def run(srv, gids, n_req, rate):
         """Submit n_req requests (all at once if rate is None, else Poisson),
         waiting for them in a second thread; returns per-request info."""
         rids = []
@@ -336,23 +350,54 @@ def bench_served(args):
         wall = time.perf_counter() - t_begin
         lat = np.array([(d["t_done"] - d["t_submit"]) / 1e6 for d in done])
         svc = np.array([(d["t_done"] - d["t_start"]) / 1e6 for d in done])
+        reload = np.array([bool(d["loaded"]) for d in done])
         return {"requests": n_req, "wall_s": wall, "requests_per_s": n_req / wall,
-                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-                "service_ms": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99))},
+                "latency_ms": pct(lat), "service_ms": pct(svc),
+                "latency_ms_without_reloads": pct(lat[~reload]), "latency_ms_reloads": pct(lat[reload]),
                 "mean_affected": float(np.mean([d["affected"] for d in done])),
-                "reloads": int(sum(d["loaded"] for d in done))}
+                "reloads": int(reload.sum())}
 
-    log("warm-up (loads)")
-    run(2 * len(graphs), None)
-    log("capacity: all requests queued at once")
-    cap = run(args.served_requests, None)
-    mu = cap["requests_per_s"]
-    rates = {}
-    for f in (0.5, 0.8, 1.0):
-        log(f"Poisson arrivals at {f} x capacity ({f * mu:.0f}/s)")
-        rates[str(f)] = run(args.served_requests, f * mu)
-    st = srv.stats()
-    srv.free()
+    def phase(budget):
+        """A fresh server under `budget`: warm-up (every graph loaded), then
+        capacity and the three Poisson rates."""
+        srv = rs.RSServer(slots=args.served_slots, hbm_budget=budget)
+        gids = [srv.add_graph(g.off, g.col, g.labels) for g in graphs]
+        log(f"budget {budget / 2**30:.1f} GiB: warm-up (loads)")
+        run(srv, gids, 2 * len(graphs), None)
+        n0 = len(picked)
+        cap = run(srv, gids, args.served_requests, None)
+        mix = picked[n0:]
+        mu = cap["requests_per_s"]
+        rates = {}
+        for f in (0.5, 0.8, 1.0):
+            log(f"Poisson arrivals at {f} x capacity ({f * mu:.0f}/s)")
+            rates[str(f)] = run(srv, gids, args.served_requests, f * mu)
+        st = srv.stats()
+        srv.free()
+        return {"hbm_budget_bytes": int(budget), "capacity": cap, "poisson": rates, "server": st}, mix
+
+    # every graph resident (a budget above the whole footprint): the served
+    # form against the plain baseline on the same request mix
+    resident, mix = phase(int(est * 1.25))
+    # half the footprint: admission, eviction and reloads
+    budgeted, _ = phase(est // 2)
+    log("plain baseline: a full pass per request")
+    plain_ms = []
+    for g in graphs:
+        h = rs.rs_load_graph(g.off, g.col, g.labels)
+        rs.rs_score(h)
+        rs.rs_topk(h, 100)
+        ts = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            rs.rs_score(h)
+            rs.rs_topk(h, 100)
+            ts.append(time.perf_counter() - t1)
+        h.free()
+        plain_ms.append(1000.0 * float(np.median(ts)))
+    per_req = np.asarray(plain_ms)[np.asarray(mix, np.int64)]
+    plain_rps = 1000.0 / float(per_req.mean())
+    mu = resident["capacity"]["requests_per_s"]
     m_total = sum(g.m for g in graphs)
     out = {
         "metric": METRIC, "value": mu, "unit": "requests/s", "n_gpus": 1, "steps": args.served_requests,
@@ -360,8 +405,15 @@ def bench_served(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"served: {len(graphs)} {WORKLOADS['served'][0]}".replace("nmax", f"{args.served_nmax:.0e}"),
                    "graphs": len(graphs), "n_total": int(sum(g.n for g in graphs)), "m_total": int(m_total),
-                   "slots": args.served_slots, "hbm_budget_bytes": int(est // 2), "top_k": 100},
-        "capacity": cap, "poisson": rates, "server": st,
+                   "n_max": int(max(g.n for g in graphs)), "slots": args.served_slots,
+                   "footprint_estimate_bytes": int(est), "top_k": 100},
+        "resident": resident,
+        "budget_half": budgeted,
+        "plain_baseline": {"what": "every graph resident on its own handle; each request of the resident run's "
+                                   "capacity mix answered by rs_score + rs_topk(100) of its graph, one after "
+                                   "another (the removal itself not counted)",
+                           "requests_per_s": plain_rps, "service_ms": pct(per_req),
+                           "served_speedup": mu / plain_rps},
     }
     print(json.dumps(out), flush=True)
 
@@ -606,8 +658,8 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=3)
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file for the batch workload (default: a fresh temporary file)")
-    ap.add_argument("--served-graphs", type=int, default=16)
-    ap.add_argument("--served-nmax", type=float, default=1e6)
+    ap.add_argument("--served-graphs", type=int, default=64)
+    ap.add_argument("--served-nmax", type=float, default=5e6)
     ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--served-requests", type=int, default=300)
     ap.add_argument("--rescore-requests", type=int, default=None,

@@ -134,8 +134,10 @@ typedef struct {
  * endpoints, their neighbours in other communities, and the members of an
  * endpoint's community adjacent to those neighbours); if w_max moves, every
  * score is rescaled.  This follows the removal model of the experiments
- * (Section VII-B).  Waits for the stream.  RS_ERR_STATE before the first
- * rs_score.
+ * (Section VII-B).  Waits for the stream once, after the removal itself
+ * (res is then complete); the re-score stays queued on the graph's stream,
+ * like rs_score's pass, and the library's readers wait for it.
+ * RS_ERR_STATE before the first rs_score.
  */
 rs_status rs_apply_removals(rs_graph *g, const rs_removals *batch, rs_removal_result *res);
 

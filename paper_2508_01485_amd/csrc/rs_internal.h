@@ -86,7 +86,20 @@ constexpr unsigned int kRowChanged = 1u;   // the row lost entries
 constexpr unsigned int kAffected = 2u;     // the score must be recomputed
 constexpr unsigned int kNearChanged = 4u;  // a neighbour's row changed: links move
 // Counters of an incremental re-score (ictr[]).
-enum IncCounter { kIcChanged = 0, kIcLinkRows, kIcRows, kIcMain, kIcBig, kIcAffected, kIcWmaxOld, kIcChunks, kIcCount };
+// Affected tile vertices are rescored in units built per pass: bin b holds
+// the vertices with a load-time foreign degree in (2^(b-1), 2^b] (bin 0: at
+// most 1), and a unit of bin b takes 256 >> b of them (<= 256 pairs).
+constexpr int kScoreBins = 9;
+// The units are found over contiguous vertex ranges, one per workgroup (at
+// most kUnitGroups), each counting its tile vertices per bin and its
+// affected vertices (kUnitRows counts per range).
+constexpr int kUnitGroups = 1024;
+constexpr int kUnitRows = kScoreBins + 1;
+enum IncCounter {
+    kIcChanged = 0, kIcLinkRows, kIcRows, kIcMain, kIcBig, kIcAffected, kIcWmaxOld, kIcChunks, kIcAList,
+    kIcBins,  // kScoreBins counts
+    kIcCount = kIcBins + kScoreBins
+};
 
 // Grid of a tiled launch: one workgroup per hub, then the tiles rounded up to
 // a multiple of the 8 XCDs.
@@ -160,9 +173,6 @@ struct __align__(16) RowTile {
 struct RowPart {
     unsigned long long wmax_bits, n_border, sum_dprime, sum_ell, sum_ell_x, pad[3];
 };
-struct ScorePart {
-    unsigned long long tI, tII;
-};
 // Partial sum of one chunk of a score hub's pairs.
 struct HubPart {
     double raw;
@@ -232,7 +242,8 @@ struct DeviceGraph {
     int32_t *vrowb = nullptr;               // [n] row block of each vertex
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
     uint8_t *rflag = nullptr, *sflag = nullptr, *hflag = nullptr;  // unit flags
-    int32_t *elist = nullptr, *llist = nullptr;                   // [n] changed rows, rows whose links move
+    int32_t *elist = nullptr, *abin = nullptr;  // [n] changed rows; affected tile vertices by bin
+    int32_t *ucnt = nullptr;                    // [kUnitRows * kUnitGroups] per-range counts, then slots
     int2 *echunk = nullptr;                 // [n + nnz / 64] chunks of 64 entries of the changed rows
     int32_t *rlist = nullptr, *slist = nullptr, *hlist = nullptr; // block lists
     unsigned long long *ictr = nullptr;     // [kIcCount]
@@ -254,11 +265,11 @@ struct DeviceGraph {
     RecDat *recdat = nullptr;   // [nnz] interaction-matrix record data
     VCard *card = nullptr;      // [n]
     double *wown = nullptr, *R = nullptr;
+    double *av = nullptr;       // [n] a_v = cbrt(own-community weight) of the last pass
     double *raw = nullptr;      // [n] Eq. RSI sums before the w_max and d(d-1) division
     long long *tI = nullptr, *tII = nullptr;
     RowPart *part_rows = nullptr;    // [row grid]
     unsigned long long *wmax_part = nullptr;  // [row grid] w_max bits per block
-    ScorePart *part_score = nullptr; // [score grid]
     DevCounters *ctr = nullptr;
     // top-k
     unsigned int *thist = nullptr;  // [kTopkBins]
@@ -355,6 +366,7 @@ struct PassLists {
     const int *big;
     int n_big;
     const unsigned long long *wmax_old;
+    long long bin_count[kScoreBins];  // affected tile vertices of each bin (in abin, bin after bin)
 };
 rs_status launch_score_lists(rs_graph *g, const PassLists &inc);
 rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);

@@ -111,6 +111,7 @@ struct RowArgs {
     PairRec *prec;     // pair facts at the foreign row entries, written by this pass
     const int *blist;  // incremental pass: the blocks to run (else every block)
     double *wown, *R, *raw;
+    double *av;  // [n] a_v = cbrt(own-community weight), dense for the score pass's run sums
     long long *tI, *tII;
     RowPart *part;
     unsigned long long *wmax_part;  // [grid] w_max bits of each block (dense copy for k_wmax)
@@ -143,6 +144,7 @@ __device__ __forceinline__ void finish_row(const RowArgs<OffT> &A, int v, int d,
     c.pad = 0;
     c.lab = lab;
     c.a = cbrt(r.wown);
+    A.av[v] = c.a;
     c.key[0] = k4.x;
     c.key[1] = k4.y;
     c.key[2] = k4.z;
@@ -748,13 +750,13 @@ struct ScoreArgs {
     const VCard *card;
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
+    const double *av;       // [n] a_v of the row pass
     const int *blist;       // incremental pass: the blocks to run (else every block)
     const unsigned long long *gwmax;  // batched graphs: w_max bits of each graph, else null
     const int32_t *vgraph;            // batched graphs: graph of each vertex
     double *R, *raw;
     long long *tI, *tII;
     const DevCounters *ctr;
-    ScorePart *part;
 };
 
 // Index of c among the n ascending keys k[0..n), or -1.  Interpolation
@@ -831,7 +833,9 @@ __device__ __forceinline__ bool lds_has_out(const int *a, int n, int x) {
 // Whether the out-list entries outl[o0, o1) in HBM hold the live id t: a
 // 16-ary search on the decoded ids (each step 15 independent loads); a list
 // of up to 16 entries is one step.
-__device__ __forceinline__ bool out_has(const int32_t *outl, long long o0, long long o1, int t) {
+// Position of the live id t in the sorted out-list outl[o0, o1) (removed
+// ids are complemented and keep their place), or -1: a 16-ary search.
+__device__ __forceinline__ long long out_find(const int32_t *outl, long long o0, long long o1, int t) {
     long long lo = o0, hi = o1;
     while (hi - lo > 16) {
         const long long st = (hi - lo + 15) >> 4;
@@ -844,13 +848,17 @@ __device__ __forceinline__ bool out_has(const int32_t *outl, long long o0, long 
         lo += cnt * st;
         hi = min(hi, lo + st);
     }
-    bool f = false;
+    long long f = -1;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const long long x = lo + j;
-        if (x < hi && outl[x] == t) f = true;
+        if (x < hi && outl[x] == t) f = x;
     }
     return f;
+}
+
+__device__ __forceinline__ bool out_has(const int32_t *outl, long long o0, long long o1, int t) {
+    return out_find(outl, o0, o1, t) >= 0;
 }
 
 // Slot of community c among a vertex's record keys: the card's first four
@@ -882,17 +890,13 @@ __device__ __forceinline__ double type2_pair(const ScoreArgs<OffT> &A, int u, co
         for (int t = 0; t < 8; ++t) x[t] = i + t < pr.f ? run[i + t] : u;
         double av[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.card[x[t]].a : 0.0;
+        for (int t = 0; t < 8; ++t) av[t] = x[t] != u ? A.av[x[t]] : 0.0;
 #pragma unroll
         for (int t = 0; t < 8; ++t) S += av[t];
     }
     const double c1 = cbrt(pr.w);
     return c1 * c1 * S;
 }
-
-struct ScoreAcc {
-    long long tI, tII;
-};
 
 // R of Algorithm 1: the raw sum over w_max and d(d-1); 0 when d < 2 or w_max = 0.
 __device__ __forceinline__ double score_value(double acc, int d, double wmax) {
@@ -901,13 +905,11 @@ __device__ __forceinline__ double score_value(double acc, int d, double wmax) {
 
 template <typename OffT>
 __device__ __forceinline__ void score_store(const ScoreArgs<OffT> &A, int u, int d, double acc, long long cI,
-                                            long long cII, double wmax, ScoreAcc &sa) {
+                                            long long cII, double wmax) {
     A.R[u] = score_value(acc, d, A.gwmax ? bitsd(A.gwmax[A.vgraph[u]]) : wmax);
     A.raw[u] = acc;
     A.tI[u] = cI;
     A.tII[u] = cII;
-    sa.tI += cI;
-    sa.tII += cII;
 }
 
 // Exclusive prefix of one int per thread over the block; total to *total.
@@ -940,7 +942,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int *ws, int &total) {
 // the block totals.
 template <typename OffT>
 __device__ void hub_chunk_store(const ScoreArgs<OffT> &A, const double *red, const long long (*ired)[kBlock / 64],
-                                int hub, int chunk, ScoreAcc &sa) {
+                                int hub, int chunk) {
     HubPart hp;
     hp.raw = 0.0;
     hp.tI = hp.tII = 0;
@@ -951,8 +953,6 @@ __device__ void hub_chunk_store(const ScoreArgs<OffT> &A, const double *red, con
         hp.tII += ired[1][i];
     }
     A.hub_part[A.hub_first[hub] + chunk] = hp;
-    sa.tI += hp.tI;
-    sa.tII += hp.tII;
 }
 
 // Per-pair facts of a unit's type-I scan, and the hits found so far.
@@ -1156,9 +1156,11 @@ struct HubListEdge {
     __device__ __forceinline__ bool operator()(int, int y) const { return lds_has(w, 0, n, y); }
 };
 
+// vl: a unit of listed vertices vl[0, vn) (the incremental pass's rescored
+// vertices) instead of the tile idx.
 template <typename OffT>
 __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hub_unit, int idx, double wmax,
-                           ScoreAcc &sa) {
+                           const int32_t *vl = nullptr, int vn = 0) {
     const int tid = threadIdx.x;
     // ---- prologue: lay out the unit's pairs
     int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;    // tile
@@ -1180,11 +1182,15 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         total = min(kBlock, max(0, hdp - chunk * kBlock));
         __syncthreads();
     } else {
-        const int2 tl = A.tiles[idx];
-        v0 = tl.x;
-        nv = tl.y - tl.x;
+        if (vl) {
+            nv = vn;
+        } else {
+            const int2 tl = A.tiles[idx];
+            v0 = tl.x;
+            nv = tl.y - tl.x;
+        }
         if (tid < nv) {
-            const int v = v0 + tid;
+            const int v = vl ? vl[tid] : v0 + tid;
             const VCard cv = A.card[v];
             const VMeta m = cv.m;
             deg = m.deg;
@@ -1224,7 +1230,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
             slot = hgo + k;
         } else {
             const int i = S.pu[tid];
-            u = v0 + i;
+            u = vl ? vl[i] : v0 + i;
             cu = S.u.v.cu[i];
             w = S.w[tid];
             slot = S.u.v.go[i] + (tid - S.pb[i]);
@@ -1267,12 +1273,12 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
                 c2 += S.u.e.t2[q];
                 c1 += S.u.e.t1[q];
             }
-            score_store(A, v0 + tid, deg, acc, c1, c2, wmax, sa);
+            score_store(A, vl ? vl[tid] : v0 + tid, deg, acc, c1, c2, wmax);
         }
         return;
     }
     chunk_tree(val, t1, t2, S.red, S.ired);
-    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
+    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk);
 }
 
 // A hub whose foreign list exceeds kHubList: u's list stays in HBM.  The
@@ -1301,8 +1307,7 @@ struct HubOutEdge {
 };
 
 template <typename OffT>
-__device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, int hub, int chunk, double wmax,
-                              ScoreAcc &sa) {
+__device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, int hub, int chunk, double wmax) {
     const int tid = threadIdx.x;
     const int u = A.hubs[hub];
     const VCard cu_ = A.card[u];
@@ -1343,30 +1348,7 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     __syncthreads();  // the staged out-list
     typeI_scan(A, S.ti, S.hits, items, E, val, t1);
     chunk_tree(val, t1, t2, S.red, S.ired);
-    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk, sa);
-}
-
-__device__ void block_reduce_score(ScoreAcc sa, ScorePart *out) {
-    __shared__ unsigned long long s_u[2][16];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        sa.tI += __shfl_xor(sa.tI, o);
-        sa.tII += __shfl_xor(sa.tII, o);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_u[0][w] = (unsigned long long)sa.tI;
-        s_u[1][w] = (unsigned long long)sa.tII;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ScorePart p = {};
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-            p.tI += s_u[0][i];
-            p.tII += s_u[1][i];
-        }
-        *out = p;
-    }
+    if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk);
 }
 
 // Algorithm 1 Step 3 (Eq. RSI) for every border vertex of the tiles and of
@@ -1375,25 +1357,43 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
     __shared__ ScoreUnitShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    ScoreAcc sa = {0, 0};
     const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
     const bool hub_unit = b < A.n_chunks_lds;
     const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
-    if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax, sa);
-    block_reduce_score(sa, &A.part[b]);
+    if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax);
 }
 
 // ... and of the hubs too large for LDS (chunks n_chunks_lds ...); partials
 // after the tile kernel's.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A, int part0) {
+__global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
     __shared__ ScoreHubBigShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    ScoreAcc sa = {0, 0};
     const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
     const int2 hc = A.hub_chunk[A.n_chunks_lds + b];
-    score_hub_big(A, S, hc.x, hc.y, wmax, sa);
-    block_reduce_score(sa, &A.part[part0 + b]);
+    score_hub_big(A, S, hc.x, hc.y, wmax);
+}
+
+// The incremental pass's rescored tile vertices: units of one bin's listed
+// vertices (256 >> b of bin b per workgroup, so at most 256 pairs).  Their
+// values are those of their tiles in a full pass (a vertex's sum does not
+// depend on its unit's other vertices).
+struct DynUnits {
+    int ufirst[kScoreBins + 1];        // first workgroup of each bin's units
+    long long off[kScoreBins];         // first listed vertex of each bin
+    long long cnt[kScoreBins];         // listed vertices of each bin
+};
+
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_score_dyn(ScoreArgs<OffT> A, const int32_t *abin, DynUnits U) {
+    __shared__ ScoreUnitShared S;
+    const double wmax = bitsd(A.ctr->wmax_bits);
+    int b = 0;
+    while (b < kScoreBins - 1 && (int)blockIdx.x >= U.ufirst[b + 1]) ++b;
+    const int vpu = kBlock >> b;
+    const long long start = U.off[b] + (long long)((int)blockIdx.x - U.ufirst[b]) * vpu;
+    const int nv = (int)min((long long)vpu, U.off[b] + U.cnt[b] - start);
+    score_unit(A, S, false, -1, wmax, abin + start, nv);
 }
 
 // Each hub's score from its chunk partials (one wavefront per hub: lane l
@@ -1434,12 +1434,16 @@ __global__ __launch_bounds__(kBlock) void k_hub_sum(const int32_t *hubs, const i
     }
 }
 
-__global__ __launch_bounds__(1024) void k_reduce_score(const ScorePart *part, int np, DevCounters *c) {
+// The pass's triad totals from the per-vertex counts (read on demand: the
+// incremental pass reruns vertices in units of its own, so per-workgroup
+// partials of the full launch would go stale).
+__global__ __launch_bounds__(1024) void k_reduce_score(const long long *tI, const long long *tII, long long n,
+                                                       DevCounters *c) {
     __shared__ unsigned long long s[2][16];
     unsigned long long a = 0, b = 0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        a += part[i].tI;
-        b += part[i].tII;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        a += (unsigned long long)tI[i];
+        b += (unsigned long long)tII[i];
     }
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);
@@ -1567,67 +1571,6 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs<OffT> L, long long n,
                 hi = mid;
         }
         link_entry(L, (int)lo, (int)(e - (long long)L.off[lo]));
-    }
-}
-
-// After removals, for every changed (compacted) row y: the links of y's own
-// foreign entries, and, in each foreign neighbour x's link to y, the index
-// of the entry (y, x), which moved with y's row.  One wavefront per chunk of
-// 64 entries of a listed row (chunks: k_row_chunks).
-template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_links_rows(LinkArgs<OffT> L, const int32_t *rows, const int2 *chunks,
-                                                       const unsigned long long *n_chunks) {
-    const long long nc = (long long)*n_chunks;
-    const int lane = threadIdx.x & 63;
-    // first position in a row holding an id >= key
-    auto lower = [&](const int32_t *row, int d, int key) {
-        int l = 0, h = d;
-        while (l < h) {
-            const int mid = (l + h) >> 1;
-            if (row[mid] < key)
-                l = mid + 1;
-            else
-                h = mid;
-        }
-        return l;
-    };
-    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
-         q += ((long long)gridDim.x * kBlock) >> 6) {
-        const int2 it = chunks[q];
-        const int y = rows[it.x];
-        const long long rb = (long long)L.off[y];
-        const int cy = L.lab[y];
-        const int dy = L.deg[y];
-        const int j = it.y * 64 + lane;
-        if (j >= dy) continue;
-        // y's own run [py, qy) in its compacted row (the same for all its entries)
-        const int py = lower(L.col + rb, dy, L.cstart[cy]);
-        const int qy = lower(L.col + rb, dy, L.cstart[cy + 1]);
-        const int x = L.col[rb + j];
-        const int cx = L.lab[x];
-        if (cx == cy) continue;
-        // the entry (x, y): its position in x's row, found once for both links
-        const long long xb = (long long)L.off[x];
-        const int dx = L.deg[x];
-        const int ex = lower(L.col + xb, dx, y);
-        // y's link for its entry j: the reverse entry and x's out-list
-        PairLink pl;
-        pl.e = xb + ex;
-        pl.oo = (int)L.oo[x];
-        pl.on = (int)(L.oo[x + 1] - L.oo[x]);
-        L.plink[L.goff[y] + (j < py ? j : j - (qy - py))] = pl;
-        // x's link for its entry ex points back at (y, x), which moved with
-        // y's row; x's own run is its card's when x's row did not change
-        int px, qx;
-        if (L.vmark[x] & kRowChanged) {
-            px = lower(L.col + xb, dx, L.cstart[cx]);
-            qx = lower(L.col + xb, dx, L.cstart[cx + 1]);
-        } else {
-            const VMeta m = L.card[x].m;
-            px = m.p;
-            qx = m.q;
-        }
-        L.plink[L.goff[x] + (ex < px ? ex : ex - (qx - px))].e = rb + j;
     }
 }
 
@@ -1780,6 +1723,7 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     A.prec = D.prec;
     A.blist = inc ? inc->rows : nullptr;
     A.wown = D.wown;
+    A.av = D.av;
     A.R = D.R;
     A.raw = D.raw;
     A.tI = D.tI;
@@ -1823,6 +1767,7 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     S.card = D.card;
     S.prec = D.prec;
     S.plink = D.plink;
+    S.av = D.av;
     S.R = D.R;
     S.raw = D.raw;
     S.gwmax = g->n_graphs > 0 ? D.gwmax : nullptr;
@@ -1830,14 +1775,13 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     S.tI = D.tI;
     S.tII = D.tII;
     S.ctr = D.ctr;
-    S.part = D.part_score;
     const int n_big = g->n_schunks - g->n_schunks_lds;
     const int grid_main = g->grid_score - n_big;
     const int run_big = inc ? inc->n_big : n_big, run_main = inc ? inc->n_main : grid_main;
     if (run_big > 0) {
         S.blist = inc ? inc->big : nullptr;
         timing_begin(g, K_SCORE_HUB, &ev);
-        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(run_big), dim3(kBlock), 0, g->stream, S, grid_main);
+        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(run_big), dim3(kBlock), 0, g->stream, S);
         timing_end(g, K_SCORE_HUB, ev);
     }
     if (run_main > 0) {
@@ -1845,6 +1789,24 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
         timing_begin(g, K_SCORE, &ev);
         hipLaunchKernelGGL(k_score<OffT>, dim3(run_main), dim3(kBlock), 0, g->stream, S);
         timing_end(g, K_SCORE, ev);
+    }
+    if (inc) {  // the rescored tile vertices, in units built for this pass
+        DynUnits U;
+        long long off = 0;
+        U.ufirst[0] = 0;
+        for (int b = 0; b < kScoreBins; ++b) {
+            U.off[b] = off;
+            U.cnt[b] = inc->bin_count[b];
+            off += inc->bin_count[b];
+            U.ufirst[b + 1] = U.ufirst[b] + (int)((inc->bin_count[b] + (kBlock >> b) - 1) / (kBlock >> b));
+        }
+        if (U.ufirst[kScoreBins] > 0) {
+            S.blist = nullptr;
+            timing_begin(g, K_SCORE, &ev);
+            hipLaunchKernelGGL(k_score_dyn<OffT>, dim3(U.ufirst[kScoreBins]), dim3(kBlock), 0, g->stream, S, D.abin,
+                               U);
+            timing_end(g, K_SCORE, ev);
+        }
     }
     if (g->n_shubs > 0) {
         timing_begin(g, K_HUB_SUM, &ev);
@@ -1874,7 +1836,7 @@ rs_status launch_score_lists(rs_graph *g, const PassLists &inc) {
 rs_status launch_reduce_counts(rs_graph *g) {
     DeviceGraph &D = g->d;
     hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, g->stream, D.part_rows, g->grid_rows, D.ctr);
-    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, D.part_score, g->grid_score, D.ctr);
+    hipLaunchKernelGGL(k_reduce_score, dim3(1), dim3(1024), 0, g->stream, D.tI, D.tII, (long long)D.n, D.ctr);
     if (D.off64)
         hipLaunchKernelGGL(k_work_I<long long>, dim3(kWorkBlocks), dim3(kBlock), 0, g->stream,
                            (const long long *)D.off, D.col, D.card, (long long)D.n, D.wpart);
@@ -1919,6 +1881,13 @@ __device__ __forceinline__ unsigned int digit0_of(double r) { return (unsigned i
 // bins to a 256-bin coarse histogram.  Few large blocks keep the number of
 // global atomics (one per non-zero bin per block) small.
 constexpr int kHistThreads = 1024;
+// Global slot of level-0 bin b: consecutive bins 256 bytes apart (bin
+// hi * 1024 + lo at lo * 64 + hi, a bijection of [0, 65536)).  Scores share
+// their leading bits, so a pass fills a few hundred neighbouring bins, and
+// every workgroup adds into all of them: spread over separate cache lines,
+// those atomics no longer queue on a handful of lines.
+__device__ __forceinline__ unsigned int hperm(unsigned int b) { return ((b & 1023u) << 6) | (b >> 10); }
+
 __global__ __launch_bounds__(kHistThreads) void k_topk_hist(const double *R, const uint8_t *alive, long long n,
                                                             long long chunk, unsigned int *hist,
                                                             unsigned int *coarse) {
@@ -1964,8 +1933,8 @@ __global__ __launch_bounds__(kHistThreads) void k_topk_hist(const double *R, con
         const unsigned int w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            if (w[t] & 0xffffu) atomicAdd(&hist[8 * i + 2 * t], w[t] & 0xffffu);
-            if (w[t] >> 16) atomicAdd(&hist[8 * i + 2 * t + 1], w[t] >> 16);
+            if (w[t] & 0xffffu) atomicAdd(&hist[hperm(8 * i + 2 * t)], w[t] & 0xffffu);
+            if (w[t] >> 16) atomicAdd(&hist[hperm(8 * i + 2 * t + 1)], w[t] >> 16);
         }
     }
     // coarse histogram: thread t < 256 sums fine bins [256 t, 256 t + 256)
@@ -2037,7 +2006,7 @@ __global__ __launch_bounds__(kBlock) void k_topk_find0(unsigned int *hist, unsig
     const int c = s_c;
     const long long above_c = s_above;
     const unsigned int bin = (unsigned int)(256 * c + 255 - t);
-    const long long mf = hist[bin];
+    const long long mf = hist[hperm(bin)];
     const long long inf = above_c + block_incl_scan_ll(mf, ws);
     if (inf - mf < k && k <= inf) {
         st->k = k;
@@ -3088,64 +3057,96 @@ struct OutLists {
     unsigned int *vmark;
 };
 
-// Tombstone y in out(x), if there; returns whether it was found.
+// Tombstone y in out(x), if there; returns whether it was found.  Only the
+// request that deleted the edge gets here, so the store does not race.
 __device__ __forceinline__ bool out_drop(const OutLists &O, int x, int y) {
-    for (long long j = O.oo[x]; j < O.oo[x + 1]; ++j)
-        if (O.outl[j] == y) {
-            O.outl[j] = ~y;
-            return true;
-        }
-    return false;
+    const long long j = out_find(O.outl, O.oo[x], O.oo[x + 1], y);
+    if (j < 0) return false;
+    O.outl[j] = ~y;
+    return true;
 }
 
 // Delete the undirected edge {a, b}; the entry in the row of min(a, b) is
-// the owner and decides which request wins.  Returns 1 if deleted here.  A
-// deleted edge between communities also leaves the out-list that holds it.
+// the owner and decides which request wins.  Returns 1 if deleted here; nx
+// and ny tell whether the rows of min(a, b) and max(a, b) were marked changed
+// here first.  A deleted edge between communities also leaves the out-list
+// that holds it.
 template <typename OffT>
 __device__ __forceinline__ int delete_edge(const OffT *off, const int32_t *deg, int32_t *col, const OutLists &O,
-                                           int a, int b) {
+                                           int a, int b, bool &nx, bool &ny) {
     const int x = min(a, b), y = max(a, b);
     const long long e = find_entry(off, deg, col, x, y);
     if (e < 0) return 0;
     if (atomicCAS(&col[e], y, ~y) != y) return 0;
     const long long f = find_entry(off, deg, col, y, x);
     if (f >= 0) col[f] = ~x;
-    atomicOr(&O.vmark[x], kRowChanged);
-    atomicOr(&O.vmark[y], kRowChanged);
+    nx = (atomicOr(&O.vmark[x], kRowChanged) & kRowChanged) == 0u;
+    ny = (atomicOr(&O.vmark[y], kRowChanged) & kRowChanged) == 0u;
     if (O.lab[x] != O.lab[y] && !out_drop(O, x, y)) out_drop(O, y, x);
     return 1;
 }
 
+// The rows first marked changed by a wavefront's lanes, appended to the list
+// of changed rows (any order; one atomic per wavefront).  All lanes call it.
+__device__ __forceinline__ void append_changed(int x, bool nx, int y, bool ny, int32_t *list,
+                                               unsigned long long *count) {
+    const int lane = (int)__lane_id();
+    const unsigned long long mx = __ballot(nx), my = __ballot(ny);
+    const int tot = __popcll(mx) + __popcll(my);
+    if (tot == 0) return;
+    unsigned long long first = 0;
+    if (lane == 0) first = atomicAdd(count, (unsigned long long)tot);
+    first = __shfl(first, 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (nx) list[first + __popcll(mx & below)] = x;
+    if (ny) list[first + __popcll(mx) + __popcll(my & below)] = y;
+}
+
 template <typename OffT>
 __global__ void k_remove_edges(const OffT *off, const int32_t *deg, int32_t *col, OutLists O, const int32_t *src,
-                               const int32_t *dst, long long m, unsigned long long *removed) {
+                               const int32_t *dst, long long m, unsigned long long *removed, int32_t *changed,
+                               unsigned long long *n_changed) {
+    const int lane = (int)__lane_id();
     unsigned long long cnt = 0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
-        const int a = src[i], b = dst[i];
-        if (a != b) cnt += (unsigned long long)delete_edge(off, deg, col, O, a, b);
+    for (long long base = (long long)blockIdx.x * blockDim.x + threadIdx.x - lane; base < m;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long i = base + lane;
+        int a = 0, b = 0;
+        bool nx = false, ny = false;
+        if (i < m) {
+            a = src[i];
+            b = dst[i];
+            if (a != b) cnt += (unsigned long long)delete_edge(off, deg, col, O, a, b, nx, ny);
+        }
+        append_changed(min(a, b), nx, max(a, b), ny, changed, n_changed);
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (__lane_id() == 0 && cnt) atomicAdd(removed, cnt);
+    if (lane == 0 && cnt) atomicAdd(removed, cnt);
 }
 
 // One wavefront per removed vertex: delete every incident edge, then mark the
 // vertex dead.  removed[0] counts edges, removed[1] newly dead vertices.
 template <typename OffT>
 __global__ void k_remove_vertices(const OffT *off, const int32_t *deg, int32_t *col, OutLists O, uint8_t *alive,
-                                  const int32_t *verts, long long nv, unsigned long long *removed) {
+                                  const int32_t *verts, long long nv, unsigned long long *removed, int32_t *changed,
+                                  unsigned long long *n_changed) {
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+    const int lane = (int)__lane_id();
     for (long long i = wave; i < nv; i += nwave) {
         const int x = verts[i];
         const long long rb = (long long)off[x];
         const int d = deg[x];
         unsigned long long cnt = 0;
-        for (int j = (int)__lane_id(); j < d; j += 64) {
-            const int y = col[rb + j];
-            if (y >= 0) cnt += (unsigned long long)delete_edge(off, deg, col, O, x, y);
+        for (int j0 = 0; j0 < d; j0 += 64) {
+            const int j = j0 + lane;
+            const int y = j < d ? col[rb + j] : -1;
+            bool nx = false, ny = false;
+            if (y >= 0) cnt += (unsigned long long)delete_edge(off, deg, col, O, x, y, nx, ny);
+            append_changed(min(x, y), nx, max(x, y), ny, changed, n_changed);
         }
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (__lane_id() == 0) {
+        if (lane == 0) {
             if (cnt) atomicAdd(&removed[0], cnt);
             if (alive[x]) {
                 alive[x] = 0;
@@ -3171,10 +3172,11 @@ rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *
     if (g->d.off64)
         hipLaunchKernelGGL(k_remove_edges<long long>, dim3(grid), dim3(256), 0, g->stream,
                            (const long long *)g->d.off, g->d.deg, g->d.col, out_lists(g), d_src, d_dst, (long long)m,
-                           d_removed);
+                           d_removed, g->d.elist, &g->d.ictr[kIcChanged]);
     else
         hipLaunchKernelGGL(k_remove_edges<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, out_lists(g), d_src, d_dst, (long long)m, d_removed);
+                           g->d.deg, g->d.col, out_lists(g), d_src, d_dst, (long long)m, d_removed, g->d.elist,
+                           &g->d.ictr[kIcChanged]);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "remove edges launch");
 }
@@ -3185,10 +3187,11 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
     if (g->d.off64)
         hipLaunchKernelGGL(k_remove_vertices<long long>, dim3(grid), dim3(256), 0, g->stream,
                            (const long long *)g->d.off, g->d.deg, g->d.col, out_lists(g), g->d.alive, d_verts,
-                           (long long)nv, d_removed);
+                           (long long)nv, d_removed, g->d.elist, &g->d.ictr[kIcChanged]);
     else
         hipLaunchKernelGGL(k_remove_vertices<int32_t>, dim3(grid), dim3(256), 0, g->stream, (const int32_t *)g->d.off,
-                           g->d.deg, g->d.col, out_lists(g), g->d.alive, d_verts, (long long)nv, d_removed);
+                           g->d.deg, g->d.col, out_lists(g), g->d.alive, d_verts, (long long)nv, d_removed,
+                           g->d.elist, &g->d.ictr[kIcChanged]);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "remove vertices launch");
 }
@@ -3201,35 +3204,11 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
 //   weights or out-lists involve it), or u is in the community of some v in
 //   E and adjacent to a foreign neighbour w of v (u's pair (u, w) sums a_v);
 // rows need recomputing only for E, and links only for E's entries and the
-// neighbours' links back to E.
-// The affected row tiles, score tiles and hub chunks are rerun whole, with
-// the block indices of the full launch, so every result and every partial is
-// what a full pass would give.
-
-// Append the vertices whose mark has one of `bits` to list (any order; one
-// atomic per workgroup and step).
-__global__ __launch_bounds__(kBlock) void k_list_marked(const unsigned int *vmark, unsigned int bits, long long n,
-                                                        int32_t *list, unsigned long long *count) {
-    __shared__ unsigned int s_cnt[kBlock / 64];
-    __shared__ unsigned long long s_base;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += (long long)gridDim.x * kBlock) {
-        const long long v = base + threadIdx.x;
-        const bool in = v < n && (vmark[v] & bits) != 0u;
-        const unsigned long long m = __ballot(in);
-        if (lane == 0) s_cnt[wave] = (unsigned int)__popcll(m);
-        __syncthreads();
-        unsigned int before = 0, total = 0;
-        for (int i = 0; i < kBlock / 64; ++i) {
-            if (i < wave) before += s_cnt[i];
-            total += s_cnt[i];
-        }
-        if (threadIdx.x == 0 && total) s_base = atomicAdd(count, (unsigned long long)total);
-        __syncthreads();
-        if (in) list[s_base + before + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)v;
-        __syncthreads();
-    }
-}
+// neighbours' links back to E.  The removal kernels list E as they mark it.
+// The row tiles and hub chunks that hold changed rows or affected hubs are
+// rerun whole, with the block indices of the full launch, and the affected
+// tile vertices are rescored in units built for the pass; every result and
+// every partial is what a full pass would give.
 
 // Compact the listed changed rows (removed entries are complemented, < 0):
 // one wavefront per row, 64 entries at a time (ballot and prefix); the freed
@@ -3245,12 +3224,19 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_
         const long long rb = (long long)off[v];
         const int d = deg[v];
         int w = 0;
-        for (int j0 = 0; j0 < d; j0 += 64) {
-            const int j = j0 + lane;
-            const int x = j < d ? col[rb + j] : -1;
-            const unsigned long long m = __ballot(x >= 0);
-            if (x >= 0) col[rb + w + __popcll(m & ((1ull << lane) - 1ull))] = x;
-            w += __popcll(m);
+        for (int j0 = 0; j0 < d; j0 += 256) {  // four groups of 64 entries loaded at once
+            int x[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = j0 + 64 * t + lane;
+                x[t] = j < d ? col[rb + j] : -1;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const unsigned long long m = __ballot(x[t] >= 0);
+                if (x[t] >= 0) col[rb + w + __popcll(m & ((1ull << lane) - 1ull))] = x[t];
+                w += __popcll(m);
+            }
         }
         for (int j = w + lane; j < d; j += 64) col[rb + j] = -1;
         if (lane == 0) deg[v] = w;
@@ -3282,91 +3268,200 @@ __global__ __launch_bounds__(kBlock) void k_row_chunks(const int32_t *deg, const
     }
 }
 
-// A changed vertex x: x and its foreign neighbours are affected (the
-// neighbours are also marked kNearChanged).  One wavefront per row chunk.
+// After removals, one wavefront per chunk of 64 entries of a changed
+// (compacted) row v (chunks: k_row_chunks), for each entry (v, w):
+// * marks: v is affected, w is near a change, and affected if foreign; for a
+//   foreign w, the members of C(v) in w's row (an id range, found by binary
+//   search) are affected;
+// * links (foreign w): v's link for the entry (the reverse entry and w's
+//   out-list), and the index of the entry (v, w), which moved with v's row,
+//   in w's link back to v.
+// Only the kRowChanged bits, set by the removals before, are read.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_mark_nbrs(const OffT *off, const int32_t *deg, const int32_t *col,
-                                                      const int32_t *lab, unsigned int *vmark, const int32_t *list,
+__global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned int *vmark, const int32_t *rows,
                                                       const int2 *chunks, const unsigned long long *n_chunks) {
     const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
-    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
-         q += ((long long)gridDim.x * kBlock) >> 6) {
-        const int2 it = chunks[q];
-        const int x = list[it.x];
-        if (it.y == 0 && lane == 0) atomicOr(&vmark[x], kAffected);
-        const int j = it.y * 64 + lane;
-        if (j >= deg[x]) continue;
-        const int cx = lab[x];
-        const int y = col[(long long)off[x] + j];
-        atomicOr(&vmark[y], lab[y] != cx ? (kNearChanged | kAffected) : kNearChanged);
-    }
-}
-
-// A changed vertex v and each foreign neighbour w: the members of C(v) in w's
-// row (an id range, found by binary search) are affected.  One wavefront per
-// row chunk of v.
-template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_mark_runs(const OffT *off, const int32_t *deg, const int32_t *col,
-                                                      const int32_t *lab, const int32_t *cstart, unsigned int *vmark,
-                                                      const int32_t *list, const int2 *chunks,
-                                                      const unsigned long long *n_chunks) {
-    const long long nc = (long long)*n_chunks;
-    const int lane = threadIdx.x & 63;
-    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
-         q += ((long long)gridDim.x * kBlock) >> 6) {
-        const int2 it = chunks[q];
-        const int v = list[it.x];
-        const int j = it.y * 64 + lane;
-        if (j >= deg[v]) continue;
-        const int c = lab[v];
-        const int w = col[(long long)off[v] + j];
-        if (lab[w] == c) continue;
-        const int id0 = cstart[c], id1 = cstart[c + 1];
-        const int32_t *row = col + off[w];
-        const int dw = deg[w];
-        int a = 0, b = dw;
-        while (a < b) {
-            const int mid = (a + b) >> 1;
-            if (row[mid] < id0)
-                a = mid + 1;
+    // first position in a row holding an id >= key
+    auto lower = [&](const int32_t *row, int d, int key) {
+        int l = 0, h = d;
+        while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (row[mid] < key)
+                l = mid + 1;
             else
-                b = mid;
+                h = mid;
         }
-        for (int t = a; t < dw && row[t] < id1; ++t) atomicOr(&vmark[row[t]], kAffected);
+        return l;
+    };
+    for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
+         q += ((long long)gridDim.x * kBlock) >> 6) {
+        const int2 it = chunks[q];
+        const int v = rows[it.x];
+        if (it.y == 0 && lane == 0) atomicOr(&vmark[v], kAffected);
+        const long long rb = (long long)L.off[v];
+        const int dv = L.deg[v];
+        const int j = it.y * 64 + lane;
+        if (j >= dv) continue;
+        const int cv = L.lab[v];
+        const int w = L.col[rb + j];
+        const int cw = L.lab[w];
+        if (cw == cv) {
+            atomicOr(&vmark[w], kNearChanged);
+            continue;
+        }
+        atomicOr(&vmark[w], kNearChanged | kAffected);
+        const long long wb = (long long)L.off[w];
+        const int dw = L.deg[w];
+        const int32_t *roww = L.col + wb;
+        const int id0 = L.cstart[cv], id1 = L.cstart[cv + 1];
+        for (int t = lower(roww, dw, id0); t < dw && roww[t] < id1; ++t) atomicOr(&vmark[roww[t]], kAffected);
+        // v's own run [pv, qv) in its compacted row, and the entry (w, v)
+        const int pv = lower(L.col + rb, dv, id0);
+        const int qv = lower(L.col + rb, dv, id1);
+        const int ew = lower(roww, dw, v);
+        PairLink pl;
+        pl.e = wb + ew;
+        pl.oo = (int)L.oo[w];
+        pl.on = (int)(L.oo[w + 1] - L.oo[w]);
+        L.plink[L.goff[v] + (j < pv ? j : j - (qv - pv))] = pl;
+        // w's own run is its card's when w's row did not change
+        int pw, qw;
+        if (L.vmark[w] & kRowChanged) {
+            pw = lower(roww, dw, L.cstart[cw]);
+            qw = lower(roww, dw, L.cstart[cw + 1]);
+        } else {
+            const VMeta m = L.card[w].m;
+            pw = m.p;
+            qw = m.q;
+        }
+        L.plink[L.goff[w] + (ew < pw ? ew : ew - (qw - pw))].e = rb + j;
     }
 }
 
-// Marks -> units: a changed row flags its row block; an affected vertex its
-// score tile block or all chunks of its score hub.  Counts the affected
-// vertices, clears the marks and keeps w_max before the pass.
-__global__ __launch_bounds__(kBlock) void k_units(unsigned int *vmark, const int32_t *vrowb, const int32_t *vscore,
-                                                  long long n, uint8_t *rflag, uint8_t *sflag, uint8_t *hflag,
-                                                  unsigned long long *ictr, const DevCounters *ctr) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ictr[kIcWmaxOld] = ctr->wmax_bits;
-    unsigned long long aff = 0;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += (long long)gridDim.x * kBlock) {
+// Marks -> units: a changed row flags its row block; an affected hub flags
+// all chunks of its score hub; an affected tile vertex is placed in abin,
+// grouped by the bin of its load-time foreign degree (units of rescored
+// vertices are built per pass, so scattered affected vertices do not rerun
+// whole tiles).  Three steps over contiguous vertex ranges, one range per
+// workgroup, so that no counter in global memory is shared: count per range
+// and bin (LDS atomics), an exclusive scan of the counts bin after bin (one
+// workgroup), and placement at the scanned offsets.  The scan also counts the
+// affected vertices and keeps w_max before the pass; placement clears the
+// marks.
+__device__ __forceinline__ int score_bin(long long fgn) {
+    int b = 0;
+    while (b < kScoreBins - 1 && (1ll << b) < fgn) ++b;
+    return b;
+}
+
+__device__ __forceinline__ void unit_range(long long n, long long &lo, long long &hi) {
+    const long long per = ((n + gridDim.x - 1) / gridDim.x + 63) & ~63ll;
+    lo = min(n, (long long)blockIdx.x * per);
+    hi = min(n, lo + per);
+}
+
+// ucnt[r * gridDim.x + range]: rows 0..kScoreBins-1 tile vertices per bin,
+// row kScoreBins affected vertices.
+__global__ __launch_bounds__(kBlock) void k_units_count(const unsigned int *vmark, const int32_t *vrowb,
+                                                        const int32_t *vscore, const int64_t *goff, long long n,
+                                                        uint8_t *rflag, uint8_t *hflag, int32_t *ucnt) {
+    __shared__ int s_cnt[kUnitRows];
+    if (threadIdx.x < kUnitRows) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    long long lo, hi;
+    unit_range(n, lo, hi);
+    int aff = 0;
+    for (long long v = lo + threadIdx.x; v < hi; v += kBlock) {
         const unsigned int m = vmark[v];
         if (!m) continue;
-        vmark[v] = 0u;
         if (m & kRowChanged) rflag[vrowb[v]] = 1;
         if (m & kAffected) {
             ++aff;
             const int sc = vscore[v];
             if (sc >= 0)
-                sflag[sc] = 1;
+                atomicAdd(&s_cnt[score_bin(goff[v + 1] - goff[v])], 1);
             else
                 hflag[-1 - sc] = 1;
         }
     }
-    __shared__ unsigned long long s_aff[kBlock / 64];
-    for (int o = 32; o > 0; o >>= 1) aff += __shfl_xor(aff, o);
-    if ((threadIdx.x & 63) == 0) s_aff[threadIdx.x >> 6] = aff;
+    if (aff) atomicAdd(&s_cnt[kScoreBins], aff);
     __syncthreads();
+    if (threadIdx.x < kUnitRows) ucnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// One workgroup: each bin's per-range counts become the ranges' first slots
+// in abin (bins in order); bin totals, the listed total and the affected
+// count go to the counters.  Thread t holds ranges 4t..4t+3 of every row
+// (all loads issued at once), and one block scan serves all bins.
+static_assert(kUnitGroups == 4 * kBlock, "k_units_scan holds four ranges per thread");
+__global__ __launch_bounds__(kBlock) void k_units_scan(int32_t *ucnt, int groups, unsigned long long *ictr,
+                                                       const DevCounters *ctr) {
+    __shared__ int ws[kUnitRows][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j0 = 4 * threadIdx.x;
+    int x[kUnitRows][4], incl[kUnitRows];
+#pragma unroll
+    for (int r = 0; r < kUnitRows; ++r) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[r][i] = j0 + i < groups ? ucnt[r * groups + j0 + i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kUnitRows; ++r) {
+        int t = x[r][0] + x[r][1] + x[r][2] + x[r][3];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(t, o);
+            if (lane >= o) t += y;
+        }
+        incl[r] = t;
+        if (lane == 63) ws[r][wave] = t;
+    }
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int r = 0; r < kScoreBins; ++r) {
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wave) before += ws[r][w];
+            total += ws[r][w];
+        }
+        int pos = base + before + incl[r] - (x[r][0] + x[r][1] + x[r][2] + x[r][3]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (j0 + i < groups) ucnt[r * groups + j0 + i] = pos;
+            pos += x[r][i];
+        }
+        if (threadIdx.x == 0) ictr[kIcBins + r] = (unsigned long long)total;
+        base += total;
+    }
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < kBlock / 64; ++i) t += s_aff[i];
-        if (t) atomicAdd(&ictr[kIcAffected], t);
+        long long aff = 0;
+        for (int w = 0; w < kBlock / 64; ++w) aff += ws[kScoreBins][w];
+        ictr[kIcAffected] = (unsigned long long)aff;
+        ictr[kIcAList] = (unsigned long long)base;
+        ictr[kIcWmaxOld] = ctr->wmax_bits;
+    }
+}
+
+// Each range's affected tile vertices to their bins' slots (any order inside
+// a range and bin; a vertex's score does not depend on its unit); the marks
+// are cleared.
+__global__ __launch_bounds__(kBlock) void k_units_place(unsigned int *vmark, const int32_t *vscore,
+                                                        const int64_t *goff, long long n, const int32_t *ucnt,
+                                                        int32_t *abin) {
+    __shared__ int s_cur[kScoreBins];
+    if (threadIdx.x < kScoreBins) s_cur[threadIdx.x] = ucnt[threadIdx.x * gridDim.x + blockIdx.x];
+    __syncthreads();
+    long long lo, hi;
+    unit_range(n, lo, hi);
+    for (long long v = lo + threadIdx.x; v < hi; v += kBlock) {
+        const unsigned int m = vmark[v];
+        if (!m) continue;
+        vmark[v] = 0u;
+        if ((m & kAffected) && vscore[v] >= 0)
+            abin[atomicAdd(&s_cur[score_bin(goff[v + 1] - goff[v])], 1)] = (int32_t)v;
     }
 }
 
@@ -3404,21 +3499,18 @@ static rs_status incremental_marks_t(rs_graph *g) {
     if (D.n == 0) return RS_OK;
     const OffT *off = (const OffT *)D.off;
     const int gn = grid_for(D.n, kBlock, 1024);
-    hipLaunchKernelGGL(k_list_marked, dim3(gn), dim3(kBlock), 0, g->stream, D.vmark, kRowChanged, (long long)D.n,
-                       D.elist, &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_compact_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.elist,
                        &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_row_chunks, dim3(gn), dim3(kBlock), 0, g->stream, D.deg, D.elist, &D.ictr[kIcChanged],
                        D.echunk, &D.ictr[kIcChunks]);
-    hipLaunchKernelGGL(k_mark_nbrs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.vmark,
+    hipLaunchKernelGGL(k_mark_link<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.vmark,
                        D.elist, D.echunk, &D.ictr[kIcChunks]);
-    hipLaunchKernelGGL(k_mark_runs<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.lab, D.cstart,
-                       D.vmark, D.elist, D.echunk, &D.ictr[kIcChunks]);
-    hipLaunchKernelGGL(k_links_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.elist,
-                       D.echunk, &D.ictr[kIcChunks]);
-    hipLaunchKernelGGL(k_units, dim3(grid_for(D.n, kBlock, 1024)), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb,
-                       D.vscore, (long long)D.n,
-                       D.rflag, D.sflag, D.hflag, D.ictr, D.ctr);
+    const int ug = grid_for(D.n, kBlock, kUnitGroups);
+    hipLaunchKernelGGL(k_units_count, dim3(ug), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb, D.vscore, D.goff,
+                       (long long)D.n, D.rflag, D.hflag, D.ucnt);
+    hipLaunchKernelGGL(k_units_scan, dim3(1), dim3(kBlock), 0, g->stream, D.ucnt, ug, D.ictr, D.ctr);
+    hipLaunchKernelGGL(k_units_place, dim3(ug), dim3(kBlock), 0, g->stream, D.vmark, D.vscore, D.goff,
+                       (long long)D.n, D.ucnt, D.abin);
     const int n_big = g->n_schunks - g->n_schunks_lds;
     const int n_main = g->grid_score - n_big;
     const int top = std::max(g->grid_rows, std::max(n_main, g->n_shubs));

@@ -433,7 +433,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
                             (void **)&D.shub_first, (void **)&D.shub_chunk, (void **)&D.hub_part,
                             (void **)&D.rflag, (void **)&D.sflag, (void **)&D.hflag, (void **)&D.rlist,
                             (void **)&D.slist, (void **)&D.hlist, (void **)&D.part_rows, (void **)&D.wmax_part,
-                            (void **)&D.part_score, (void **)&D.vrowb, (void **)&D.vscore};
+                            (void **)&D.vrowb, (void **)&D.vscore};
     for (void **p : tile_arrays) dev_free(g, p);
     const size_t N = (size_t)std::max<int64_t>(D.n, 1);
     g->n_rtiles = (int)H.rtiles.size();
@@ -467,7 +467,6 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
         {(void **)&D.hlist, 4 * nch},
         {(void **)&D.part_rows, sizeof(RowPart) * gr},
         {(void **)&D.wmax_part, 8 * gr},
-        {(void **)&D.part_score, sizeof(ScorePart) * gs},
         {(void **)&D.vrowb, 4 * N},
         {(void **)&D.vscore, 4 * N},
     };
@@ -491,7 +490,6 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
     if (e == hipSuccess) e = hipMemsetAsync(D.rflag, 0, gr, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.sflag, 0, gs, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.hflag, 0, nsh, s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.part_score, 0, sizeof(ScorePart) * gs, s);
     return e == hipSuccess ? RS_OK : hip_fail(e, "schedule upload");
 }
 
@@ -522,7 +520,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.raw, 8 * N},
         {(void **)&D.vmark, 4 * N},
         {(void **)&D.elist, 4 * N},
-        {(void **)&D.llist, 4 * N},
+        {(void **)&D.ucnt, 4 * (size_t)kUnitRows * kUnitGroups},
+        {(void **)&D.abin, 4 * N},
         {(void **)&D.echunk, sizeof(int2) * (N + Z / 64 + 1)},
         {(void **)&D.ictr, 8 * (size_t)kIcCount},
         {(void **)&g->rem_cnt, 8 * 4},
@@ -531,6 +530,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.recdat, sizeof(RecDat) * Z},
         {(void **)&D.card, sizeof(VCard) * N},
         {(void **)&D.wown, 8 * N},
+        {(void **)&D.av, 8 * N},
         {(void **)&D.R, 8 * N},
         {(void **)&D.tI, 8 * N},
         {(void **)&D.tII, 8 * N},
@@ -1141,9 +1141,12 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
     if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
     if (st == RS_OK) st = launch_incremental_marks(g);
-    unsigned long long *ic = g->rem_cnt_host + 4;
+    // one round trip: the removal counts (final once the removal kernels
+    // ran) and the unit counts, which size the launches below
+    unsigned long long *cnt = g->rem_cnt_host, *ic = g->rem_cnt_host + 4;
     if (st == RS_OK) {
-        e = hipMemcpyAsync(ic, g->d.ictr, 8 * (size_t)kIcCount, hipMemcpyDeviceToHost, g->stream);
+        e = hipMemcpyAsync(cnt, d_cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(ic, g->d.ictr, 8 * (size_t)kIcCount, hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = hip_fail(e, "incremental counts");
     }
@@ -1151,7 +1154,8 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
         // Rerun the listed units, or, when they are a large share of the
         // pass (a removed hub touches much of the graph), the whole pass:
         // its bits are the same, and full launches run faster per unit.
-        const int64_t n_units = (int64_t)ic[kIcRows] + (int64_t)ic[kIcMain] + (int64_t)ic[kIcBig];
+        int64_t n_units = (int64_t)ic[kIcRows] + (int64_t)ic[kIcMain] + (int64_t)ic[kIcBig];
+        for (int b = 0; b < kScoreBins; ++b) n_units += ((int64_t)ic[kIcBins + b] + (256 >> b) - 1) / (256 >> b);
         if (10 * n_units > kFullPassTenths * ((int64_t)g->grid_rows + (int64_t)g->grid_score)) {
             st = launch_score_pass(g);
         } else {
@@ -1163,15 +1167,11 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
             L.big = g->d.hlist;
             L.n_big = (int)ic[kIcBig];
             L.wmax_old = &g->d.ictr[kIcWmaxOld];
+            for (int b = 0; b < kScoreBins; ++b) L.bin_count[b] = (long long)ic[kIcBins + b];
             st = launch_score_lists(g, L);
         }
     }
-    unsigned long long *cnt = g->rem_cnt_host;
-    if (st == RS_OK) {
-        e = hipMemcpyAsync(cnt, d_cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-        if (e != hipSuccess) st = hip_fail(e, "removal result");
-    }
+    // the re-score stays queued on the graph's stream (as rs_score's pass)
     if (st != RS_OK) return st;
     g->n_alive -= (int64_t)cnt[3];
     if (res) {
