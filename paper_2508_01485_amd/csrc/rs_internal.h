@@ -340,6 +340,7 @@ struct rs_graph {
     int64_t rem_host_cap = 0;
     unsigned long long *rem_cnt = nullptr;       // device [4]: edges removed, -, edges of removed vertices, vertices
     unsigned long long *rem_cnt_host = nullptr;  // pinned [4 + kIcCount]
+    hipEvent_t rem_ev = nullptr;                 // the removal counts have reached rem_cnt_host
 };
 
 namespace rs {
@@ -355,20 +356,13 @@ void timing_end(rs_graph *g, int kid, hipEvent_t ev);
 
 // Kernel launchers (rs_kernels.hip).  All enqueue on g->stream.
 rs_status launch_score_pass(rs_graph *g);
-// An incremental pass: the row blocks, the main score blocks and the big-hub
-// chunks to rerun (indices of the full launches), then w_max from every
-// block's partial and, if it moved from *wmax_old, every score rescaled.
-struct PassLists {
-    const int *rows;
-    int n_rows;
-    const int *main;
-    int n_main;
-    const int *big;
-    int n_big;
-    const unsigned long long *wmax_old;
-    long long bin_count[kScoreBins];  // affected tile vertices of each bin (in abin, bin after bin)
-};
-rs_status launch_score_lists(rs_graph *g, const PassLists &inc);
+// An incremental pass after launch_incremental_marks, sized on the device:
+// the row blocks, main score blocks and big-hub chunks listed by the marks
+// (indices of the full launches; every index when the units exceed
+// kFullPassTenths of the full pass) and the units of the affected tile
+// vertices, then w_max from every block's partial and, if it moved, every
+// score rescaled.  No host round trip.
+rs_status launch_score_incremental(rs_graph *g);
 rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int64_t *count);
 // Read the timing events of completed replays into the timing totals.
 void drain_replays(rs_graph *g);

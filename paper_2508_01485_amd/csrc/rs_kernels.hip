@@ -109,7 +109,7 @@ struct RowArgs {
     VCard *card;
     const int64_t *goff;
     PairRec *prec;     // pair facts at the foreign row entries, written by this pass
-    const int *blist;  // incremental pass: the blocks to run (else every block)
+    const int *blist;  // incremental pass: the listed blocks (k_rows_inc)
     double *wown, *R, *raw;
     double *av;  // [n] a_v = cbrt(own-community weight), dense for the score pass's run sums
     long long *tI, *tII;
@@ -674,7 +674,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
     __shared__ RowTileShared S;
     RowAcc acc = {0.0, 0, 0, 0, 0};
-    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
+    const int b = (int)blockIdx.x;
     if (b < A.n_hubs) {
         hub_row(A, S, A.hubs[b], acc);
     } else {
@@ -682,6 +682,42 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs<OffT> A) {
         if (t < A.n_tiles) row_tile(A, S, t, acc);
     }
     block_reduce_row(acc, &A.part[b], &A.wmax_part[b]);
+}
+
+// Whether an incremental pass runs every block of the full launches: its
+// units (listed row blocks, main score blocks and big-hub chunks, and the
+// units of the affected tile vertices) exceed kFullPassTenths of the full
+// pass's workgroups (a removed hub touches much of the graph; full launches
+// run faster per unit, and the bits are the same).  Every kernel of the
+// pass decides alike from the marks' counters.
+__device__ __forceinline__ bool inc_full(const unsigned long long *ictr, int grid_rows, int grid_score) {
+    long long u = (long long)ictr[kIcRows] + (long long)ictr[kIcMain] + (long long)ictr[kIcBig];
+#pragma unroll
+    for (int b = 0; b < kScoreBins; ++b) u += ((long long)ictr[kIcBins + b] + (kBlock >> b) - 1) / (kBlock >> b);
+    return 10 * u > (long long)kFullPassTenths * ((long long)grid_rows + grid_score);
+}
+
+// The incremental pass's row blocks: block i of a capped grid takes the
+// listed blocks i, i + gridDim.x, ... (every block of the full launch in a
+// full pass), each exactly as k_rows runs it.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_rows_inc(RowArgs<OffT> A, const unsigned long long *ictr, int grid_rows,
+                                                     int grid_score) {
+    __shared__ RowTileShared S;
+    const bool full = inc_full(ictr, grid_rows, grid_score);
+    const long long cnt = full ? (long long)grid_rows : (long long)ictr[kIcRows];
+    for (long long i = blockIdx.x; i < cnt; i += gridDim.x) {
+        RowAcc acc = {0.0, 0, 0, 0, 0};
+        const int b = full ? (int)i : A.blist[i];
+        if (b < A.n_hubs) {
+            hub_row(A, S, A.hubs[b], acc);
+        } else {
+            const int t = tile_of_block(b, A.n_hubs, A.tiles_per_xcd);
+            if (t < A.n_tiles) row_tile(A, S, t, acc);
+        }
+        block_reduce_row(acc, &A.part[b], &A.wmax_part[b]);
+        __syncthreads();  // the next block's LDS
+    }
 }
 
 // w_max of a pass from the dense per-block maxima of the row kernel (one
@@ -751,7 +787,7 @@ struct ScoreArgs {
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
     const double *av;       // [n] a_v of the row pass
-    const int *blist;       // incremental pass: the blocks to run (else every block)
+    const int *blist;       // unused by the score kernels (the incremental lists are arguments)
     const unsigned long long *gwmax;  // batched graphs: w_max bits of each graph, else null
     const int32_t *vgraph;            // batched graphs: graph of each vertex
     double *R, *raw;
@@ -1357,7 +1393,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
     __shared__ ScoreUnitShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
+    const int b = (int)blockIdx.x;
     const bool hub_unit = b < A.n_chunks_lds;
     const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
     if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax);
@@ -1369,31 +1405,69 @@ template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
     __shared__ ScoreHubBigShared S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    const int b = A.blist ? A.blist[blockIdx.x] : (int)blockIdx.x;
+    const int b = (int)blockIdx.x;
     const int2 hc = A.hub_chunk[A.n_chunks_lds + b];
     score_hub_big(A, S, hc.x, hc.y, wmax);
 }
 
-// The incremental pass's rescored tile vertices: units of one bin's listed
-// vertices (256 >> b of bin b per workgroup, so at most 256 pairs).  Their
-// values are those of their tiles in a full pass (a vertex's sum does not
-// depend on its unit's other vertices).
-struct DynUnits {
-    int ufirst[kScoreBins + 1];        // first workgroup of each bin's units
-    long long off[kScoreBins];         // first listed vertex of each bin
-    long long cnt[kScoreBins];         // listed vertices of each bin
-};
-
+// The incremental pass's score work in one launch (the parts are
+// independent and overlap): block i of a capped grid takes the work items
+// i, i + gridDim.x, ... of one queue,
+//   1. the listed big-hub chunks (all of them in a full pass),
+//   2. the listed main blocks, LDS-hub chunks and tiles (all in a full pass),
+//   3. the units of the affected tile vertices, largest bin first: 256 >> b
+//      listed vertices of bin b per unit, so at most 256 pairs (none in a
+//      full pass, whose tiles run whole).
+// Every item runs as in the full launches; a unit's values are those of its
+// vertices' tiles (a vertex's sum does not depend on the unit's others).
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_score_dyn(ScoreArgs<OffT> A, const int32_t *abin, DynUnits U) {
-    __shared__ ScoreUnitShared S;
+__global__ __launch_bounds__(kBlock) void k_score_inc(ScoreArgs<OffT> A, const int32_t *big, const int32_t *main_,
+                                                      const int32_t *abin, const unsigned long long *ictr,
+                                                      int grid_rows, int grid_score, int grid_main) {
+    __shared__ union {
+        ScoreUnitShared u;
+        ScoreHubBigShared h;
+    } S;
     const double wmax = bitsd(A.ctr->wmax_bits);
-    int b = 0;
-    while (b < kScoreBins - 1 && (int)blockIdx.x >= U.ufirst[b + 1]) ++b;
-    const int vpu = kBlock >> b;
-    const long long start = U.off[b] + (long long)((int)blockIdx.x - U.ufirst[b]) * vpu;
-    const int nv = (int)min((long long)vpu, U.off[b] + U.cnt[b] - start);
-    score_unit(A, S, false, -1, wmax, abin + start, nv);
+    const bool full = inc_full(ictr, grid_rows, grid_score);
+    const long long n_big = full ? (long long)(A.n_chunks - A.n_chunks_lds) : (long long)ictr[kIcBig];
+    const long long n_main = full ? (long long)grid_main : (long long)ictr[kIcMain];
+    // units of bin b: ufirst[b] after the bins above b
+    long long ufirst[kScoreBins], voff[kScoreBins], vcnt[kScoreBins], n_units = 0, off = 0;
+#pragma unroll
+    for (int b = 0; b < kScoreBins; ++b) {
+        vcnt[b] = full ? 0 : (long long)ictr[kIcBins + b];
+        voff[b] = off;
+        off += vcnt[b];
+    }
+#pragma unroll
+    for (int b = kScoreBins - 1; b >= 0; --b) {
+        ufirst[b] = n_units;
+        n_units += (vcnt[b] + (kBlock >> b) - 1) / (kBlock >> b);
+    }
+    const long long total = n_big + n_main + n_units;
+    for (long long i = blockIdx.x; i < total; i += gridDim.x) {
+        if (i < n_big) {
+            const int c = full ? (int)i : big[i];
+            const int2 hc = A.hub_chunk[A.n_chunks_lds + c];
+            score_hub_big(A, S.h, hc.x, hc.y, wmax);
+        } else if (i < n_big + n_main) {
+            const long long j = i - n_big;
+            const int bl = full ? (int)j : main_[j];
+            const bool hub_unit = bl < A.n_chunks_lds;
+            const int idx = hub_unit ? bl : tile_of_block(bl, A.n_chunks_lds, A.tiles_per_xcd);
+            if (hub_unit || idx < A.n_tiles) score_unit(A, S.u, hub_unit, idx, wmax);
+        } else {
+            const long long u = i - n_big - n_main;
+            int b = 0;  // units of bin b are [ufirst[b], ufirst[b - 1]); ufirst[kScoreBins - 1] = 0
+            while (ufirst[b] > u) ++b;
+            const int vpu = kBlock >> b;
+            const long long start = voff[b] + (u - ufirst[b]) * vpu;
+            const int nv = (int)min((long long)vpu, voff[b] + vcnt[b] - start);
+            score_unit(A, S.u, false, -1, wmax, abin + start, nv);
+        }
+        __syncthreads();  // the next item's LDS
+    }
 }
 
 // Each hub's score from its chunk partials (one wavefront per hub: lane l
@@ -1518,6 +1592,45 @@ __global__ __launch_bounds__(kBlock) void k_reduce_work(const unsigned long long
 // foreign entries (x's row without its own-community id range).  Rows are
 // sorted, so positions are binary searches.  Run at load and after removals
 // (compaction shifts rows).
+// Lower bounds (first position holding an id >= key) of N keys, key i in the
+// sorted row row[i][0, d[i]), found together: binary searches in lockstep,
+// each step one independent load per key still searching.  DEC: removed
+// entries (complemented in place, the row still ordered on the original
+// ids) compare by their id.
+template <int N, bool DEC>
+__device__ __forceinline__ void lower_n(const int32_t *const *row, const int *d, const int *key, int *pos) {
+    int lo[N], hi[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        lo[i] = 0;
+        hi[i] = d[i];
+    }
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int i = 0; i < N; ++i) more |= lo[i] < hi[i];
+        if (!more) break;
+        int mid[N], y[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            mid[i] = (lo[i] + hi[i]) >> 1;
+            y[i] = lo[i] < hi[i] ? row[i][mid[i]] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            if (lo[i] < hi[i]) {
+                const int yi = DEC && y[i] < 0 ? ~y[i] : y[i];
+                if (yi < key[i])
+                    lo[i] = mid[i] + 1;
+                else
+                    hi[i] = mid[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) pos[i] = lo[i];
+}
+
 template <typename OffT>
 struct LinkArgs {
     const OffT *off;
@@ -1702,8 +1815,12 @@ static rs_status replay(rs_graph *g, Replay &R, long long key, F enqueue) {
 }
 
 // ------------------------------------------------------------ pass launcher
+// Workgroups of an incremental pass's launches (each loops over its list):
+// enough to fill the chip, few enough that an empty list costs little.
+constexpr int kIncGrid = 2048;
+
 template <typename OffT>
-static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
+static rs_status score_pass_t(rs_graph *g, bool inc) {
     DeviceGraph &D = g->d;
     hipEvent_t ev;
     RowArgs<OffT> A;
@@ -1721,7 +1838,7 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     A.card = D.card;
     A.goff = D.goff;
     A.prec = D.prec;
-    A.blist = inc ? inc->rows : nullptr;
+    A.blist = inc ? D.rlist : nullptr;
     A.wown = D.wown;
     A.av = D.av;
     A.R = D.R;
@@ -1730,10 +1847,16 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     A.tII = D.tII;
     A.part = D.part_rows;
     A.wmax_part = D.wmax_part;
-    const int grid_rows = inc ? inc->n_rows : g->grid_rows;
-    if (grid_rows > 0) {
+    const int n_big = g->n_schunks - g->n_schunks_lds;
+    const int grid_main = g->grid_score - n_big;
+    if (inc) {
         timing_begin(g, K_ROWS, &ev);
-        hipLaunchKernelGGL(k_rows<OffT>, dim3(grid_rows), dim3(kBlock), 0, g->stream, A);
+        hipLaunchKernelGGL(k_rows_inc<OffT>, dim3(std::max(1, std::min(g->grid_rows, kIncGrid))), dim3(kBlock), 0,
+                           g->stream, A, (const unsigned long long *)D.ictr, g->grid_rows, g->grid_score);
+        timing_end(g, K_ROWS, ev);
+    } else if (g->grid_rows > 0) {
+        timing_begin(g, K_ROWS, &ev);
+        hipLaunchKernelGGL(k_rows<OffT>, dim3(g->grid_rows), dim3(kBlock), 0, g->stream, A);
         timing_end(g, K_ROWS, ev);
     }
     timing_begin(g, K_WMAX, &ev);
@@ -1775,36 +1898,25 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
     S.tI = D.tI;
     S.tII = D.tII;
     S.ctr = D.ctr;
-    const int n_big = g->n_schunks - g->n_schunks_lds;
-    const int grid_main = g->grid_score - n_big;
-    const int run_big = inc ? inc->n_big : n_big, run_main = inc ? inc->n_main : grid_main;
-    if (run_big > 0) {
-        S.blist = inc ? inc->big : nullptr;
-        timing_begin(g, K_SCORE_HUB, &ev);
-        hipLaunchKernelGGL(k_score_hub<OffT>, dim3(run_big), dim3(kBlock), 0, g->stream, S);
-        timing_end(g, K_SCORE_HUB, ev);
-    }
-    if (run_main > 0) {
-        S.blist = inc ? inc->main : nullptr;
+    const unsigned long long *ictr = D.ictr;
+    if (inc) {
+        S.blist = nullptr;
         timing_begin(g, K_SCORE, &ev);
-        hipLaunchKernelGGL(k_score<OffT>, dim3(run_main), dim3(kBlock), 0, g->stream, S);
+        hipLaunchKernelGGL(k_score_inc<OffT>, dim3(kIncGrid), dim3(kBlock), 0, g->stream, S, (const int32_t *)D.hlist,
+                           (const int32_t *)D.slist, (const int32_t *)D.abin, ictr, g->grid_rows, g->grid_score,
+                           grid_main);
         timing_end(g, K_SCORE, ev);
-    }
-    if (inc) {  // the rescored tile vertices, in units built for this pass
-        DynUnits U;
-        long long off = 0;
-        U.ufirst[0] = 0;
-        for (int b = 0; b < kScoreBins; ++b) {
-            U.off[b] = off;
-            U.cnt[b] = inc->bin_count[b];
-            off += inc->bin_count[b];
-            U.ufirst[b + 1] = U.ufirst[b] + (int)((inc->bin_count[b] + (kBlock >> b) - 1) / (kBlock >> b));
+    } else {
+        if (n_big > 0) {
+            S.blist = nullptr;
+            timing_begin(g, K_SCORE_HUB, &ev);
+            hipLaunchKernelGGL(k_score_hub<OffT>, dim3(n_big), dim3(kBlock), 0, g->stream, S);
+            timing_end(g, K_SCORE_HUB, ev);
         }
-        if (U.ufirst[kScoreBins] > 0) {
+        if (grid_main > 0) {
             S.blist = nullptr;
             timing_begin(g, K_SCORE, &ev);
-            hipLaunchKernelGGL(k_score_dyn<OffT>, dim3(U.ufirst[kScoreBins]), dim3(kBlock), 0, g->stream, S, D.abin,
-                               U);
+            hipLaunchKernelGGL(k_score<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
             timing_end(g, K_SCORE, ev);
         }
     }
@@ -1816,8 +1928,8 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
         timing_end(g, K_HUB_SUM, ev);
     }
     if (inc && D.n > 0)  // w_max moved: every score is rescaled from its raw sum
-        hipLaunchKernelGGL(k_rescale, dim3(grid_for(D.n, kBlock, 4096)), dim3(kBlock), 0, g->stream, inc->wmax_old,
-                           D.ctr, D.card, D.raw, D.R, (long long)D.n);
+        hipLaunchKernelGGL(k_rescale, dim3(grid_for(D.n, kBlock, 4096)), dim3(kBlock), 0, g->stream,
+                           (const unsigned long long *)&D.ictr[kIcWmaxOld], D.ctr, D.card, D.raw, D.R, (long long)D.n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "score pass launch");
     return RS_OK;
@@ -1825,12 +1937,12 @@ static rs_status score_pass_t(rs_graph *g, const PassLists *inc) {
 
 rs_status launch_score_pass(rs_graph *g) {
     return replay(g, g->pass_rep, 0, [g]() {
-        return g->d.off64 ? score_pass_t<long long>(g, nullptr) : score_pass_t<int32_t>(g, nullptr);
+        return g->d.off64 ? score_pass_t<long long>(g, false) : score_pass_t<int32_t>(g, false);
     });
 }
 
-rs_status launch_score_lists(rs_graph *g, const PassLists &inc) {
-    return g->d.off64 ? score_pass_t<long long>(g, &inc) : score_pass_t<int32_t>(g, &inc);
+rs_status launch_score_incremental(rs_graph *g) {
+    return g->d.off64 ? score_pass_t<long long>(g, true) : score_pass_t<int32_t>(g, true);
 }
 
 rs_status launch_reduce_counts(rs_graph *g) {
@@ -3032,22 +3144,6 @@ rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_s
 // every row ordered on the decoded value until the compaction below.
 __device__ __forceinline__ int decode(int x) { return x < 0 ? ~x : x; }
 
-template <typename OffT>
-__device__ __forceinline__ long long find_entry(const OffT *off, const int32_t *deg, const int32_t *col, int u, int v) {
-    long long lo = (long long)off[u], hi = lo + deg[u];
-    while (lo < hi) {
-        const long long mid = (lo + hi) >> 1;
-        const int x = decode(col[mid]);
-        if (x < v)
-            lo = mid + 1;
-        else if (x > v)
-            hi = mid;
-        else
-            return mid;
-    }
-    return -1;
-}
-
 // The out-lists that a removal must update, and the marks of the vertices
 // whose rows change (bit kRowChanged).
 struct OutLists {
@@ -3060,9 +3156,14 @@ struct OutLists {
 // Tombstone y in out(x), if there; returns whether it was found.  Only the
 // request that deleted the edge gets here, so the store does not race.
 __device__ __forceinline__ bool out_drop(const OutLists &O, int x, int y) {
-    const long long j = out_find(O.outl, O.oo[x], O.oo[x + 1], y);
-    if (j < 0) return false;
-    O.outl[j] = ~y;
+    const long long o0 = O.oo[x];
+    const int32_t *row[1] = {O.outl + o0};
+    const int d[1] = {(int)(O.oo[x + 1] - o0)};
+    const int key[1] = {y};
+    int k[1];
+    lower_n<1, true>(row, d, key, k);
+    if (k[0] >= d[0] || O.outl[o0 + k[0]] != y) return false;
+    O.outl[o0 + k[0]] = ~y;
     return true;
 }
 
@@ -3075,11 +3176,17 @@ template <typename OffT>
 __device__ __forceinline__ int delete_edge(const OffT *off, const int32_t *deg, int32_t *col, const OutLists &O,
                                            int a, int b, bool &nx, bool &ny) {
     const int x = min(a, b), y = max(a, b);
-    const long long e = find_entry(off, deg, col, x, y);
-    if (e < 0) return 0;
-    if (atomicCAS(&col[e], y, ~y) != y) return 0;
-    const long long f = find_entry(off, deg, col, y, x);
-    if (f >= 0) col[f] = ~x;
+    // y in x's row and x in y's row, searched together (entries keep their
+    // places until the compaction, so the second position stays valid)
+    const long long xb = (long long)off[x], yb = (long long)off[y];
+    const int32_t *rows[2] = {col + xb, col + yb};
+    const int ds[2] = {deg[x], deg[y]};
+    const int keys[2] = {y, x};
+    int k[2];
+    lower_n<2, true>(rows, ds, keys, k);
+    if (k[0] >= ds[0] || decode(col[xb + k[0]]) != y) return 0;
+    if (atomicCAS(&col[xb + k[0]], y, ~y) != y) return 0;
+    if (k[1] < ds[1] && decode(col[yb + k[1]]) == x) col[yb + k[1]] = ~x;
     nx = (atomicOr(&O.vmark[x], kRowChanged) & kRowChanged) == 0u;
     ny = (atomicOr(&O.vmark[y], kRowChanged) & kRowChanged) == 0u;
     if (O.lab[x] != O.lab[y] && !out_drop(O, x, y)) out_drop(O, y, x);
@@ -3282,18 +3389,6 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
                                                       const int2 *chunks, const unsigned long long *n_chunks) {
     const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
-    // first position in a row holding an id >= key
-    auto lower = [&](const int32_t *row, int d, int key) {
-        int l = 0, h = d;
-        while (l < h) {
-            const int mid = (l + h) >> 1;
-            if (row[mid] < key)
-                l = mid + 1;
-            else
-                h = mid;
-        }
-        return l;
-    };
     for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
          q += ((long long)gridDim.x * kBlock) >> 6) {
         const int2 it = chunks[q];
@@ -3315,11 +3410,15 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
         const int dw = L.deg[w];
         const int32_t *roww = L.col + wb;
         const int id0 = L.cstart[cv], id1 = L.cstart[cv + 1];
-        for (int t = lower(roww, dw, id0); t < dw && roww[t] < id1; ++t) atomicOr(&vmark[roww[t]], kAffected);
-        // v's own run [pv, qv) in its compacted row, and the entry (w, v)
-        const int pv = lower(L.col + rb, dv, id0);
-        const int qv = lower(L.col + rb, dv, id1);
-        const int ew = lower(roww, dw, v);
+        // in w's row: C(v)'s run [k[0], k[1]) and the entry (w, v) at k[2];
+        // in v's row: v's own run [k[3], k[4])
+        const int32_t *rws[5] = {roww, roww, roww, L.col + rb, L.col + rb};
+        const int ds[5] = {dw, dw, dw, dv, dv};
+        const int keys[5] = {id0, id1, v, id0, id1};
+        int k[5];
+        lower_n<5, false>(rws, ds, keys, k);
+        for (int t = k[0]; t < k[1]; ++t) atomicOr(&vmark[roww[t]], kAffected);
+        const int pv = k[3], qv = k[4], ew = k[2];
         PairLink pl;
         pl.e = wb + ew;
         pl.oo = (int)L.oo[w];
@@ -3328,8 +3427,13 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
         // w's own run is its card's when w's row did not change
         int pw, qw;
         if (L.vmark[w] & kRowChanged) {
-            pw = lower(roww, dw, L.cstart[cw]);
-            qw = lower(roww, dw, L.cstart[cw + 1]);
+            const int32_t *rw2[2] = {roww, roww};
+            const int dw2[2] = {dw, dw};
+            const int kw2[2] = {L.cstart[cw], L.cstart[cw + 1]};
+            int pq[2];
+            lower_n<2, false>(rw2, dw2, kw2, pq);
+            pw = pq[0];
+            qw = pq[1];
         } else {
             const VMeta m = L.card[w].m;
             pw = m.p;

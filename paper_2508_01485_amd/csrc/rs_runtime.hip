@@ -98,6 +98,8 @@ static void release(rs_graph *g) {
     if (g->rem_buf) (void)hipFree(g->rem_buf);
     if (g->rem_host) (void)hipHostFree(g->rem_host);
     if (g->rem_cnt_host) (void)hipHostFree(g->rem_cnt_host);
+    if (g->rem_ev) (void)hipEventDestroy(g->rem_ev);
+    g->rem_ev = nullptr;
     if (g->reach_hflag) (void)hipHostFree(g->reach_hflag);
     g->reach_hflag = nullptr;
     g->reach_comp = g->reach_src = nullptr;
@@ -556,6 +558,11 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         if (eh != hipSuccess) {
             g->rem_cnt_host = nullptr;
             return hip_fail(eh, "pinned counters");
+        }
+        const hipError_t ee = hipEventCreateWithFlags(&g->rem_ev, hipEventDisableTiming);
+        if (ee != hipSuccess) {
+            g->rem_ev = nullptr;
+            return hip_fail(ee, "removal event");
         }
     }
     std::vector<int32_t> off32, deg(n);
@@ -1141,35 +1148,20 @@ rs_status rs_apply_removals(rs_graph *g, const rs_removals *b, rs_removal_result
     if (st == RS_OK) st = launch_remove_edges(g, d_buf, d_buf + m, m, d_cnt);
     if (st == RS_OK) st = launch_remove_vertices(g, d_buf + 2 * m, nv, d_cnt + 2);
     if (st == RS_OK) st = launch_incremental_marks(g);
-    // one round trip: the removal counts (final once the removal kernels
-    // ran) and the unit counts, which size the launches below
+    // The counts reach pinned host memory behind an event, and the pass
+    // (sized on the device) is queued right after it: the host waits for the
+    // counts while the GPU goes on.
     unsigned long long *cnt = g->rem_cnt_host, *ic = g->rem_cnt_host + 4;
     if (st == RS_OK) {
         e = hipMemcpyAsync(cnt, d_cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(ic, g->d.ictr, 8 * (size_t)kIcCount, hipMemcpyDeviceToHost, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e == hipSuccess) e = hipEventRecord(g->rem_ev, g->stream);
         if (e != hipSuccess) st = hip_fail(e, "incremental counts");
     }
+    if (st == RS_OK) st = launch_score_incremental(g);
     if (st == RS_OK) {
-        // Rerun the listed units, or, when they are a large share of the
-        // pass (a removed hub touches much of the graph), the whole pass:
-        // its bits are the same, and full launches run faster per unit.
-        int64_t n_units = (int64_t)ic[kIcRows] + (int64_t)ic[kIcMain] + (int64_t)ic[kIcBig];
-        for (int b = 0; b < kScoreBins; ++b) n_units += ((int64_t)ic[kIcBins + b] + (256 >> b) - 1) / (256 >> b);
-        if (10 * n_units > kFullPassTenths * ((int64_t)g->grid_rows + (int64_t)g->grid_score)) {
-            st = launch_score_pass(g);
-        } else {
-            PassLists L;
-            L.rows = g->d.rlist;
-            L.n_rows = (int)ic[kIcRows];
-            L.main = g->d.slist;
-            L.n_main = (int)ic[kIcMain];
-            L.big = g->d.hlist;
-            L.n_big = (int)ic[kIcBig];
-            L.wmax_old = &g->d.ictr[kIcWmaxOld];
-            for (int b = 0; b < kScoreBins; ++b) L.bin_count[b] = (long long)ic[kIcBins + b];
-            st = launch_score_lists(g, L);
-        }
+        e = hipEventSynchronize(g->rem_ev);
+        if (e != hipSuccess) st = hip_fail(e, "incremental counts");
     }
     // the re-score stays queued on the graph's stream (as rs_score's pass)
     if (st != RS_OK) return st;
