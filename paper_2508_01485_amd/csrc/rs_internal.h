@@ -84,7 +84,6 @@ struct Tiling {
 // Vertex marks of an incremental re-score (after removals).
 constexpr unsigned int kRowChanged = 1u;   // the row lost entries
 constexpr unsigned int kAffected = 2u;     // the score must be recomputed
-constexpr unsigned int kNearChanged = 4u;  // a neighbour's row changed: links move
 // Counters of an incremental re-score (ictr[]).
 // Affected tile vertices are rescored in units built per pass: bin b holds
 // the vertices with a load-time foreign degree in (2^(b-1), 2^b] (bin 0: at
@@ -238,10 +237,10 @@ struct DeviceGraph {
     int32_t *cstart = nullptr;  // [k+1] first internal id of each community
     unsigned long long *wpart = nullptr;  // [kWorkBlocks] partials of the on-demand W1 count
     // incremental re-score
-    unsigned int *vmark = nullptr;          // [n] kRowChanged | kAffected | kNearChanged
+    unsigned int *vmark = nullptr;          // [n] kRowChanged | kAffected
     int32_t *vrowb = nullptr;               // [n] row block of each vertex
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
-    uint8_t *rflag = nullptr, *sflag = nullptr, *hflag = nullptr;  // unit flags
+    uint8_t *rflag = nullptr, *cflag = nullptr, *hflag = nullptr;  // flags: row blocks, score-hub chunks, score hubs (whole)
     int32_t *elist = nullptr, *abin = nullptr;  // [n] changed rows; affected tile vertices by bin
     int32_t *ucnt = nullptr;                    // [kUnitRows * kUnitGroups] per-range counts, then slots
     int2 *echunk = nullptr;                 // [n + nnz / 64] chunks of 64 entries of the changed rows

@@ -1423,11 +1423,13 @@ __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score_inc(ScoreArgs<OffT> A, const int32_t *big, const int32_t *main_,
                                                       const int32_t *abin, const unsigned long long *ictr,
-                                                      int grid_rows, int grid_score, int grid_main) {
+                                                      uint8_t *hflag, int grid_rows, int grid_score, int grid_main) {
     __shared__ union {
         ScoreUnitShared u;
         ScoreHubBigShared h;
     } S;
+    // the whole-hub flags of the marks were turned into lists: clear them
+    for (int h = blockIdx.x * kBlock + threadIdx.x; h < A.n_hubs; h += gridDim.x * kBlock) hflag[h] = 0;
     const double wmax = bitsd(A.ctr->wmax_bits);
     const bool full = inc_full(ictr, grid_rows, grid_score);
     const long long n_big = full ? (long long)(A.n_chunks - A.n_chunks_lds) : (long long)ictr[kIcBig];
@@ -1903,8 +1905,8 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
         S.blist = nullptr;
         timing_begin(g, K_SCORE, &ev);
         hipLaunchKernelGGL(k_score_inc<OffT>, dim3(kIncGrid), dim3(kBlock), 0, g->stream, S, (const int32_t *)D.hlist,
-                           (const int32_t *)D.slist, (const int32_t *)D.abin, ictr, g->grid_rows, g->grid_score,
-                           grid_main);
+                           (const int32_t *)D.slist, (const int32_t *)D.abin, ictr, D.hflag, g->grid_rows,
+                           g->grid_score, grid_main);
         timing_end(g, K_SCORE, ev);
     } else {
         if (n_big > 0) {
@@ -3375,20 +3377,73 @@ __global__ __launch_bounds__(kBlock) void k_row_chunks(const int32_t *deg, const
     }
 }
 
-// After removals, one wavefront per chunk of 64 entries of a changed
-// (compacted) row v (chunks: k_row_chunks), for each entry (v, w):
-// * marks: v is affected, w is near a change, and affected if foreign; for a
-//   foreign w, the members of C(v) in w's row (an id range, found by binary
-//   search) are affected;
-// * links (foreign w): v's link for the entry (the reverse entry and w's
-//   out-list), and the index of the entry (v, w), which moved with v's row,
-//   in w's link back to v.
-// Only the kRowChanged bits, set by the removals before, are read.
+// The marks of the pair (x, w) of a member x of C(v) in the row of v's
+// foreign neighbour w (the pair sums a_v): a score hub whose row did not
+// change flags the chunk holding the pair (w's place in x's foreign list);
+// any other x is affected whole.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned int *vmark, const int32_t *rows,
+__device__ __forceinline__ void mark_run_member(const LinkArgs<OffT> &L, unsigned int *vmark, const int32_t *vscore,
+                                                const int32_t *hub_first, uint8_t *cflag, int x, int w) {
+    const int sx = vscore[x];
+    if (sx < 0 && !(L.vmark[x] & kRowChanged)) {
+        const int32_t *row[1] = {L.col + L.off[x]};
+        const int d[1] = {L.deg[x]};
+        const int key[1] = {w};
+        int k[1];
+        lower_n<1, false>(row, d, key, k);
+        const VMeta m = L.card[x].m;
+        const int kx = k[0] < m.p ? k[0] : k[0] - (m.q - m.p);
+        cflag[hub_first[-1 - sx] + kx / kScoreTileP] = 1;
+    } else {
+        atomicOr(&vmark[x], kAffected);
+    }
+}
+
+// Item g of a wavefront's flattened work: its owner lane (pre: the lanes'
+// inclusive item counts, in LDS) and its index among the owner's items.
+__device__ __forceinline__ int flat_owner(const int *pre, int g, int &idx) {
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] > g)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    idx = g - (lo > 0 ? pre[lo - 1] : 0);
+    return lo;
+}
+
+// Longest changed row whose triangles at a hub neighbour are listed pair by
+// pair; a hub next to a longer changed row is rescored whole.
+constexpr int kTriRow = 512;
+
+// After removals, one wavefront per chunk of 64 entries of a changed
+// (compacted) row v (chunks: k_row_chunks), for each entry (v, w) with w in
+// another community:
+// * links: v's link for the entry (the reverse entry and w's out-list), and
+//   the index of the entry (v, w), which moved with v's row, in w's link
+//   back to v;
+// * marks: v is affected whole.  The pairs whose terms read v's row are
+//   (a) (w, v) itself (w's pair facts, out-list scan, a-run),
+//   (b) (w, y) for each y adjacent to both, in a third community (the
+//       triangle {w, y, v} reads v's record weights),
+//   (c) (x, w) for each member x of C(v) in w's row (its a-run sums a_v).
+//   A tile vertex with such a pair is affected whole (its unit reruns); a
+//   score hub whose own row did not change flags only the chunks holding the
+//   pairs (the others keep their partials), so a changed vertex next to a
+//   hub costs a few chunks, not the hub.
+// The long lists of (b) and (c) are worked by the whole wavefront (items
+// flattened over the lanes).  Only the kRowChanged bits, set by the
+// removals before, are read.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned int *vmark, const int32_t *vscore,
+                                                      const int32_t *hub_first, uint8_t *cflag, const int32_t *rows,
                                                       const int2 *chunks, const unsigned long long *n_chunks) {
+    __shared__ int s_pre[kBlock / 64][64];
     const long long nc = (long long)*n_chunks;
     const int lane = threadIdx.x & 63;
+    int *pre = s_pre[threadIdx.x >> 6];
     for (long long q = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nc;
          q += ((long long)gridDim.x * kBlock) >> 6) {
         const int2 it = chunks[q];
@@ -3396,50 +3451,129 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
         if (it.y == 0 && lane == 0) atomicOr(&vmark[v], kAffected);
         const long long rb = (long long)L.off[v];
         const int dv = L.deg[v];
-        const int j = it.y * 64 + lane;
-        if (j >= dv) continue;
         const int cv = L.lab[v];
-        const int w = L.col[rb + j];
-        const int cw = L.lab[w];
-        if (cw == cv) {
-            atomicOr(&vmark[w], kNearChanged);
-            continue;
-        }
-        atomicOr(&vmark[w], kNearChanged | kAffected);
-        const long long wb = (long long)L.off[w];
-        const int dw = L.deg[w];
-        const int32_t *roww = L.col + wb;
         const int id0 = L.cstart[cv], id1 = L.cstart[cv + 1];
-        // in w's row: C(v)'s run [k[0], k[1]) and the entry (w, v) at k[2];
-        // in v's row: v's own run [k[3], k[4])
-        const int32_t *rws[5] = {roww, roww, roww, L.col + rb, L.col + rb};
-        const int ds[5] = {dw, dw, dw, dv, dv};
-        const int keys[5] = {id0, id1, v, id0, id1};
-        int k[5];
-        lower_n<5, false>(rws, ds, keys, k);
-        for (int t = k[0]; t < k[1]; ++t) atomicOr(&vmark[roww[t]], kAffected);
-        const int pv = k[3], qv = k[4], ew = k[2];
-        PairLink pl;
-        pl.e = wb + ew;
-        pl.oo = (int)L.oo[w];
-        pl.on = (int)(L.oo[w + 1] - L.oo[w]);
-        L.plink[L.goff[v] + (j < pv ? j : j - (qv - pv))] = pl;
-        // w's own run is its card's when w's row did not change
-        int pw, qw;
-        if (L.vmark[w] & kRowChanged) {
-            const int32_t *rw2[2] = {roww, roww};
-            const int dw2[2] = {dw, dw};
-            const int kw2[2] = {L.cstart[cw], L.cstart[cw + 1]};
-            int pq[2];
-            lower_n<2, false>(rw2, dw2, kw2, pq);
-            pw = pq[0];
-            qw = pq[1];
-        } else {
-            const VMeta m = L.card[w].m;
-            pw = m.p;
-            qw = m.q;
+        const int j = it.y * 64 + lane;
+        int w = 0, cw = cv;
+        if (j < dv) {
+            w = L.col[rb + j];
+            cw = L.lab[w];
         }
-        L.plink[L.goff[w] + (ew < pw ? ew : ew - (qw - pw))].e = rb + j;
+        const bool fw = j < dv && cw != cv;
+        long long wb = 0;
+        int dw = 0, k0 = 0, k1 = 0, wh = 0, pw = 0, qw = 0;
+        bool whub = false;  // w: a score hub with its row unchanged
+        if (fw) {
+            wb = (long long)L.off[w];
+            dw = L.deg[w];
+            const int32_t *roww = L.col + wb;
+            // in w's row: C(v)'s run [k[0], k[1]) and the entry (w, v) at
+            // k[2]; in v's row: v's own run [k[3], k[4])
+            const int32_t *rws[5] = {roww, roww, roww, L.col + rb, L.col + rb};
+            const int ds[5] = {dw, dw, dw, dv, dv};
+            const int keys[5] = {id0, id1, v, id0, id1};
+            int k[5];
+            lower_n<5, false>(rws, ds, keys, k);
+            k0 = k[0];
+            k1 = k[1];
+            const int pv = k[3], qv = k[4], ew = k[2];
+            PairLink pl;
+            pl.e = wb + ew;
+            pl.oo = (int)L.oo[w];
+            pl.on = (int)(L.oo[w + 1] - L.oo[w]);
+            L.plink[L.goff[v] + (j < pv ? j : j - (qv - pv))] = pl;
+            // w's own run is its card's when w's row did not change
+            const bool wch = (L.vmark[w] & kRowChanged) != 0u;
+            if (wch) {
+                const int32_t *rw2[2] = {roww, roww};
+                const int dw2[2] = {dw, dw};
+                const int kw2[2] = {L.cstart[cw], L.cstart[cw + 1]};
+                int pq[2];
+                lower_n<2, false>(rw2, dw2, kw2, pq);
+                pw = pq[0];
+                qw = pq[1];
+            } else {
+                const VMeta m = L.card[w].m;
+                pw = m.p;
+                qw = m.q;
+            }
+            const int kw = ew < pw ? ew : ew - (qw - pw);
+            L.plink[L.goff[w] + kw].e = rb + j;
+            const int sw = vscore[w];
+            whub = sw < 0 && !wch;
+            if (whub) {
+                wh = -1 - sw;
+                cflag[hub_first[wh] + kw / kScoreTileP] = 1;  // (a)
+            } else {
+                atomicOr(&vmark[w], kAffected);
+            }
+        }
+        // (c) the runs of C(v) in the foreign neighbours' rows
+        {
+            const int cnt = fw ? k1 - k0 : 0;
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            pre[lane] = incl;
+            const int total = __shfl(incl, 63);
+            wave_sync();
+            for (int g0 = 0; g0 < total; g0 += 64) {
+                const int g = g0 + lane;
+                int idx = 0, l = 0;
+                if (g < total) l = flat_owner(pre, g, idx);
+                const int wl = __shfl(w, l), kl = __shfl(k0, l);
+                const long long wbl = ((long long)__shfl((int)(wb >> 32), l) << 32) | (unsigned int)__shfl((int)wb, l);
+                if (g < total) mark_run_member(L, vmark, vscore, hub_first, cflag, L.col[wbl + kl + idx], wl);
+            }
+            wave_sync();
+        }
+        // (b) the triangles {w, y, v} at the hub neighbours w: the pairs
+        // (w, y) for the foreign neighbours y of v in a third community
+        const unsigned long long hubs = __ballot(whub);
+        if (hubs) {
+            if (dv > kTriRow) {  // too long to intersect: the hub reruns whole
+                if (whub) atomicOr(&vmark[w], kAffected);
+            } else {
+                const int cnt = whub ? dv : 0;
+                int incl = cnt;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                pre[lane] = incl;
+                const int total = __shfl(incl, 63);
+                wave_sync();
+                for (int g0 = 0; g0 < total; g0 += 64) {
+                    const int g = g0 + lane;
+                    int t = 0, l = 0;
+                    if (g < total) l = flat_owner(pre, g, t);
+                    const int wl = __shfl(w, l), cwl = __shfl(cw, l), hl = __shfl(wh, l), pwl = __shfl(pw, l),
+                              qwl = __shfl(qw, l), dwl = __shfl(dw, l);
+                    const long long wbl =
+                        ((long long)__shfl((int)(wb >> 32), l) << 32) | (unsigned int)__shfl((int)wb, l);
+                    if (g < total) {
+                        const int y = L.col[rb + t];
+                        const int cy = L.lab[y];
+                        if (cy != cv && cy != cwl) {
+                            const int32_t *row[1] = {L.col + wbl};
+                            const int d[1] = {dwl};
+                            const int key[1] = {y};
+                            int k[1];
+                            lower_n<1, false>(row, d, key, k);
+                            if (k[0] < dwl && L.col[wbl + k[0]] == y) {
+                                const int ky = k[0] < pwl ? k[0] : k[0] - (qwl - pwl);
+                                cflag[hub_first[hl] + ky / kScoreTileP] = 1;
+                            }
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
     }
 }
 
@@ -3569,31 +3703,42 @@ __global__ __launch_bounds__(kBlock) void k_units_place(unsigned int *vmark, con
     }
 }
 
-// Flags -> block lists of the full launches (row blocks; main score blocks,
-// LDS-hub chunks included; big-hub chunks); the flags are cleared.
-__global__ __launch_bounds__(kBlock) void k_unit_lists(uint8_t *rflag, int n_rows, uint8_t *sflag, int n_main,
-                                                       uint8_t *hflag, int n_hubs, const int32_t *hub_first,
+// Append the lanes' values whose pred holds to list (one atomic per
+// wavefront; all lanes call it).
+__device__ __forceinline__ void wave_append(bool pred, int val, int32_t *list, unsigned long long *count) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(pred);
+    if (!m) return;
+    unsigned long long first = 0;
+    if (lane == 0) first = atomicAdd(count, (unsigned long long)__popcll(m));
+    first = __shfl(first, 0);
+    if (pred) list[first + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
+// Flags -> the incremental launches' lists (indices of the full launches):
+// the flagged row blocks, and the score-hub chunks to rerun, each chunk of a
+// hub flagged whole and each chunk flagged by itself (the main list takes
+// the LDS-hub chunks, the big list the others).  Clears the row and chunk
+// flags; the hub flags are cleared by the score pass that follows.
+__global__ __launch_bounds__(kBlock) void k_unit_lists(uint8_t *rflag, int n_rows, uint8_t *cflag,
+                                                       const uint8_t *hflag, const int2 *hub_chunk, int n_chunks,
                                                        int n_chunks_lds, int32_t *rlist, int32_t *slist,
                                                        int32_t *hlist, unsigned long long *ictr) {
-    const int top = max(n_rows, max(n_main, n_hubs));
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < top; i += gridDim.x * kBlock) {
-        if (i < n_rows && rflag[i]) {
-            rflag[i] = 0;
-            rlist[atomicAdd(&ictr[kIcRows], 1ull)] = i;
+    const int lane = threadIdx.x & 63;
+    const int top = max(n_rows, n_chunks);
+    for (int base = blockIdx.x * kBlock + (threadIdx.x & ~63); base < top; base += gridDim.x * kBlock) {
+        const int i = base + lane;
+        const bool r = i < n_rows && rflag[i] != 0;
+        if (r) rflag[i] = 0;
+        bool c = false;
+        if (i < n_chunks) {
+            const bool own = cflag[i] != 0;
+            if (own) cflag[i] = 0;
+            c = own || hflag[hub_chunk[i].x] != 0;
         }
-        if (i < n_main && sflag[i]) {
-            sflag[i] = 0;
-            slist[atomicAdd(&ictr[kIcMain], 1ull)] = i;
-        }
-        if (i < n_hubs && hflag[i]) {
-            hflag[i] = 0;
-            for (int c = hub_first[i]; c < hub_first[i + 1]; ++c) {
-                if (c < n_chunks_lds)
-                    slist[atomicAdd(&ictr[kIcMain], 1ull)] = c;
-                else
-                    hlist[atomicAdd(&ictr[kIcBig], 1ull)] = c - n_chunks_lds;
-            }
-        }
+        wave_append(r, i, rlist, &ictr[kIcRows]);
+        wave_append(c && i < n_chunks_lds, i, slist, &ictr[kIcMain]);
+        wave_append(c && i >= n_chunks_lds, i - n_chunks_lds, hlist, &ictr[kIcBig]);
     }
 }
 
@@ -3608,19 +3753,18 @@ static rs_status incremental_marks_t(rs_graph *g) {
     hipLaunchKernelGGL(k_row_chunks, dim3(gn), dim3(kBlock), 0, g->stream, D.deg, D.elist, &D.ictr[kIcChanged],
                        D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_mark_link<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.vmark,
-                       D.elist, D.echunk, &D.ictr[kIcChunks]);
+                       (const int32_t *)D.vscore, (const int32_t *)D.shub_first, D.cflag, D.elist, D.echunk,
+                       &D.ictr[kIcChunks]);
     const int ug = grid_for(D.n, kBlock, kUnitGroups);
     hipLaunchKernelGGL(k_units_count, dim3(ug), dim3(kBlock), 0, g->stream, D.vmark, D.vrowb, D.vscore, D.goff,
                        (long long)D.n, D.rflag, D.hflag, D.ucnt);
     hipLaunchKernelGGL(k_units_scan, dim3(1), dim3(kBlock), 0, g->stream, D.ucnt, ug, D.ictr, D.ctr);
     hipLaunchKernelGGL(k_units_place, dim3(ug), dim3(kBlock), 0, g->stream, D.vmark, D.vscore, D.goff,
                        (long long)D.n, D.ucnt, D.abin);
-    const int n_big = g->n_schunks - g->n_schunks_lds;
-    const int n_main = g->grid_score - n_big;
-    const int top = std::max(g->grid_rows, std::max(n_main, g->n_shubs));
+    const int top = std::max(g->grid_rows, g->n_schunks);
     hipLaunchKernelGGL(k_unit_lists, dim3(grid_for(top, kBlock, 4096)), dim3(kBlock), 0, g->stream, D.rflag,
-                       g->grid_rows, D.sflag, n_main, D.hflag, g->n_shubs, D.shub_first, g->n_schunks_lds, D.rlist,
-                       D.slist, D.hlist, D.ictr);
+                       g->grid_rows, D.cflag, (const uint8_t *)D.hflag, (const int2 *)D.shub_chunk, g->n_schunks,
+                       g->n_schunks_lds, D.rlist, D.slist, D.hlist, D.ictr);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RS_OK : hip_fail(e, "incremental marks launch");
 }

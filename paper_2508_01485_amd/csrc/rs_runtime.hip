@@ -433,7 +433,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
     DeviceGraph &D = g->d;
     void **tile_arrays[] = {(void **)&D.rtiles, (void **)&D.rhubs, (void **)&D.stiles, (void **)&D.shubs,
                             (void **)&D.shub_first, (void **)&D.shub_chunk, (void **)&D.hub_part,
-                            (void **)&D.rflag, (void **)&D.sflag, (void **)&D.hflag, (void **)&D.rlist,
+                            (void **)&D.rflag, (void **)&D.cflag, (void **)&D.hflag, (void **)&D.rlist,
                             (void **)&D.slist, (void **)&D.hlist, (void **)&D.part_rows, (void **)&D.wmax_part,
                             (void **)&D.vrowb, (void **)&D.vscore};
     for (void **p : tile_arrays) dev_free(g, p);
@@ -462,7 +462,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
         {(void **)&D.shub_chunk, sizeof(int2) * nch},
         {(void **)&D.hub_part, sizeof(HubPart) * nch},
         {(void **)&D.rflag, gr},
-        {(void **)&D.sflag, gs},
+        {(void **)&D.cflag, nch},
         {(void **)&D.hflag, nsh},
         {(void **)&D.rlist, 4 * gr},
         {(void **)&D.slist, 4 * gs},
@@ -490,7 +490,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
     put(D.vrowb, H.vrowb.data(), 4 * H.vrowb.size());
     put(D.vscore, H.vscore.data(), 4 * H.vscore.size());
     if (e == hipSuccess) e = hipMemsetAsync(D.rflag, 0, gr, s);
-    if (e == hipSuccess) e = hipMemsetAsync(D.sflag, 0, gs, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.cflag, 0, nch, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.hflag, 0, nsh, s);
     return e == hipSuccess ? RS_OK : hip_fail(e, "schedule upload");
 }

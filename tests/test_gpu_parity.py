@@ -334,6 +334,56 @@ def test_removals_on_triangle_rich_hubs(rs):
     topk_matches(ids1, exp_ids, ora["R"], 50, alive=alive)
 
 
+def test_removals_next_to_hubs_chain_equals_full_pass(rs):
+    """Removals next to score hubs of several chunks (foreign lists beyond
+    the LDS size and within it) whose own rows stay intact, so that only the
+    chunks holding pairs that read a changed row rerun: the pair with the
+    changed neighbour, the triangles through it, and the a_v run sums.  Four
+    batches in a row on one handle (no full pass in between), each equal bit
+    for bit to a second handle of the same schedule that runs a full pass
+    after the same removals; the last state also against the oracle."""
+    rng = np.random.default_rng(31)
+    n = 8000
+    labels = rng.integers(0, 60, n).astype(np.int32)
+    m = 6 * n
+    a = rng.integers(6, n, m)
+    b = rng.integers(6, n, m)
+    sizes = [3000, 2400, 1800, 1100, 700, 400]  # four hubs beyond 1024 foreign entries, two within
+    hub_e = [(h, int(x)) for h, sz in enumerate(sizes) for x in rng.choice(np.arange(6, n), sz, replace=False)]
+    g = from_edges(n, np.concatenate([np.stack([a, b], 1), np.array(hub_e)]), labels)
+    gu, gv = g.edges()
+    cross = np.flatnonzero((labels[gu] != labels[gv]) & (gu >= 6) & (gv >= 6))
+    h_inc = rs.rs_load_graph(g.off, g.col, g.labels)
+    h_ref = rs.rs_load_graph(g.off, g.col, g.labels)
+    try:
+        rs.rs_score(h_inc)
+        rs.rs_score(h_ref)
+        keep = np.ones(gu.size, bool)
+        for step in range(4):
+            live = cross[keep[cross]]
+            pick = rng.choice(live, 300, replace=False)
+            e = np.stack([gu[pick], gv[pick]], 1)
+            res = rs.rs_apply_removals(h_inc, edges=e)
+            assert res["edges_removed"] == 300
+            rs.rs_apply_removals(h_ref, edges=e)
+            rs.rs_score(h_ref)
+            keep[pick] = False
+            R1, R2 = rs.rs_read_scores(h_inc), rs.rs_read_scores(h_ref)
+            assert R1.tobytes() == R2.tobytes(), f"batch {step}"
+            c1, c2 = rs.rs_read_vertex_counts(h_inc), rs.rs_read_vertex_counts(h_ref)
+            for key in ("border", "ell", "dprime", "tI", "tII"):
+                assert np.array_equal(c1[key], c2[key]), (step, key)
+            _say(f"[parity] hub-neighbour batch {step}: {res['affected']} vertices affected, bits equal")
+        g2 = from_edges(n, np.stack([gu[keep], gv[keep]], 1), labels)
+        o2 = oracle.score(g2)
+        rel_close(R1, o2["R"], 1e-6)
+        assert np.array_equal(c1["tI"], o2["tI"]) and np.array_equal(c1["tII"], o2["tII"])
+        assert int(o2["tI"].sum()) > 0
+    finally:
+        h_inc.free()
+        h_ref.free()
+
+
 def _apply_and_check_full(rs, h):
     """After rs_apply_removals: a full pass gives the same bits and counts."""
     R1 = rs.rs_read_scores(h)
