@@ -220,6 +220,7 @@ struct DeviceGraph {
     void *off = nullptr;        // OffT[n+1]
     int32_t *deg = nullptr;     // [n] current degree
     int32_t *col = nullptr;     // [nnz]
+    int32_t *clab = nullptr;    // [nnz] the community of each entry's neighbour (-1: removed tail), the row pass's input
     int32_t *lab = nullptr;     // [n] internal community id
     int32_t *new2old = nullptr; // [n]
     uint8_t *alive = nullptr;   // [n]
@@ -372,6 +373,7 @@ rs_status launch_remove_edges(rs_graph *g, const int32_t *d_src, const int32_t *
 rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv,
                                  unsigned long long *d_removed_edges);
 rs_status launch_links(rs_graph *g);
+rs_status launch_col_labels(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);

@@ -101,6 +101,7 @@ template <typename OffT>
 struct RowArgs {
     const OffT *off;
     const int32_t *deg, *col, *lab;
+    const int32_t *clab;  // the community of each entry's neighbour (read in place of col and lab)
     const RowTile *tiles;
     const int32_t *hubs;
     int n_tiles, n_hubs, tiles_per_xcd;
@@ -267,7 +268,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
 #pragma unroll
     for (int i = 0; i < kRowU; ++i) {
         const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
-        L[i] = e < TE ? A.col[e0 + e] : -2;
+        L[i] = e < TE ? A.clab[e0 + e] : -2;
     }
     int vo[kVU], vc[kVU], vdeg[kVU], vlab[kVU];
     long long vgo[kVU];
@@ -285,8 +286,6 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
             vgo[j] = A.goff[v0 + i];
         }
     }
-#pragma unroll
-    for (int i = 0; i < kRowU; ++i) L[i] = L[i] >= 0 ? A.lab[L[i]] : L[i];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kVU; ++j)
@@ -453,10 +452,8 @@ __device__ void hub_pass(const RowArgs<OffT> &A, RowTileShared &S, OffT rb, int 
 #pragma unroll
         for (int i = 0; i < kRowU; ++i) {
             const int e = wave * (kRowTile / kRowW) + i * 64 + lane;
-            L[i] = e < TE ? A.col[rb + seg0 + e] : -2;
+            L[i] = e < TE ? A.clab[rb + seg0 + e] : -2;
         }
-#pragma unroll
-        for (int i = 0; i < kRowU; ++i) L[i] = L[i] >= 0 ? A.lab[L[i]] : L[i];
         __syncthreads();  // the previous segment is done with S
         if (lane == 63) S.wlast[wave] = L[kRowU - 1];
 #pragma unroll
@@ -1719,6 +1716,25 @@ static rs_status links_t(rs_graph *g) {
 
 rs_status launch_links(rs_graph *g) { return g->d.off64 ? links_t<long long>(g) : links_t<int32_t>(g); }
 
+// Each entry's neighbour community (once at load; compaction moves it with
+// the entry): the row pass reads it in place of the id and its label.
+__global__ __launch_bounds__(kBlock) void k_col_labels(const int32_t *col, const int32_t *lab, long long nnz,
+                                                       int32_t *clab) {
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (long long)gridDim.x * kBlock) {
+        const int x = col[e];
+        clab[e] = x >= 0 ? lab[x] : -1;
+    }
+}
+
+rs_status launch_col_labels(rs_graph *g) {
+    DeviceGraph &D = g->d;
+    if (D.nnz == 0) return RS_OK;
+    hipLaunchKernelGGL(k_col_labels, dim3(grid_for(D.nnz, kBlock, 65536)), dim3(kBlock), 0, g->stream, D.col, D.lab,
+                       (long long)D.nnz, D.clab);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "entry label launch");
+}
+
 
 __global__ void k_zero_u64(unsigned long long *p, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
@@ -1830,6 +1846,7 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
     A.deg = D.deg;
     A.col = D.col;
     A.lab = D.lab;
+    A.clab = D.clab;
     A.tiles = D.rtiles;
     A.hubs = D.rhubs;
     A.n_tiles = g->n_rtiles;
@@ -3323,7 +3340,7 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
 // one wavefront per row, 64 entries at a time (ballot and prefix); the freed
 // tail of the capacity is set to -1.
 template <typename OffT>
-__global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_t *deg, int32_t *col,
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_t *deg, int32_t *col, int32_t *clab,
                                                          const int32_t *list, const unsigned long long *count) {
     const long long nl = (long long)*count;
     const int lane = threadIdx.x & 63;
@@ -3334,20 +3351,28 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_
         const int d = deg[v];
         int w = 0;
         for (int j0 = 0; j0 < d; j0 += 256) {  // four groups of 64 entries loaded at once
-            int x[4];
+            int x[4], c[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int j = j0 + 64 * t + lane;
                 x[t] = j < d ? col[rb + j] : -1;
+                c[t] = j < d ? clab[rb + j] : -1;
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const unsigned long long m = __ballot(x[t] >= 0);
-                if (x[t] >= 0) col[rb + w + __popcll(m & ((1ull << lane) - 1ull))] = x[t];
+                if (x[t] >= 0) {
+                    const long long to = rb + w + __popcll(m & ((1ull << lane) - 1ull));
+                    col[to] = x[t];
+                    clab[to] = c[t];
+                }
                 w += __popcll(m);
             }
         }
-        for (int j = w + lane; j < d; j += 64) col[rb + j] = -1;
+        for (int j = w + lane; j < d; j += 64) {
+            col[rb + j] = -1;
+            clab[rb + j] = -1;
+        }
         if (lane == 0) deg[v] = w;
     }
 }
@@ -3748,8 +3773,8 @@ static rs_status incremental_marks_t(rs_graph *g) {
     if (D.n == 0) return RS_OK;
     const OffT *off = (const OffT *)D.off;
     const int gn = grid_for(D.n, kBlock, 1024);
-    hipLaunchKernelGGL(k_compact_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.elist,
-                       &D.ictr[kIcChanged]);
+    hipLaunchKernelGGL(k_compact_rows<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, off, D.deg, D.col, D.clab,
+                       D.elist, &D.ictr[kIcChanged]);
     hipLaunchKernelGGL(k_row_chunks, dim3(gn), dim3(kBlock), 0, g->stream, D.deg, D.elist, &D.ictr[kIcChanged],
                        D.echunk, &D.ictr[kIcChunks]);
     hipLaunchKernelGGL(k_mark_link<OffT>, dim3(gn), dim3(kBlock), 0, g->stream, link_args<OffT>(g), D.vmark,

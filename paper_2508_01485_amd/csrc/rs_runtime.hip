@@ -510,6 +510,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {&D.off, offb * (N + 1)},
         {(void **)&D.deg, 4 * N},
         {(void **)&D.col, 4 * Z},
+        {(void **)&D.clab, 4 * Z},
         {(void **)&D.lab, 4 * N},
         {(void **)&D.new2old, 4 * N},
         {(void **)&D.alive, N},
@@ -612,6 +613,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     if (tst != RS_OK) return tst;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
+    const rs_status lst = launch_col_labels(g);  // each entry's neighbour community
+    if (lst != RS_OK) return lst;
     const rs_status rst = launch_links(g);  // each G' entry's reverse entry and out-list range
     if (rst != RS_OK) return rst;
     e = hipStreamSynchronize(s);
