@@ -2533,6 +2533,11 @@ __device__ __forceinline__ void sort_desc_keys(TopkKey *s2, int n2, int kf, int3
     }
 }
 
+// Selected lists up to this size are ordered by counting in k_topk_small
+// (each thread counts the keys above its own), larger ones by the bitonic sort
+// (one workgroup: counting does n^2 comparisons on a single CU).
+constexpr int kCountSmall = 256;
+
 __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const TopkKey *fin, const TopkKey *tie,
                                                      long long keff, const double *R, const int32_t *new2old,
                                                      int32_t *out_ids, double *out_sc, unsigned int *flag) {
@@ -2620,6 +2625,23 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
     int pos = base + incl - cnt;
     for (int i = i0; i < min(total, i0 + per); ++i)
         if (mark[i] == 1) s2[pos++] = s[i];
+    if (nsel <= kCountSmall) {
+        // a key's place is the number of selected keys above it (keys are
+        // unique): every thread counts over the list in LDS (broadcast reads)
+        __syncthreads();
+        for (int i = tid; i < nsel; i += nthr) {
+            const TopkKey me = s2[i];
+            int rank = 0;
+#pragma unroll 8
+            for (int j = 0; j < nsel; ++j) rank += key_gt(s2[j], me) ? 1 : 0;
+            if (rank < kf) {
+                out_ids[rank] = new2old[me.v];
+                out_sc[rank] = R[me.v];
+            }
+        }
+        if (tid == 0) *flag = 1u;
+        return;
+    }
     const int n2 = sort_all ? pt : pk;
     for (int i = nsel + tid; i < n2; i += nthr) {  // padding: below every real key (lo >= 2^31)
         s2[i].hi = 0;
@@ -2637,16 +2659,19 @@ __global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const 
 }
 
 
-// ------------------------------------------------------------ rank by sorted chunks
-// Ranking of a key list of up to kMergeChunks * kChunkKeys keys without
-// pairwise comparison of every pair: each chunk of kChunkKeys keys is sorted
-// (descending, bitonic in LDS), then every key's rank is its index in its own
-// chunk plus, for every other chunk, the number of that chunk's keys above it
-// (a binary search of the chunk staged in LDS).  Keys are unique (the caller
-// id is part of the key), so the ranks are a permutation.
-constexpr int kChunkKeys = 2048;
-constexpr int kMergeChunks = 32;
-static_assert(kChunkKeys == 2 * 1024, "a chunk is two keys per thread of a 1024-thread block");
+// ------------------------------------------------------------ rank by counting
+// Ranking of a list of unique keys (the caller id is part of the key): a
+// key's rank is the number of keys above it.  A workgroup of 1024 threads
+// takes 64 keys (one per lane) and its 16 wavefronts each count over every
+// 16th key of the list, staged in LDS tiles that every lane of a wavefront
+// reads at the same place (broadcast); the 16 counts are summed.  Sixteen
+// wavefronts per group keep enough of them on every CU to hide the LDS
+// latency of the comparisons.
+constexpr int kCountKeys = 64;
+constexpr int kCountThreads = 1024;
+constexpr int kCountSubs = kCountThreads / 64;
+constexpr int kCountTile = 2048;
+constexpr int kRankMax = 65536;  // longest list ranked here (final lists beyond: k_final_rank)
 
 // The list a rank pass works on, and whether it is needed: the tie class of
 // the threshold bin (mode 0, skipped when the bin was taken whole or is too
@@ -2661,92 +2686,54 @@ __device__ __forceinline__ long long rank_count(const TopkState *st, int mode, l
     return (st->overflow || have != keff) ? -1 : keff;
 }
 
-__global__ __launch_bounds__(1024) void k_chunk_sort(const TopkKey *in, TopkState *st, int mode, long long keff,
-                                                     TopkKey *out) {
-    __shared__ TopkKey s[kChunkKeys];
+// Mode 0: a tie key of rank r < take goes to the final list after the keys
+// above the bin (a class too large to rank here is flagged for refinement
+// digit by digit); mode 1: the key of rank r is the r-th output.
+__global__ __launch_bounds__(kCountThreads) void k_count_rank(const TopkKey *list, TopkState *st, int mode,
+                                                              long long keff, TopkKey *fin, const double *R,
+                                                              const int32_t *new2old, int32_t *out_ids,
+                                                              double *out_sc) {
+    __shared__ unsigned long long s_hi[kCountTile];
+    __shared__ unsigned int s_lo[kCountTile];
+    __shared__ int s_part[kCountSubs][kCountKeys];
     const long long n = rank_count(st, mode, keff);
-    // a tie class too large to rank here is refined digit by digit instead
     if (mode == 0 && n < 0 && !st->done && blockIdx.x == 0 && threadIdx.x == 0) st->overflow = 1u;
-    const long long c0 = (long long)blockIdx.x * kChunkKeys;
-    if (n < 0 || c0 >= n) return;
-    const int cnt = (int)min((long long)kChunkKeys, n - c0);
-    for (int i = threadIdx.x; i < kChunkKeys; i += blockDim.x) {
-        if (i < cnt) {
-            s[i] = in[c0 + i];
-        } else {
-            s[i].hi = 0;
-            s[i].lo = 0;  // below every real key (a real key has lo >= 2^31)
-            s[i].v = -1;
-        }
-    }
-    __syncthreads();
-    for (int k = 2; k <= kChunkKeys; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < kChunkKeys; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool desc = (i & k) == 0;
-                    const TopkKey x = s[i], y = s[l];
-                    if (desc ? key_gt(y, x) : key_gt(x, y)) {
-                        s[i] = y;
-                        s[l] = x;
-                    }
-                }
+    if (n < 0) return;
+    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    for (long long base = (long long)blockIdx.x * kCountKeys; base < n; base += (long long)gridDim.x * kCountKeys) {
+        const long long i = base + lane;
+        TopkKey me;
+        me.hi = 0;
+        me.lo = 0;
+        me.v = -1;
+        if (i < n) me = list[i];
+        int cnt = 0;
+        for (long long t0 = 0; t0 < n; t0 += kCountTile) {
+            const int lim = (int)min((long long)kCountTile, n - t0);
+            __syncthreads();  // the previous tile (and group) is done with LDS
+            for (int j = threadIdx.x; j < lim; j += kCountThreads) {
+                const TopkKey x = list[t0 + j];
+                s_hi[j] = x.hi;
+                s_lo[j] = x.lo;
             }
             __syncthreads();
+#pragma unroll 8
+            for (int j = sub; j < lim; j += kCountSubs)
+                cnt += (s_hi[j] > me.hi || (s_hi[j] == me.hi && s_lo[j] > me.lo)) ? 1 : 0;
         }
-    }
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) out[c0 + i] = s[i];
-}
-
-// Ranks from the sorted chunks (256 keys per block, all in one chunk).  Mode
-// 0: a tie key of rank r < take goes to the final list after the keys above
-// the bin; mode 1: the key of rank r is the r-th output.
-__global__ __launch_bounds__(kBlock) void k_merge_rank(const TopkKey *sorted, const TopkState *st, int mode,
-                                                       long long keff, TopkKey *fin, const double *R,
-                                                       const int32_t *new2old, int32_t *out_ids, double *out_sc) {
-    __shared__ unsigned long long s_hi[kChunkKeys];
-    __shared__ unsigned int s_lo[kChunkKeys];
-    static_assert(kChunkKeys % kBlock == 0, "a block's keys lie in one chunk");
-    const long long n = rank_count(st, mode, keff);
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (n < 0 || (long long)blockIdx.x * kBlock >= n) return;
-    const int mine = (int)(((long long)blockIdx.x * kBlock) / kChunkKeys);
-    const int nch = (int)((n + kChunkKeys - 1) / kChunkKeys);
-    TopkKey me;
-    me.hi = 0;
-    me.lo = 0;
-    me.v = -1;
-    if (i < n) me = sorted[i];
-    long long rank = i - (long long)mine * kChunkKeys;
-    for (int c = 0; c < nch; ++c) {
-        if (c == mine) continue;
-        const long long c0 = (long long)c * kChunkKeys;
-        const int cnt = (int)min((long long)kChunkKeys, n - c0);
+        s_part[sub][lane] = cnt;
         __syncthreads();
-        for (int j = threadIdx.x; j < cnt; j += kBlock) {
-            const TopkKey x = sorted[c0 + j];
-            s_hi[j] = x.hi;
-            s_lo[j] = x.lo;
+        if (sub == 0 && i < n) {
+            long long rank = 0;
+#pragma unroll
+            for (int q = 0; q < kCountSubs; ++q) rank += s_part[q][lane];
+            if (mode == 0) {
+                if (rank < st->take) fin[(long long)st->n_final + rank] = me;
+            } else {
+                out_ids[rank] = new2old[me.v];
+                out_sc[rank] = R[me.v];
+            }
         }
-        __syncthreads();
-        int lo = 0, hi = cnt;  // keys of chunk c above me: a prefix of it
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            const bool gt = s_hi[mid] > me.hi || (s_hi[mid] == me.hi && s_lo[mid] > me.lo);
-            if (gt)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        rank += lo;
-    }
-    if (i >= n) return;
-    if (mode == 0) {
-        if (rank < st->take) fin[(long long)st->n_final + rank] = me;
-    } else {
-        out_ids[rank] = new2old[me.v];
-        out_sc[rank] = R[me.v];
     }
 }
 
@@ -2757,11 +2744,10 @@ static rs_status final_order(rs_graph *g, long long keff) {
     if (keff <= kSortCap) {
         hipLaunchKernelGGL(k_final_sort, dim3(1), dim3(1024), 0, g->stream, D.tfinal, keff, D.tstate, D.R,
                            D.new2old, D.tout_ids, D.tout_sc);
-    } else if (keff <= (long long)kMergeChunks * kChunkKeys) {
-        hipLaunchKernelGGL(k_chunk_sort, dim3((int)((keff + kChunkKeys - 1) / kChunkKeys)), dim3(1024), 0, g->stream,
-                           D.tfinal, D.tstate, 1, keff, D.ttie2);
-        hipLaunchKernelGGL(k_merge_rank, dim3((int)((keff + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream,
-                           D.ttie2, D.tstate, 1, keff, D.tfinal, D.R, D.new2old, D.tout_ids, D.tout_sc);
+    } else if (keff <= kRankMax) {
+        hipLaunchKernelGGL(k_count_rank, dim3((int)((keff + kCountKeys - 1) / kCountKeys)), dim3(kCountThreads), 0,
+                           g->stream, (const TopkKey *)D.tfinal, D.tstate, 1, keff, (TopkKey *)nullptr, D.R,
+                           D.new2old, D.tout_ids, D.tout_sc);
     } else {
         hipLaunchKernelGGL(k_final_rank, dim3(grid_for(keff, kBlock, 4096)), dim3(kBlock), 0, g->stream, D.tfinal,
                            keff, D.tstate, D.R, D.new2old, D.tout_ids, D.tout_sc);
@@ -2842,13 +2828,11 @@ rs_status launch_topk(rs_graph *g, int64_t k, int32_t *ids, double *scores, int6
     }
     TopkState st;
 
-    // General path: rank the tie class (sorted chunks), then order the final list.
+    // General path: rank the tie class (by counting), then order the final list.
     timing_begin(g, K_TOPK_TIE, &ev);
-    static_assert(kTieCap <= kMergeChunks * kChunkKeys, "a rankable tie class fits the merge");
-    hipLaunchKernelGGL(k_chunk_sort, dim3(kTieCap / kChunkKeys), dim3(1024), 0, g->stream, D.ttie, D.tstate, 0, 0ll,
-                       D.ttie2);
-    hipLaunchKernelGGL(k_merge_rank, dim3(kTieCap / kBlock), dim3(kBlock), 0, g->stream, D.ttie2, D.tstate, 0, 0ll,
-                       D.tfinal, D.R, D.new2old, D.tout_ids, D.tout_sc);
+    static_assert(kTieCap <= kRankMax, "a rankable tie class fits the counting ranker");
+    hipLaunchKernelGGL(k_count_rank, dim3(kTieCap / kCountKeys), dim3(kCountThreads), 0, g->stream,
+                       (const TopkKey *)D.ttie, D.tstate, 0, 0ll, D.tfinal, D.R, D.new2old, D.tout_ids, D.tout_sc);
     timing_end(g, K_TOPK_TIE, ev);
     rs_status rs_st = final_order(g, keff);
     if (rs_st != RS_OK) return rs_st;
@@ -3576,8 +3560,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
                     const int g = g0 + lane;
                     int t = 0, l = 0;
                     if (g < total) l = flat_owner(pre, g, t);
-                    const int wl = __shfl(w, l), cwl = __shfl(cw, l), hl = __shfl(wh, l), pwl = __shfl(pw, l),
-                              qwl = __shfl(qw, l), dwl = __shfl(dw, l);
+                    const int cwl = __shfl(cw, l), hl = __shfl(wh, l), pwl = __shfl(pw, l), qwl = __shfl(qw, l),
+                              dwl = __shfl(dw, l);
                     const long long wbl =
                         ((long long)__shfl((int)(wb >> 32), l) << 32) | (unsigned int)__shfl((int)wb, l);
                     if (g < total) {
