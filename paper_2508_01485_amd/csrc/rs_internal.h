@@ -54,6 +54,8 @@ constexpr int kScoreTileP = 256;     // foreign entries (load-time bound) of one
 constexpr int kScoreTileV = 256;     // vertices of one score tile (one per thread)
 constexpr int kHubKeys = 1024;       // score hubs with at most this many records keep their keys in LDS
 constexpr int kHubList = 1024;       // score hubs with at most this many foreign entries stage them in LDS
+constexpr int kFilterBits = 18;      // a big hub's neighbour filter: 2^18 bits (32 KB), one hash
+constexpr int kFilterWords = (1 << kFilterBits) / 32;
 constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
 constexpr int kTieCap = 16384;       // largest tie class ranked through sorted chunks
@@ -241,6 +243,7 @@ struct DeviceGraph {
     unsigned int *vmark = nullptr;          // [n] kRowChanged | kAffected
     int32_t *vrowb = nullptr;               // [n] row block of each vertex
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
+    uint32_t *hfilter = nullptr;  // [big hubs][kFilterWords] membership filter of each big hub's foreign neighbours
     uint8_t *rflag = nullptr, *cflag = nullptr, *hflag = nullptr;  // flags: row blocks, score-hub chunks, score hubs (whole)
     int32_t *elist = nullptr, *abin = nullptr;  // [n] changed rows; affected tile vertices by bin
     int32_t *ucnt = nullptr;                    // [kUnitRows * kUnitGroups] per-range counts, then slots
@@ -315,6 +318,7 @@ struct rs_graph {
     int64_t dev_bytes = 0;  // device memory held by the graph
     int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0, n_schunks = 0;
     int n_schunks_lds = 0;               // chunks of hubs whose foreign list fits in LDS (listed first)
+    int n_shubs_lds = 0;                 // those hubs (the big hubs follow)
     int grid_rows = 0, grid_score = 0;   // hubs first, then the tiles in XCD-major order
     std::vector<int32_t> h_new2old, h_old2new, h_comm2orig;
     rs::DeviceGraph d;

@@ -782,6 +782,8 @@ struct ScoreArgs {
     const RecDat *recdat;
     const VCard *card;
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
+    const uint32_t *hfilter;  // big hubs' neighbour filters (hub n_hubs_lds + i at i * kFilterWords)
+    int n_hubs_lds;
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
     const double *av;       // [n] a_v of the row pass
     const int *blist;       // unused by the score kernels (the incremental lists are arguments)
@@ -1326,14 +1328,25 @@ struct ScoreHubBigShared {
     HitBuf hits;
 };
 
+// A big hub's neighbour filter: bit h(y) is set for every current foreign
+// neighbour y of the hub (one multiplicative hash into 2^kFilterBits bits,
+// built at the start of the score pass).  A clear bit proves that y is no
+// neighbour; a set bit is checked exactly.
+__device__ __forceinline__ uint32_t filter_hash(int y) {
+    return ((uint32_t)y * 2654435761u) >> (32 - kFilterBits);
+}
+
 struct HubOutEdge {
     const int *stage;      // out(u) in LDS (n_stage entries), or null
     int n_stage;
     const int32_t *outl;
     const int64_t *oo;
     long long uo0, uo1;    // out(u) in HBM
+    const uint32_t *filt;  // u's neighbour filter
     int u;
     __device__ __forceinline__ bool operator()(int, int y) const {
+        const uint32_t h = filter_hash(y);
+        if (!((filt[h >> 5] >> (h & 31)) & 1u)) return false;
         if (stage ? lds_has_out(stage, n_stage, y) : out_has(outl, uo0, uo1, y)) return true;
         return out_has(outl, oo[y], oo[y + 1], u);
     }
@@ -1377,11 +1390,34 @@ __device__ void score_hub_big(const ScoreArgs<OffT> &A, ScoreHubBigShared &S, in
     E.oo = A.oo;
     E.uo0 = uo0;
     E.uo1 = uo1;
+    E.filt = A.hfilter + (size_t)(hub - A.n_hubs_lds) * kFilterWords;
     E.u = u;
     __syncthreads();  // the staged out-list
     typeI_scan(A, S.ti, S.hits, items, E, val, t1);
     chunk_tree(val, t1, t2, S.red, S.ired);
     if (tid == 0) hub_chunk_store(A, S.red, S.ired, hub, chunk);
+}
+
+// Each big hub's neighbour filter from its current foreign list (after the
+// row pass: the card's own run [p, q)): built in LDS by one workgroup per
+// hub, then written out whole.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_hub_filters(const int32_t *hubs, int h0, const VCard *card,
+                                                        const int32_t *col, uint32_t *filters) {
+    __shared__ uint32_t f[kFilterWords];
+    const int h = h0 + (int)blockIdx.x;
+    for (int i = threadIdx.x; i < kFilterWords; i += kBlock) f[i] = 0u;
+    __syncthreads();
+    const VCard c = card[hubs[h]];
+    const int hp = c.m.q - c.m.p;
+    const int dp = c.m.deg - hp;
+    for (int j = threadIdx.x; j < dp; j += kBlock) {
+        const uint32_t x = filter_hash(col[c.off + (j < c.m.p ? j : j + hp)]);
+        atomicOr(&f[x >> 5], 1u << (x & 31));
+    }
+    __syncthreads();
+    uint32_t *out = filters + (size_t)blockIdx.x * kFilterWords;
+    for (int i = threadIdx.x; i < kFilterWords; i += kBlock) out[i] = f[i];
 }
 
 // Algorithm 1 Step 3 (Eq. RSI) for every border vertex of the tiles and of
@@ -1908,6 +1944,8 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
     S.recdat = D.recdat;
     S.card = D.card;
     S.prec = D.prec;
+    S.hfilter = D.hfilter;
+    S.n_hubs_lds = g->n_shubs_lds;
     S.plink = D.plink;
     S.av = D.av;
     S.R = D.R;
@@ -1917,6 +1955,10 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
     S.tI = D.tI;
     S.tII = D.tII;
     S.ctr = D.ctr;
+    const int n_big_hubs = g->n_shubs - g->n_shubs_lds;
+    if (n_big_hubs > 0)  // the big hubs' neighbour filters for the edge tests below
+        hipLaunchKernelGGL(k_hub_filters<OffT>, dim3(n_big_hubs), dim3(kBlock), 0, g->stream, D.shubs,
+                           g->n_shubs_lds, D.card, D.col, D.hfilter);
     const unsigned long long *ictr = D.ictr;
     if (inc) {
         S.blist = nullptr;

@@ -208,6 +208,7 @@ struct HostTiles {
     std::vector<int32_t> rhubs, shubs, sfirst;
     std::vector<int32_t> gblk_off, gblk;  // batches: the row blocks of each graph
     int n_chunks_lds = 0;
+    int n_hubs_lds = 0;  // score hubs whose foreign list fits in LDS (listed first)
 };
 
 struct HostGraph : HostTiles {
@@ -276,7 +277,9 @@ static void cut_all(int64_t n, const std::vector<int64_t> &off, const std::vecto
     std::stable_partition(H.shubs.begin(), H.shubs.end(), [&](int32_t v) { return fgn[v] <= T.hub_list; });
     H.sfirst.assign(1, 0);
     H.n_chunks_lds = 0;
+    H.n_hubs_lds = 0;
     for (size_t h = 0; h < H.shubs.size(); ++h) {
+        if (fgn[H.shubs[h]] <= T.hub_list) H.n_hubs_lds = (int)h + 1;
         const int64_t nch = (fgn[H.shubs[h]] + kScoreTileP - 1) / kScoreTileP;
         for (int64_t c = 0; c < nch; ++c) H.schunk.push_back(make_int2((int)h, (int)c));
         H.sfirst.push_back((int32_t)H.schunk.size());
@@ -435,7 +438,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
                             (void **)&D.shub_first, (void **)&D.shub_chunk, (void **)&D.hub_part,
                             (void **)&D.rflag, (void **)&D.cflag, (void **)&D.hflag, (void **)&D.rlist,
                             (void **)&D.slist, (void **)&D.hlist, (void **)&D.part_rows, (void **)&D.wmax_part,
-                            (void **)&D.vrowb, (void **)&D.vscore};
+                            (void **)&D.vrowb, (void **)&D.vscore, (void **)&D.hfilter};
     for (void **p : tile_arrays) dev_free(g, p);
     const size_t N = (size_t)std::max<int64_t>(D.n, 1);
     g->n_rtiles = (int)H.rtiles.size();
@@ -444,6 +447,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
     g->n_shubs = (int)H.shubs.size();
     g->n_schunks = (int)H.schunk.size();
     g->n_schunks_lds = H.n_chunks_lds;
+    g->n_shubs_lds = H.n_hubs_lds;
     g->grid_rows = tile_grid(g->n_rhubs, g->n_rtiles);
     g->grid_score = tile_grid(g->n_schunks, g->n_stiles);
     const size_t nch = std::max<size_t>(H.schunk.size(), 1);
@@ -471,6 +475,7 @@ static rs_status upload_tiles(rs_graph *g, const HostTiles &H) {
         {(void **)&D.wmax_part, 8 * gr},
         {(void **)&D.vrowb, 4 * N},
         {(void **)&D.vscore, 4 * N},
+        {(void **)&D.hfilter, 4 * (size_t)kFilterWords * std::max<size_t>(H.shubs.size() - H.n_hubs_lds, 1)},
     };
     for (auto &r : reqs) {
         hipError_t e = dev_alloc(g, r.p, r.bytes);
