@@ -119,6 +119,7 @@ enum KernelId {
     K_HUB_SUM,
     K_TOPK_GRAPHS,
     K_WMAX_GRAPHS,
+    K_HUB_FILTERS,
     K_COUNT
 };
 

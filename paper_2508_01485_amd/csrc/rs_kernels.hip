@@ -1956,9 +1956,12 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
     S.tII = D.tII;
     S.ctr = D.ctr;
     const int n_big_hubs = g->n_shubs - g->n_shubs_lds;
-    if (n_big_hubs > 0)  // the big hubs' neighbour filters for the edge tests below
+    if (n_big_hubs > 0) {  // the big hubs' neighbour filters for the edge tests below
+        timing_begin(g, K_HUB_FILTERS, &ev);
         hipLaunchKernelGGL(k_hub_filters<OffT>, dim3(n_big_hubs), dim3(kBlock), 0, g->stream, D.shubs,
                            g->n_shubs_lds, D.card, D.col, D.hfilter);
+        timing_end(g, K_HUB_FILTERS, ev);
+    }
     const unsigned long long *ictr = D.ictr;
     if (inc) {
         S.blist = nullptr;

@@ -1524,7 +1524,7 @@ rs_status rs_read_gprime(rs_graph *g, int64_t *goff, int32_t *gcol) {
 
 static const char *kKernelNames[K_COUNT] = {
     "k_rows", "k_wmax", "k_score_hub", "k_score", "k_topk_hist", "k_topk_find", "k_topk_collect", "k_tie_rank", "k_final_order",
-    "k_hub_sum", "k_topk_graphs", "k_wmax_graphs"};
+    "k_hub_sum", "k_topk_graphs", "k_wmax_graphs", "k_hub_filters"};
 
 const char *rs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : nullptr; }
 
