@@ -244,6 +244,8 @@ struct DeviceGraph {
     unsigned int *vmark = nullptr;          // [n] kRowChanged | kAffected
     int32_t *vrowb = nullptr;               // [n] row block of each vertex
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
+    unsigned long long *wblk = nullptr;  // [64] per-workgroup maxima of k_wmax
+    unsigned int *wticket = nullptr;     // k_wmax's finishing ticket (zero between passes)
     uint32_t *hfilter = nullptr;  // [big hubs][kFilterWords] membership filter of each big hub's foreign neighbours
     uint8_t *rflag = nullptr, *cflag = nullptr, *hflag = nullptr;  // flags: row blocks, score-hub chunks, score hubs (whole)
     int32_t *elist = nullptr, *abin = nullptr;  // [n] changed rows; affected tile vertices by bin

@@ -717,18 +717,27 @@ __global__ __launch_bounds__(kBlock) void k_rows_inc(RowArgs<OffT> A, const unsi
     }
 }
 
-// w_max of a pass from the dense per-block maxima of the row kernel (one
-// workgroup of 1024 threads, eight loads per thread in flight together); the
-// other row totals are reduced only when a reader asks for them.
-__global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, int np, DevCounters *c) {
+// w_max of a pass from the dense per-block maxima of the row kernel: up to
+// kWmaxBlocks workgroups of 1,024 threads each take a contiguous slice
+// (eight loads per thread in flight together) and store its maximum; the
+// workgroup that finishes last (a ticket) takes the maximum of those and
+// resets the ticket.  A maximum does not depend on the order, so the bits are
+// those of a single workgroup's.  The other row totals are reduced only when
+// a reader asks for them.
+constexpr int kWmaxBlocks = 64;
+__global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, int np, unsigned long long *wblk,
+                                               unsigned int *ticket, DevCounters *c) {
     __shared__ unsigned long long s[16];
+    __shared__ bool last;
+    const int per = (np + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * per, hi = min(np, lo + per);
     unsigned long long w = 0;
-    for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 1024) {
+    for (int i0 = lo + threadIdx.x; i0 < hi; i0 += 8 * 1024) {
         unsigned long long q[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int i = i0 + j * 1024;
-            q[j] = i < np ? wpart[i] : 0ull;
+            q[j] = i < hi ? wpart[i] : 0ull;
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) w = max(w, q[j]);
@@ -739,7 +748,17 @@ __global__ __launch_bounds__(1024) void k_wmax(const unsigned long long *wpart, 
     if (threadIdx.x == 0) {
         unsigned long long m = 0;
         for (int i = 0; i < 16; ++i) m = max(m, s[i]);
+        wblk[blockIdx.x] = m;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        unsigned long long m = 0;
+        for (unsigned int i = 0; i < gridDim.x; ++i) m = max(m, ((volatile unsigned long long *)wblk)[i]);
         c->wmax_bits = m;
+        *ticket = 0u;
     }
 }
 
@@ -1915,7 +1934,8 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
         timing_end(g, K_ROWS, ev);
     }
     timing_begin(g, K_WMAX, &ev);
-    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(1024), 0, g->stream, D.wmax_part, g->grid_rows, D.ctr);
+    hipLaunchKernelGGL(k_wmax, dim3(std::max(1, std::min(kWmaxBlocks, (g->grid_rows + 8191) / 8192))), dim3(1024), 0,
+                       g->stream, D.wmax_part, g->grid_rows, D.wblk, D.wticket, D.ctr);
     timing_end(g, K_WMAX, ev);
     if (g->n_graphs > 0) {
         timing_begin(g, K_WMAX_GRAPHS, &ev);

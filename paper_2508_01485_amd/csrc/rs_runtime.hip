@@ -532,6 +532,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.abin, 4 * N},
         {(void **)&D.echunk, sizeof(int2) * (N + Z / 64 + 1)},
         {(void **)&D.ictr, 8 * (size_t)kIcCount},
+        {(void **)&D.wblk, 8 * 64},
+        {(void **)&D.wticket, 8},
         {(void **)&g->rem_cnt, 8 * 4},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
@@ -612,6 +614,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     if (e == hipSuccess) e = hipMemsetAsync(D.thist, 0, 4 * (size_t)kTopkBins, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.thist_c, 0, 4 * 256, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.ctr, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.wticket, 0, 8, s);
     if (e == hipSuccess) e = hipMemsetAsync(D.tstate, 0, sizeof(TopkState), s);
     if (e != hipSuccess) return hip_fail(e, "graph upload");
     const rs_status tst = upload_tiles(g, H);
