@@ -1156,8 +1156,13 @@ __device__ void typeI_scan(const ScoreArgs<OffT> &A, TypeIShared &T, HitBuf &H, 
 // fixed order).
 static_assert(kScoreTileV == kBlock && kScoreTileP == kBlock, "score unit size: one vertex and one pair per thread");
 
-struct ScoreUnitShared {
-    int w[kHubList];                 // foreign neighbours
+// A score unit's LDS: kW foreign neighbours (a tile's at most kScoreTileP,
+// an LDS hub's at most kHubList); tiles launch with the smaller form, which
+// leaves room for one more workgroup per CU.
+template <int kW>
+struct ScoreUnitSharedT {
+    static constexpr int kWords = kW;
+    int w[kW];                       // foreign neighbours
     int pb[kScoreTileV + 1];         // tile: first pair of each vertex
     unsigned short pu[kScoreTileP];  // tile: vertex of each pair
     int ws[kBlock / 64];
@@ -1176,6 +1181,8 @@ struct ScoreUnitShared {
         } e;
     } u;
 };
+using ScoreUnitShared = ScoreUnitSharedT<kHubList>;
+using ScoreTileShared = ScoreUnitSharedT<kScoreTileP>;
 
 // A hub chunk's partial: block tree sum of the lanes' terms (thread 0 gets it).
 __device__ __forceinline__ void chunk_tree(double x, long long y1, long long y2, double *red,
@@ -1197,8 +1204,9 @@ __device__ __forceinline__ void chunk_tree(double x, long long y1, long long y2,
 
 // Edge tests of a unit's type-I scan: u's foreign list is in LDS (a tile
 // vertex's slice, or a hub's whole list).
+template <class SU>
 struct TileEdge {
-    const ScoreUnitShared *S;
+    const SU *S;
     __device__ __forceinline__ bool operator()(int p, int y) const {
         const int i = S->pu[p];
         return lds_has(S->w, S->pb[i], S->pb[i + 1], y);
@@ -1212,9 +1220,11 @@ struct HubListEdge {
 
 // vl: a unit of listed vertices vl[0, vn) (the incremental pass's rescored
 // vertices) instead of the tile idx.
-template <typename OffT>
-__device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hub_unit, int idx, double wmax,
+template <typename OffT, class SU>
+__device__ void score_unit(const ScoreArgs<OffT> &A, SU &S, bool hub_unit_arg, int idx, double wmax,
                            const int32_t *vl = nullptr, int vn = 0) {
+    // a hub chunk needs room for the hub's whole foreign list
+    const bool hub_unit = SU::kWords >= kHubList && hub_unit_arg;
     const int tid = threadIdx.x;
     // ---- prologue: lay out the unit's pairs
     int v0 = 0, nv = 0, total = 0, dp = 0, deg = 0, pb = 0;    // tile
@@ -1308,7 +1318,7 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, ScoreUnitShared &S, bool hu
         E.n = hdp;
         typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
     } else {
-        TileEdge E;
+        TileEdge<SU> E;
         E.S = &S;
         typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
     }
@@ -1439,20 +1449,40 @@ __global__ __launch_bounds__(kBlock) void k_hub_filters(const int32_t *hubs, int
     for (int i = threadIdx.x; i < kFilterWords; i += kBlock) out[i] = f[i];
 }
 
-// Algorithm 1 Step 3 (Eq. RSI) for every border vertex of the tiles and of
-// the LDS-sized score hubs (their chunks first, so they start early).
+// Algorithm 1 Step 3 (Eq. RSI) for every border vertex of the LDS-sized
+// score hubs (one chunk of 256 pairs per workgroup) ...
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_score_lds_hubs(ScoreArgs<OffT> A) {
+    __shared__ ScoreUnitShared S;
+    score_unit(A, S, true, (int)blockIdx.x, bitsd(A.ctr->wmax_bits));
+}
+
+// ... and of the score tiles (tile t of XCD x = t / per runs on a block of
+// that XCD: blocks are dealt to the XCDs round-robin, so consecutive tiles
+// share an L2).
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs<OffT> A) {
+    __shared__ ScoreTileShared S;
+    const int idx = tile_of_block((int)blockIdx.x, 0, A.tiles_per_xcd);
+    if (idx < A.n_tiles) score_unit(A, S, false, idx, bitsd(A.ctr->wmax_bits));
+}
+
+// Both in one launch (the LDS hubs' chunks first, so they start early, then
+// the tiles), with the larger LDS form for every workgroup: used when the
+// LDS hubs are few, where a launch of their own would end on one chunk's
+// latency with nothing beside it.
+constexpr int kSplitHubChunks = 4096;
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_score_all(ScoreArgs<OffT> A) {
     __shared__ ScoreUnitShared S;
-    const double wmax = bitsd(A.ctr->wmax_bits);
     const int b = (int)blockIdx.x;
     const bool hub_unit = b < A.n_chunks_lds;
     const int idx = hub_unit ? b : tile_of_block(b, A.n_chunks_lds, A.tiles_per_xcd);
-    if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, wmax);
+    if (hub_unit || idx < A.n_tiles) score_unit(A, S, hub_unit, idx, bitsd(A.ctr->wmax_bits));
 }
 
 // ... and of the hubs too large for LDS (chunks n_chunks_lds ...); partials
-// after the tile kernel's.
+// summed by k_hub_sum after the score kernels.
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_score_hub(ScoreArgs<OffT> A) {
     __shared__ ScoreHubBigShared S;
@@ -1997,12 +2027,16 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
             hipLaunchKernelGGL(k_score_hub<OffT>, dim3(n_big), dim3(kBlock), 0, g->stream, S);
             timing_end(g, K_SCORE_HUB, ev);
         }
-        if (grid_main > 0) {
-            S.blist = nullptr;
-            timing_begin(g, K_SCORE, &ev);
-            hipLaunchKernelGGL(k_score<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
-            timing_end(g, K_SCORE, ev);
+        S.blist = nullptr;
+        const int grid_tiles = grid_main - g->n_schunks_lds;  // the tiles, rounded up to the 8 XCDs
+        timing_begin(g, K_SCORE, &ev);
+        if (g->n_schunks_lds >= kSplitHubChunks) {  // many LDS hubs: tiles with the smaller LDS form
+            hipLaunchKernelGGL(k_score_lds_hubs<OffT>, dim3(g->n_schunks_lds), dim3(kBlock), 0, g->stream, S);
+            if (grid_tiles > 0) hipLaunchKernelGGL(k_score<OffT>, dim3(grid_tiles), dim3(kBlock), 0, g->stream, S);
+        } else if (grid_main > 0) {
+            hipLaunchKernelGGL(k_score_all<OffT>, dim3(grid_main), dim3(kBlock), 0, g->stream, S);
         }
+        timing_end(g, K_SCORE, ev);
     }
     if (g->n_shubs > 0) {
         timing_begin(g, K_HUB_SUM, &ev);
