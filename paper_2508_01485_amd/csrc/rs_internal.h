@@ -156,6 +156,12 @@ struct __align__(16) PairRec {
     int back;
 };
 
+// An out-list entry x -> y: the indices of the row entries (x, y) in x's row
+// and (y, x) in y's row (a type-I hit reads the pair facts at both).
+struct __align__(16) OutEnt {
+    long long xy, yx;
+};
+
 // A link slot (u, w): the index of the row entry (w, u) and w's out-list
 // range (tombstones included).
 struct __align__(16) PairLink {
@@ -246,6 +252,7 @@ struct DeviceGraph {
     int32_t *vscore = nullptr;              // [n] score tile block, or -1 - score hub index
     unsigned long long *wblk = nullptr;  // [64] per-workgroup maxima of k_wmax
     unsigned int *wticket = nullptr;     // k_wmax's finishing ticket (zero between passes)
+    OutEnt *oe = nullptr;         // [out-list entries] row entries of each out-list entry's edge
     uint32_t *hfilter = nullptr;  // [big hubs][kFilterWords] membership filter of each big hub's foreign neighbours
     uint8_t *rflag = nullptr, *cflag = nullptr, *hflag = nullptr;  // flags: row blocks, score-hub chunks, score hubs (whole)
     int32_t *elist = nullptr, *abin = nullptr;  // [n] changed rows; affected tile vertices by bin
@@ -322,6 +329,7 @@ struct rs_graph {
     int n_rtiles = 0, n_rhubs = 0, n_stiles = 0, n_shubs = 0, n_schunks = 0;
     int n_schunks_lds = 0;               // chunks of hubs whose foreign list fits in LDS (listed first)
     int n_shubs_lds = 0;                 // those hubs (the big hubs follow)
+    int64_t n_out = 0;                   // out-list entries (G' edges)
     int grid_rows = 0, grid_score = 0;   // hubs first, then the tiles in XCD-major order
     std::vector<int32_t> h_new2old, h_old2new, h_comm2orig;
     rs::DeviceGraph d;
@@ -381,6 +389,7 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
                                  unsigned long long *d_removed_edges);
 rs_status launch_links(rs_graph *g);
 rs_status launch_col_labels(rs_graph *g);
+rs_status launch_out_entries(rs_graph *g);
 rs_status launch_incremental_marks(rs_graph *g);
 rs_status launch_topk_graphs(rs_graph *g, int64_t k, int32_t *d_ids, double *d_scores, int64_t *d_counts);
 rs_status launch_gather_scores(rs_graph *g, double *d_out, int raw);

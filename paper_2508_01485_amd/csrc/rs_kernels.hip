@@ -802,6 +802,7 @@ struct ScoreArgs {
     const VCard *card;
     const PairRec *prec;    // pair facts at the foreign row entries, written by the row pass
     const uint32_t *hfilter;  // big hubs' neighbour filters (hub n_hubs_lds + i at i * kFilterWords)
+    const OutEnt *oe;         // each out-list entry's row entries (x, y) and (y, x)
     int n_hubs_lds;
     const PairLink *plink;  // link slots: reverse entry and out-list range of each G' entry
     const double *av;       // [n] a_v of the row pass
@@ -870,6 +871,19 @@ __device__ __forceinline__ bool lds_has(const int *a, int lo, int hi, int x) {
 // Out-lists keep removed entries complemented (~id) in place, so a list is
 // ascending in the decoded id.
 __device__ __forceinline__ int out_id(int x) { return x < 0 ? ~x : x; }
+
+// Position of the live id x among the n out-list entries a[0..n) in LDS, or -1.
+__device__ __forceinline__ int lds_find_out(const int *a, int n, int x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (out_id(a[mid]) < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < n && a[lo] == x ? lo : -1;
+}
 
 // Whether the n out-list entries a[0..n) in LDS hold the live id x.
 __device__ __forceinline__ bool lds_has_out(const int *a, int n, int x) {
@@ -1024,7 +1038,8 @@ struct TypeIShared {
 };
 struct HitBuf {
     int hitp[kHitCap];     // pair of each hit (per wavefront: ascending)
-    int hity[kHitCap];     // third vertex of each hit
+    int hitc[kHitCap];     // where the edge test found (u, v): the edge test's code
+    int hito[kHitCap];     // the out-list position of v (the entry w -> v)
     double hitv[kHitCap];  // the hit's two ordered triads
 };
 
@@ -1038,21 +1053,19 @@ __device__ __forceinline__ void wave_sync() {
 
 // The terms of a wavefront's nb held hits (from slot h0), then each pair's
 // own lane adds its hits (a contiguous range of the list) in list order.
-template <typename OffT>
-__device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const TypeIShared &T, HitBuf &H, int h0, int nb,
-                                            int lane, int me, bool mine, double &val, int &t1) {
+template <class Edge, typename OffT>
+__device__ __forceinline__ void typeI_flush(const ScoreArgs<OffT> &A, const TypeIShared &T, HitBuf &H, const Edge &edge,
+                                            int h0, int nb, int lane, int me, bool mine, double &val, int &t1) {
     for (int h = lane; h < nb; h += 64) {
-        const int q = H.hitp[h0 + h], v = H.hity[h0 + h];
-        const int w = T.pw[q], cu = T.pcu[q];
+        // the weights of the triangle {u, w, v} are the pair facts at its
+        // row entries: w_v(C(u)) at (v, u), w_w(C(v)) at (w, v), w_v(C(w))
+        // at (v, w) (the out-list entry w -> v holds the last two indices)
+        const int q = H.hitp[h0 + h];
         const double W = T.pW[q];
-        const VCard cv = A.card[v];
-        const VCard cw = A.card[w];
-        const int s1 = card_find(cv, A.reckey, cu);
-        const int s2 = card_find(cv, A.reckey, cw.lab);
-        const int s3 = card_find(cw, A.reckey, cv.lab);
-        const double w_vu = s1 >= 0 ? A.recdat[cv.off + s1].w : 0.0;
-        const double w_vw = s2 >= 0 ? A.recdat[cv.off + s2].w : 0.0;
-        const double w_wv = s3 >= 0 ? A.recdat[cw.off + s3].w : 0.0;
+        const OutEnt e = A.oe[H.hito[h0 + h]];
+        const double w_wv = A.prec[e.xy].w;
+        const double w_vw = A.prec[e.yx].w;
+        const double w_vu = edge.wvu(A, T, H.hitc[h0 + h]);
         H.hitv[h0 + h] = cbrt(w_vu * w_wv * W) + cbrt(W * w_vw * w_vu);
     }
     wave_sync();
@@ -1107,12 +1120,13 @@ __device__ void typeI_scan(const ScoreArgs<OffT> &A, TypeIShared &T, HitBuf &H, 
     wave_sync();
     int nb = 0;  // held hits of this wavefront
     for (int base = 0; base < total; base += 64 * kScanR) {
-        int y[kScanR], p[kScanR];
+        int y[kScanR], p[kScanR], op[kScanR];
 #pragma unroll
         for (int r = 0; r < kScanR; ++r) {
             const int i = base + r * 64 + lane;
             p[r] = w0;
             y[r] = -1;
+            op[r] = 0;
             if (i < total) {
                 int lo = 0, hi = 64;  // the last pair of the wavefront whose first item is <= i
                 while (hi - lo > 1) {
@@ -1123,23 +1137,26 @@ __device__ void typeI_scan(const ScoreArgs<OffT> &A, TypeIShared &T, HitBuf &H, 
                         hi = mid;
                 }
                 p[r] = w0 + lo;
-                y[r] = A.outl[T.ioo[w0 + lo] + (i - T.ibeg[w0 + lo])];
+                op[r] = T.ioo[w0 + lo] + (i - T.ibeg[w0 + lo]);
+                y[r] = A.outl[op[r]];
             }
         }
 #pragma unroll
         for (int r = 0; r < kScanR; ++r) {
-            const bool hit = y[r] >= 0 && y[r] != T.pv[p[r]] && edge(p[r], y[r]);
+            int code = 0;
+            const bool hit = y[r] >= 0 && y[r] != T.pv[p[r]] && edge(p[r], y[r], code);
             const unsigned long long m = __ballot(hit);
             if (hit) {
                 const int s = nb + __popcll(m & ((1ull << lane) - 1ull));
                 H.hitp[h0 + s] = p[r];
-                H.hity[h0 + s] = y[r];
+                H.hitc[h0 + s] = code;
+                H.hito[h0 + s] = op[r];
             }
             nb += __popcll(m);
         }
         if (nb > kWaveHitCap - 64 * kScanR || (base + 64 * kScanR >= total && nb > 0)) {
             wave_sync();
-            typeI_flush(A, T, H, h0, nb, lane, tid, items > 0, val, t1);
+            typeI_flush(A, T, H, edge, h0, nb, lane, tid, items > 0, val, t1);
             nb = 0;
         }
     }
@@ -1205,17 +1222,36 @@ __device__ __forceinline__ void chunk_tree(double x, long long y1, long long y2,
 // Edge tests of a unit's type-I scan: u's foreign list is in LDS (a tile
 // vertex's slice, or a hub's whole list).
 template <class SU>
+// Each also gives a code for its hits, from which wvu() reads w_v(C(u)),
+// the pair fact at the row entry (v, u).
 struct TileEdge {
     const SU *S;
-    __device__ __forceinline__ bool operator()(int p, int y) const {
+    __device__ __forceinline__ bool operator()(int p, int y, int &code) const {
         const int i = S->pu[p];
-        return lds_has(S->w, S->pb[i], S->pb[i + 1], y);
+        const int k = lds_lower(S->w, S->pb[i], S->pb[i + 1], y);
+        code = k;  // (u, v) is the unit's pair k: its W is w_v(C(u))
+        return k < S->pb[i + 1] && S->w[k] == y;
+    }
+    template <typename OffT>
+    __device__ __forceinline__ double wvu(const ScoreArgs<OffT> &, const TypeIShared &T, int code) const {
+        return T.pW[code];
     }
 };
 struct HubListEdge {
     const int *w;
     int n;
-    __device__ __forceinline__ bool operator()(int, int y) const { return lds_has(w, 0, n, y); }
+    int cbase, ccnt;  // the chunk's pairs: list positions [cbase, cbase + ccnt)
+    long long go;     // the hub's first link slot
+    __device__ __forceinline__ bool operator()(int, int y, int &code) const {
+        const int k = lds_lower(w, 0, n, y);
+        code = k;  // (u, v) is the hub's pair k
+        return k < n && w[k] == y;
+    }
+    template <typename OffT>
+    __device__ __forceinline__ double wvu(const ScoreArgs<OffT> &A, const TypeIShared &T, int code) const {
+        if (code >= cbase && code < cbase + ccnt) return T.pW[code - cbase];
+        return A.prec[A.plink[go + code].e].w;
+    }
 };
 
 // vl: a unit of listed vertices vl[0, vn) (the incremental pass's rescored
@@ -1316,6 +1352,9 @@ __device__ void score_unit(const ScoreArgs<OffT> &A, SU &S, bool hub_unit_arg, i
         HubListEdge E;
         E.w = S.w;
         E.n = hdp;
+        E.cbase = chunk * kBlock;
+        E.ccnt = total;
+        E.go = hgo;
         typeI_scan(A, S.ti, S.u.hits, items, E, val, t1);
     } else {
         TileEdge<SU> E;
@@ -1373,11 +1412,30 @@ struct HubOutEdge {
     long long uo0, uo1;    // out(u) in HBM
     const uint32_t *filt;  // u's neighbour filter
     int u;
-    __device__ __forceinline__ bool operator()(int, int y) const {
+    // code: the out-list position of the edge, times two, plus 1 when it is
+    // the entry v -> u (else u -> v)
+    __device__ __forceinline__ bool operator()(int, int y, int &code) const {
         const uint32_t h = filter_hash(y);
         if (!((filt[h >> 5] >> (h & 31)) & 1u)) return false;
-        if (stage ? lds_has_out(stage, n_stage, y) : out_has(outl, uo0, uo1, y)) return true;
-        return out_has(outl, oo[y], oo[y + 1], u);
+        long long o = -1;
+        if (stage) {
+            const int k = lds_find_out(stage, n_stage, y);
+            if (k >= 0) o = uo0 + k;
+        } else {
+            o = out_find(outl, uo0, uo1, y);
+        }
+        if (o >= 0) {
+            code = (int)(o << 1);
+            return true;
+        }
+        o = out_find(outl, oo[y], oo[y + 1], u);
+        code = (int)(o << 1) | 1;
+        return o >= 0;
+    }
+    template <typename OffT>
+    __device__ __forceinline__ double wvu(const ScoreArgs<OffT> &A, const TypeIShared &, int code) const {
+        const OutEnt e = A.oe[code >> 1];
+        return A.prec[(code & 1) ? e.xy : e.yx].w;
     }
 };
 
@@ -1721,6 +1779,8 @@ struct LinkArgs {
     const int32_t *deg, *col, *lab, *cstart;
     const int64_t *goff, *oo;
     PairLink *plink;
+    const int32_t *outl;        // out-lists (tombstones complemented)
+    OutEnt *oe;                 // each out-list entry's row entries
     const unsigned int *vmark;  // after removals: kRowChanged marks the rows that changed
     const VCard *card;          // the last pass's own-run bounds [p, q) of the unchanged rows
 };
@@ -1785,6 +1845,8 @@ static LinkArgs<OffT> link_args(rs_graph *g) {
     L.vmark = D.vmark;
     L.card = D.card;
     L.plink = D.plink;
+    L.outl = D.outl;
+    L.oe = D.oe;
     return L;
 }
 
@@ -1800,6 +1862,49 @@ static rs_status links_t(rs_graph *g) {
 }
 
 rs_status launch_links(rs_graph *g) { return g->d.off64 ? links_t<long long>(g) : links_t<int32_t>(g); }
+
+// Each out-list entry x -> y (at load): the indices of the row entries
+// (x, y) and (y, x); the owner x is the last with oo[x] <= o.
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k_out_entries(LinkArgs<OffT> L, long long n, long long n_out) {
+    for (long long o = (long long)blockIdx.x * kBlock + threadIdx.x; o < n_out; o += (long long)gridDim.x * kBlock) {
+        long long lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const long long mid = (lo + hi) >> 1;
+            if (L.oo[mid] <= o)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int x = (int)lo;
+        const int y = out_id(L.outl[o]);
+        const long long xb = (long long)L.off[x], yb = (long long)L.off[y];
+        const int32_t *rows[2] = {L.col + xb, L.col + yb};
+        const int ds[2] = {L.deg[x], L.deg[y]};
+        const int keys[2] = {y, x};
+        int k[2];
+        lower_n<2, true>(rows, ds, keys, k);
+        OutEnt e;
+        e.xy = xb + k[0];
+        e.yx = yb + k[1];
+        L.oe[o] = e;
+    }
+}
+
+template <typename OffT>
+static rs_status out_entries_t(rs_graph *g) {
+    DeviceGraph &D = g->d;
+    const long long n_out = g->n_out;
+    if (n_out == 0) return RS_OK;
+    hipLaunchKernelGGL(k_out_entries<OffT>, dim3(grid_for(n_out, kBlock, 65536)), dim3(kBlock), 0, g->stream,
+                       link_args<OffT>(g), (long long)D.n, n_out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e, "out-entry launch");
+}
+
+rs_status launch_out_entries(rs_graph *g) {
+    return g->d.off64 ? out_entries_t<long long>(g) : out_entries_t<int32_t>(g);
+}
 
 // Each entry's neighbour community (once at load; compaction moves it with
 // the entry): the row pass reads it in place of the id and its label.
@@ -1995,6 +2100,7 @@ static rs_status score_pass_t(rs_graph *g, bool inc) {
     S.card = D.card;
     S.prec = D.prec;
     S.hfilter = D.hfilter;
+    S.oe = D.oe;
     S.n_hubs_lds = g->n_shubs_lds;
     S.plink = D.plink;
     S.av = D.av;
@@ -3607,6 +3713,25 @@ __global__ __launch_bounds__(kBlock) void k_mark_link(LinkArgs<OffT> L, unsigned
             }
             const int kw = ew < pw ? ew : ew - (qw - pw);
             L.plink[L.goff[w] + kw].e = rb + j;
+            {
+                // the out-list entry of {v, w} (in the list of the lower
+                // rank: load-time foreign degree, then id) gets both entries
+                const long long fv = L.goff[v + 1] - L.goff[v], fw = L.goff[w + 1] - L.goff[w];
+                const bool v_low = fv < fw || (fv == fw && v < w);
+                const int a = v_low ? v : w, bkey = v_low ? w : v;
+                const long long o0 = L.oo[a];
+                const int32_t *orow[1] = {L.outl + o0};
+                const int od[1] = {(int)(L.oo[a + 1] - o0)};
+                const int okey[1] = {bkey};
+                int ok[1];
+                lower_n<1, true>(orow, od, okey, ok);
+                if (ok[0] < od[0] && L.outl[o0 + ok[0]] == bkey) {
+                    OutEnt e;
+                    e.xy = v_low ? rb + j : wb + ew;
+                    e.yx = v_low ? wb + ew : rb + j;
+                    L.oe[o0 + ok[0]] = e;
+                }
+            }
             const int sw = vscore[w];
             whub = sw < 0 && !wch;
             if (whub) {

@@ -506,6 +506,9 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     D.nnz = nnz;
     D.k = (int32_t)H.comm2orig.size();
     D.off64 = nnz > (int64_t)INT32_MAX || g->wide_offsets;
+    if (H.outl.size() >= ((size_t)1 << 30))
+        return fail(RS_ERR_RANGE, "more than 2^30 edges between communities (out-list positions are 30-bit in hit records)");
+    g->n_out = (int64_t)H.outl.size();
     const size_t N = (size_t)std::max<int64_t>(n, 1), Z = (size_t)std::max<int64_t>(nnz, 1);
     const size_t offb = D.off64 ? 8 : 4;
     struct Req {
@@ -536,6 +539,7 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
         {(void **)&D.wticket, 8},
         {(void **)&g->rem_cnt, 8 * 4},
         {(void **)&D.outl, 4 * std::max<size_t>(H.outl.size(), 1)},
+        {(void **)&D.oe, sizeof(OutEnt) * std::max<size_t>(H.outl.size(), 1)},
         {(void **)&D.reckey, 4 * Z},
         {(void **)&D.recdat, sizeof(RecDat) * Z},
         {(void **)&D.card, sizeof(VCard) * N},
@@ -625,6 +629,8 @@ static rs_status upload(rs_graph *g, HostGraph &H, int64_t n, int64_t nnz, bool 
     if (lst != RS_OK) return lst;
     const rs_status rst = launch_links(g);  // each G' entry's reverse entry and out-list range
     if (rst != RS_OK) return rst;
+    const rs_status ost = launch_out_entries(g);  // each out-list entry's two row entries
+    if (ost != RS_OK) return ost;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "pair-slot map");
     if (keep) {
