@@ -261,9 +261,9 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
     const OffT e0 = (OffT)tl.e0;
     const int TE = tl.te;
     for (int x = tid; x < kRowTile / 32; x += kBlock) S.bm[x] = 0u;
-    fill_tables(S.tab);
     // the tile's entries and the facts of this thread's vertices, all
-    // independent loads issued together
+    // independent loads issued together (the tables are filled while they
+    // are in flight)
     int L[kRowU];
 #pragma unroll
     for (int i = 0; i < kRowU; ++i) {
@@ -286,6 +286,7 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
             vgo[j] = A.goff[v0 + i];
         }
     }
+    fill_tables(S.tab);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kVU; ++j)
@@ -389,21 +390,19 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
         rd.w = w;
         A.recdat[idx] = rd;
         acc.wmax = fmax(acc.wmax, w);
-    }
-    // pair facts at the foreign entries: entry (w, u) gets the record of
-    // C(u) in w's row (contiguous writes along the runs)
-    for (int e = tid; e < TE; e += kBlock) {
-        const int r = run_index(S, e) + (int)((S.mask[e >> 6] >> (e & 63)) & 1ull) - 1;
-        const int lb = S.runlab[r];
-        if (lb < 0) continue;  // removed tail
-        const int i = S.runv[r];
-        if (lb == S.vlab[i]) continue;  // own community
-        const int f = (int)S.runpos[r + 1] - (int)S.runpos[r];
-        PairRec pr;
-        pr.w = weight_present_t(S.tab, S.vd[i], S.vX[i], S.vell[i], f);
-        pr.f = f;
-        pr.back = e - (int)S.runpos[r];
-        A.prec[e0 + e] = pr;
+        // pair facts at the run's entries when it is another community's:
+        // entry (w, u) gets the record of C(u) in w's row (the weight computed
+        // once per run; neighbouring threads' runs are neighbouring entries)
+        if (lb != S.vlab[i]) {
+            const int p0 = (int)S.runpos[r];
+            PairRec pr;
+            pr.w = w;
+            pr.f = f;
+            for (int t = 0; t < f; ++t) {
+                pr.back = t;
+                A.prec[e0 + (OffT)(p0 + t)] = pr;
+            }
+        }
     }
 }
 
