@@ -60,7 +60,7 @@ constexpr int kTopkBins = 65536;     // 16-bit digits of the 96-bit ranking key
 constexpr int kHistChunk = 49152;    // keys per block of the histogram kernel (< 2^16)
 constexpr int kTieCap = 16384;       // largest tie class ranked through sorted chunks
 constexpr int kSortCap = 2048;       // final lists up to this size are bitonic-sorted in LDS
-constexpr int kSmallCap = 4096;      // final list + threshold bin up to this size: one LDS sort
+constexpr int kSmallCap = 4096;      // fewest candidates (final list + threshold bin) the common path ranks
 constexpr int kWorkBlocks = 1024;    // blocks (and partials) of the on-demand W1 count
 constexpr int kMaxReachSources = 1024;  // sources per rs_reachable_communities call
 constexpr size_t kStaticScratchBytes = size_t(32) << 20;  // per-device array of rs_reachable_communities_static

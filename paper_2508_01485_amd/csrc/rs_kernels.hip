@@ -274,23 +274,23 @@ __device__ void row_tile(const RowArgs<OffT> &A, RowTileShared &S, int t, RowAcc
     long long vgo[kVU];
 #pragma unroll
     for (int j = 0; j < kVU; ++j) {
+        // a slot past the tile loads the tile's first vertex (tiles are never
+        // empty), and every use below skips it: no branch around the loads,
+        // which would wait for them before the next slot's
         const int i = tid + j * kBlock;
-        vo[j] = vc[j] = vdeg[j] = vlab[j] = 0;
-        vgo[j] = 0;
-        if (i < nv) {
-            const OffT a0 = A.off[v0 + i], a1 = A.off[v0 + i + 1];
-            vo[j] = (int)(a0 - e0);
-            vc[j] = (int)(a1 - a0);
-            vdeg[j] = A.deg[v0 + i];
-            vlab[j] = A.lab[v0 + i];
-            vgo[j] = A.goff[v0 + i];
-        }
+        const int ic = i < nv ? i : 0;
+        const OffT a0 = A.off[v0 + ic], a1 = A.off[v0 + ic + 1];
+        vo[j] = (int)(a0 - e0);
+        vc[j] = (int)(a1 - a0);
+        vdeg[j] = A.deg[v0 + ic];
+        vlab[j] = A.lab[v0 + ic];
+        vgo[j] = A.goff[v0 + ic];
     }
     fill_tables(S.tab);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kVU; ++j)
-        if (vc[j] > 0) atomicOr(&S.bm[vo[j] >> 5], 1u << (vo[j] & 31));
+        if (tid + j * kBlock < nv && vc[j] > 0) atomicOr(&S.bm[vo[j] >> 5], 1u << (vo[j] & 31));
     if (lane == 63) S.wlast[wave] = L[kRowU - 1];
     __syncthreads();
     unsigned long long m[kRowU];
@@ -2209,6 +2209,10 @@ __device__ __forceinline__ unsigned long long score_bits(double r) {
 // Level-0 digit: the top 16 bits of the key (score bits only).
 __device__ __forceinline__ unsigned int digit0_of(double r) { return (unsigned int)(score_bits(r) >> 48); }
 
+// Level-0 bins: a score key's sign bit is clear, so its top 16 bits take
+// values below 2^15.
+constexpr int kHist0Bins = 32768;
+
 // Level-0 histogram: each block (1024 threads) counts a contiguous chunk
 // (< 2^16 keys) in an LDS histogram of 16-bit counters packed two per word
 // (digit 0, which holds every zero score, is counted in registers), then adds
@@ -2216,6 +2220,8 @@ __device__ __forceinline__ unsigned int digit0_of(double r) { return (unsigned i
 // bins to a 256-bin coarse histogram.  Few large blocks keep the number of
 // global atomics (one per non-zero bin per block) small.
 constexpr int kHistThreads = 1024;
+constexpr int kHistPer = 16;  // keys per thread per step, loads all in flight together
+
 // Global slot of level-0 bin b: consecutive bins 256 bytes apart (bin
 // hi * 1024 + lo at lo * 64 + hi, a bijection of [0, 65536)).  Scores share
 // their leading bits, so a pass fills a few hundred neighbouring bins, and
@@ -2223,29 +2229,53 @@ constexpr int kHistThreads = 1024;
 // those atomics no longer queue on a handful of lines.
 __device__ __forceinline__ unsigned int hperm(unsigned int b) { return ((b & 1023u) << 6) | (b >> 10); }
 
+// Loads of one step of a chunk scan [lo, hi) (hi > lo): kPer keys per thread,
+// kThreads apart from v0.  Indexes past the chunk load its last key, which
+// the caller skips, so no branch or select touches a loaded value before its
+// use (either would wait for the load).  The flags are kept one per register:
+// packed bytes would wait for their loads too.
+template <int kPer, int kThreads>
+__device__ __forceinline__ void load_keys(const double *R, const uint8_t *alive, long long v0, long long hi,
+                                          double (&r)[kPer], unsigned int (&al)[kPer]) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const long long v = v0 + (long long)j * kThreads;
+        const long long vc = v < hi ? v : hi - 1;
+        r[j] = R[vc];
+        al[j] = alive[vc];
+    }
+}
+
+// Block 0 also resets the selection's list counters for the collect kernel.
 __global__ __launch_bounds__(kHistThreads) void k_topk_hist(const double *R, const uint8_t *alive, long long n,
                                                             long long chunk, unsigned int *hist,
-                                                            unsigned int *coarse) {
-    __shared__ uint4 sh4[kTopkBins / 8];
+                                                            unsigned int *coarse, TopkState *st) {
+    __shared__ uint4 sh4[kHist0Bins / 8];
     __shared__ unsigned int s_zero[kHistThreads / 64];
     unsigned int *sh = (unsigned int *)sh4;
-    for (int i = threadIdx.x; i < kTopkBins / 8; i += kHistThreads) sh4[i] = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_final = 0;
+        st->n_tie = 0;
+        st->overflow = 0;
+    }
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
+    constexpr long long kStep = (long long)kHistPer * kHistThreads;
+    const int steps = (int)((hi - lo + kStep - 1) / kStep);
+    if (steps <= 0) return;  // (uniform; the grid never holds an empty chunk)
     unsigned int zeros = 0;
-    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += 8 * kHistThreads) {
-        double r[8];
-        uint8_t al[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {  // independent loads, all in flight together
-            const long long v = v0 + (long long)j * kHistThreads;
-            r[j] = v < hi ? R[v] : 0.0;
-            al[j] = v < hi ? alive[v] : (uint8_t)0;
+    for (int s = 0; s < steps; ++s) {
+        const long long v0 = lo + (long long)s * kStep + threadIdx.x;
+        double r[kHistPer];
+        unsigned int al[kHistPer];
+        load_keys<kHistPer, kHistThreads>(R, alive, v0, hi, r, al);
+        if (s == 0) {  // clear the LDS histogram while the first loads are in flight
+            for (int i = threadIdx.x; i < kHist0Bins / 8; i += kHistThreads) sh4[i] = make_uint4(0u, 0u, 0u, 0u);
+            __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (!al[j]) continue;
+        for (int j = 0; j < kHistPer; ++j) {
+            if (v0 + (long long)j * kHistThreads >= hi || !al[j]) continue;
             const unsigned int dig = digit0_of(r[j]);
             if (dig == 0u)
                 ++zeros;
@@ -2257,104 +2287,121 @@ __global__ __launch_bounds__(kHistThreads) void k_topk_hist(const double *R, con
     for (int o = 32; o > 0; o >>= 1) zeros += __shfl_xor(zeros, o);
     if ((threadIdx.x & 63) == 0) s_zero[threadIdx.x >> 6] = zeros;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int z = 0;
-        for (int w = 0; w < kHistThreads / 64; ++w) z += s_zero[w];
-        sh[0] += z;  // bin 0 is the low half of word 0 (z < 2^16: the chunk is smaller)
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kTopkBins / 8; i += kHistThreads) {
+    // flush: thread t takes the 16-byte words t, t + 1024, ... (8 bins each);
+    // the 32 words of a coarse bin are 32 consecutive lanes of one wavefront,
+    // whose sums a shuffle reduction adds.  Wavefronts whose words are all
+    // zero (most: scores fill a few hundred bins) skip both.
+    static_assert(kHist0Bins / 8 % kHistThreads == 0, "whole wavefronts per flush step");
+    for (int i = threadIdx.x; i < kHist0Bins / 8; i += kHistThreads) {
         const uint4 x = sh4[i];
-        const unsigned int w[4] = {x.x, x.y, x.z, x.w};
+        unsigned int w[4] = {x.x, x.y, x.z, x.w};
+        if (i == 0) {  // bin 0 (the low half of word 0) holds no LDS count: the zeros (< 2^16: the chunk is smaller)
+            unsigned int z = 0;
+            for (int q = 0; q < kHistThreads / 64; ++q) z += s_zero[q];
+            w[0] += z;
+        }
+        unsigned int cs = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cs += (w[t] & 0xffffu) + (w[t] >> 16);
+        if (!__any(cs != 0u)) continue;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (w[t] & 0xffffu) atomicAdd(&hist[hperm(8 * i + 2 * t)], w[t] & 0xffffu);
             if (w[t] >> 16) atomicAdd(&hist[hperm(8 * i + 2 * t + 1)], w[t] >> 16);
         }
-    }
-    // coarse histogram: thread t < 256 sums fine bins [256 t, 256 t + 256)
-    // (16-byte words [32 t, 32 t + 32), visited in a skewed order to spread
-    // LDS banks)
-    static_assert(kTopkBins == 256 * 256, "256 coarse bins of 256 fine bins");
-    if (threadIdx.x < 256) {
-        unsigned int cs = 0;
-        for (int j = 0; j < 32; ++j) {
-            const uint4 x = sh4[32 * threadIdx.x + ((j + threadIdx.x) & 31)];
-            cs += (x.x & 0xffffu) + (x.x >> 16) + (x.y & 0xffffu) + (x.y >> 16) + (x.z & 0xffffu) + (x.z >> 16) +
-                  (x.w & 0xffffu) + (x.w >> 16);
-        }
-        if (cs) atomicAdd(&coarse[threadIdx.x], cs);
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) cs += __shfl_xor(cs, o);
+        if ((threadIdx.x & 31) == 0 && cs) atomicAdd(&coarse[i >> 5], cs);
     }
 }
 
-// Level-0 threshold (one workgroup): reset the selection state for k, find
-// the coarse bin where the count from the top reaches k, then the fine bin
-// inside it; clear the coarse histogram (the collect kernel clears the fine
-// one).
-__device__ __forceinline__ long long block_incl_scan_ll(long long x, long long *ws) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// The level-0 threshold, found by wavefront 0 of every block of the collect
+// kernel from the finished histograms, with no barrier: lane l holds the
+// positions 4l .. 4l + 3 of 256 counts in descending bin order.  wave_find
+// returns, in every lane, the position where the running count reaches k,
+// the count above it and the count at it (k <= the total; the caller checks).
+struct Thresh0 {
+    unsigned int bin;
+    bool done;  // the bin is taken whole
+};
+
+__device__ __forceinline__ void wave_find(const long long (&c)[4], long long k, int &pos, long long &above,
+                                          long long &at, long long &total) {
+    const int lane = threadIdx.x & 63;
+    const long long s = c[0] + c[1] + c[2] + c[3];
+    long long incl = s;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(x, o);
-        if (lane >= o) x += y;
+        const long long y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
     }
-    if (lane == 63) ws[wave] = x;
-    __syncthreads();
-    long long base = 0;
-    for (int i = 0; i < wave; ++i) base += ws[i];
-    __syncthreads();
-    return base + x;
+    total = __shfl(incl, 63);
+    const long long excl = incl - s;
+    const unsigned long long m = __ballot(excl < k && k <= incl);
+    const int L = m ? __ffsll((long long)m) - 1 : 0;
+    long long a = __shfl(excl, L);
+    long long q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = __shfl(c[j], L);
+    int j = 0;
+    while (j < 3 && a + q[j] < k) a += q[j++];
+    pos = 4 * L + j;
+    above = a;
+    at = q[j];
 }
 
-__global__ __launch_bounds__(kBlock) void k_topk_find0(unsigned int *hist, unsigned int *coarse, TopkState *st,
-                                                       long long k) {
-    __shared__ long long ws[kBlock / 64];
-    __shared__ long long s_total;
-    __shared__ int s_c;
-    __shared__ long long s_above;
-    const int t = threadIdx.x;
-    // descending bins: thread t holds coarse bin 255 - t
-    const long long mc = coarse[kBlock - 1 - t];
-    const long long ic = block_incl_scan_ll(mc, ws);
-    if (t == kBlock - 1) s_total = ic;
-    if (ic - mc < k && k <= ic) {
-        s_c = kBlock - 1 - t;
-        s_above = ic - mc;
-    }
-    coarse[kBlock - 1 - t] = 0u;
-    __syncthreads();
-    if (s_total < k) {  // cannot happen for k <= live keys: take all
-        if (t == 0) {
-            st->k = k;
-            st->digit = 0;
-            st->thresh = 0;
-            st->above = 0;
-            st->take = 0;
-            st->binsize = 0;
-            st->n_final = 0;
-            st->n_tie = 0;
-            st->overflow = 0;
-            st->done = 1u;
+// Wavefront 0 of a 1024-thread block: the coarse bin where the count from
+// the top reaches k (cc: its lane's four coarse counts, loaded by the caller
+// before anything else so that waiting for them waits for no later load),
+// then the fine bin inside it.  Block 0 records the selection state for the
+// later kernels.  Returns through LDS after one barrier of the whole block.
+__device__ Thresh0 find_threshold0(const long long (&cc)[4], const unsigned int *hist, TopkState *st,
+                                   long long k) {
+    __shared__ Thresh0 s_res;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const bool publish = blockIdx.x == 0 && lane == 0;
+        int pc;
+        long long ac, mc, tot;
+        wave_find(cc, k, pc, ac, mc, tot);
+        Thresh0 res;
+        if (tot < k) {  // cannot happen for k <= live keys: take all
+            res.bin = 0u;
+            res.done = true;
+            if (publish) {
+                st->k = k;
+                st->digit = 0;
+                st->thresh = 0;
+                st->above = 0;
+                st->take = 0;
+                st->binsize = 0;
+                st->done = 1u;
+            }
+        } else {
+            const int c = 255 - pc;
+            long long fc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fc[j] = hist[hperm((unsigned int)(256 * c + 255 - (4 * lane + j)))];
+            int pf;
+            long long af, mf, tf;
+            wave_find(fc, k - ac, pf, af, mf, tf);
+            const long long above = ac + af;
+            res.bin = (unsigned int)(256 * c + 255 - pf);
+            res.done = k == above + mf;
+            if (publish) {
+                st->k = k;
+                st->digit = 0;
+                st->thresh = res.bin;
+                st->above = above;
+                st->take = k - above;
+                st->binsize = mf;
+                st->done = res.done ? 1u : 0u;
+            }
         }
-        return;
+        if (lane == 0) s_res = res;
     }
-    const int c = s_c;
-    const long long above_c = s_above;
-    const unsigned int bin = (unsigned int)(256 * c + 255 - t);
-    const long long mf = hist[hperm(bin)];
-    const long long inf = above_c + block_incl_scan_ll(mf, ws);
-    if (inf - mf < k && k <= inf) {
-        st->k = k;
-        st->digit = 0;
-        st->thresh = bin;
-        st->above = inf - mf;
-        st->take = k - (inf - mf);
-        st->binsize = mf;
-        st->n_final = 0;
-        st->n_tie = 0;
-        st->overflow = 0;
-        st->done = (k == inf) ? 1u : 0u;
-    }
+    __syncthreads();
+    return s_res;
 }
 
 // Histogram of digit j over a key list (refinement of a large tie class).
@@ -2484,60 +2531,67 @@ __device__ __forceinline__ void block_push(TopkKey *list, unsigned long long *co
 }
 
 // Level-0 collect: keys above the threshold bin go to the final list, keys in
-// it to the tie list.  Each block (1024 threads) scans one contiguous chunk
-// and stages its keys in LDS, then reserves room in each list with one atomic
-// (keys beyond the staging capacity are reserved one by one).
+// it to the tie list.  Each block (1024 threads) issues its first loads, finds
+// the threshold from the histograms while they are in flight, scans one
+// contiguous chunk and stages its keys in LDS, then reserves room in each
+// list with one atomic (keys beyond the staging capacity are reserved one by
+// one).  The histograms are cleared by the ranking kernel that follows.
 constexpr int kCollThreads = 1024;
+constexpr int kCollPer = 8;       // keys per thread per step, loads all in flight together
 constexpr int kCollStage = 2048;  // staged keys per list and block
 __global__ __launch_bounds__(kCollThreads) void k_topk_collect(const double *R, const int32_t *new2old,
                                                                const uint8_t *alive, long long n, long long chunk,
-                                                               TopkState *st, TopkKey *fin, TopkKey *tie,
-                                                               unsigned int *hist) {
+                                                               long long k, const unsigned int *hist,
+                                                               const unsigned int *coarse, TopkState *st,
+                                                               TopkKey *fin, TopkKey *tie) {
     __shared__ TopkKey sf[kCollStage], stl[kCollStage];
     __shared__ unsigned int s_nf, s_nt;
     __shared__ unsigned long long s_bf, s_bt;
-    // the fine histogram is no longer needed: clear it for the next call
-    for (int i = blockIdx.x * kCollThreads + threadIdx.x; i < kTopkBins / 4; i += gridDim.x * kCollThreads)
-        ((uint4 *)hist)[i] = make_uint4(0u, 0u, 0u, 0u);
     if (threadIdx.x == 0) {
         s_nf = 0u;
         s_nt = 0u;
     }
-    __syncthreads();
-    const unsigned int th = st->thresh;
-    const bool done = st->done != 0u;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    constexpr int kPer = 8;  // keys per thread per step, loads all in flight together
-    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += (long long)kPer * kCollThreads) {
-        double r[kPer];
-        uint8_t al[kPer];
+    constexpr long long kStep = (long long)kCollPer * kCollThreads;
+    const int steps = (int)((hi - lo + kStep - 1) / kStep);
+    if (steps <= 0) return;  // (uniform; the grid never holds an empty chunk, and block 0 starts at key 0)
+    // the coarse counts first (wavefront 0 searches them; every lane loads
+    // its four, no branch), then the first step's keys
+    long long cc[4];
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const long long v = v0 + (long long)j * kCollThreads;
-            r[j] = v < hi ? R[v] : 0.0;
-            al[j] = v < hi ? alive[v] : (uint8_t)0;
-        }
+    for (int j = 0; j < 4; ++j) cc[j] = (long long)coarse[255 - (4 * (threadIdx.x & 63) + j)];
+    double r[kCollPer];
+    unsigned int al[kCollPer];
+    load_keys<kCollPer, kCollThreads>(R, alive, lo + threadIdx.x, hi, r, al);
+    __builtin_amdgcn_sched_barrier(0);  // no use of the loaded keys moves above the search
+    const Thresh0 t0 = find_threshold0(cc, hist, st, k);
+    const unsigned int th = t0.bin;
+    const bool done = t0.done;
+    for (int s = 0;;) {
+        const long long v0 = lo + (long long)s * kStep + threadIdx.x;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            if (!al[j]) continue;
+        for (int j = 0; j < kCollPer; ++j) {
+            if (v0 + (long long)j * kCollThreads >= hi || !al[j]) continue;
             const unsigned int dig = digit0_of(r[j]);
             const bool f = dig > th || (dig == th && done);
             const bool t = dig == th && !done;
             if (!f && !t) continue;
             const long long v = v0 + (long long)j * kCollThreads;
-            TopkKey k;
-            k.hi = score_bits(r[j]);
-            k.lo = 0xffffffffu - (unsigned int)new2old[v];
-            k.v = (int)v;
+            TopkKey key;
+            key.hi = score_bits(r[j]);
+            key.lo = 0xffffffffu - (unsigned int)new2old[v];
+            key.v = (int)v;
             const unsigned int i = atomicAdd(f ? &s_nf : &s_nt, 1u);
             if (i < (unsigned int)kCollStage)
-                (f ? sf : stl)[i] = k;
+                (f ? sf : stl)[i] = key;
             else if (f)
-                fin[atomicAdd(&st->n_final, 1ull)] = k;
+                fin[atomicAdd(&st->n_final, 1ull)] = key;
             else
-                tie[atomicAdd(&st->n_tie, 1ull)] = k;
+                tie[atomicAdd(&st->n_tie, 1ull)] = key;
         }
+        if (++s >= steps) break;
+        load_keys<kCollPer, kCollThreads>(R, alive, lo + (long long)s * kStep + threadIdx.x, hi, r, al);
     }
     __syncthreads();
     const unsigned int cf = min(s_nf, (unsigned int)kCollStage), ct = min(s_nt, (unsigned int)kCollStage);
@@ -2651,218 +2705,6 @@ __global__ __launch_bounds__(kBlock) void k_final_rank(const TopkKey *fin, long 
     }
 }
 
-// 8-bit digit d (0..9) of a key below its first 16 bits: hi bits 47..0,
-// then lo bits 31..0.
-__device__ __forceinline__ unsigned int key_byte(unsigned long long hi, unsigned int lo, int d) {
-    return d < 6 ? (unsigned int)(hi >> (40 - 8 * d)) & 0xffu : (lo >> (24 - 8 * (d - 6))) & 0xffu;
-}
-
-// Common case: the final list plus the threshold bin hold at most
-// kSmallCap keys.  One block loads them into LDS, radix-selects the `take`
-// largest keys of the threshold bin with 8-bit digits (LDS histograms), and
-// bitonic-sorts the keff selected keys (descending; keys are unique since the
-// id is part of the key, so the order is exact).  flag = 1 if done here, 0
-// if the general path must run.
-static_assert(kSmallCap <= 4 * 1024, "the final sort holds at most four keys per thread");
-// Bitonic sort, descending, of the n2 (a power of two, >= E) keys of s2, by
-// all threads of the block; the first kf go out.  Thread t < n2 / E holds
-// positions [E t, E t + E): pairs closer than E are exchanged in registers,
-// pairs within a wavefront by shuffles, the others through LDS.  Only the key
-// moves: id and score are recovered from it (key = (score bits, 0xffffffff -
-// caller id), scores >= +0).
-template <int E>
-__device__ __forceinline__ void sort_desc_keys(TopkKey *s2, int n2, int kf, int32_t *out_ids, double *out_sc) {
-    const int tid = threadIdx.x;
-    const int T = n2 / E;
-    const bool part = tid < T;
-    TopkKey x[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) x[e] = part ? s2[E * tid + e] : s2[0];
-    for (int kk = 2; kk <= n2; kk <<= 1) {
-        for (int j = kk >> 1; j >= E; j >>= 1) {
-            const int tj = j / E;  // partner thread distance
-            const bool desc = ((E * tid) & kk) == 0;
-            const bool lower = (tid & tj) == 0;
-            if (tj >= 64) {
-                __syncthreads();
-                if (part) {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) s2[E * tid + e] = x[e];
-                }
-                __syncthreads();
-                if (part) {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const TopkKey o = s2[E * (tid ^ tj) + e];
-                        if ((lower == desc) ? key_gt(o, x[e]) : key_gt(x[e], o)) x[e] = o;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    TopkKey o;
-                    o.hi = (unsigned long long)__shfl_xor((long long)x[e].hi, tj);
-                    o.lo = (unsigned int)__shfl_xor((int)x[e].lo, tj);
-                    o.v = x[e].v;
-                    if (part && ((lower == desc) ? key_gt(o, x[e]) : key_gt(x[e], o))) x[e] = o;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = E / 2; j >= 1; j >>= 1) {
-            if (j >= kk) continue;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int f = e ^ j;
-                if (f <= e) continue;
-                // positions e < f of one thread; the lower keeps the larger key in a descending run
-                const bool desc = ((E * tid + e) & kk) == 0;
-                if (desc ? key_gt(x[f], x[e]) : key_gt(x[e], x[f])) {
-                    const TopkKey y = x[e];
-                    x[e] = x[f];
-                    x[f] = y;
-                }
-            }
-        }
-    }
-    if (part) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = E * tid + e;
-            if (p < kf) {
-                out_ids[p] = (int32_t)(0xffffffffu - x[e].lo);
-                out_sc[p] = __longlong_as_double((long long)x[e].hi);
-            }
-        }
-    }
-}
-
-// Selected lists up to this size are ordered by counting in k_topk_small
-// (each thread counts the keys above its own), larger ones by the bitonic sort
-// (one workgroup: counting does n^2 comparisons on a single CU).
-constexpr int kCountSmall = 256;
-
-__global__ __launch_bounds__(1024) void k_topk_small(const TopkState *st, const TopkKey *fin, const TopkKey *tie,
-                                                     long long keff, const double *R, const int32_t *new2old,
-                                                     int32_t *out_ids, double *out_sc, unsigned int *flag) {
-    __shared__ TopkKey s[kSmallCap], s2[kSmallCap];
-    __shared__ unsigned char mark[kSmallCap];  // 1 in, 0 out, 2 undecided
-    __shared__ unsigned int hcount[256];
-    __shared__ int s_bin, s_above, s_wsum[16];
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const long long nfl = (long long)st->n_final;
-    const long long ntl = st->done ? 0 : (long long)st->n_tie;
-    if (nfl + ntl > kSmallCap || nfl + ntl < keff) {
-        if (tid == 0) *flag = 0u;
-        return;
-    }
-    const int nf = (int)nfl, total = (int)(nfl + ntl), kf = (int)keff;
-    int pk = 1, pt = 1;
-    while (pk < kf) pk <<= 1;
-    while (pt < total) pt <<= 1;
-    // when every candidate fits the sort the kf selected keys need anyway,
-    // sort them all and skip the selection
-    const bool sort_all = pt == pk;
-    const int nsel = sort_all ? total : kf;
-    for (int i = tid; i < total; i += nthr) {
-        if (i < nf) {
-            s[i] = fin[i];
-            mark[i] = 1;
-        } else {
-            s[i] = tie[i - nf];
-            mark[i] = sort_all ? 1 : 2;
-        }
-    }
-    int need = sort_all ? 0 : kf - nf;  // threshold-bin keys still to take (uniform)
-    __syncthreads();
-    for (int d = 0; d < 10 && need > 0; ++d) {
-        for (int i = tid; i < 256; i += nthr) hcount[i] = 0u;
-        __syncthreads();
-        for (int i = nf + tid; i < total; i += nthr)
-            if (mark[i] == 2) atomicAdd(&hcount[key_byte(s[i].hi, s[i].lo, d)], 1u);
-        __syncthreads();
-        {
-            // descending bins: thread t < 256 holds bin 255 - t
-            const int mine = tid < 256 ? (int)hcount[255 - tid] : 0;
-            int incl = mine;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o);
-                if ((tid & 63) >= o) incl += y;
-            }
-            if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
-            __syncthreads();
-            for (int w = 0; w < (tid >> 6); ++w) incl += s_wsum[w];
-            if (tid < 256 && incl - mine < need && need <= incl) {
-                s_bin = 255 - tid;
-                s_above = incl - mine;
-            }
-            __syncthreads();
-        }
-        const int b = s_bin, above = s_above;
-        const bool whole = above + (int)hcount[b] == need;
-        for (int i = nf + tid; i < total; i += nthr) {
-            if (mark[i] == 2) {
-                const unsigned int dg = key_byte(s[i].hi, s[i].lo, d);
-                mark[i] = (dg > (unsigned int)b || (dg == (unsigned int)b && whole)) ? 1 : (dg < (unsigned int)b ? 0 : 2);
-            }
-        }
-        need = whole ? 0 : need - above;
-        __syncthreads();
-    }
-    // compact the selected keys (in index order) into s2
-    const int per = (total + nthr - 1) / nthr;
-    const int i0 = tid * per;
-    int cnt = 0;
-    for (int i = i0; i < min(total, i0 + per); ++i) cnt += mark[i] == 1 ? 1 : 0;
-    int incl = cnt;
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) s_wsum[wave] = incl;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wave; ++w) base += s_wsum[w];
-    int pos = base + incl - cnt;
-    for (int i = i0; i < min(total, i0 + per); ++i)
-        if (mark[i] == 1) s2[pos++] = s[i];
-    if (nsel <= kCountSmall) {
-        // a key's place is the number of selected keys above it (keys are
-        // unique): every thread counts over the list in LDS (broadcast reads)
-        __syncthreads();
-        for (int i = tid; i < nsel; i += nthr) {
-            const TopkKey me = s2[i];
-            int rank = 0;
-#pragma unroll 8
-            for (int j = 0; j < nsel; ++j) rank += key_gt(s2[j], me) ? 1 : 0;
-            if (rank < kf) {
-                out_ids[rank] = new2old[me.v];
-                out_sc[rank] = R[me.v];
-            }
-        }
-        if (tid == 0) *flag = 1u;
-        return;
-    }
-    const int n2 = sort_all ? pt : pk;
-    for (int i = nsel + tid; i < n2; i += nthr) {  // padding: below every real key (lo >= 2^31)
-        s2[i].hi = 0;
-        s2[i].lo = 0;
-        s2[i].v = -1;
-    }
-    __syncthreads();
-    if (n2 <= 1024)
-        sort_desc_keys<1>(s2, n2, kf, out_ids, out_sc);
-    else if (n2 <= 2048)
-        sort_desc_keys<2>(s2, n2, kf, out_ids, out_sc);
-    else
-        sort_desc_keys<4>(s2, n2, kf, out_ids, out_sc);
-    if (tid == 0) *flag = 1u;
-}
-
-
 // ------------------------------------------------------------ rank by counting
 // Ranking of a list of unique keys (the caller id is part of the key): a
 // key's rank is the number of keys above it.  A workgroup of 1024 threads
@@ -2876,6 +2718,15 @@ constexpr int kCountThreads = 1024;
 constexpr int kCountSubs = kCountThreads / 64;
 constexpr int kCountTile = 2048;
 constexpr int kRankMax = 65536;  // longest list ranked here (final lists beyond: k_final_rank)
+
+// 1 if the key (hi, lo) ranks above `me`, both halves compared without a
+// branch: a short-circuit test waits for the score half's LDS read before
+// issuing the id half's, which costs more than the extra read in the
+// latency-bound ranking of a few thousand candidates (k_topk_rank).  The long
+// lists of k_count_rank, bound by LDS issue instead, keep the short circuit.
+__device__ __forceinline__ int key_above(unsigned long long hi, unsigned int lo, const TopkKey &me) {
+    return (int)((hi > me.hi) | ((hi == me.hi) & (lo > me.lo)));
+}
 
 // The list a rank pass works on, and whether it is needed: the tie class of
 // the threshold bin (mode 0, skipped when the bin was taken whole or is too
@@ -2941,6 +2792,80 @@ __global__ __launch_bounds__(kCountThreads) void k_count_rank(const TopkKey *lis
     }
 }
 
+// Common case: the final list and the threshold bin's keys together, at most
+// `cap` candidates (the grid's 64 keys per workgroup), ordered by counting in
+// the same layout as k_count_rank.  The final list's keys all lie above the
+// bin's and keys are unique, so a candidate's place among all candidates is
+// its place in the top-k; places below keff are written as ids and scores,
+// recovered from the key (key = (score bits, 0xffffffff - caller id), scores
+// >= +0), into the compact output block.  No selection inside the bin is
+// needed.  flag = 1 when ranked here, 0 when the general path must run.
+__global__ __launch_bounds__(kCountThreads) void k_topk_rank(const TopkState *st, const TopkKey *fin,
+                                                             const TopkKey *tie, long long keff, long long cap,
+                                                             int32_t *out_ids, double *out_sc, unsigned int *flag,
+                                                             unsigned int *hist, unsigned int *coarse) {
+    __shared__ unsigned long long s_hi[kCountTile];
+    __shared__ unsigned int s_lo[kCountTile];
+    __shared__ int s_part[kCountSubs][kCountKeys];
+    // the level-0 histograms are no longer read: clear them for the next
+    // call (and for the refinement levels of the general path)
+    for (long long i = (long long)blockIdx.x * kCountThreads + threadIdx.x; i < kTopkBins / 4;
+         i += (long long)gridDim.x * kCountThreads)
+        ((uint4 *)hist)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x < 256) coarse[threadIdx.x] = 0u;
+    const long long nf = (long long)st->n_final;
+    const long long n = nf + (st->done ? 0 : (long long)st->n_tie);
+    const bool ok = n <= cap && n >= keff;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = ok ? 1u : 0u;
+    const long long base = (long long)blockIdx.x * kCountKeys;
+    if (!ok || base >= n) return;  // uniform per workgroup
+    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const long long i = base + lane;
+    TopkKey me;
+    me.hi = 0;
+    me.lo = 0;
+    me.v = -1;
+    if (i < n) me = i < nf ? fin[i] : tie[i - nf];
+    int cnt = 0;
+    for (long long t0 = 0; t0 < n; t0 += kCountTile) {
+        const int lim = (int)min((long long)kCountTile, n - t0);
+        if (t0) __syncthreads();  // the previous tile is done with LDS
+        for (int j = threadIdx.x; j < lim; j += kCountThreads) {
+            const long long q = t0 + j;
+            const TopkKey x = q < nf ? fin[q] : tie[q - nf];
+            s_hi[j] = x.hi;
+            s_lo[j] = x.lo;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int j = sub; j < lim; j += kCountSubs) cnt += key_above(s_hi[j], s_lo[j], me);
+    }
+    s_part[sub][lane] = cnt;
+    __syncthreads();
+    if (sub == 0 && i < n) {
+        long long rank = 0;
+#pragma unroll
+        for (int q = 0; q < kCountSubs; ++q) rank += s_part[q][lane];
+        if (rank < keff) {
+            out_ids[rank] = (int32_t)(0xffffffffu - me.lo);
+            out_sc[rank] = __longlong_as_double((long long)me.hi);
+        }
+    }
+}
+
+// Candidates the common path ranks at most: the kSmallCap floor, or twice the
+// requested count (the bin holding the k-th key rarely holds as many keys as
+// lie above it), in whole workgroups.  Counting costs the square of the
+// candidates, so beyond kUnionMax the general path (the threshold bin ranked
+// alone, then the final list) is cheaper: 0, and the ranking kernel runs as
+// one workgroup that only clears the histograms and sends the host there.
+constexpr long long kUnionMax = 20480;
+static long long rank_cap(long long keff) {
+    long long cap = std::max<long long>(kSmallCap, 2 * keff);
+    cap = (cap + kCountKeys - 1) / kCountKeys * kCountKeys;
+    return cap <= kUnionMax ? cap : 0;
+}
+
 static rs_status final_order(rs_graph *g, long long keff) {
     DeviceGraph &D = g->d;
     hipEvent_t ev;
@@ -2979,22 +2904,21 @@ static rs_status topk_common(rs_graph *g, long long keff) {
     const int grid_h = (int)((D.n + chunk - 1) / chunk);
     timing_begin(g, K_TOPK_HIST, &ev);
     hipLaunchKernelGGL(k_topk_hist, dim3(grid_h), dim3(kHistThreads), 0, g->stream, D.R, D.alive, D.n, chunk,
-                       D.thist, D.thist_c);
+                       D.thist, D.thist_c, D.tstate);
     timing_end(g, K_TOPK_HIST, ev);
-    timing_begin(g, K_TOPK_FIND, &ev);
-    hipLaunchKernelGGL(k_topk_find0, dim3(1), dim3(kBlock), 0, g->stream, D.thist, D.thist_c, D.tstate, keff);
-    timing_end(g, K_TOPK_FIND, ev);
     timing_begin(g, K_TOPK_COLLECT, &ev);
     long long cchunk = (D.n + 255) / 256;  // 64 to 256 blocks
     if (cchunk < 16384) cchunk = 16384;
     hipLaunchKernelGGL(k_topk_collect, dim3((int)((D.n + cchunk - 1) / cchunk)), dim3(kCollThreads), 0, g->stream,
-                       D.R, D.new2old, D.alive, D.n, cchunk, D.tstate, D.tfinal, D.ttie, D.thist);
+                       D.R, D.new2old, D.alive, D.n, cchunk, keff, D.thist, D.thist_c, D.tstate, D.tfinal, D.ttie);
     timing_end(g, K_TOPK_COLLECT, ev);
     const size_t sc_off = 16 + ((4 * (size_t)keff + 7) & ~(size_t)7);
     char *dblk = D.tblk;
+    const long long cap = rank_cap(keff);
     timing_begin(g, K_TOPK_RANK, &ev);
-    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, g->stream, D.tstate, D.tfinal, D.ttie, keff, D.R,
-                       D.new2old, (int32_t *)(dblk + 16), (double *)(dblk + sc_off), (unsigned int *)dblk);
+    hipLaunchKernelGGL(k_topk_rank, dim3((int)std::max<long long>(cap / kCountKeys, 1)), dim3(kCountThreads), 0,
+                       g->stream, D.tstate, D.tfinal, D.ttie, keff, cap, (int32_t *)(dblk + 16),
+                       (double *)(dblk + sc_off), (unsigned int *)dblk, D.thist, D.thist_c);
     timing_end(g, K_TOPK_RANK, ev);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(g->hpin, dblk, sc_off + 8 * (size_t)keff, hipMemcpyDeviceToHost, g->stream);
