@@ -3449,8 +3449,10 @@ rs_status launch_remove_vertices(rs_graph *g, const int32_t *d_verts, int64_t nv
 // every partial is what a full pass would give.
 
 // Compact the listed changed rows (removed entries are complemented, < 0):
-// one wavefront per row, 64 entries at a time (ballot and prefix); the freed
-// tail of the capacity is set to -1.
+// one wavefront per row, kCompactGroups groups of 64 entries loaded at once
+// (a hub's long row takes one round trip per 1,024 entries), each group
+// packed by a ballot and prefix; the freed tail of the capacity is set to -1.
+constexpr int kCompactGroups = 16;
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_t *deg, int32_t *col, int32_t *clab,
                                                          const int32_t *list, const unsigned long long *count) {
@@ -3462,16 +3464,16 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const OffT *off, int32_
         const long long rb = (long long)off[v];
         const int d = deg[v];
         int w = 0;
-        for (int j0 = 0; j0 < d; j0 += 256) {  // four groups of 64 entries loaded at once
-            int x[4], c[4];
+        for (int j0 = 0; j0 < d; j0 += 64 * kCompactGroups) {  // groups of 64 entries loaded at once
+            int x[kCompactGroups], c[kCompactGroups];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < kCompactGroups; ++t) {
                 const int j = j0 + 64 * t + lane;
                 x[t] = j < d ? col[rb + j] : -1;
                 c[t] = j < d ? clab[rb + j] : -1;
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < kCompactGroups; ++t) {
                 const unsigned long long m = __ballot(x[t] >= 0);
                 if (x[t] >= 0) {
                     const long long to = rb + w + __popcll(m & ((1ull << lane) - 1ull));
@@ -3755,6 +3757,19 @@ __device__ __forceinline__ void unit_range(long long n, long long &lo, long long
     hi = min(n, lo + per);
 }
 
+// The marks of kMarkPer vertices of a range per thread, loaded together (a
+// loop that tests each mark before loading the next waits for every load):
+// slots past the range load its last mark and are skipped by the caller.
+constexpr int kMarkPer = 8;
+__device__ __forceinline__ void load_marks(const unsigned int *vmark, long long v0, long long hi,
+                                           unsigned int (&mk)[kMarkPer]) {
+#pragma unroll
+    for (int j = 0; j < kMarkPer; ++j) {
+        const long long v = v0 + (long long)j * kBlock;
+        mk[j] = vmark[v < hi ? v : hi - 1];
+    }
+}
+
 // ucnt[r * gridDim.x + range]: rows 0..kScoreBins-1 tile vertices per bin,
 // row kScoreBins affected vertices.
 __global__ __launch_bounds__(kBlock) void k_units_count(const unsigned int *vmark, const int32_t *vrowb,
@@ -3766,17 +3781,23 @@ __global__ __launch_bounds__(kBlock) void k_units_count(const unsigned int *vmar
     long long lo, hi;
     unit_range(n, lo, hi);
     int aff = 0;
-    for (long long v = lo + threadIdx.x; v < hi; v += kBlock) {
-        const unsigned int m = vmark[v];
-        if (!m) continue;
-        if (m & kRowChanged) rflag[vrowb[v]] = 1;
-        if (m & kAffected) {
-            ++aff;
-            const int sc = vscore[v];
-            if (sc >= 0)
-                atomicAdd(&s_cnt[score_bin(goff[v + 1] - goff[v])], 1);
-            else
-                hflag[-1 - sc] = 1;
+    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += (long long)kMarkPer * kBlock) {
+        unsigned int mk[kMarkPer];
+        load_marks(vmark, v0, hi, mk);
+#pragma unroll
+        for (int j = 0; j < kMarkPer; ++j) {
+            const long long v = v0 + (long long)j * kBlock;
+            const unsigned int m = mk[j];
+            if (v >= hi || !m) continue;
+            if (m & kRowChanged) rflag[vrowb[v]] = 1;
+            if (m & kAffected) {
+                ++aff;
+                const int sc = vscore[v];
+                if (sc >= 0)
+                    atomicAdd(&s_cnt[score_bin(goff[v + 1] - goff[v])], 1);
+                else
+                    hflag[-1 - sc] = 1;
+            }
         }
     }
     if (aff) atomicAdd(&s_cnt[kScoreBins], aff);
@@ -3850,12 +3871,18 @@ __global__ __launch_bounds__(kBlock) void k_units_place(unsigned int *vmark, con
     __syncthreads();
     long long lo, hi;
     unit_range(n, lo, hi);
-    for (long long v = lo + threadIdx.x; v < hi; v += kBlock) {
-        const unsigned int m = vmark[v];
-        if (!m) continue;
-        vmark[v] = 0u;
-        if ((m & kAffected) && vscore[v] >= 0)
-            abin[atomicAdd(&s_cur[score_bin(goff[v + 1] - goff[v])], 1)] = (int32_t)v;
+    for (long long v0 = lo + threadIdx.x; v0 < hi; v0 += (long long)kMarkPer * kBlock) {
+        unsigned int mk[kMarkPer];
+        load_marks(vmark, v0, hi, mk);
+#pragma unroll
+        for (int j = 0; j < kMarkPer; ++j) {
+            const long long v = v0 + (long long)j * kBlock;
+            const unsigned int m = mk[j];
+            if (v >= hi || !m) continue;
+            vmark[v] = 0u;
+            if ((m & kAffected) && vscore[v] >= 0)
+                abin[atomicAdd(&s_cur[score_bin(goff[v + 1] - goff[v])], 1)] = (int32_t)v;
+        }
     }
 }
 
