@@ -813,44 +813,6 @@ struct ScoreArgs {
     const DevCounters *ctr;
 };
 
-// Index of c among the n ascending keys k[0..n), or -1.  Interpolation
-// search: a vertex's record keys are community ids spread over [0, k), so
-// the position of c is predicted from the keys at the two ends of the range
-// and the 16 keys around it (one memory line) are read together; a miss
-// narrows the range to one side of them.  Each step is two dependent loads,
-// and a near-uniform spread of keys needs one step.
-__device__ __forceinline__ int kfind(const int32_t *k, int n, int c) {
-    int lo = 0, hi = n;
-    while (hi - lo > 16) {
-        const int klo = k[lo], khi = k[hi - 1];
-        if (c < klo || c > khi) return -1;
-        const long long span = (long long)khi - klo;
-        const int guess = lo + (span > 0 ? (int)((long long)(c - klo) * (hi - 1 - lo) / span) : 0);
-        const int b = max(lo, min(guess - 7, hi - 16));
-        int x[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = k[b + j];
-        if (c < x[0]) {
-            hi = b;
-        } else if (c > x[15]) {
-            lo = b + 16;
-        } else {
-            int f = -1;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (x[j] == c) f = b + j;
-            return f;
-        }
-    }
-    int f = -1;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int x = lo + j;
-        if (x < hi && k[x] == c) f = x;
-    }
-    return f;
-}
-
 // Sorted-range helpers on LDS arrays.
 __device__ __forceinline__ int lds_lower(const int *a, int lo, int hi, int x) {
     while (lo < hi) {
@@ -897,48 +859,38 @@ __device__ __forceinline__ bool lds_has_out(const int *a, int n, int x) {
     return lo < n && a[lo] == x;
 }
 
-// Whether the out-list entries outl[o0, o1) in HBM hold the live id t: a
-// 16-ary search on the decoded ids (each step 15 independent loads); a list
-// of up to 16 entries is one step.
-// Position of the live id t in the sorted out-list outl[o0, o1) (removed
-// ids are complemented and keep their place), or -1: a 16-ary search.
+// Position of the live id t in the sorted out-list outl[o0, o1) in HBM
+// (removed ids are complemented and keep their place), or -1: a 16-ary
+// search on the decoded ids, each step 15 loads issued together (a list of up
+// to 16 entries is one step).  Probes past the range load its last entry and
+// are discarded after the load: a test before the load would make each
+// probe wait for the previous one.
 __device__ __forceinline__ long long out_find(const int32_t *outl, long long o0, long long o1, int t) {
     long long lo = o0, hi = o1;
+    if (hi <= lo) return -1;
     while (hi - lo > 16) {
         const long long st = (hi - lo + 15) >> 4;
+        int y[15];
+#pragma unroll
+        for (int j = 1; j < 16; ++j) y[j - 1] = outl[min(lo + j * st, hi - 1)];
         int cnt = 0;
 #pragma unroll
-        for (int j = 1; j < 16; ++j) {
-            const long long x = lo + j * st;
-            cnt += (x < hi && out_id(outl[x]) <= t) ? 1 : 0;
-        }
+        for (int j = 1; j < 16; ++j) cnt += (int)((lo + j * st < hi) & (out_id(y[j - 1]) <= t));
         lo += cnt * st;
         hi = min(hi, lo + st);
     }
+    int y[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) y[j] = outl[min(lo + j, hi - 1)];
     long long f = -1;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const long long x = lo + j;
-        if (x < hi && outl[x] == t) f = x;
-    }
+    for (int j = 0; j < 16; ++j)
+        if (lo + j < hi && y[j] == t) f = lo + j;
     return f;
 }
 
 __device__ __forceinline__ bool out_has(const int32_t *outl, long long o0, long long o1, int t) {
     return out_find(outl, o0, o1, t) >= 0;
-}
-
-// Slot of community c among a vertex's record keys: the card's first four
-// keys, else a 16-ary search of the key array (-1 if absent).
-__device__ __forceinline__ int card_find(const VCard &c, const int32_t *reckey, int x) {
-    if (c.m.ell <= 4) {
-        int sl = -1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (c.key[j] == x) sl = j;
-        return sl;
-    }
-    return kfind(reckey + c.off, c.m.ell, x);
 }
 
 // The type-II terms of the pair (u, w), w a foreign neighbour of u (Lemma 2,
