@@ -165,15 +165,18 @@ def test_lfr_small(rs):
 
 
 def test_topk_sort_widths(rs):
-    """Top-k sizes whose final sort holds one, two and four keys per thread
-    (k above 1,024 and 2,048), plus one beyond the single-block sort."""
+    """Top-k sizes on both sides of the common path's bound: up to k = 10,240
+    the final list and the threshold bin are ranked together by counting
+    across workgroups; beyond it (10,241 and 12,000, where the top-k also
+    reaches into the zero scores) the general path ranks the bin, then the
+    final list."""
     g = lfr(30000, 20.0, 800, 0.2, seed=4, cmin=20, cmax=2000)
     ora = oracle.score(g)
     from tests.parity import topk_matches
     h = rs.rs_load_graph(g.off, g.col, g.labels)
     try:
         rs.rs_score(h)
-        for k in (700, 1100, 2100, 3500, 6000):
+        for k in (700, 1100, 2100, 3500, 6000, 10240, 10241, 12000):
             ids, sc = rs.rs_topk(h, k)
             exp_ids, _ = oracle.topk(ora["R"], k)
             used = topk_matches(ids, exp_ids, ora["R"], k)
