@@ -676,7 +676,7 @@ def main():
                     help="removal requests timed after the steps (0: skip; default 200, 20 above 1e8 entries)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build scores one resident graph per device and "
+        print("bench.py measures one GPU only: the library scores one resident graph per device and "
               "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

@@ -1,5 +1,5 @@
 """bench.py's command-line contract on the CPU: more than one GPU is refused
-with a message (this build measures one device), and the help lists the
+with a message (the benchmark measures one device), and the help lists the
 workloads."""
 import os
 import subprocess
