@@ -2844,9 +2844,10 @@ static hipError_t copy_out(rs_graph *g, long long keff, int32_t *ids, double *sc
     return e;
 }
 
-// The common path of top-k: histogram, threshold, collect, and one
-// workgroup that ranks the candidates into a compact device block
-// [flag | ids | scores], copied once into pinned host memory.
+// The common path of top-k: the histogram, the collect (each block finds the
+// threshold itself), and the ranking of the candidates by counting across
+// workgroups into a compact device block [flag | ids | scores], copied once
+// into pinned host memory.
 static rs_status topk_common(rs_graph *g, long long keff) {
     DeviceGraph &D = g->d;
     hipEvent_t ev;
