@@ -783,7 +783,9 @@ def main():
         "load_s": load_s,
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom),
+            "frac": achieved / HBM_PEAK_GBS,
+            # the counters were taken on the whole graph; target mode scores another one
+            "traffic": measured_traffic(args.workload, dom) if not args.targets else None,
             "bytes_per_launch": kb[dom], "avg_us": avg_us[dom],
         },
         "kernels_us": {k: round(1000.0 * v[0] / v[1], 3) for k, v in timings.items() if v[1]},
